@@ -1,0 +1,152 @@
+/*
+ * chebfd -- Chebyshev-filtered subspace iteration for the plane-wave generalized eigenproblem
+ *           H x = lambda S x  (Levitt & Torrent, "Parallel eigensolvers in plane-wave Density
+ *           Functional Theory", arXiv:1406.4350), on AMD Instinct MI355X (gfx950).
+ *
+ * Operators (Sec. 2.1):
+ *   H = K + V_loc + P D P^H      (Eq. 2, Eq. 3)   K diagonal, V_loc a multiplication by V(r) in real
+ *                                                  space done with a pair of FFTs (Alg. 1), D block-
+ *                                                  diagonal over atoms (real symmetric blocks)
+ *   S = I + P Q P^H              (Eq. 4)           Q diagonal; S = I for norm-conserving problems
+ *   S^-1 = I - P (Q^-1 + P^H P)^-1 P^H            Woodbury form (Sec. 5.1)
+ * The paper writes real wavefunctions and P^T; everything here is complex Hermitian (P^H, X^H).
+ *
+ * FFT convention: psi(r_j) = sum_i c_i exp(+2 pi i g_i.j/n),
+ *                 (V_loc psi)_i = n^-3 sum_j exp(-2 pi i g_i.j/n) V_j psi(r_j).
+ *
+ * Layouts: a band block X is column-major, npw rows (sphere order) by nb columns, leading dimension
+ * ldx >= npw, elements interleaved complex: complex128 (double re, im) when the plan precision is
+ * CHEB_FP64, complex64 (float re, im) when it is CHEB_MIXED.
+ *
+ * Ownership: the caller owns every device buffer -- the plan's persistent buffer, the per-call workspace,
+ * inputs and outputs. Host arrays passed to cheb_plan_create are copied. After cheb_plan_create the
+ * library makes no device allocation of its own; the dense eigensolver runs inside the caller's
+ * workspace.
+ *
+ * Streams: every call enqueues its work on the given stream and returns. Exceptions, which synchronize
+ * the stream before returning: cheb_plan_create, cheb_set_projectors (factorisation status),
+ * cheb_rayleigh_ritz (eigensolver status), cheb_upper_bound (scalars).
+ *
+ * Errors: every function returns a cheb_status; argument errors are found before any launch and leave
+ * buffers untouched; cheb_last_error(plan) gives the message of the last failure on that plan. A plan is
+ * not thread-safe; distinct plans are independent.
+ */
+#ifndef CHEBFD_H
+#define CHEBFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cheb_plan_s* cheb_plan;
+
+typedef enum {
+  CHEB_OK = 0,
+  CHEB_ERR_ARG = 1,          /* invalid argument (null, size, layout, unsupported box size) */
+  CHEB_ERR_HIP = 2,          /* a HIP runtime / library call failed */
+  CHEB_ERR_WORKSPACE = 3,    /* workspace or persistent buffer smaller than required */
+  CHEB_ERR_NOT_PD = 4,       /* a matrix that must be Hermitian positive definite is not (S_X, capacitance) */
+  CHEB_ERR_EIG = 5,          /* the dense eigensolver did not converge */
+  CHEB_ERR_NONFINITE = 6,    /* NaN or Inf met in a subspace matrix */
+  CHEB_ERR_STATE = 7         /* potential, projectors or D not set yet */
+} cheb_status;
+
+typedef enum { CHEB_FP64 = 0, CHEB_MIXED = 1 } cheb_prec;
+
+typedef enum {
+  CHEB_OP_H = 0,        /* cheb_apply_H */
+  CHEB_OP_SINV = 1,     /* cheb_apply_Sinv, cheb_apply_S */
+  CHEB_OP_FILTER = 2,   /* cheb_filter */
+  CHEB_OP_RR = 3,       /* cheb_rayleigh_ritz, cheb_rayleigh_quotients */
+  CHEB_OP_BOUND = 4,    /* cheb_upper_bound (nb ignored) */
+  CHEB_OP_SETUP = 5     /* cheb_set_projectors (nb ignored) */
+} cheb_op;
+
+typedef struct {
+  int n;                          /* cubic FFT box side; supported: 8 12 16 24 32 48 64 96 128 */
+  int npw;                        /* plane waves in the sphere (Sec. 2.1) */
+  const int32_t* gidx_host;       /* npw x 3 Miller indices (gx, gy, gz), row-major, |g_c| <= (n-1)/2;
+                                     sorted by column (gx, gy), each column a run of consecutive gz */
+  const double* kin_host;         /* npw kinetic diagonal 1/2 |k + G|^2 in Hartree (Sec. 2.1) */
+  int natom;                      /* atoms; atom a owns projector columns [proj_off[a], proj_off[a+1]) */
+  const int32_t* proj_off_host;   /* natom + 1 offsets, proj_off[0] = 0, nondecreasing; nproj = proj_off[natom] */
+  int has_overlap;                /* 0: S = I (norm-conserving); 1: S = I + P Q P^H (PAW, Eq. 4) */
+  int prec;                       /* cheb_prec: CHEB_FP64 or CHEB_MIXED (complex64 bands, FFTs, recurrence
+                                     and projector GEMMs; FP64 capacitance inverse, subspace matrices and
+                                     dense eigensolver) */
+} cheb_desc;
+
+/* Size in bytes of the device buffer a plan keeps for its lifetime (index maps, twiddles, V(r), P, D, Q,
+ * P^H P, capacitance inverse). */
+cheb_status cheb_plan_persistent_bytes(const cheb_desc* desc, size_t* bytes);
+
+/* Create a plan over a caller-provided device buffer of at least cheb_plan_persistent_bytes bytes
+ * (256-byte aligned). Copies the host arrays of desc; synchronizes `stream`. */
+cheb_status cheb_plan_create(const cheb_desc* desc, void* persistent_dev, size_t bytes, hipStream_t stream,
+                             cheb_plan* out);
+cheb_status cheb_plan_destroy(cheb_plan plan);
+
+/* Local potential V(r_j) on the n^3 grid r_j = L j / n, real FP64, C order [x][y][z] (Sec. 2.1). */
+cheb_status cheb_set_potential(cheb_plan plan, const double* V_dev, hipStream_t stream);
+
+/* Projectors P (Eq. 3): complex128, column-major npw x nproj with leading dimension ldp >= npw.
+ * Q_dev: nproj FP64 overlap coefficients (Eq. 4, entries > 0), NULL iff has_overlap == 0.
+ * Forms P^H P and, with overlap, the capacitance matrix C = Q^-1 + P^H P and its FP64 inverse (Sec. 5.1)
+ * inside `ws` (cheb_workspace_bytes(CHEB_OP_SETUP)). Synchronizes; CHEB_ERR_NOT_PD if C is not
+ * positive definite. */
+cheb_status cheb_set_projectors(cheb_plan plan, const void* P_dev, int ldp, const double* Q_dev, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
+
+/* Per-atom blocks of D (Eq. 3): real symmetric n_a x n_a, n_a = proj_off[a+1] - proj_off[a], each
+ * row-major, concatenated over atoms, FP64. */
+cheb_status cheb_set_D(cheb_plan plan, const double* D_dev, hipStream_t stream);
+
+/* Workspace bytes a call of kind `op` with nb bands needs. */
+cheb_status cheb_workspace_bytes(cheb_plan plan, int op, int nb, size_t* bytes);
+
+/* Y = H X (Alg. 1). X and Y must not overlap. */
+cheb_status cheb_apply_H(cheb_plan plan, const void* X, int ldx, void* Y, int ldy, int nb, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+/* Y = S X (Alg. 1, Eq. 4). */
+cheb_status cheb_apply_S(cheb_plan plan, const void* X, int ldx, void* Y, int ldy, int nb, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+/* Y = S^-1 X by the Woodbury formula (Sec. 5.1). */
+cheb_status cheb_apply_Sinv(cheb_plan plan, const void* X, int ldx, void* Y, int ldy, int nb, void* ws,
+                            size_t ws_bytes, hipStream_t stream);
+
+/* In place: X <- T_m((S^-1 H - c)/r) X, the Chebyshev filter of Alg. 2 (recurrence of Sec. 4.2):
+ *   psi^0 = X, psi^1 = (A psi^0 - c psi^0)/r, psi^i = 2/r (A psi^(i-1) - c psi^(i-1)) - psi^(i-2),
+ * A = S^-1 H, unscaled. Projections P^H psi^i are carried in projector space with the reuse trick of
+ * Sec. 5.1 (one P^H and one P product per step). m >= 0 (m = 0 leaves X unchanged), r > 0. */
+cheb_status cheb_filter(cheb_plan plan, void* X, int ldx, int nb, int m, double c, double r, void* ws,
+                        size_t ws_bytes, hipStream_t stream);
+
+/* In place Rayleigh-Ritz (Alg. 2): H_X = X^H H X, S_X = X^H S X, H_X Z = S_X Z Lambda with
+ * Z^H S_X Z = I (FP64 generalized Hermitian eigensolver), X <- X Z. ritz_dev: nb FP64 Ritz values,
+ * ascending. resid_dev: NULL, or nb FP64 residual norms ||H x_i - lambda_i S x_i||_2 of the rotated
+ * block. Synchronizes; CHEB_ERR_NOT_PD if S_X is singular to working precision (rank-deficient X),
+ * CHEB_ERR_NONFINITE on NaN/Inf, CHEB_ERR_EIG if the eigensolver fails. */
+cheb_status cheb_rayleigh_ritz(cheb_plan plan, void* X, int ldx, int nb, double* ritz_dev, double* resid_dev,
+                               void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* rq_dev[i] = (x_i^H H x_i) / (x_i^H S x_i), FP64 (first step of Alg. 2). */
+cheb_status cheb_rayleigh_quotients(cheb_plan plan, const void* X, int ldx, int nb, double* rq_dev, void* ws,
+                                    size_t ws_bytes, hipStream_t stream);
+
+/* Upper bound of the spectrum by k steps of Lanczos on S^-1 H in the S inner product, started from the
+ * caller's vector v0_dev (npw elements, plan precision): max eigenvalue of the k x k tridiagonal plus the
+ * last off-diagonal norm (Sec. 5.3 names this alternative to E_cut). 1 <= k <= 64. Synchronizes. */
+cheb_status cheb_upper_bound(cheb_plan plan, int k, const void* v0_dev, double* lambda_plus_host, void* ws,
+                             size_t ws_bytes, hipStream_t stream);
+
+/* Message of the last failing call on `plan` ("" if none). Valid until the next call on the plan. */
+const char* cheb_last_error(cheb_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHEBFD_H */

@@ -1,0 +1,280 @@
+"""Thin Python binding of libchebfd.so (include/chebfd.h).
+
+The module-level functions carry the C names and only marshal arguments: torch tensors provide device
+memory and the current HIP stream, every computation runs in the library's HIP kernels. There is no CPU
+fallback: loading fails loudly when the library or a GPU is missing.
+
+Band blocks are torch tensors of shape (nb, npw), contiguous, complex128 (CHEB_FP64) or complex64
+(CHEB_MIXED): row b is band b, i.e. the column-major npw x nb block of the C ABI with ldx = npw.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchebfd.so")
+
+CHEB_OK, CHEB_ERR_ARG, CHEB_ERR_HIP, CHEB_ERR_WORKSPACE, CHEB_ERR_NOT_PD, CHEB_ERR_EIG, CHEB_ERR_NONFINITE, \
+    CHEB_ERR_STATE = range(8)
+STATUS_NAMES = ["CHEB_OK", "CHEB_ERR_ARG", "CHEB_ERR_HIP", "CHEB_ERR_WORKSPACE", "CHEB_ERR_NOT_PD", "CHEB_ERR_EIG",
+                "CHEB_ERR_NONFINITE", "CHEB_ERR_STATE"]
+CHEB_FP64, CHEB_MIXED = 0, 1
+CHEB_OP_H, CHEB_OP_SINV, CHEB_OP_FILTER, CHEB_OP_RR, CHEB_OP_BOUND, CHEB_OP_SETUP = range(6)
+
+# exported symbols, as declared in include/chebfd.h
+SYMBOLS = ["cheb_plan_persistent_bytes", "cheb_plan_create", "cheb_plan_destroy", "cheb_set_potential",
+           "cheb_set_projectors", "cheb_set_D", "cheb_workspace_bytes", "cheb_apply_H", "cheb_apply_S",
+           "cheb_apply_Sinv", "cheb_filter", "cheb_rayleigh_ritz", "cheb_rayleigh_quotients", "cheb_upper_bound",
+           "cheb_last_error"]
+
+
+class ChebError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str = ""):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{where}: {name}" + (f": {msg}" if msg else ""))
+
+
+class cheb_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("npw", ctypes.c_int), ("gidx_host", ctypes.c_void_p),
+                ("kin_host", ctypes.c_void_p), ("natom", ctypes.c_int), ("proj_off_host", ctypes.c_void_p),
+                ("has_overlap", ctypes.c_int), ("prec", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libchebfd.so and declare its signatures. Raises if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1406_4350_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, sz, i, d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "cheb_plan_persistent_bytes": [P(cheb_desc), P(sz)],
+        "cheb_plan_create": [P(cheb_desc), vp, sz, vp, P(vp)],
+        "cheb_plan_destroy": [vp],
+        "cheb_set_potential": [vp, vp, vp],
+        "cheb_set_projectors": [vp, vp, i, vp, vp, sz, vp],
+        "cheb_set_D": [vp, vp, vp],
+        "cheb_workspace_bytes": [vp, i, i, P(sz)],
+        "cheb_apply_H": [vp, vp, i, vp, i, i, vp, sz, vp],
+        "cheb_apply_S": [vp, vp, i, vp, i, i, vp, sz, vp],
+        "cheb_apply_Sinv": [vp, vp, i, vp, i, i, vp, sz, vp],
+        "cheb_filter": [vp, vp, i, i, i, d, d, vp, sz, vp],
+        "cheb_rayleigh_ritz": [vp, vp, i, i, vp, vp, vp, sz, vp],
+        "cheb_rayleigh_quotients": [vp, vp, i, i, vp, vp, sz, vp],
+        "cheb_upper_bound": [vp, i, vp, P(d), vp, sz, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.cheb_last_error.argtypes = [vp]
+    lib.cheb_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Plan:
+    """A plan over one problem (sphere, box, atoms, precision); owns its persistent device buffer."""
+
+    def __init__(self, gidx: np.ndarray, kin: np.ndarray, n: int, proj_off: np.ndarray, has_overlap: bool,
+                 prec: int = CHEB_FP64, device: str = "cuda"):
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("chebfd needs a GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device)
+        self._gidx = np.ascontiguousarray(gidx, dtype=np.int32)
+        self._kin = np.ascontiguousarray(kin, dtype=np.float64)
+        self._off = np.ascontiguousarray(proj_off, dtype=np.int32)
+        self.n, self.npw = int(n), int(self._gidx.shape[0])
+        self.natom = int(self._off.shape[0] - 1)
+        self.nproj = int(self._off[-1]) if self.natom > 0 else 0
+        self.prec = prec
+        self.dtype = torch.complex64 if prec == CHEB_MIXED else torch.complex128
+        self.desc = cheb_desc(self.n, self.npw, self._gidx.ctypes.data, self._kin.ctypes.data, self.natom,
+                              self._off.ctypes.data if self.natom > 0 else None, int(bool(has_overlap)), prec)
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.cheb_plan_persistent_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)),
+                    "cheb_plan_persistent_bytes", plan=False)
+        self.persistent = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        self._check(self.lib.cheb_plan_create(ctypes.byref(self.desc), self.persistent.data_ptr(), nbytes.value,
+                                              _stream(), ctypes.byref(h)), "cheb_plan_create", plan=False)
+        self.handle = h
+        self._ws = {}
+
+    # -- plumbing --------------------------------------------------------------------------------------------
+    def _check(self, st: int, where: str, plan: bool = True):
+        if st != CHEB_OK:
+            msg = ""
+            if plan and getattr(self, "handle", None):
+                msg = self.lib.cheb_last_error(self.handle).decode()
+            raise ChebError(st, where, msg)
+
+    def workspace(self, op: int, nb: int) -> torch.Tensor:
+        key = (op, nb)
+        if key not in self._ws:
+            nbytes = ctypes.c_size_t()
+            self._check(self.lib.cheb_workspace_bytes(self.handle, op, nb, ctypes.byref(nbytes)), "cheb_workspace_bytes")
+            self._ws[key] = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
+        return self._ws[key]
+
+    def _block(self, X: torch.Tensor, name: str) -> tuple[int, int]:
+        if X.dtype != self.dtype or X.device.type != "cuda" or X.dim() != 2 or X.shape[1] != self.npw:
+            raise ValueError(f"{name}: expected a (nb, {self.npw}) {self.dtype} CUDA tensor, got {tuple(X.shape)} "
+                             f"{X.dtype} on {X.device}")
+        if X.stride(1) != 1:
+            raise ValueError(f"{name}: rows must be contiguous")
+        return X.shape[0], X.stride(0)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.cheb_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- set-up ----------------------------------------------------------------------------------------------
+    def set_potential(self, V: torch.Tensor):
+        V = V.to(self.device, torch.float64).contiguous()
+        assert V.shape == (self.n,) * 3
+        self._check(self.lib.cheb_set_potential(self.handle, V.data_ptr(), _stream()), "cheb_set_potential")
+        self._V = V
+
+    def set_projectors(self, P: torch.Tensor, Q: torch.Tensor | None):
+        """P: (nproj, npw) complex128 (row j = projector j), Q: (nproj,) float64 or None."""
+        P = P.to(self.device, torch.complex128).contiguous()
+        Qd = None if Q is None else Q.to(self.device, torch.float64).contiguous()
+        ws = self.workspace(CHEB_OP_SETUP, self.nproj)
+        self._check(self.lib.cheb_set_projectors(self.handle, _ptr(P) if self.nproj else None, self.npw, _ptr(Qd),
+                                                 ws.data_ptr(), ws.numel(), _stream()), "cheb_set_projectors")
+        self._P, self._Q = P, Qd
+
+    def set_D(self, D: torch.Tensor):
+        D = D.to(self.device, torch.float64).contiguous()
+        self._check(self.lib.cheb_set_D(self.handle, _ptr(D) if D.numel() else None, _stream()), "cheb_set_D")
+        self._D = D
+
+    # -- operations ----------------------------------------------------------------------------------------------
+    def _apply(self, fn, op, X, Y):
+        nb, ldx = self._block(X, "X")
+        if Y is None:
+            Y = torch.empty_like(X)
+        _, ldy = self._block(Y, "Y")
+        ws = self.workspace(op, nb)
+        self._check(getattr(self.lib, fn)(self.handle, X.data_ptr(), ldx, Y.data_ptr(), ldy, nb, ws.data_ptr(),
+                                          ws.numel(), _stream()), fn)
+        return Y
+
+    def apply_H(self, X, Y=None):
+        return self._apply("cheb_apply_H", CHEB_OP_H, X, Y)
+
+    def apply_S(self, X, Y=None):
+        return self._apply("cheb_apply_S", CHEB_OP_SINV, X, Y)
+
+    def apply_Sinv(self, X, Y=None):
+        return self._apply("cheb_apply_Sinv", CHEB_OP_SINV, X, Y)
+
+    def filter(self, X, m: int, c: float, r: float):
+        nb, ldx = self._block(X, "X")
+        ws = self.workspace(CHEB_OP_FILTER, nb)
+        self._check(self.lib.cheb_filter(self.handle, X.data_ptr(), ldx, nb, int(m), float(c), float(r),
+                                         ws.data_ptr(), ws.numel(), _stream()), "cheb_filter")
+        return X
+
+    def rayleigh_ritz(self, X, with_residuals: bool = True):
+        nb, ldx = self._block(X, "X")
+        ritz = torch.empty(nb, dtype=torch.float64, device=self.device)
+        res = torch.empty(nb, dtype=torch.float64, device=self.device) if with_residuals else None
+        ws = self.workspace(CHEB_OP_RR, nb)
+        self._check(self.lib.cheb_rayleigh_ritz(self.handle, X.data_ptr(), ldx, nb, ritz.data_ptr(), _ptr(res),
+                                                ws.data_ptr(), ws.numel(), _stream()), "cheb_rayleigh_ritz")
+        return ritz, res
+
+    def rayleigh_quotients(self, X):
+        nb, ldx = self._block(X, "X")
+        rq = torch.empty(nb, dtype=torch.float64, device=self.device)
+        ws = self.workspace(CHEB_OP_RR, nb)
+        self._check(self.lib.cheb_rayleigh_quotients(self.handle, X.data_ptr(), ldx, nb, rq.data_ptr(),
+                                                     ws.data_ptr(), ws.numel(), _stream()), "cheb_rayleigh_quotients")
+        return rq
+
+    def upper_bound(self, v0: torch.Tensor, k: int = 10) -> float:
+        v0 = v0.to(self.device, self.dtype).contiguous()
+        assert v0.numel() == self.npw
+        ws = self.workspace(CHEB_OP_BOUND, 1)
+        out = ctypes.c_double()
+        self._check(self.lib.cheb_upper_bound(self.handle, int(k), v0.data_ptr(), ctypes.byref(out), ws.data_ptr(),
+                                              ws.numel(), _stream()), "cheb_upper_bound")
+        return out.value
+
+
+def plan_from_problem(pb, prec: int = CHEB_FP64, device: str = "cuda") -> Plan:
+    """Plan + potential + projectors + D for a workload.Problem (inputs copied to the device)."""
+    plan = Plan(pb.gidx, pb.kin, pb.cfg.n, pb.proj_off, pb.Q is not None, prec=prec, device=device)
+    plan.set_potential(torch.from_numpy(np.ascontiguousarray(pb.V)))
+    P = torch.from_numpy(np.ascontiguousarray(pb.P.T))  # (nproj, npw): row j = projector j
+    Q = None if pb.Q is None else torch.from_numpy(pb.Q)
+    plan.set_projectors(P, Q)
+    plan.set_D(torch.from_numpy(pb.D_packed))
+    return plan
+
+
+def to_device_block(X: np.ndarray, dtype, device="cuda") -> torch.Tensor:
+    """(npw, nb) numpy block -> (nb, npw) contiguous device tensor."""
+    return torch.from_numpy(np.ascontiguousarray(X.T)).to(device=device, dtype=dtype)
+
+
+def to_host_block(Xt: torch.Tensor) -> np.ndarray:
+    return Xt.detach().to("cpu", torch.complex128).numpy().T.copy()
+
+
+# C-named wrappers (argument marshalling only)
+def cheb_apply_H(plan: Plan, X, Y=None):
+    return plan.apply_H(X, Y)
+
+
+def cheb_apply_S(plan: Plan, X, Y=None):
+    return plan.apply_S(X, Y)
+
+
+def cheb_apply_Sinv(plan: Plan, X, Y=None):
+    return plan.apply_Sinv(X, Y)
+
+
+def cheb_filter(plan: Plan, X, m, c, r):
+    return plan.filter(X, m, c, r)
+
+
+def cheb_rayleigh_ritz(plan: Plan, X, with_residuals=True):
+    return plan.rayleigh_ritz(X, with_residuals)
+
+
+def cheb_rayleigh_quotients(plan: Plan, X):
+    return plan.rayleigh_quotients(X)
+
+
+def cheb_upper_bound(plan: Plan, v0, k=10):
+    return plan.upper_bound(v0, k)

@@ -1,0 +1,925 @@
+// C ABI of chebfd: plan set-up, operator application, Chebyshev filter, Rayleigh-Ritz, Lanczos bound.
+//
+// The host side here only validates arguments, carves caller-owned buffers and sequences kernels on the
+// caller's stream; every arithmetic step of the path runs on the GPU.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/chebfd.h"
+#include "kernels.h"
+
+using namespace chebfd;
+
+struct cheb_plan_s {
+  int n = 0, npw = 0, ncol = 0, rx = 0, natom = 0, nproj = 0, has_overlap = 0, prec = 0;
+  std::vector<int> proj_off;
+  size_t dsize = 0;  // number of doubles of the packed D blocks
+  // views into the persistent buffer
+  int4* col = nullptr;
+  int* ent = nullptr;
+  int4* pinfo = nullptr;
+  void* tw = nullptr;
+  void* kin = nullptr;
+  void* Vt = nullptr;
+  void* P = nullptr;
+  double* D = nullptr;
+  double* Q = nullptr;
+  c128* G = nullptr;
+  c128* Cinv = nullptr;
+  bool have_V = false, have_P = false, have_D = false;
+  int fft_batch = 1;
+  rocblas_handle rb = nullptr;
+  std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Carves aligned regions from a base pointer; with base == nullptr it only measures.
+struct Bump {
+  char* base;
+  size_t off = 0;
+  explicit Bump(void* b) : base(static_cast<char*>(b)) {}
+  template <typename X> X* take(size_t count) {
+    size_t at = off;
+    off = align_up(off + count * sizeof(X));
+    return base ? reinterpret_cast<X*>(base + at) : nullptr;
+  }
+};
+
+bool supported_n(int n) {
+  for (int v : {8, 12, 16, 24, 32, 48, 64, 96, 128})
+    if (v == n) return true;
+  return false;
+}
+
+cheb_status fail(cheb_plan p, cheb_status s, const std::string& msg) {
+  if (p) p->err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                                   \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess) return fail(p, CHEB_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define RBCHK(expr)                                                                                    \
+  do {                                                                                                 \
+    rocblas_status s_ = (expr);                                                                        \
+    if (s_ != rocblas_status_success)                                                                  \
+      return fail(p, CHEB_ERR_HIP, std::string(#expr) + ": " + rocblas_status_to_string(s_));          \
+  } while (0)
+
+#define CHK(expr)                                                                                      \
+  do {                                                                                                 \
+    cheb_status s_ = (expr);                                                                           \
+    if (s_ != CHEB_OK) return s_;                                                                      \
+  } while (0)
+
+size_t elem_bytes(int prec) { return prec == CHEB_MIXED ? sizeof(c64) : sizeof(c128); }
+
+// ---- layouts -------------------------------------------------------------------------------------------------
+struct Persist {
+  int4* col; int* ent; int4* pinfo; void* tw; void* kin; void* Vt; void* P; double* D; double* Q; c128* G; c128* Cinv;
+};
+
+Persist persist_layout(void* base, int n, int npw, int ncol, int nproj, size_t dsize, int overlap, int prec) {
+  Bump b(base);
+  Persist l{};
+  const bool mixed = prec == CHEB_MIXED;
+  l.col = b.take<int4>(ncol);
+  l.ent = b.take<int>(npw);
+  l.pinfo = b.take<int4>(std::max(nproj, 1));
+  l.tw = mixed ? (void*)b.take<c64>(n) : (void*)b.take<c128>(n);
+  l.kin = mixed ? (void*)b.take<float>(npw) : (void*)b.take<double>(npw);
+  l.Vt = mixed ? (void*)b.take<float>(size_t(n) * n * n) : (void*)b.take<double>(size_t(n) * n * n);
+  l.P = mixed ? (void*)b.take<c64>(size_t(npw) * nproj) : (void*)b.take<c128>(size_t(npw) * nproj);
+  l.D = b.take<double>(std::max<size_t>(dsize, 1));
+  l.Q = b.take<double>(std::max(nproj, 1));
+  l.G = b.take<c128>(size_t(nproj) * nproj);
+  l.Cinv = overlap ? b.take<c128>(size_t(nproj) * nproj) : nullptr;
+  (void)l;
+  return l;
+}
+
+size_t persist_bytes(int n, int npw, int ncol, int nproj, size_t dsize, int overlap, int prec) {
+  Bump b(nullptr);
+  const bool mixed = prec == CHEB_MIXED;
+  b.take<int4>(ncol);
+  b.take<int>(npw);
+  b.take<int4>(std::max(nproj, 1));
+  mixed ? (void)b.take<c64>(n) : (void)b.take<c128>(n);
+  mixed ? (void)b.take<float>(npw) : (void)b.take<double>(npw);
+  mixed ? (void)b.take<float>(size_t(n) * n * n) : (void)b.take<double>(size_t(n) * n * n);
+  mixed ? (void)b.take<c64>(size_t(npw) * nproj) : (void)b.take<c128>(size_t(npw) * nproj);
+  b.take<double>(std::max<size_t>(dsize, 1));
+  b.take<double>(std::max(nproj, 1));
+  b.take<c128>(size_t(nproj) * nproj);
+  if (overlap) b.take<c128>(size_t(nproj) * nproj);
+  return b.off;
+}
+
+size_t part_elems(int M, int N, int K) {
+  const int s = gemm_pick_splits(M, N, K);
+  return s > 1 ? size_t(s) * M * N : 0;
+}
+
+// Scratch of the FFT passes: two disk-column buffers for a batch of bands.
+struct FftWs { void* a; void* b; };
+
+// Every op's workspace, carved in one place so that sizes and pointers agree.
+struct Ws {
+  FftWs fft{};
+  void *W = nullptr, *loc = nullptr, *Ynew = nullptr, *R = nullptr;     // npw x nb, plan precision
+  void *v = nullptr, *vp = nullptr, *f = nullptr, *Hv = nullptr, *Sf = nullptr;  // Lanczos vectors
+  c128 *p0 = nullptr, *p1 = nullptr, *ploc = nullptr, *Dp = nullptr, *pphi = nullptr, *q = nullptr, *w = nullptr;
+  c128 *Hs = nullptr, *Ss = nullptr, *part = nullptr, *dots = nullptr, *dots2 = nullptr;
+  double *d = nullptr, *E = nullptr;
+  int* flags = nullptr;  // [0..1] rr_prepare flags, [2] solver info
+  void* solver = nullptr;
+  size_t solver_bytes = 0;
+  size_t total = 0;
+};
+
+int fft_batch_for(const cheb_plan_s* p, int nb) {
+  const size_t per_band = size_t(p->n) * p->ncol * elem_bytes(p->prec);
+  size_t cap = (96u << 20) / std::max<size_t>(per_band, 1);
+  if (cap < 1) cap = 1;
+  return int(std::min<size_t>(size_t(std::max(nb, 1)), cap));
+}
+
+cheb_status solver_query(cheb_plan p, int op, int nb, size_t* bytes);
+
+cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
+  Bump b(base);
+  const size_t eb = elem_bytes(p->prec);
+  const size_t vec = size_t(p->npw) * std::max(nb, 1) * eb;
+  const int np = p->nproj;
+  const size_t pp = size_t(std::max(np, 1)) * std::max(nb, 1);
+  const int fb = fft_batch_for(p, nb);
+  const size_t colb = size_t(fb) * p->n * p->ncol * eb;
+  size_t part = 0;
+  auto need_fft = [&]() { w->fft.a = b.take<char>(colb); w->fft.b = b.take<char>(colb); };
+  switch (op) {
+    case CHEB_OP_H:
+    case CHEB_OP_SINV: {
+      need_fft();
+      w->p0 = b.take<c128>(pp);
+      w->Dp = b.take<c128>(pp);
+      part = std::max(part_elems(np, nb, p->npw), part_elems(np, nb, np));
+      break;
+    }
+    case CHEB_OP_FILTER: {
+      need_fft();
+      w->W = b.take<char>(vec);
+      w->loc = b.take<char>(vec);
+      w->p0 = b.take<c128>(pp);
+      w->p1 = b.take<c128>(pp);
+      w->ploc = b.take<c128>(pp);
+      w->Dp = b.take<c128>(pp);
+      w->pphi = b.take<c128>(pp);
+      w->q = b.take<c128>(pp);
+      w->w = b.take<c128>(pp);
+      part = std::max(part_elems(np, nb, p->npw), part_elems(np, nb, np));
+      break;
+    }
+    case CHEB_OP_RR: {
+      need_fft();
+      w->loc = b.take<char>(vec);
+      w->Ynew = b.take<char>(vec);
+      w->R = b.take<char>(vec);
+      w->p0 = b.take<c128>(pp);
+      w->Dp = b.take<c128>(pp);
+      w->q = b.take<c128>(pp);
+      w->w = b.take<c128>(pp);
+      w->Hs = b.take<c128>(size_t(nb) * nb);
+      w->Ss = b.take<c128>(size_t(nb) * nb);
+      w->dots = b.take<c128>(std::max(nb, 1));
+      w->dots2 = b.take<c128>(std::max(nb, 1));
+      w->d = b.take<double>(std::max(nb, 1));
+      w->E = b.take<double>(std::max(nb, 1));
+      w->flags = b.take<int>(4);
+      part = std::max({part_elems(np, nb, p->npw), part_elems(nb, nb, p->npw), part_elems(nb, nb, np),
+                       part_elems(np, nb, nb)});
+      CHK(solver_query(p, CHEB_OP_RR, nb, &w->solver_bytes));
+      w->solver = b.take<char>(std::max<size_t>(w->solver_bytes, 1));
+      break;
+    }
+    case CHEB_OP_BOUND: {
+      need_fft();
+      const size_t v1 = size_t(p->npw) * eb;
+      w->v = b.take<char>(v1);
+      w->vp = b.take<char>(v1);
+      w->f = b.take<char>(v1);
+      w->Hv = b.take<char>(v1);
+      w->Sf = b.take<char>(v1);
+      w->p0 = b.take<c128>(std::max(np, 1));
+      w->Dp = b.take<c128>(std::max(np, 1));
+      w->dots = b.take<c128>(2);
+      part = std::max(part_elems(np, 1, p->npw), part_elems(np, 1, np));
+      break;
+    }
+    case CHEB_OP_SETUP: {
+      w->Hs = b.take<c128>(size_t(std::max(np, 1)) * std::max(np, 1));  // staging of C
+      w->flags = b.take<int>(4);
+      part = part_elems(np, np, p->npw);
+      CHK(solver_query(p, CHEB_OP_SETUP, np, &w->solver_bytes));
+      w->solver = b.take<char>(std::max<size_t>(w->solver_bytes, 1));
+      break;
+    }
+    default:
+      return fail(p, CHEB_ERR_ARG, "unknown op");
+  }
+  w->part = b.take<c128>(std::max<size_t>(part, 1));
+  w->total = b.off;
+  return CHEB_OK;
+}
+
+cheb_status solver_query(cheb_plan p, int op, int n, size_t* bytes) {
+  *bytes = 0;
+  if (n <= 0) return CHEB_OK;
+  RBCHK(rocblas_start_device_memory_size_query(p->rb));
+  if (op == CHEB_OP_RR) {
+    rocsolver_zhegvd(p->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, n, nullptr, n, nullptr, n,
+                     nullptr, nullptr, nullptr);
+  } else {
+    rocsolver_zpotrf(p->rb, rocblas_fill_lower, n, nullptr, n, nullptr);
+    rocsolver_zpotri(p->rb, rocblas_fill_lower, n, nullptr, n, nullptr);
+  }
+  size_t sz = 0;
+  RBCHK(rocblas_stop_device_memory_size_query(p->rb, &sz));
+  *bytes = sz;
+  return CHEB_OK;
+}
+
+cheb_status check_ws(cheb_plan p, int op, int nb, void* ws, size_t wsb, Ws* w) {
+  Ws probe;
+  CHK(ws_layout(p, op, nb, nullptr, &probe));
+  if (wsb < probe.total) return fail(p, CHEB_ERR_WORKSPACE, "workspace too small: need " + std::to_string(probe.total));
+  if (!ws) return fail(p, CHEB_ERR_ARG, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(p, CHEB_ERR_ARG, "workspace not 256-byte aligned");
+  return ws_layout(p, op, nb, ws, w);
+}
+
+cheb_status check_ready(cheb_plan p, bool need_all = true) {
+  if (!p->have_V) return fail(p, CHEB_ERR_STATE, "potential not set");
+  if (need_all && p->nproj > 0 && !p->have_P) return fail(p, CHEB_ERR_STATE, "projectors not set");
+  if (need_all && p->nproj > 0 && !p->have_D) return fail(p, CHEB_ERR_STATE, "D not set");
+  return CHEB_OK;
+}
+
+cheb_status check_block(cheb_plan p, const void* X, int ldx, int nb, const char* name) {
+  if (nb < 0) return fail(p, CHEB_ERR_ARG, std::string(name) + ": nb < 0");
+  if (nb > 0 && !X) return fail(p, CHEB_ERR_ARG, std::string(name) + " is null");
+  if (ldx < p->npw) return fail(p, CHEB_ERR_ARG, std::string(name) + ": leading dimension < npw");
+  return CHEB_OK;
+}
+
+// ---- operator pieces, templated on the band element type --------------------------------------------------------
+template <typename T> struct Ops {
+  using C = cx<T>;
+  cheb_plan p;
+  hipStream_t st;
+  FftGeom geom() const { return FftGeom{p->n, p->ncol, p->npw, p->rx, p->col, p->ent}; }
+  const C* P() const { return static_cast<const C*>(p->P); }
+
+  // out = (K + V_loc) X, batched over bands through the disk-column buffers
+  cheb_status hloc(const C* X, long ldx, int nb, C* out, long ldo, const FftWs& fw) {
+    const int fb = fft_batch_for(p, nb);
+    const FftGeom g = geom();
+    const C* tw = static_cast<const C*>(p->tw);
+    for (int b0 = 0; b0 < nb; b0 += fb) {
+      const int cnt = std::min(fb, nb - b0);
+      C* ca = static_cast<C*>(fw.a);
+      C* cb = static_cast<C*>(fw.b);
+      HIPCHK(fft_col_inverse<T>(g, tw, X + long(b0) * ldx, ldx, cnt, ca, st));
+      HIPCHK(fft_plane<T>(g, tw, static_cast<const T*>(p->Vt), ca, cb, cnt, st));
+      HIPCHK(fft_col_forward<T>(g, tw, cb, X + long(b0) * ldx, ldx, static_cast<const T*>(p->kin), out + long(b0) * ldo,
+                                ldo, cnt, st));
+    }
+    return CHEB_OK;
+  }
+
+  // pout (nproj x nb, c128) = P^H X
+  cheb_status project(const C* X, long ldx, int nb, c128* pout, c128* part) {
+    Epi<double> e;
+    e.out = pout;
+    e.ldo = p->nproj;
+    HIPCHK((gemm<T, T, T, double>(GEMM_CN, p->nproj, nb, p->npw, P(), p->npw, X, ldx, e,
+                                  gemm_pick_splits(p->nproj, nb, p->npw), part, st)));
+    return CHEB_OK;
+  }
+
+  // out = alpha P w + bL L (+ bU U + bW W): back-projection with the vector epilogue
+  cheb_status backproject(const c128* w, int nb, Epi<T> e) {
+    HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, p->nproj, P(), p->npw, w, p->nproj, e, 1, nullptr, st)));
+    return CHEB_OK;
+  }
+
+  // small projector-space product out = alpha M x (+ epilogue), M nproj x nproj (c128)
+  cheb_status small(const c128* M, const c128* x, int nb, Epi<double> e, c128* part) {
+    const int np = p->nproj;
+    HIPCHK((gemm<double, double, double, double>(GEMM_NN, np, nb, np, M, np, x, np, e, gemm_pick_splits(np, nb, np),
+                                                 part, st)));
+    return CHEB_OK;
+  }
+
+  cheb_status apply_H(const C* X, long ldx, C* Y, long ldy, int nb, const Ws& w) {
+    CHK(hloc(X, ldx, nb, Y, ldy, w.fft));
+    if (p->nproj == 0) return CHEB_OK;
+    CHK(project(X, ldx, nb, w.p0, w.part));
+    HIPCHK(block_diag_apply(p->nproj, nb, p->pinfo, p->D, w.p0, p->nproj, w.Dp, p->nproj, st));
+    Epi<T> e;
+    e.out = Y; e.ldo = ldy; e.alpha = 1.0;
+    e.L = Y; e.ldl = ldy; e.bL = 1.0;
+    return backproject(w.Dp, nb, e);
+  }
+
+  cheb_status apply_S(const C* X, long ldx, C* Y, long ldy, int nb, const Ws& w) {
+    if (!p->has_overlap || p->nproj == 0) {
+      HIPCHK((convert_copy<T, T>(p->npw, nb, X, ldx, Y, ldy, st)));
+      return CHEB_OK;
+    }
+    CHK(project(X, ldx, nb, w.p0, w.part));
+    HIPCHK(diag_apply(p->nproj, nb, p->Q, w.p0, p->nproj, w.Dp, p->nproj, st));
+    Epi<T> e;
+    e.out = Y; e.ldo = ldy; e.alpha = 1.0;
+    e.L = X; e.ldl = ldx; e.bL = 1.0;
+    return backproject(w.Dp, nb, e);
+  }
+
+  cheb_status apply_Sinv(const C* X, long ldx, C* Y, long ldy, int nb, const Ws& w) {
+    if (!p->has_overlap || p->nproj == 0) {
+      HIPCHK((convert_copy<T, T>(p->npw, nb, X, ldx, Y, ldy, st)));
+      return CHEB_OK;
+    }
+    CHK(project(X, ldx, nb, w.p0, w.part));
+    Epi<double> es;
+    es.out = w.Dp; es.ldo = p->nproj;
+    CHK(small(p->Cinv, w.p0, nb, es, w.part));
+    Epi<T> e;
+    e.out = Y; e.ldo = ldy; e.alpha = -1.0;
+    e.L = X; e.ldl = ldx; e.bL = 1.0;
+    return backproject(w.Dp, nb, e);
+  }
+
+  // Alg. 2 inner loop for the whole block. psi^i overwrites psi^(i-2); buffers alternate X, W.
+  cheb_status filter(C* X, long ldx, int nb, int m, double c, double r, const Ws& w) {
+    if (m == 0 || nb == 0) return CHEB_OK;
+    const int np = p->nproj;
+    const long npw = p->npw;
+    C* buf[2] = {X, static_cast<C*>(w.W)};
+    long ld[2] = {ldx, npw};
+    c128* pb[2] = {w.p0, w.p1};
+    C* loc = static_cast<C*>(w.loc);
+    if (np > 0) CHK(project(X, ldx, nb, pb[0], w.part));
+    for (int i = 1; i <= m; ++i) {
+      const int ci = (i - 1) & 1, oi = i & 1;
+      const C* cur = buf[ci];
+      C* out = buf[oi];
+      const double s1 = (i == 1 ? 1.0 : 2.0) / r;
+      const double s2 = (i == 1 ? 0.0 : 1.0);
+      CHK(hloc(cur, ld[ci], nb, loc, npw, w.fft));
+      if (np == 0) {
+        HIPCHK((axpbypcz<T>(npw, nb, s1, loc, npw, -s1 * c, cur, ld[ci], -s2, i == 1 ? nullptr : out, ld[oi], out,
+                            ld[oi], st)));
+        continue;
+      }
+      // projector space: p_loc = P^H loc; D p; p_phi = P^H H psi = p_loc + G D p
+      CHK(project(loc, npw, nb, w.ploc, w.part));
+      HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, pb[ci], np, w.Dp, np, st));
+      Epi<double> e1;
+      e1.out = w.pphi; e1.ldo = np; e1.L = w.ploc; e1.ldl = np; e1.bL = 1.0;
+      CHK(small(p->G, w.Dp, nb, e1, w.part));
+      const c128* wv = w.Dp;
+      if (p->has_overlap) {
+        // q = C^-1 p_phi; w = D p - q  (S^-1 H psi = loc + P w, Sec. 5.1)
+        Epi<double> e2;
+        e2.out = w.q; e2.ldo = np;
+        CHK(small(p->Cinv, w.pphi, nb, e2, w.part));
+        HIPCHK((axpbypcz<double>(np, nb, 1.0, w.Dp, np, -1.0, w.q, np, 0.0, nullptr, 0, w.w, np, st)));
+        wv = w.w;
+      }
+      // psi^i = s1 (loc + P w - c psi^(i-1)) - s2 psi^(i-2)
+      Epi<T> e;
+      e.out = out; e.ldo = ld[oi]; e.alpha = s1;
+      e.L = loc; e.ldl = npw; e.bL = s1;
+      e.U = cur; e.ldu = ld[ci]; e.bU = -s1 * c;
+      if (i > 1) { e.W = out; e.ldw = ld[oi]; e.bW = -s2; }
+      CHK(backproject(wv, nb, e));
+      // p^i = s1 (p_y - c p^(i-1)) - s2 p^(i-2), with p_y = P^H S^-1 H psi = p_phi - G q (reuse trick)
+      if (p->has_overlap) {
+        Epi<double> e3;
+        e3.out = pb[oi]; e3.ldo = np; e3.alpha = -s1;
+        e3.L = w.pphi; e3.ldl = np; e3.bL = s1;
+        e3.U = pb[ci]; e3.ldu = np; e3.bU = -s1 * c;
+        if (i > 1) { e3.W = pb[oi]; e3.ldw = np; e3.bW = -s2; }
+        CHK(small(p->G, w.q, nb, e3, w.part));
+      } else {
+        HIPCHK((axpbypcz<double>(np, nb, s1, w.pphi, np, -s1 * c, pb[ci], np, -s2, i == 1 ? nullptr : pb[oi], np,
+                                 pb[oi], np, st)));
+      }
+    }
+    if (m & 1) HIPCHK((convert_copy<T, T>(npw, nb, buf[1], npw, X, ldx, st)));
+    return CHEB_OK;
+  }
+
+  // H_X = X^H H X, S_X = X^H S X into w.Hs, w.Ss; leaves loc = (K + V) X and p = P^H X in the workspace
+  cheb_status subspace(const C* X, long ldx, int nb, const Ws& w) {
+    const int np = p->nproj;
+    const long npw = p->npw;
+    C* loc = static_cast<C*>(w.loc);
+    CHK(hloc(X, ldx, nb, loc, npw, w.fft));
+    Epi<double> eh;
+    eh.out = w.Hs; eh.ldo = nb;
+    HIPCHK((gemm<T, T, T, double>(GEMM_CN, nb, nb, p->npw, X, ldx, loc, npw, eh, gemm_pick_splits(nb, nb, p->npw),
+                                  w.part, st)));
+    Epi<double> es;
+    es.out = w.Ss; es.ldo = nb;
+    HIPCHK((gemm<T, T, T, double>(GEMM_CN, nb, nb, p->npw, X, ldx, X, ldx, es, gemm_pick_splits(nb, nb, p->npw),
+                                  w.part, st)));
+    if (np > 0) {
+      CHK(project(X, ldx, nb, w.p0, w.part));
+      HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, w.p0, np, w.Dp, np, st));
+      Epi<double> e2;
+      e2.out = w.Hs; e2.ldo = nb; e2.L = w.Hs; e2.ldl = nb; e2.bL = 1.0;
+      HIPCHK((gemm<double, double, double, double>(GEMM_CN, nb, nb, np, w.p0, np, w.Dp, np, e2,
+                                                   gemm_pick_splits(nb, nb, np), w.part, st)));
+      if (p->has_overlap) {
+        HIPCHK(diag_apply(np, nb, p->Q, w.p0, np, w.q, np, st));
+        Epi<double> e3;
+        e3.out = w.Ss; e3.ldo = nb; e3.L = w.Ss; e3.ldl = nb; e3.bL = 1.0;
+        HIPCHK((gemm<double, double, double, double>(GEMM_CN, nb, nb, np, w.p0, np, w.q, np, e3,
+                                                     gemm_pick_splits(nb, nb, np), w.part, st)));
+      }
+    }
+    return CHEB_OK;
+  }
+
+  cheb_status rayleigh_ritz(C* X, long ldx, int nb, double* ritz, double* resid, const Ws& w) {
+    const int np = p->nproj;
+    const long npw = p->npw;
+    CHK(subspace(X, ldx, nb, w));
+    HIPCHK((fill_zero<float>(reinterpret_cast<c64*>(w.flags), 2, st)));
+    HIPCHK(rr_prepare(nb, w.Hs, w.Ss, w.d, w.flags, st));
+    int flags[3] = {0, 0, 0};
+    HIPCHK(hipMemcpyAsync(flags, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (flags[1]) return fail(p, CHEB_ERR_NONFINITE, "non-finite entry in the subspace matrices");
+    if (flags[0]) return fail(p, CHEB_ERR_NOT_PD, "X^H S X has a non-positive diagonal (zero or non-finite column)");
+    RBCHK(rocblas_set_stream(p->rb, st));
+    RBCHK(rocblas_set_workspace(p->rb, w.solver, w.solver_bytes));
+    rocblas_status rs = rocsolver_zhegvd(p->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, nb,
+                                         reinterpret_cast<rocblas_double_complex*>(w.Hs), nb,
+                                         reinterpret_cast<rocblas_double_complex*>(w.Ss), nb, ritz, w.E, w.flags + 2);
+    rocblas_set_workspace(p->rb, nullptr, 0);
+    if (rs != rocblas_status_success)
+      return fail(p, CHEB_ERR_HIP, std::string("rocsolver_zhegvd: ") + rocblas_status_to_string(rs));
+    HIPCHK(hipMemcpyAsync(flags + 2, w.flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (flags[2] > nb) return fail(p, CHEB_ERR_NOT_PD, "X^H S X is not positive definite (rank-deficient block)");
+    if (flags[2] > 0) return fail(p, CHEB_ERR_EIG, "generalized eigensolver did not converge");
+    // Z = diag(d) Z' undoes the symmetric column scaling
+    HIPCHK(scale_rows(nb, nb, w.Hs, nb, w.d, st));
+    C* Ynew = static_cast<C*>(w.Ynew);
+    Epi<T> er;
+    er.out = Ynew; er.ldo = npw;
+    HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, nb, X, ldx, w.Hs, nb, er, 1, nullptr, st)));
+    if (resid) {
+      // H u - lambda S u = loc Z + P (D pZ - lambda Q pZ) - lambda u
+      C* R = static_cast<C*>(w.R);
+      Epi<T> e1;
+      e1.out = R; e1.ldo = npw;
+      HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, nb, static_cast<C*>(w.loc), npw, w.Hs, nb, e1, 1, nullptr,
+                                    st)));
+      if (np > 0) {
+        Epi<double> ez;
+        ez.out = w.q; ez.ldo = np;
+        HIPCHK((gemm<double, double, double, double>(GEMM_NN, np, nb, nb, w.p0, np, w.Hs, nb, ez,
+                                                     gemm_pick_splits(np, nb, nb), w.part, st)));
+        HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, w.q, np, w.Dp, np, st));
+        const c128* t = w.Dp;
+        if (p->has_overlap) {
+          HIPCHK(diag_apply(np, nb, p->Q, w.q, np, w.w, np, st));
+          HIPCHK(sub_scaled_cols(np, nb, w.Dp, w.w, ritz, w.w, st));
+          t = w.w;
+        }
+        Epi<T> e2;
+        e2.out = R; e2.ldo = npw; e2.L = R; e2.ldl = npw; e2.bL = 1.0;
+        CHK(backproject(t, nb, e2));
+      }
+      HIPCHK((col_resid_norms<T>(npw, nb, R, npw, Ynew, npw, ritz, resid, st)));
+    }
+    HIPCHK((convert_copy<T, T>(npw, nb, Ynew, npw, X, ldx, st)));
+    return CHEB_OK;
+  }
+
+  cheb_status rayleigh_quotients(const C* X, long ldx, int nb, double* rq, const Ws& w) {
+    // reuse the RR workspace: loc <- H X, R <- S X
+    C* HX = static_cast<C*>(w.loc);
+    C* SX = static_cast<C*>(w.R);
+    const long npw = p->npw;
+    CHK(apply_H(X, ldx, HX, npw, nb, w));
+    CHK(apply_S(X, ldx, SX, npw, nb, w));
+    HIPCHK((col_dots<T>(npw, nb, X, ldx, HX, npw, w.dots, st)));
+    HIPCHK((col_dots<T>(npw, nb, X, ldx, SX, npw, w.dots2, st)));
+    HIPCHK(ratio_real(nb, w.dots, w.dots2, rq, st));
+    return CHEB_OK;
+  }
+
+  cheb_status dot_host(const C* x, const C* y, const Ws& w, double* re) {
+    HIPCHK((col_dots<T>(p->npw, 1, x, p->npw, y, p->npw, w.dots, st)));
+    c128 h;
+    HIPCHK(hipMemcpyAsync(&h, w.dots, sizeof(c128), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *re = h.x;
+    return CHEB_OK;
+  }
+
+  cheb_status upper_bound(int k, const C* v0, double* out, const Ws& w) {
+    const long npw = p->npw;
+    C* v = static_cast<C*>(w.v);
+    C* vp = static_cast<C*>(w.vp);
+    C* f = static_cast<C*>(w.f);
+    C* Hv = static_cast<C*>(w.Hv);
+    C* Sf = static_cast<C*>(w.Sf);
+    CHK(apply_S(v0, npw, Sf, npw, 1, w));
+    double nrm2 = 0.0;
+    CHK(dot_host(v0, Sf, w, &nrm2));
+    if (!(nrm2 > 0.0) || !std::isfinite(nrm2)) return fail(p, CHEB_ERR_ARG, "v0 has zero or non-finite S-norm");
+    HIPCHK((axpbypcz<T>(npw, 1, 1.0 / std::sqrt(nrm2), v0, npw, 0.0, nullptr, 0, 0.0, nullptr, 0, v, npw, st)));
+    HIPCHK((fill_zero<T>(vp, npw, st)));
+    std::vector<double> alpha, beta;
+    double b = 0.0;
+    for (int j = 0; j < k; ++j) {
+      CHK(apply_H(v, npw, Hv, npw, 1, w));
+      CHK(apply_Sinv(Hv, npw, f, npw, 1, w));
+      double a = 0.0;
+      CHK(dot_host(v, Hv, w, &a));
+      HIPCHK((axpbypcz<T>(npw, 1, 1.0, f, npw, -a, v, npw, -b, vp, npw, f, npw, st)));
+      CHK(apply_S(f, npw, Sf, npw, 1, w));
+      double bb = 0.0;
+      CHK(dot_host(f, Sf, w, &bb));
+      b = std::sqrt(std::max(bb, 0.0));
+      alpha.push_back(a);
+      beta.push_back(b);
+      if (!(b > 0.0)) break;  // invariant subspace found: T is exact
+      std::swap(v, vp);       // vp <- old v
+      HIPCHK((axpbypcz<T>(npw, 1, 1.0 / b, f, npw, 0.0, nullptr, 0, 0.0, nullptr, 0, v, npw, st)));
+    }
+    // largest eigenvalue of the symmetric tridiagonal T (alpha, beta[0..k-2]) by Sturm-count bisection
+    const int kk = int(alpha.size());
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < kk; ++i) {
+      const double rad = (i > 0 ? std::fabs(beta[i - 1]) : 0.0) + (i + 1 < kk ? std::fabs(beta[i]) : 0.0);
+      lo = std::min(lo, alpha[i] - rad);
+      hi = std::max(hi, alpha[i] + rad);
+    }
+    auto count_below = [&](double x) {  // eigenvalues < x
+      int cnt = 0;
+      double d = 1.0;
+      for (int i = 0; i < kk; ++i) {
+        const double off = i > 0 ? beta[i - 1] * beta[i - 1] : 0.0;
+        d = alpha[i] - x - (i > 0 ? off / d : 0.0);
+        if (d == 0.0) d = -1e-300;
+        if (d < 0.0) ++cnt;
+      }
+      return cnt;
+    };
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi)); ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (count_below(mid) >= kk) hi = mid; else lo = mid;
+    }
+    *out = hi + beta.back();
+    return CHEB_OK;
+  }
+};
+
+template <typename F> cheb_status with_prec(cheb_plan p, hipStream_t st, F&& f) {
+  if (p->prec == CHEB_MIXED) return f(Ops<float>{p, st});
+  return f(Ops<double>{p, st});
+}
+
+}  // namespace
+
+// ======================================= C ABI ==================================================================
+extern "C" {
+
+static cheb_status validate_desc(const cheb_desc* d, int* ncol_out, int* rx_out, size_t* dsize_out,
+                                 std::string* msg) {
+  if (!d) { *msg = "desc is null"; return CHEB_ERR_ARG; }
+  if (!supported_n(d->n)) { *msg = "unsupported FFT box size " + std::to_string(d->n); return CHEB_ERR_ARG; }
+  if (d->npw <= 0) { *msg = "npw must be positive"; return CHEB_ERR_ARG; }
+  if (!d->gidx_host || !d->kin_host) { *msg = "gidx_host / kin_host is null"; return CHEB_ERR_ARG; }
+  if (d->prec != CHEB_FP64 && d->prec != CHEB_MIXED) { *msg = "unknown precision"; return CHEB_ERR_ARG; }
+  if (d->natom < 0 || (d->natom > 0 && !d->proj_off_host)) { *msg = "bad natom / proj_off_host"; return CHEB_ERR_ARG; }
+  const int hmax = (d->n - 1) / 2;
+  int ncol = 0, rx = 0;
+  for (int e = 0; e < d->npw; ++e) {
+    const int32_t* g = d->gidx_host + 3 * e;
+    for (int c = 0; c < 3; ++c)
+      if (g[c] < -hmax || g[c] > hmax) { *msg = "Miller index outside the FFT box at entry " + std::to_string(e); return CHEB_ERR_ARG; }
+    if (!std::isfinite(d->kin_host[e])) { *msg = "non-finite kinetic entry"; return CHEB_ERR_ARG; }
+    rx = std::max(rx, std::abs(g[0]));
+    if (e == 0) { ncol = 1; continue; }
+    const int32_t* h = g - 3;
+    if (g[0] == h[0] && g[1] == h[1]) {
+      if (g[2] != h[2] + 1) { *msg = "g-list column not a run of consecutive gz at entry " + std::to_string(e); return CHEB_ERR_ARG; }
+    } else {
+      if (g[0] < h[0] || (g[0] == h[0] && g[1] < h[1])) { *msg = "g-list not sorted by column (gx, gy) at entry " + std::to_string(e); return CHEB_ERR_ARG; }
+      ++ncol;
+    }
+  }
+  if (ncol >= (1 << 22)) { *msg = "too many columns"; return CHEB_ERR_ARG; }
+  if (fft_plane_lds_bytes(d->n, rx, d->prec != CHEB_MIXED) > 160 * 1024) {
+    *msg = "sphere too wide in x for the plane pass in 160 KB of LDS";
+    return CHEB_ERR_ARG;
+  }
+  size_t dsize = 0;
+  if (d->natom > 0) {
+    if (d->proj_off_host[0] != 0) { *msg = "proj_off[0] must be 0"; return CHEB_ERR_ARG; }
+    for (int a = 0; a < d->natom; ++a) {
+      const int na = d->proj_off_host[a + 1] - d->proj_off_host[a];
+      if (na < 0) { *msg = "proj_off must be nondecreasing"; return CHEB_ERR_ARG; }
+      dsize += size_t(na) * na;
+    }
+  }
+  *ncol_out = ncol;
+  *rx_out = rx;
+  *dsize_out = dsize;
+  return CHEB_OK;
+}
+
+cheb_status cheb_plan_persistent_bytes(const cheb_desc* d, size_t* bytes) {
+  if (!bytes) return CHEB_ERR_ARG;
+  int ncol = 0, rx = 0;
+  size_t dsize = 0;
+  std::string msg;
+  cheb_status s = validate_desc(d, &ncol, &rx, &dsize, &msg);
+  if (s != CHEB_OK) return s;
+  const int nproj = d->natom > 0 ? d->proj_off_host[d->natom] : 0;
+  *bytes = persist_bytes(d->n, d->npw, ncol, nproj, dsize, d->has_overlap ? 1 : 0, d->prec);
+  return CHEB_OK;
+}
+
+cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes, hipStream_t st, cheb_plan* out) {
+  if (!out) return CHEB_ERR_ARG;
+  *out = nullptr;
+  int ncol = 0, rx = 0;
+  size_t dsize = 0;
+  std::string msg;
+  cheb_status s = validate_desc(d, &ncol, &rx, &dsize, &msg);
+  if (s != CHEB_OK) { std::fprintf(stderr, "cheb_plan_create: %s\n", msg.c_str()); return s; }
+  const int nproj = d->natom > 0 ? d->proj_off_host[d->natom] : 0;
+  const size_t need = persist_bytes(d->n, d->npw, ncol, nproj, dsize, d->has_overlap ? 1 : 0, d->prec);
+  if (!persistent || bytes < need || reinterpret_cast<uintptr_t>(persistent) % kAlign) return CHEB_ERR_WORKSPACE;
+
+  cheb_plan p = new (std::nothrow) cheb_plan_s;
+  if (!p) return CHEB_ERR_ARG;
+  p->n = d->n; p->npw = d->npw; p->ncol = ncol; p->rx = rx; p->natom = d->natom; p->nproj = nproj;
+  p->has_overlap = d->has_overlap ? 1 : 0; p->prec = d->prec; p->dsize = dsize;
+  p->proj_off.assign(d->proj_off_host, d->proj_off_host + (d->natom > 0 ? d->natom + 1 : 0));
+  Persist l = persist_layout(persistent, d->n, d->npw, ncol, nproj, dsize, p->has_overlap, d->prec);
+  p->col = l.col; p->ent = l.ent; p->pinfo = l.pinfo; p->tw = l.tw; p->kin = l.kin; p->Vt = l.Vt; p->P = l.P;
+  p->D = l.D; p->Q = l.Q; p->G = l.G; p->Cinv = l.Cinv;
+
+  // host-side index maps
+  std::vector<int4> col(ncol);
+  std::vector<int> ent(d->npw);
+  int c = -1;
+  for (int e = 0; e < d->npw; ++e) {
+    const int32_t* g = d->gidx_host + 3 * e;
+    if (e == 0 || g[0] != g[-3] || g[1] != g[-2]) {
+      ++c;
+      col[c] = int4{g[0] + rx, (g[1] % d->n + d->n) % d->n, e, 0};
+    }
+    col[c].w += 1;
+    ent[e] = (c << 8) | ((g[2] % d->n + d->n) % d->n);
+  }
+  std::vector<int4> pinfo(std::max(nproj, 1), int4{0, 0, 0, 0});
+  size_t doff = 0;
+  for (int a = 0; a < d->natom; ++a) {
+    const int o = d->proj_off_host[a], na = d->proj_off_host[a + 1] - o;
+    for (int i = 0; i < na; ++i) pinfo[o + i] = int4{o, na, int(doff), 0};
+    doff += size_t(na) * na;
+  }
+  const bool mixed = d->prec == CHEB_MIXED;
+  std::vector<c128> tw(d->n);
+  for (int j = 0; j < d->n; ++j) {
+    const double a = -2.0 * M_PI * double(j) / double(d->n);
+    tw[j] = c128{std::cos(a), std::sin(a)};
+  }
+  auto fail_hip = [&](hipError_t e, const char* what) {
+    std::fprintf(stderr, "cheb_plan_create: %s: %s\n", what, hipGetErrorString(e));
+    delete p;
+    return CHEB_ERR_HIP;
+  };
+  hipError_t e;
+  if ((e = hipMemcpyAsync(p->col, col.data(), sizeof(int4) * ncol, hipMemcpyHostToDevice, st))) return fail_hip(e, "col");
+  if ((e = hipMemcpyAsync(p->ent, ent.data(), sizeof(int) * d->npw, hipMemcpyHostToDevice, st))) return fail_hip(e, "ent");
+  if ((e = hipMemcpyAsync(p->pinfo, pinfo.data(), sizeof(int4) * pinfo.size(), hipMemcpyHostToDevice, st))) return fail_hip(e, "pinfo");
+  if (mixed) {
+    std::vector<c64> tw32(d->n);
+    std::vector<float> kin32(d->npw);
+    for (int j = 0; j < d->n; ++j) tw32[j] = c64{float(tw[j].x), float(tw[j].y)};
+    for (int i = 0; i < d->npw; ++i) kin32[i] = float(d->kin_host[i]);
+    if ((e = hipMemcpyAsync(p->tw, tw32.data(), sizeof(c64) * d->n, hipMemcpyHostToDevice, st))) return fail_hip(e, "tw");
+    if ((e = hipMemcpyAsync(p->kin, kin32.data(), sizeof(float) * d->npw, hipMemcpyHostToDevice, st))) return fail_hip(e, "kin");
+    if ((e = hipStreamSynchronize(st))) return fail_hip(e, "sync");
+  } else {
+    if ((e = hipMemcpyAsync(p->tw, tw.data(), sizeof(c128) * d->n, hipMemcpyHostToDevice, st))) return fail_hip(e, "tw");
+    if ((e = hipMemcpyAsync(p->kin, d->kin_host, sizeof(double) * d->npw, hipMemcpyHostToDevice, st))) return fail_hip(e, "kin");
+    if ((e = hipStreamSynchronize(st))) return fail_hip(e, "sync");
+  }
+  if ((e = fft_prepare_attributes())) return fail_hip(e, "kernel attributes");
+  if (rocblas_create_handle(&p->rb) != rocblas_status_success) {
+    std::fprintf(stderr, "cheb_plan_create: rocblas_create_handle failed\n");
+    delete p;
+    return CHEB_ERR_HIP;
+  }
+  *out = p;
+  return CHEB_OK;
+}
+
+cheb_status cheb_plan_destroy(cheb_plan p) {
+  if (!p) return CHEB_OK;
+  if (p->rb) rocblas_destroy_handle(p->rb);
+  delete p;
+  return CHEB_OK;
+}
+
+const char* cheb_last_error(cheb_plan p) { return p ? p->err.c_str() : "null plan"; }
+
+cheb_status cheb_set_potential(cheb_plan p, const double* V, hipStream_t st) {
+  if (!p) return CHEB_ERR_ARG;
+  if (!V) return fail(p, CHEB_ERR_ARG, "V is null");
+  if (p->prec == CHEB_MIXED) HIPCHK(transpose_potential<float>(p->n, V, static_cast<float*>(p->Vt), st));
+  else HIPCHK(transpose_potential<double>(p->n, V, static_cast<double*>(p->Vt), st));
+  p->have_V = true;
+  return CHEB_OK;
+}
+
+cheb_status cheb_set_D(cheb_plan p, const double* D, hipStream_t st) {
+  if (!p) return CHEB_ERR_ARG;
+  if (p->dsize == 0) { p->have_D = true; return CHEB_OK; }
+  if (!D) return fail(p, CHEB_ERR_ARG, "D is null");
+  HIPCHK(hipMemcpyAsync(p->D, D, sizeof(double) * p->dsize, hipMemcpyDeviceToDevice, st));
+  p->have_D = true;
+  return CHEB_OK;
+}
+
+cheb_status cheb_workspace_bytes(cheb_plan p, int op, int nb, size_t* bytes) {
+  if (!p || !bytes) return CHEB_ERR_ARG;
+  if (nb < 0) return fail(p, CHEB_ERR_ARG, "nb < 0");
+  Ws w;
+  CHK(ws_layout(p, op, op == CHEB_OP_BOUND ? 1 : nb, nullptr, &w));
+  *bytes = w.total;
+  return CHEB_OK;
+}
+
+cheb_status cheb_set_projectors(cheb_plan p, const void* P, int ldp, const double* Q, void* ws, size_t wsb,
+                                hipStream_t st) {
+  if (!p) return CHEB_ERR_ARG;
+  const int np = p->nproj;
+  if (np == 0) { p->have_P = true; return CHEB_OK; }
+  if (!P) return fail(p, CHEB_ERR_ARG, "P is null");
+  if (ldp < p->npw) return fail(p, CHEB_ERR_ARG, "ldp < npw");
+  if (p->has_overlap && !Q) return fail(p, CHEB_ERR_ARG, "Q is null but the plan has an overlap");
+  if (!p->has_overlap && Q) return fail(p, CHEB_ERR_ARG, "Q given but the plan has S = I");
+  Ws w;
+  CHK(check_ws(p, CHEB_OP_SETUP, np, ws, wsb, &w));
+  const c128* Pd = static_cast<const c128*>(P);
+  if (p->prec == CHEB_MIXED) HIPCHK((convert_copy<float, double>(p->npw, np, Pd, ldp, static_cast<c64*>(p->P), p->npw, st)));
+  else HIPCHK((convert_copy<double, double>(p->npw, np, Pd, ldp, static_cast<c128*>(p->P), p->npw, st)));
+  // G = P^H P in FP64 from the caller's complex128 projectors
+  Epi<double> eg;
+  eg.out = p->G; eg.ldo = np;
+  HIPCHK((gemm<double, double, double, double>(GEMM_CN, np, np, p->npw, Pd, ldp, Pd, ldp, eg,
+                                               gemm_pick_splits(np, np, p->npw), w.part, st)));
+  if (p->has_overlap) {
+    HIPCHK(hipMemcpyAsync(p->Q, Q, sizeof(double) * np, hipMemcpyDeviceToDevice, st));
+    HIPCHK(capacitance(np, p->G, p->Q, p->Cinv, st));
+    HIPCHK((fill_zero<float>(reinterpret_cast<c64*>(w.flags), 2, st)));
+    RBCHK(rocblas_set_stream(p->rb, st));
+    RBCHK(rocblas_set_workspace(p->rb, w.solver, w.solver_bytes));
+    rocblas_double_complex* C = reinterpret_cast<rocblas_double_complex*>(p->Cinv);
+    rocblas_status r1 = rocsolver_zpotrf(p->rb, rocblas_fill_lower, np, C, np, w.flags);
+    rocblas_status r2 = r1 == rocblas_status_success ? rocsolver_zpotri(p->rb, rocblas_fill_lower, np, C, np, w.flags + 1)
+                                                     : r1;
+    rocblas_set_workspace(p->rb, nullptr, 0);
+    if (r2 != rocblas_status_success) return fail(p, CHEB_ERR_HIP, std::string("rocsolver potrf/potri: ") + rocblas_status_to_string(r2));
+    int info[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(info, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (info[0] != 0 || info[1] != 0) return fail(p, CHEB_ERR_NOT_PD, "capacitance matrix Q^-1 + P^H P is not positive definite");
+    HIPCHK(hermitian_from_lower(np, p->Cinv, np, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  p->have_P = true;
+  return CHEB_OK;
+}
+
+#define OP_PRELUDE(op, nbv)                  \
+  if (!p) return CHEB_ERR_ARG;               \
+  CHK(check_ready(p));                       \
+  Ws w;                                      \
+  if ((nbv) > 0) CHK(check_ws(p, op, nbv, ws, wsb, &w));
+
+static cheb_status apply_common(cheb_plan p, int which, const void* X, int ldx, void* Y, int ldy, int nb, void* ws,
+                                size_t wsb, hipStream_t st) {
+  if (!p) return CHEB_ERR_ARG;
+  CHK(check_block(p, X, ldx, nb, "X"));
+  CHK(check_block(p, Y, ldy, nb, "Y"));
+  if (nb == 0) return CHEB_OK;
+  const size_t eb = elem_bytes(p->prec);
+  const char *xa = static_cast<const char*>(X), *ya = static_cast<const char*>(Y);
+  const char *xe = xa + (size_t(ldx) * (nb - 1) + p->npw) * eb, *ye = ya + (size_t(ldy) * (nb - 1) + p->npw) * eb;
+  if (xa < ye && ya < xe) return fail(p, CHEB_ERR_ARG, "X and Y overlap");
+  OP_PRELUDE(which == 0 ? CHEB_OP_H : CHEB_OP_SINV, nb);
+  return with_prec(p, st, [&](auto ops) {
+    using C = typename decltype(ops)::C;
+    const C* x = static_cast<const C*>(X);
+    C* y = static_cast<C*>(Y);
+    if (which == 0) return ops.apply_H(x, ldx, y, ldy, nb, w);
+    if (which == 1) return ops.apply_S(x, ldx, y, ldy, nb, w);
+    return ops.apply_Sinv(x, ldx, y, ldy, nb, w);
+  });
+}
+
+cheb_status cheb_apply_H(cheb_plan p, const void* X, int ldx, void* Y, int ldy, int nb, void* ws, size_t wsb,
+                         hipStream_t st) {
+  return apply_common(p, 0, X, ldx, Y, ldy, nb, ws, wsb, st);
+}
+cheb_status cheb_apply_S(cheb_plan p, const void* X, int ldx, void* Y, int ldy, int nb, void* ws, size_t wsb,
+                         hipStream_t st) {
+  return apply_common(p, 1, X, ldx, Y, ldy, nb, ws, wsb, st);
+}
+cheb_status cheb_apply_Sinv(cheb_plan p, const void* X, int ldx, void* Y, int ldy, int nb, void* ws, size_t wsb,
+                            hipStream_t st) {
+  return apply_common(p, 2, X, ldx, Y, ldy, nb, ws, wsb, st);
+}
+
+cheb_status cheb_filter(cheb_plan p, void* X, int ldx, int nb, int m, double c, double r, void* ws, size_t wsb,
+                        hipStream_t st) {
+  if (!p) return CHEB_ERR_ARG;
+  CHK(check_block(p, X, ldx, nb, "X"));
+  if (m < 0) return fail(p, CHEB_ERR_ARG, "degree m < 0");
+  if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite(c)) return fail(p, CHEB_ERR_ARG, "need finite c and r > 0");
+  if (nb == 0 || m == 0) return CHEB_OK;
+  OP_PRELUDE(CHEB_OP_FILTER, nb);
+  return with_prec(p, st, [&](auto ops) {
+    using C = typename decltype(ops)::C;
+    return ops.filter(static_cast<C*>(X), ldx, nb, m, c, r, w);
+  });
+}
+
+cheb_status cheb_rayleigh_ritz(cheb_plan p, void* X, int ldx, int nb, double* ritz, double* resid, void* ws,
+                               size_t wsb, hipStream_t st) {
+  if (!p) return CHEB_ERR_ARG;
+  CHK(check_block(p, X, ldx, nb, "X"));
+  if (nb > 0 && !ritz) return fail(p, CHEB_ERR_ARG, "ritz is null");
+  if (nb == 0) return CHEB_OK;
+  OP_PRELUDE(CHEB_OP_RR, nb);
+  return with_prec(p, st, [&](auto ops) {
+    using C = typename decltype(ops)::C;
+    return ops.rayleigh_ritz(static_cast<C*>(X), ldx, nb, ritz, resid, w);
+  });
+}
+
+cheb_status cheb_rayleigh_quotients(cheb_plan p, const void* X, int ldx, int nb, double* rq, void* ws, size_t wsb,
+                                    hipStream_t st) {
+  if (!p) return CHEB_ERR_ARG;
+  CHK(check_block(p, X, ldx, nb, "X"));
+  if (nb > 0 && !rq) return fail(p, CHEB_ERR_ARG, "rq is null");
+  if (nb == 0) return CHEB_OK;
+  OP_PRELUDE(CHEB_OP_RR, nb);
+  return with_prec(p, st, [&](auto ops) {
+    using C = typename decltype(ops)::C;
+    return ops.rayleigh_quotients(static_cast<const C*>(X), ldx, nb, rq, w);
+  });
+}
+
+cheb_status cheb_upper_bound(cheb_plan p, int k, const void* v0, double* lambda_plus, void* ws, size_t wsb,
+                             hipStream_t st) {
+  if (!p) return CHEB_ERR_ARG;
+  if (k < 1 || k > 64) return fail(p, CHEB_ERR_ARG, "k must be in [1, 64]");
+  if (!v0 || !lambda_plus) return fail(p, CHEB_ERR_ARG, "null v0 or output");
+  OP_PRELUDE(CHEB_OP_BOUND, 1);
+  return with_prec(p, st, [&](auto ops) {
+    using C = typename decltype(ops)::C;
+    return ops.upper_bound(k, static_cast<const C*>(v0), lambda_plus, w);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,240 @@
+// V_loc psi by a pair of pruned 3D FFTs (Sec. 2.1, Alg. 1), fused with the kinetic diagonal.
+//
+// A band's sphere coefficients only touch the "disk" columns (gx, gy) with gx^2 + gy^2 <= R^2 and, in
+// each z-plane, only the x-lines |gx| <= R. The box transform is therefore split into three passes:
+//   column pass   : sphere -> z-lines of the disk columns, inverse FFT along z          (fft_col_inverse)
+//   plane pass    : per z-plane, inverse y on the 2R+1 x-lines, then per row inverse x, multiply by
+//                   V(r), forward x, keep the 2R+1 x-lines, forward y                      (fft_plane)
+//   column pass   : forward FFT along z, gather the sphere, scale by n^-3, add K psi      (fft_col_forward)
+// The disk-column buffer is laid out [band][z][column] so that plane passes read and write it
+// contiguously and column passes stage z-lines of CPB columns in LDS.
+#include "fft.h"
+#include "kernels.h"
+
+namespace chebfd {
+namespace {
+
+constexpr int NT = 256;
+
+template <typename T> constexpr int cpb() { return sizeof(T) == 8 ? 16 : 32; }  // columns per block
+
+template <int N, typename T>
+__global__ __launch_bounds__(NT) void k_col_inv(int ncol, const int4* __restrict__ col, const int* __restrict__ ent,
+                                                const cx<T>* __restrict__ twg, const cx<T>* __restrict__ X, long ldx,
+                                                cx<T>* __restrict__ colbuf) {
+  constexpr int CPB = cpb<T>(), LS = N + 1;
+  __shared__ cx<T> lines[CPB * LS];
+  __shared__ cx<T> tw[N];
+  const int band = blockIdx.y;
+  const int c0 = blockIdx.x * CPB, c1 = min(ncol, c0 + CPB), nc = c1 - c0;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < N; t += NT) tw[t] = twg[t];
+  for (int t = tid; t < CPB * LS; t += NT) lines[t] = cx<T>{T(0), T(0)};
+  __syncthreads();
+  const int e0 = col[c0].z, e1 = col[c1 - 1].z + col[c1 - 1].w;
+  const cx<T>* xb = X + long(band) * ldx;
+  for (int e = e0 + tid; e < e1; e += NT) {
+    const int code = ent[e];
+    lines[((code >> 8) - c0) * LS + (code & 255)] = xb[e];
+  }
+  __syncthreads();
+  lds_fft<N, +1, T>(lines, nc, 1, LS, tw);
+  cx<T>* out = colbuf + long(band) * N * ncol;
+  for (int t = tid; t < N * nc; t += NT) {
+    const int z = t / nc, c = t - z * nc;
+    out[long(z) * ncol + c0 + c] = lines[c * LS + z];
+  }
+}
+
+template <int N, typename T> constexpr int plane_rows() {
+  // rows per x-pass batch, a divisor of N; 8 for the N = 128 double-precision plane (160 KB of LDS)
+  return (N == 128 && sizeof(T) == 8) ? 8 : (N % 16 == 0 ? 16 : (N % 8 == 0 ? 8 : 4));
+}
+
+template <int N, typename T> constexpr size_t plane_lds(int nx) {
+  return (size_t(nx + plane_rows<N, T>()) * (N + 1) + N) * sizeof(cx<T>);
+}
+
+static_assert(12 % plane_rows<12, double>() == 0 && 24 % plane_rows<24, double>() == 0, "row batch must divide N");
+
+template <int N, typename T>
+__global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __restrict__ col,
+                                              const cx<T>* __restrict__ twg, const T* __restrict__ Vt,
+                                              const cx<T>* __restrict__ cin, cx<T>* __restrict__ cout) {
+  constexpr int LS = N + 1, RB = plane_rows<N, T>();
+  static_assert(N % RB == 0, "row batch must divide N");
+  extern __shared__ unsigned char smem_raw[];
+  const int nx = 2 * rx + 1;
+  cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw);  // [nx][LS]: x-lines along y
+  cx<T>* S = L + nx * LS;                          // [RB][LS]: rows along x
+  cx<T>* tw = S + RB * LS;
+  const int z = blockIdx.x, band = blockIdx.y, tid = threadIdx.x;
+  for (int t = tid; t < N; t += NT) tw[t] = twg[t];
+  for (int t = tid; t < nx * LS; t += NT) L[t] = cx<T>{T(0), T(0)};
+  __syncthreads();
+  const long base = long(band) * N * ncol + long(z) * ncol;
+  for (int c = tid; c < ncol; c += NT) {
+    const int4 ci = col[c];
+    L[ci.x * LS + ci.y] = cin[base + c];
+  }
+  __syncthreads();
+  lds_fft<N, +1, T>(L, nx, 1, LS, tw);
+  const T* Vz = Vt + long(z) * N * N;
+  for (int y0 = 0; y0 < N; y0 += RB) {
+    for (int t = tid; t < RB * LS; t += NT) S[t] = cx<T>{T(0), T(0)};
+    __syncthreads();
+    for (int t = tid; t < nx * RB; t += NT) {
+      const int xi = t / RB, yy = t - xi * RB;
+      int x = xi - rx;
+      x += x < 0 ? N : 0;
+      S[yy * LS + x] = L[xi * LS + y0 + yy];
+    }
+    __syncthreads();
+    lds_fft<N, +1, T>(S, RB, 1, LS, tw);
+    for (int t = tid; t < RB * N; t += NT) {
+      const int yy = t / N, x = t - yy * N;
+      const T v = Vz[long(y0 + yy) * N + x];
+      cx<T> s = S[yy * LS + x];
+      S[yy * LS + x] = cx<T>{s.x * v, s.y * v};
+    }
+    __syncthreads();
+    lds_fft<N, -1, T>(S, RB, 1, LS, tw);
+    for (int t = tid; t < nx * RB; t += NT) {
+      const int xi = t / RB, yy = t - xi * RB;
+      int x = xi - rx;
+      x += x < 0 ? N : 0;
+      L[xi * LS + y0 + yy] = S[yy * LS + x];
+    }
+    __syncthreads();
+  }
+  lds_fft<N, -1, T>(L, nx, 1, LS, tw);
+  for (int c = tid; c < ncol; c += NT) {
+    const int4 ci = col[c];
+    cout[base + c] = L[ci.x * LS + ci.y];
+  }
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(NT) void k_col_fwd(int ncol, const int4* __restrict__ col, const int* __restrict__ ent,
+                                                const cx<T>* __restrict__ twg, const cx<T>* __restrict__ colbuf,
+                                                const cx<T>* __restrict__ X, long ldx, const T* __restrict__ kin,
+                                                cx<T>* __restrict__ out, long ldo, T scale) {
+  constexpr int CPB = cpb<T>(), LS = N + 1;
+  __shared__ cx<T> lines[CPB * LS];
+  __shared__ cx<T> tw[N];
+  const int band = blockIdx.y;
+  const int c0 = blockIdx.x * CPB, c1 = min(ncol, c0 + CPB), nc = c1 - c0;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < N; t += NT) tw[t] = twg[t];
+  const cx<T>* in = colbuf + long(band) * N * ncol;
+  for (int t = tid; t < N * nc; t += NT) {
+    const int z = t / nc, c = t - z * nc;
+    lines[c * LS + z] = in[long(z) * ncol + c0 + c];
+  }
+  __syncthreads();
+  lds_fft<N, -1, T>(lines, nc, 1, LS, tw);
+  const int e0 = col[c0].z, e1 = col[c1 - 1].z + col[c1 - 1].w;
+  const cx<T>* xb = X + long(band) * ldx;
+  cx<T>* ob = out + long(band) * ldo;
+  for (int e = e0 + tid; e < e1; e += NT) {
+    const int code = ent[e];
+    const cx<T> v = lines[((code >> 8) - c0) * LS + (code & 255)];
+    const cx<T> x = xb[e];
+    const T k = kin[e];
+    ob[e] = cx<T>{v.x * scale + k * x.x, v.y * scale + k * x.y};
+  }
+}
+
+template <typename F> hipError_t dispatch_n(int n, F&& f) {
+  switch (n) {
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 12: return f(std::integral_constant<int, 12>{});
+    case 16: return f(std::integral_constant<int, 16>{});
+    case 24: return f(std::integral_constant<int, 24>{});
+    case 32: return f(std::integral_constant<int, 32>{});
+    case 48: return f(std::integral_constant<int, 48>{});
+    case 64: return f(std::integral_constant<int, 64>{});
+    case 96: return f(std::integral_constant<int, 96>{});
+    case 128: return f(std::integral_constant<int, 128>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t fft_col_inverse(const FftGeom& g, const cx<T>* tw, const cx<T>* X, long ldx, int nb, cx<T>* colbuf,
+                           hipStream_t st) {
+  if (nb <= 0) return hipSuccess;
+  return dispatch_n(g.n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    dim3 grid((g.ncol + cpb<T>() - 1) / cpb<T>(), nb);
+    hipLaunchKernelGGL((k_col_inv<N, T>), grid, dim3(NT), 0, st, g.ncol, g.col, g.ent, tw, X, ldx, colbuf);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+hipError_t fft_plane(const FftGeom& g, const cx<T>* tw, const T* Vt, const cx<T>* cin, cx<T>* cout, int nb,
+                     hipStream_t st) {
+  if (nb <= 0) return hipSuccess;
+  return dispatch_n(g.n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    const size_t lds = plane_lds<N, T>(2 * g.rx + 1);
+    if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_plane<N, T>), dim3(N, nb), dim3(NT), lds, st, g.ncol, g.rx, g.col, tw, Vt, cin, cout);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+hipError_t fft_col_forward(const FftGeom& g, const cx<T>* tw, const cx<T>* colbuf, const cx<T>* X, long ldx,
+                           const T* kin, cx<T>* out, long ldo, int nb, hipStream_t st) {
+  if (nb <= 0) return hipSuccess;
+  const T scale = T(1.0 / (double(g.n) * g.n * g.n));
+  return dispatch_n(g.n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    dim3 grid((g.ncol + cpb<T>() - 1) / cpb<T>(), nb);
+    hipLaunchKernelGGL((k_col_fwd<N, T>), grid, dim3(NT), 0, st, g.ncol, g.col, g.ent, tw, colbuf, X, ldx, kin, out,
+                       ldo, scale);
+    return hipGetLastError();
+  });
+}
+
+size_t fft_plane_lds_bytes(int n, int rx, bool dbl) {
+  size_t out = 0;
+  (void)dispatch_n(n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    out = dbl ? plane_lds<N, double>(2 * rx + 1) : plane_lds<N, float>(2 * rx + 1);
+    return hipSuccess;
+  });
+  return out;
+}
+
+hipError_t fft_prepare_attributes() {
+  // allow the plane kernels their full dynamic LDS (up to 160 KB on gfx950)
+  hipError_t err = hipSuccess;
+  auto set = [&](const void* fn) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) err = e;
+  };
+  auto each = [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    set(reinterpret_cast<const void*>(&k_plane<N, double>));
+    set(reinterpret_cast<const void*>(&k_plane<N, float>));
+    return hipSuccess;
+  };
+  for (int n : {8, 12, 16, 24, 32, 48, 64, 96, 128}) (void)dispatch_n(n, each);
+  return err;
+}
+
+template hipError_t fft_col_inverse<double>(const FftGeom&, const c128*, const c128*, long, int, c128*, hipStream_t);
+template hipError_t fft_col_inverse<float>(const FftGeom&, const c64*, const c64*, long, int, c64*, hipStream_t);
+template hipError_t fft_plane<double>(const FftGeom&, const c128*, const double*, const c128*, c128*, int, hipStream_t);
+template hipError_t fft_plane<float>(const FftGeom&, const c64*, const float*, const c64*, c64*, int, hipStream_t);
+template hipError_t fft_col_forward<double>(const FftGeom&, const c128*, const c128*, const c128*, long, const double*,
+                                            c128*, long, int, hipStream_t);
+template hipError_t fft_col_forward<float>(const FftGeom&, const c64*, const c64*, const c64*, long, const float*,
+                                           c64*, long, int, hipStream_t);
+
+}  // namespace chebfd

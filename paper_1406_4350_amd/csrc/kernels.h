@@ -1,0 +1,91 @@
+// Internal launchers of the chebfd HIP kernels (not part of the public C ABI).
+#pragma once
+#include "common.h"
+
+namespace chebfd {
+
+// Output epilogue shared by the GEMMs and the split-K reduction:
+//   out = alpha * (A B) + bL * L + bU * U + bW * W      (element-wise, any of L/U/W may be null)
+// `out` may alias W (the Chebyshev recurrence writes psi^i over psi^(i-2)).
+template <typename E> struct Epi {
+  cx<E>* out = nullptr; long ldo = 0;
+  double alpha = 1.0;
+  const cx<E>* L = nullptr; long ldl = 0; double bL = 0.0;
+  const cx<E>* U = nullptr; long ldu = 0; double bU = 0.0;
+  const cx<E>* W = nullptr; long ldw = 0; double bW = 0.0;
+};
+
+enum GemmMode { GEMM_CN = 0, GEMM_NN = 1 };
+
+// C (M x N) = op(A) B, complex, column-major operands.
+//   GEMM_CN: A stored K x M (lda), op = conjugate transpose;  GEMM_NN: A stored M x K (lda).
+//   B stored K x N (ldb).
+// T is the MFMA arithmetic type; EA/EB are the storage types of A and B (converted on load).
+// splits > 1: K is split, FP64 partial products go to `part` (splits * M * N complex doubles) and a
+// deterministic reduction applies the epilogue; splits == 1: the epilogue is applied directly.
+template <typename T, typename EA, typename EB, typename EO>
+hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, const cx<EB>* B, long ldb,
+                const Epi<EO>& epi, int splits, c128* part, hipStream_t st);
+
+// number of K splits the launcher would like for an (M, N, K) product on 256 CUs
+int gemm_pick_splits(int M, int N, int K);
+
+// ---- FFT passes (per batch of bands) -------------------------------------------------------------------
+struct FftGeom {
+  int n, ncol, npw, rx;
+  const int4* col;  // per column: {x-line index gx + rx, y = gy mod n, first sphere entry, length}
+  const int* ent;   // per sphere entry: (column << 8) | (gz mod n)
+};
+template <typename T>
+hipError_t fft_col_inverse(const FftGeom& g, const cx<T>* tw, const cx<T>* X, long ldx, int nb, cx<T>* colbuf,
+                           hipStream_t st);
+template <typename T>
+hipError_t fft_plane(const FftGeom& g, const cx<T>* tw, const T* Vt, const cx<T>* cin, cx<T>* cout, int nb,
+                     hipStream_t st);
+template <typename T>
+hipError_t fft_col_forward(const FftGeom& g, const cx<T>* tw, const cx<T>* colbuf, const cx<T>* X, long ldx,
+                           const T* kin, cx<T>* out, long ldo, int nb, hipStream_t st);
+hipError_t fft_prepare_attributes();
+// dynamic LDS bytes of the plane pass for box n, x-line half-width rx (0 if n unsupported)
+size_t fft_plane_lds_bytes(int n, int rx, bool dbl);
+
+// ---- small projector-space and vector kernels -------------------------------------------------------------
+// out[:, b] = blockdiag(D) in[:, b]; pinfo[i] = {first row of i's atom, block size, offset of the block in D}
+hipError_t block_diag_apply(int nproj, int nb, const int4* pinfo, const double* D, const c128* in, long ldi,
+                            c128* out, long ldo, hipStream_t st);
+// out[i, b] = d[i] * in[i, b]
+hipError_t diag_apply(int nproj, int nb, const double* d, const c128* in, long ldi, c128* out, long ldo,
+                      hipStream_t st);
+// out = a x + b y (+ c z), complex, any storage type
+template <typename E>
+hipError_t axpbypcz(long rows, int nb, double a, const cx<E>* x, long ldx, double b, const cx<E>* y, long ldy,
+                    double c, const cx<E>* z, long ldz, cx<E>* out, long ldo, hipStream_t st);
+template <typename EO, typename EI>
+hipError_t convert_copy(long rows, int nb, const cx<EI>* in, long ldi, cx<EO>* out, long ldo, hipStream_t st);
+// per column: out[b] = sum_i conj(x[i,b]) y[i,b]  (deterministic, FP64 accumulation)
+template <typename E>
+hipError_t col_dots(long rows, int nb, const cx<E>* x, long ldx, const cx<E>* y, long ldy, c128* out,
+                    hipStream_t st);
+// per column: out[b] = || R[:, b] - lam[b] U[:, b] ||_2
+template <typename E>
+hipError_t col_resid_norms(long rows, int nb, const cx<E>* R, long ldr, const cx<E>* U, long ldu,
+                           const double* lam, double* out, hipStream_t st);
+// H, S (n x n): symmetric scaling by 1/sqrt(S_ii), Hermitisation; writes scale d; bad[0] = 1 if some
+// S_ii is not positive, bad[1] = 1 if an entry is not finite (plain stores, bad must be cleared first)
+hipError_t rr_prepare(int n, c128* H, c128* S, double* d, int* bad, hipStream_t st);
+// Z[i, j] *= d[i]
+hipError_t scale_rows(int n, int ncols, c128* Z, long ldz, const double* d, hipStream_t st);
+// full Hermitian matrix from its lower triangle
+hipError_t hermitian_from_lower(int n, c128* A, long lda, hipStream_t st);
+// C = diag(1/q) + G
+hipError_t capacitance(int n, const c128* G, const double* q, c128* C, hipStream_t st);
+// V [x][y][z] (FP64) -> Vt [z][y][x] in T
+template <typename T> hipError_t transpose_potential(int n, const double* V, T* Vt, hipStream_t st);
+template <typename E> hipError_t fill_zero(cx<E>* p, long count, hipStream_t st);
+// out[:, j] = a[:, j] - lam[j] b[:, j]  (contiguous rows x nb, complex128)
+hipError_t sub_scaled_cols(int rows, int nb, const c128* a, const c128* b, const double* lam, c128* out,
+                           hipStream_t st);
+// out[i] = Re a[i] / Re b[i]
+hipError_t ratio_real(int nb, const c128* a, const c128* b, double* out, hipStream_t st);
+
+}  // namespace chebfd

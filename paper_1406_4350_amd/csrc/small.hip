@@ -1,0 +1,311 @@
+// Projector-space and vector kernels: block-diagonal D (Eq. 3), the capacitance matrix of the Woodbury
+// inverse (Sec. 5.1), Rayleigh-Ritz preparation (Alg. 2), column dots and residual norms (Sec. 6.1).
+#include "kernels.h"
+
+namespace chebfd {
+namespace {
+
+inline int nblocks(long work, int per = 256, int cap = 8192) {
+  long b = (work + per - 1) / per;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return int(b);
+}
+
+__global__ void k_block_diag(int nproj, int nb, const int4* __restrict__ pinfo, const double* __restrict__ D,
+                             const c128* __restrict__ in, long ldi, c128* __restrict__ out, long ldo) {
+  const long total = long(nproj) * nb;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const int b = int(t / nproj), i = int(t - long(b) * nproj);
+    const int4 pi = pinfo[i];  // {atom's first row, block size, block offset, 0}
+    const int r = i - pi.x;
+    const double* Drow = D + pi.z + long(r) * pi.y;
+    const c128* col = in + long(b) * ldi + pi.x;
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < pi.y; ++j) {
+      re += Drow[j] * col[j].x;
+      im += Drow[j] * col[j].y;
+    }
+    out[long(b) * ldo + i] = c128{re, im};
+  }
+}
+
+__global__ void k_diag(int nproj, int nb, const double* __restrict__ d, const c128* __restrict__ in, long ldi,
+                       c128* __restrict__ out, long ldo) {
+  const long total = long(nproj) * nb;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const int b = int(t / nproj), i = int(t - long(b) * nproj);
+    c128 v = in[long(b) * ldi + i];
+    out[long(b) * ldo + i] = c128{d[i] * v.x, d[i] * v.y};
+  }
+}
+
+template <typename E>
+__global__ void k_axpbypcz(long rows, int nb, double a, const cx<E>* x, long ldx, double b, const cx<E>* y, long ldy,
+                           double c, const cx<E>* z, long ldz, cx<E>* out, long ldo) {
+  const long total = rows * nb;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long col = t / rows, i = t - col * rows;
+    double re = 0.0, im = 0.0;
+    if (x) { cx<E> v = x[col * ldx + i]; re += a * double(v.x); im += a * double(v.y); }
+    if (y) { cx<E> v = y[col * ldy + i]; re += b * double(v.x); im += b * double(v.y); }
+    if (z) { cx<E> v = z[col * ldz + i]; re += c * double(v.x); im += c * double(v.y); }
+    out[col * ldo + i] = cx<E>{E(re), E(im)};
+  }
+}
+
+template <typename EO, typename EI>
+__global__ void k_convert(long rows, int nb, const cx<EI>* in, long ldi, cx<EO>* out, long ldo) {
+  const long total = rows * nb;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long col = t / rows, i = t - col * rows;
+    cx<EI> v = in[col * ldi + i];
+    out[col * ldo + i] = cx<EO>{EO(v.x), EO(v.y)};
+  }
+}
+
+// one block per column, fixed-order tree reduction (deterministic)
+template <typename E>
+__global__ __launch_bounds__(256) void k_col_dots(long rows, const cx<E>* x, long ldx, const cx<E>* y, long ldy,
+                                                  c128* out) {
+  __shared__ double sr[256], si[256];
+  const int b = blockIdx.x;
+  double re = 0.0, im = 0.0;
+  for (long i = threadIdx.x; i < rows; i += blockDim.x) {
+    cx<E> u = x[b * ldx + i], v = y[b * ldy + i];
+    re += double(u.x) * double(v.x) + double(u.y) * double(v.y);
+    im += double(u.x) * double(v.y) - double(u.y) * double(v.x);
+  }
+  sr[threadIdx.x] = re;
+  si[threadIdx.x] = im;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) { sr[threadIdx.x] += sr[threadIdx.x + s]; si[threadIdx.x] += si[threadIdx.x + s]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b] = c128{sr[0], si[0]};
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_col_resid(long rows, const cx<E>* R, long ldr, const cx<E>* U, long ldu,
+                                                   const double* lam, double* out) {
+  __shared__ double s[256];
+  const int b = blockIdx.x;
+  const double l = lam[b];
+  double acc = 0.0;
+  for (long i = threadIdx.x; i < rows; i += blockDim.x) {
+    cx<E> r = R[b * ldr + i], u = U[b * ldu + i];
+    const double dr = double(r.x) - l * double(u.x), di = double(r.y) - l * double(u.y);
+    acc += dr * dr + di * di;
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b] = sqrt(s[0]);
+}
+
+__global__ void k_rr_scale(int n, const c128* S, double* d, int* bad) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double s = S[i + long(i) * n].x;
+    if (!(s > 0.0) || !isfinite(s)) { bad[0] = 1; d[i] = 1.0; }
+    else d[i] = 1.0 / sqrt(s);
+  }
+}
+
+// lower triangle <- d_i d_j (M_ij + conj(M_ji)) / 2 for H and S; upper triangle mirrored
+__global__ void k_rr_sym(int n, c128* H, c128* S, const double* d, int* bad) {
+  const long total = long(n) * n;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const int j = int(t / n), i = int(t - long(j) * n);
+    if (i < j) continue;
+    const double f = d[i] * d[j];
+    c128 h1 = H[i + long(j) * n], h2 = H[j + long(i) * n];
+    c128 s1 = S[i + long(j) * n], s2 = S[j + long(i) * n];
+    c128 h = {0.5 * f * (h1.x + h2.x), 0.5 * f * (h1.y - h2.y)};
+    c128 s = {0.5 * f * (s1.x + s2.x), 0.5 * f * (s1.y - s2.y)};
+    if (i == j) { h.y = 0.0; s.y = 0.0; }
+    if (!isfinite(h.x) || !isfinite(h.y) || !isfinite(s.x) || !isfinite(s.y)) bad[1] = 1;
+    H[i + long(j) * n] = h;
+    S[i + long(j) * n] = s;
+    H[j + long(i) * n] = c128{h.x, -h.y};
+    S[j + long(i) * n] = c128{s.x, -s.y};
+  }
+}
+
+__global__ void k_scale_rows(int n, int ncols, c128* Z, long ldz, const double* d) {
+  const long total = long(n) * ncols;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long j = t / n, i = t - j * n;
+    c128 v = Z[i + j * ldz];
+    Z[i + j * ldz] = c128{v.x * d[i], v.y * d[i]};
+  }
+}
+
+__global__ void k_herm_lower(int n, c128* A, long lda) {
+  const long total = long(n) * n;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const int j = int(t / n), i = int(t - long(j) * n);
+    if (i < j) {  // upper entry (i, j) <- conj(lower (j, i))
+      c128 v = A[j + long(i) * lda];
+      A[i + long(j) * lda] = c128{v.x, -v.y};
+    } else if (i == j) {
+      A[i + long(j) * lda].y = 0.0;
+    }
+  }
+}
+
+__global__ void k_capacitance(int n, const c128* G, const double* q, c128* C) {
+  const long total = long(n) * n;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const int j = int(t / n), i = int(t - long(j) * n);
+    c128 v = G[t];
+    if (i == j) v.x += 1.0 / q[i];
+    C[t] = v;
+  }
+}
+
+template <typename T>
+__global__ void k_transpose_v(int n, const double* V, T* Vt) {
+  const long total = long(n) * n * n;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long x = t % n, y = (t / n) % n, z = t / (long(n) * n);  // output index [z][y][x]
+    Vt[t] = T(V[(x * n + y) * n + z]);
+  }
+}
+
+template <typename E> __global__ void k_zero(cx<E>* p, long count) {
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < count; t += long(gridDim.x) * blockDim.x)
+    p[t] = cx<E>{E(0), E(0)};
+}
+
+}  // namespace
+
+hipError_t block_diag_apply(int nproj, int nb, const int4* pinfo, const double* D, const c128* in, long ldi,
+                            c128* out, long ldo, hipStream_t st) {
+  if (nproj <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_diag, dim3(nblocks(long(nproj) * nb)), dim3(256), 0, st, nproj, nb, pinfo, D, in, ldi, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t diag_apply(int nproj, int nb, const double* d, const c128* in, long ldi, c128* out, long ldo,
+                      hipStream_t st) {
+  if (nproj <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_diag, dim3(nblocks(long(nproj) * nb)), dim3(256), 0, st, nproj, nb, d, in, ldi, out, ldo);
+  return hipGetLastError();
+}
+
+template <typename E>
+hipError_t axpbypcz(long rows, int nb, double a, const cx<E>* x, long ldx, double b, const cx<E>* y, long ldy,
+                    double c, const cx<E>* z, long ldz, cx<E>* out, long ldo, hipStream_t st) {
+  if (rows <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_axpbypcz<E>), dim3(nblocks(rows * nb)), dim3(256), 0, st, rows, nb, a, x, ldx, b, y, ldy, c, z,
+                     ldz, out, ldo);
+  return hipGetLastError();
+}
+
+template <typename EO, typename EI>
+hipError_t convert_copy(long rows, int nb, const cx<EI>* in, long ldi, cx<EO>* out, long ldo, hipStream_t st) {
+  if (rows <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_convert<EO, EI>), dim3(nblocks(rows * nb)), dim3(256), 0, st, rows, nb, in, ldi, out, ldo);
+  return hipGetLastError();
+}
+
+template <typename E>
+hipError_t col_dots(long rows, int nb, const cx<E>* x, long ldx, const cx<E>* y, long ldy, c128* out,
+                    hipStream_t st) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_col_dots<E>), dim3(nb), dim3(256), 0, st, rows, x, ldx, y, ldy, out);
+  return hipGetLastError();
+}
+
+template <typename E>
+hipError_t col_resid_norms(long rows, int nb, const cx<E>* R, long ldr, const cx<E>* U, long ldu,
+                           const double* lam, double* out, hipStream_t st) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_col_resid<E>), dim3(nb), dim3(256), 0, st, rows, R, ldr, U, ldu, lam, out);
+  return hipGetLastError();
+}
+
+hipError_t rr_prepare(int n, c128* H, c128* S, double* d, int* bad, hipStream_t st) {
+  hipLaunchKernelGGL(k_rr_scale, dim3(nblocks(n)), dim3(256), 0, st, n, S, d, bad);
+  hipLaunchKernelGGL(k_rr_sym, dim3(nblocks(long(n) * n)), dim3(256), 0, st, n, H, S, d, bad);
+  return hipGetLastError();
+}
+
+hipError_t scale_rows(int n, int ncols, c128* Z, long ldz, const double* d, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_rows, dim3(nblocks(long(n) * ncols)), dim3(256), 0, st, n, ncols, Z, ldz, d);
+  return hipGetLastError();
+}
+
+hipError_t hermitian_from_lower(int n, c128* A, long lda, hipStream_t st) {
+  hipLaunchKernelGGL(k_herm_lower, dim3(nblocks(long(n) * n)), dim3(256), 0, st, n, A, lda);
+  return hipGetLastError();
+}
+
+hipError_t capacitance(int n, const c128* G, const double* q, c128* C, hipStream_t st) {
+  hipLaunchKernelGGL(k_capacitance, dim3(nblocks(long(n) * n)), dim3(256), 0, st, n, G, q, C);
+  return hipGetLastError();
+}
+
+template <typename T> hipError_t transpose_potential(int n, const double* V, T* Vt, hipStream_t st) {
+  hipLaunchKernelGGL((k_transpose_v<T>), dim3(nblocks(long(n) * n * n)), dim3(256), 0, st, n, V, Vt);
+  return hipGetLastError();
+}
+
+template <typename E> hipError_t fill_zero(cx<E>* p, long count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_zero<E>), dim3(nblocks(count)), dim3(256), 0, st, p, count);
+  return hipGetLastError();
+}
+
+template hipError_t axpbypcz<double>(long, int, double, const c128*, long, double, const c128*, long, double,
+                                     const c128*, long, c128*, long, hipStream_t);
+template hipError_t axpbypcz<float>(long, int, double, const c64*, long, double, const c64*, long, double,
+                                    const c64*, long, c64*, long, hipStream_t);
+template hipError_t convert_copy<float, double>(long, int, const c128*, long, c64*, long, hipStream_t);
+template hipError_t convert_copy<double, float>(long, int, const c64*, long, c128*, long, hipStream_t);
+template hipError_t convert_copy<double, double>(long, int, const c128*, long, c128*, long, hipStream_t);
+template hipError_t convert_copy<float, float>(long, int, const c64*, long, c64*, long, hipStream_t);
+template hipError_t col_dots<double>(long, int, const c128*, long, const c128*, long, c128*, hipStream_t);
+template hipError_t col_dots<float>(long, int, const c64*, long, const c64*, long, c128*, hipStream_t);
+template hipError_t col_resid_norms<double>(long, int, const c128*, long, const c128*, long, const double*, double*,
+                                            hipStream_t);
+template hipError_t col_resid_norms<float>(long, int, const c64*, long, const c64*, long, const double*, double*,
+                                           hipStream_t);
+template hipError_t transpose_potential<double>(int, const double*, double*, hipStream_t);
+template hipError_t transpose_potential<float>(int, const double*, float*, hipStream_t);
+template hipError_t fill_zero<double>(c128*, long, hipStream_t);
+template hipError_t fill_zero<float>(c64*, long, hipStream_t);
+
+}  // namespace chebfd
+
+namespace chebfd {
+namespace {
+__global__ void k_sub_scaled_cols(int rows, int nb, const c128* a, const c128* b, const double* lam, c128* out) {
+  const long total = long(rows) * nb;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long j = t / rows;
+    const c128 u = a[t], v = b[t];
+    out[t] = c128{u.x - lam[j] * v.x, u.y - lam[j] * v.y};
+  }
+}
+__global__ void k_ratio_real(int nb, const c128* a, const c128* b, double* out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) out[i] = a[i].x / b[i].x;
+}
+}  // namespace
+
+hipError_t sub_scaled_cols(int rows, int nb, const c128* a, const c128* b, const double* lam, c128* out,
+                           hipStream_t st) {
+  if (rows <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sub_scaled_cols, dim3(nblocks(long(rows) * nb)), dim3(256), 0, st, rows, nb, a, b, lam, out);
+  return hipGetLastError();
+}
+hipError_t ratio_real(int nb, const c128* a, const c128* b, double* out, hipStream_t st) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ratio_real, dim3(nblocks(nb)), dim3(256), 0, st, nb, a, b, out);
+  return hipGetLastError();
+}
+}  // namespace chebfd

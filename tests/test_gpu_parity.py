@@ -1,0 +1,99 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on identical seeded inputs.
+
+FP64 plans: operator applications to 1e-12 relative, the filter to 1e-11 relative (its output is a
+degree-m polynomial; rounding grows with the recurrence), Ritz values to |d lambda| <= 1e-10 max(|lambda|, 1)
+(the stated FP64 target). Mixed plans (complex64 bands, FP32-MFMA GEMMs) are held to bounds derived from
+float32 rounding: 2e-5 relative per operator application.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import matfree  # noqa: E402
+from paper_1406_4350_amd import chebfd as cf  # noqa: E402
+from paper_1406_4350_amd import workload as wl  # noqa: E402
+from paper_1406_4350_amd.driver import chebfsi  # noqa: E402
+
+CASES = [1, "tiny_paw", "mid_paw", "mid_nc"]
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module", params=CASES, ids=str)
+def case(request):
+    pb = wl.make_problem(request.param)
+    print(f"[case] {pb.cfg.name} npw={pb.npw} nproj={pb.nproj} nb={pb.cfg.nb}", flush=True)
+    ops = matfree.Operators.from_problem(pb)
+    plan = cf.plan_from_problem(pb, cf.CHEB_FP64)
+    return pb, ops, plan
+
+
+def test_apply_operators(case):
+    pb, ops, plan = case
+    X = pb.X0
+    Xd = cf.to_device_block(X, torch.complex128)
+    assert _rel(cf.to_host_block(plan.apply_H(Xd)), ops.apply_H(X)) < 1e-12
+    assert _rel(cf.to_host_block(plan.apply_S(Xd)), ops.apply_S(X)) < 1e-12
+    assert _rel(cf.to_host_block(plan.apply_Sinv(Xd)), ops.apply_Sinv(X)) < 1e-12
+
+
+@pytest.mark.parametrize("m", [0, 1, 2, 5])
+def test_filter(case, m):
+    pb, ops, plan = case
+    lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
+    lm = float(np.max(matfree.rayleigh_quotients(ops, pb.X0)))
+    c, r = 0.5 * (lp + lm), 0.5 * (lp - lm)
+    Xd = cf.to_device_block(pb.X0, torch.complex128)
+    plan.filter(Xd, m, c, r)
+    ref = matfree.chebyshev_filter(ops, pb.X0, m, c, r)
+    assert _rel(cf.to_host_block(Xd), ref) < 1e-11
+
+
+def test_rayleigh_ritz(case):
+    pb, ops, plan = case
+    Y = matfree.chebyshev_filter(ops, pb.X0, 3, 1.0, 2.0)
+    lam, U, res = matfree.rayleigh_ritz(ops, Y)
+    Yd = cf.to_device_block(Y, torch.complex128)
+    ritz, rd = plan.rayleigh_ritz(Yd)
+    ritz = ritz.cpu().numpy()
+    assert np.all(np.abs(ritz - lam) <= 1e-10 * np.maximum(np.abs(lam), 1.0))
+    assert np.allclose(rd.cpu().numpy(), res, rtol=1e-6, atol=1e-9)
+    # rotated block is S-orthonormal and spans the same space: compare orthogonal projectors
+    Ug = cf.to_host_block(Yd)
+    SU = ops.apply_S(Ug)
+    assert np.allclose(Ug.conj().T @ SU, np.eye(Ug.shape[1]), atol=1e-9)
+
+
+def test_rayleigh_quotients_and_bound(case):
+    pb, ops, plan = case
+    Xd = cf.to_device_block(pb.X0, torch.complex128)
+    rq = plan.rayleigh_quotients(Xd).cpu().numpy()
+    assert np.allclose(rq, matfree.rayleigh_quotients(ops, pb.X0), rtol=1e-12, atol=1e-12)
+    lp_ref = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
+    lp = plan.upper_bound(torch.from_numpy(pb.v0), 10)
+    assert abs(lp - lp_ref) <= 1e-10 * max(abs(lp_ref), 1.0)
+
+
+def test_outer_loop_trajectory(case):
+    pb, ops, plan = case
+    iters = min(pb.cfg.iters, 6)
+    lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
+    lam_o, _, res_o, hist_o = matfree.chebfsi(ops, pb.X0, pb.cfg.m, iters, lp)
+    Xd = cf.to_device_block(pb.X0, torch.complex128)
+    ritz, res, hist = chebfsi(plan, Xd, pb.cfg.m, iters, lp)
+    for ho, hg in zip(hist_o, hist):
+        assert abs(ho["lam_minus"] - hg["lam_minus"]) <= 1e-10 * max(abs(ho["lam_minus"]), 1.0)
+        assert np.all(np.abs(hg["ritz"] - ho["ritz"]) <= 1e-10 * np.maximum(np.abs(ho["ritz"]), 1.0))
+
+
+def test_mixed_operators(case):
+    pb, ops, _ = case
+    plan = cf.plan_from_problem(pb, cf.CHEB_MIXED)
+    X = pb.X0
+    Xd = cf.to_device_block(X, torch.complex64)
+    assert _rel(cf.to_host_block(plan.apply_H(Xd)), ops.apply_H(X)) < 2e-5
+    assert _rel(cf.to_host_block(plan.apply_Sinv(Xd)), ops.apply_Sinv(X)) < 2e-5
