@@ -143,6 +143,30 @@ cheb_status cheb_rayleigh_quotients(cheb_plan plan, const void* X, int ldx, int 
 cheb_status cheb_upper_bound(cheb_plan plan, int k, const void* v0_dev, double* lambda_plus_host, void* ws,
                              size_t ws_bytes, hipStream_t stream);
 
+/* Kernel-class timers (diagnostics). While enabled, each launch of a class below made by calls on the plan is
+ * bracketed by HIP events on the call's own stream, and the algorithmic bytes and flops of the launch
+ * (from its shapes: the bytes the operation must move and the flops it must do, not what the kernel
+ * actually fetches) are tallied per class. */
+typedef enum {
+  CHEB_T_FFT_COL_INV = 0,   /* sphere -> disk columns, inverse z-FFT */
+  CHEB_T_FFT_PLANE = 1,     /* per z-plane inverse y, x, V(r) multiply, forward x, y */
+  CHEB_T_FFT_COL_FWD = 2,   /* forward z-FFT, sphere gather, kinetic */
+  CHEB_T_PROJECT = 3,       /* P^H X products (Npw-long reductions, with their split-K reduction) */
+  CHEB_T_BACKPROJECT = 4,   /* P w products with the fused vector epilogue (Chebyshev recurrence) */
+  CHEB_T_SMALL = 5,         /* projector-space products with P^H P and the capacitance inverse */
+  CHEB_T_RR_GRAM = 6,       /* subspace matrices X^H H X, X^H S X */
+  CHEB_T_RR_EIG = 7,        /* dense generalized eigensolver */
+  CHEB_T_RR_ROTATE = 8,     /* X Z rotation and residual products */
+  CHEB_T_COUNT = 9
+} cheb_timer;
+
+/* on != 0: reset the tallies and start timing; on == 0: stop. */
+cheb_status cheb_profile_enable(cheb_plan plan, int on);
+/* Totals of one class since the last enable: summed event time in ms, launches, algorithmic bytes and
+ * flops. Waits for the recorded events. */
+cheb_status cheb_profile_read(cheb_plan plan, int timer, double* ms, int64_t* launches, double* algo_bytes,
+                              double* algo_flops);
+
 /* Message of the last failing call on `plan` ("" if none). Valid until the next call on the plan. */
 const char* cheb_last_error(cheb_plan plan);
 

@@ -29,7 +29,9 @@ CHEB_OP_H, CHEB_OP_SINV, CHEB_OP_FILTER, CHEB_OP_RR, CHEB_OP_BOUND, CHEB_OP_SETU
 SYMBOLS = ["cheb_plan_persistent_bytes", "cheb_plan_create", "cheb_plan_destroy", "cheb_set_potential",
            "cheb_set_projectors", "cheb_set_D", "cheb_workspace_bytes", "cheb_apply_H", "cheb_apply_S",
            "cheb_apply_Sinv", "cheb_filter", "cheb_rayleigh_ritz", "cheb_rayleigh_quotients", "cheb_upper_bound",
-           "cheb_last_error"]
+           "cheb_profile_enable", "cheb_profile_read", "cheb_last_error"]
+TIMERS = ["fft_col_inverse", "fft_plane", "fft_col_forward", "project", "backproject", "small", "rr_gram", "rr_eig",
+          "rr_rotate"]
 
 
 class ChebError(RuntimeError):
@@ -73,6 +75,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cheb_rayleigh_ritz": [vp, vp, i, i, vp, vp, vp, sz, vp],
         "cheb_rayleigh_quotients": [vp, vp, i, i, vp, vp, sz, vp],
         "cheb_upper_bound": [vp, i, vp, P(d), vp, sz, vp],
+        "cheb_profile_enable": [vp, i],
+        "cheb_profile_read": [vp, i, P(d), P(ctypes.c_int64), P(d), P(d)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -229,6 +233,20 @@ class Plan:
         self._check(self.lib.cheb_upper_bound(self.handle, int(k), v0.data_ptr(), ctypes.byref(out), ws.data_ptr(),
                                               ws.numel(), _stream()), "cheb_upper_bound")
         return out.value
+
+
+    def profile_enable(self, on: bool = True):
+        self._check(self.lib.cheb_profile_enable(self.handle, int(bool(on))), "cheb_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{timer name: dict(ms, launches, bytes, flops)} since the last profile_enable(True)."""
+        out = {}
+        for k, name in enumerate(TIMERS):
+            ms, n, b, f = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+            self._check(self.lib.cheb_profile_read(self.handle, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b),
+                                                   ctypes.byref(f)), "cheb_profile_read")
+            out[name] = dict(ms=ms.value, launches=n.value, bytes=b.value, flops=f.value)
+        return out
 
 
 def plan_from_problem(pb, prec: int = CHEB_FP64, device: str = "cuda") -> Plan:

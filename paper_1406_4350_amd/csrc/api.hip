@@ -38,6 +38,13 @@ struct cheb_plan_s {
   int fft_batch = 1;
   rocblas_handle rb = nullptr;
   std::string err;
+  // kernel-class timers
+  struct TimerRec { hipEvent_t a, b; int kind; };
+  bool prof_on = false;
+  std::vector<TimerRec> prof_pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_free;
+  double prof_ms[CHEB_T_COUNT] = {}, prof_bytes[CHEB_T_COUNT] = {}, prof_flops[CHEB_T_COUNT] = {};
+  int64_t prof_n[CHEB_T_COUNT] = {};
 };
 
 namespace {
@@ -88,6 +95,32 @@ cheb_status fail(cheb_plan p, cheb_status s, const std::string& msg) {
   } while (0)
 
 size_t elem_bytes(int prec) { return prec == CHEB_MIXED ? sizeof(c64) : sizeof(c128); }
+
+// Brackets the launches of one kernel class with events on the launching stream while profiling is on.
+struct Timed {
+  cheb_plan p;
+  hipStream_t st;
+  hipEvent_t end = nullptr;
+  Timed(cheb_plan p_, hipStream_t st_, int kind, double bytes, double flops) : p(p_), st(st_) {
+    if (!p->prof_on) return;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (!p->prof_free.empty()) {
+      ev = p->prof_free.back();
+      p->prof_free.pop_back();
+    } else if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+      return;
+    }
+    if (hipEventRecord(ev.first, st) != hipSuccess) return;
+    end = ev.second;
+    p->prof_pending.push_back({ev.first, ev.second, kind});
+    p->prof_bytes[kind] += bytes;
+    p->prof_flops[kind] += flops;
+    p->prof_n[kind] += 1;
+  }
+  ~Timed() {
+    if (end) (void)hipEventRecord(end, st);
+  }
+};
 
 // ---- layouts -------------------------------------------------------------------------------------------------
 struct Persist {
@@ -303,10 +336,20 @@ template <typename T> struct Ops {
       const int cnt = std::min(fb, nb - b0);
       C* ca = static_cast<C*>(fw.a);
       C* cb = static_cast<C*>(fw.b);
-      HIPCHK(fft_col_inverse<T>(g, tw, X + long(b0) * ldx, ldx, cnt, ca, st));
-      HIPCHK(fft_plane<T>(g, tw, static_cast<const T*>(p->Vt), ca, cb, cnt, st));
-      HIPCHK(fft_col_forward<T>(g, tw, cb, X + long(b0) * ldx, ldx, static_cast<const T*>(p->kin), out + long(b0) * ldo,
-                                ldo, cnt, st));
+      const double b = sizeof(C), colv = double(p->n) * p->ncol, npw = p->npw;
+      {
+        Timed t(p, st, CHEB_T_FFT_COL_INV, cnt * (npw + colv) * b, 0.0);
+        HIPCHK(fft_col_inverse<T>(g, tw, X + long(b0) * ldx, ldx, cnt, ca, st));
+      }
+      {
+        Timed t(p, st, CHEB_T_FFT_PLANE, cnt * 2.0 * colv * b, 0.0);
+        HIPCHK(fft_plane<T>(g, tw, static_cast<const T*>(p->Vt), ca, cb, cnt, st));
+      }
+      {
+        Timed t(p, st, CHEB_T_FFT_COL_FWD, cnt * (colv + 2.0 * npw) * b, 0.0);
+        HIPCHK(fft_col_forward<T>(g, tw, cb, X + long(b0) * ldx, ldx, static_cast<const T*>(p->kin),
+                                  out + long(b0) * ldo, ldo, cnt, st));
+      }
     }
     return CHEB_OK;
   }
@@ -316,20 +359,28 @@ template <typename T> struct Ops {
     Epi<double> e;
     e.out = pout;
     e.ldo = p->nproj;
+    const double b = sizeof(C), np = p->nproj, npw = p->npw;
+    Timed t(p, st, CHEB_T_PROJECT, (npw * np + npw * nb) * b + np * nb * 16.0, 8.0 * np * nb * npw);
     HIPCHK((gemm<T, T, T, double>(GEMM_CN, p->nproj, nb, p->npw, P(), p->npw, X, ldx, e,
-                                  gemm_pick_splits(p->nproj, nb, p->npw), part, st)));
+                                  gemm_pick_splits(p->nproj, nb, p->npw), part, st, ROLE_PROJECT)));
     return CHEB_OK;
   }
 
   // out = alpha P w + bL L (+ bU U + bW W): back-projection with the vector epilogue
   cheb_status backproject(const c128* w, int nb, Epi<T> e) {
-    HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, p->nproj, P(), p->npw, w, p->nproj, e, 1, nullptr, st)));
+    const double b = sizeof(C), np = p->nproj, npw = p->npw;
+    const double vecs = 1.0 + (e.L ? 1 : 0) + (e.U ? 1 : 0) + (e.W ? 1 : 0);
+    Timed t(p, st, CHEB_T_BACKPROJECT, npw * np * b + np * nb * 16.0 + vecs * npw * nb * b, 8.0 * npw * nb * np);
+    HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, p->nproj, P(), p->npw, w, p->nproj, e, 1, nullptr, st,
+                                  ROLE_BACKPROJECT)));
     return CHEB_OK;
   }
 
   // small projector-space product out = alpha M x (+ epilogue), M nproj x nproj (c128)
   cheb_status small(const c128* M, const c128* x, int nb, Epi<double> e, c128* part) {
     const int np = p->nproj;
+    const double vecs = 2.0 + (e.L ? 1 : 0) + (e.U ? 1 : 0) + (e.W ? 1 : 0);
+    Timed t(p, st, CHEB_T_SMALL, double(np) * np * 16.0 + vecs * np * nb * 16.0, 8.0 * np * np * nb);
     HIPCHK((gemm<double, double, double, double>(GEMM_NN, np, nb, np, M, np, x, np, e, gemm_pick_splits(np, nb, np),
                                                  part, st)));
     return CHEB_OK;
@@ -441,14 +492,15 @@ template <typename T> struct Ops {
     const long npw = p->npw;
     C* loc = static_cast<C*>(w.loc);
     CHK(hloc(X, ldx, nb, loc, npw, w.fft));
+    Timed t(p, st, CHEB_T_RR_GRAM, 3.0 * npw * nb * sizeof(C) + 2.0 * nb * nb * 16.0, 16.0 * npw * nb * nb);
     Epi<double> eh;
     eh.out = w.Hs; eh.ldo = nb;
     HIPCHK((gemm<T, T, T, double>(GEMM_CN, nb, nb, p->npw, X, ldx, loc, npw, eh, gemm_pick_splits(nb, nb, p->npw),
-                                  w.part, st)));
+                                  w.part, st, ROLE_SUBSPACE)));
     Epi<double> es;
     es.out = w.Ss; es.ldo = nb;
     HIPCHK((gemm<T, T, T, double>(GEMM_CN, nb, nb, p->npw, X, ldx, X, ldx, es, gemm_pick_splits(nb, nb, p->npw),
-                                  w.part, st)));
+                                  w.part, st, ROLE_SUBSPACE)));
     if (np > 0) {
       CHK(project(X, ldx, nb, w.p0, w.part));
       HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, w.p0, np, w.Dp, np, st));
@@ -480,9 +532,13 @@ template <typename T> struct Ops {
     if (flags[0]) return fail(p, CHEB_ERR_NOT_PD, "X^H S X has a non-positive diagonal (zero or non-finite column)");
     RBCHK(rocblas_set_stream(p->rb, st));
     RBCHK(rocblas_set_workspace(p->rb, w.solver, w.solver_bytes));
-    rocblas_status rs = rocsolver_zhegvd(p->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, nb,
+    rocblas_status rs;
+    {
+      Timed t(p, st, CHEB_T_RR_EIG, 0.0, 0.0);
+      rs = rocsolver_zhegvd(p->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, nb,
                                          reinterpret_cast<rocblas_double_complex*>(w.Hs), nb,
                                          reinterpret_cast<rocblas_double_complex*>(w.Ss), nb, ritz, w.E, w.flags + 2);
+    }
     rocblas_set_workspace(p->rb, nullptr, 0);
     if (rs != rocblas_status_success)
       return fail(p, CHEB_ERR_HIP, std::string("rocsolver_zhegvd: ") + rocblas_status_to_string(rs));
@@ -493,16 +549,18 @@ template <typename T> struct Ops {
     // Z = diag(d) Z' undoes the symmetric column scaling
     HIPCHK(scale_rows(nb, nb, w.Hs, nb, w.d, st));
     C* Ynew = static_cast<C*>(w.Ynew);
+    Timed tr(p, st, CHEB_T_RR_ROTATE, (resid ? 4.0 : 2.0) * npw * nb * sizeof(C) + nb * nb * 16.0,
+             (resid ? 16.0 : 8.0) * npw * nb * nb);
     Epi<T> er;
     er.out = Ynew; er.ldo = npw;
-    HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, nb, X, ldx, w.Hs, nb, er, 1, nullptr, st)));
+    HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, nb, X, ldx, w.Hs, nb, er, 1, nullptr, st, ROLE_SUBSPACE)));
     if (resid) {
       // H u - lambda S u = loc Z + P (D pZ - lambda Q pZ) - lambda u
       C* R = static_cast<C*>(w.R);
       Epi<T> e1;
       e1.out = R; e1.ldo = npw;
       HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, nb, static_cast<C*>(w.loc), npw, w.Hs, nb, e1, 1, nullptr,
-                                    st)));
+                                    st, ROLE_SUBSPACE)));
       if (np > 0) {
         Epi<double> ez;
         ez.out = w.q; ez.ldo = np;
@@ -754,12 +812,47 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
 
 cheb_status cheb_plan_destroy(cheb_plan p) {
   if (!p) return CHEB_OK;
+  for (auto& r : p->prof_pending) { (void)hipEventSynchronize(r.b); (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  for (auto& r : p->prof_free) { (void)hipEventDestroy(r.first); (void)hipEventDestroy(r.second); }
   if (p->rb) rocblas_destroy_handle(p->rb);
   delete p;
   return CHEB_OK;
 }
 
 const char* cheb_last_error(cheb_plan p) { return p ? p->err.c_str() : "null plan"; }
+
+static cheb_status prof_collect(cheb_plan p) {
+  for (auto& r : p->prof_pending) {
+    HIPCHK(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    p->prof_ms[r.kind] += ms;
+    p->prof_free.push_back({r.a, r.b});
+  }
+  p->prof_pending.clear();
+  return CHEB_OK;
+}
+
+cheb_status cheb_profile_enable(cheb_plan p, int on) {
+  if (!p) return CHEB_ERR_ARG;
+  CHK(prof_collect(p));
+  if (on) {
+    for (int k = 0; k < CHEB_T_COUNT; ++k) { p->prof_ms[k] = 0; p->prof_bytes[k] = 0; p->prof_flops[k] = 0; p->prof_n[k] = 0; }
+  }
+  p->prof_on = on != 0;
+  return CHEB_OK;
+}
+
+cheb_status cheb_profile_read(cheb_plan p, int timer, double* ms, int64_t* launches, double* bytes, double* flops) {
+  if (!p) return CHEB_ERR_ARG;
+  if (timer < 0 || timer >= CHEB_T_COUNT) return fail(p, CHEB_ERR_ARG, "unknown timer");
+  CHK(prof_collect(p));
+  if (ms) *ms = p->prof_ms[timer];
+  if (launches) *launches = p->prof_n[timer];
+  if (bytes) *bytes = p->prof_bytes[timer];
+  if (flops) *flops = p->prof_flops[timer];
+  return CHEB_OK;
+}
 
 cheb_status cheb_set_potential(cheb_plan p, const double* V, hipStream_t st) {
   if (!p) return CHEB_ERR_ARG;

@@ -36,7 +36,8 @@ __device__ __forceinline__ void epi_store(const Epi<E>& e, long m, long n, doubl
 
 // One 64 x 64 complex output tile per block of 4 waves; wave w owns the 32 x 32 quadrant
 // (w & 1, w >> 1) as 2 x 2 MFMA blocks with separate real and imaginary accumulators.
-template <typename T, typename EA, typename EB, typename EO, int MODE>
+// ROLE only separates kernel names per use (projection, back-projection, small, subspace) for profiling.
+template <typename T, typename EA, typename EB, typename EO, int MODE, int ROLE>
 __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, const cx<EA>* __restrict__ A,
                                              long lda, const cx<EB>* __restrict__ B, long ldb, Epi<EO> epi,
                                              c128* __restrict__ part) {
@@ -167,7 +168,7 @@ int gemm_pick_splits(int M, int N, int K) {
 
 template <typename T, typename EA, typename EB, typename EO>
 hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, const cx<EB>* B, long ldb,
-                const Epi<EO>& epi, int splits, c128* part, hipStream_t st) {
+                const Epi<EO>& epi, int splits, c128* part, hipStream_t st, GemmRole role) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (splits < 1) splits = 1;
   int kchunk = (K + splits - 1) / splits;
@@ -178,10 +179,18 @@ hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, c
   if (use_part && !part) return hipErrorInvalidValue;
   dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, splits);
   c128* pp = use_part ? part : nullptr;
-  if (mode == GEMM_CN)
-    hipLaunchKernelGGL((k_gemm<T, EA, EB, EO, GEMM_CN>), grid, dim3(NT), 0, st, M, N, K, kchunk, A, lda, B, ldb, epi, pp);
-  else
-    hipLaunchKernelGGL((k_gemm<T, EA, EB, EO, GEMM_NN>), grid, dim3(NT), 0, st, M, N, K, kchunk, A, lda, B, ldb, epi, pp);
+  auto launch = [&](auto modec, auto rolec) {
+    constexpr int MO = decltype(modec)::value, RO = decltype(rolec)::value;
+    hipLaunchKernelGGL((k_gemm<T, EA, EB, EO, MO, RO>), grid, dim3(NT), 0, st, M, N, K, kchunk, A, lda, B, ldb, epi, pp);
+  };
+  using CN = std::integral_constant<int, GEMM_CN>;
+  using NNm = std::integral_constant<int, GEMM_NN>;
+  switch (role) {
+    case ROLE_PROJECT: mode == GEMM_CN ? launch(CN{}, std::integral_constant<int, 1>{}) : launch(NNm{}, std::integral_constant<int, 1>{}); break;
+    case ROLE_BACKPROJECT: mode == GEMM_CN ? launch(CN{}, std::integral_constant<int, 2>{}) : launch(NNm{}, std::integral_constant<int, 2>{}); break;
+    case ROLE_SUBSPACE: mode == GEMM_CN ? launch(CN{}, std::integral_constant<int, 3>{}) : launch(NNm{}, std::integral_constant<int, 3>{}); break;
+    default: mode == GEMM_CN ? launch(CN{}, std::integral_constant<int, 0>{}) : launch(NNm{}, std::integral_constant<int, 0>{}); break;
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !use_part) return e;
   const long total = long(M) * N;
@@ -193,7 +202,7 @@ hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, c
 
 #define INST(T, EA, EB, EO)                                                                               \
   template hipError_t gemm<T, EA, EB, EO>(GemmMode, int, int, int, const cx<EA>*, long, const cx<EB>*, long, \
-                                          const Epi<EO>&, int, c128*, hipStream_t);
+                                          const Epi<EO>&, int, c128*, hipStream_t, GemmRole);
 INST(double, double, double, double)
 INST(float, float, float, float)
 INST(float, float, double, float)

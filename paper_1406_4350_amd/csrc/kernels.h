@@ -16,6 +16,8 @@ template <typename E> struct Epi {
 };
 
 enum GemmMode { GEMM_CN = 0, GEMM_NN = 1 };
+// separate kernel instances per use, so that profiles tell them apart
+enum GemmRole { ROLE_SMALL = 0, ROLE_PROJECT = 1, ROLE_BACKPROJECT = 2, ROLE_SUBSPACE = 3 };
 
 // C (M x N) = op(A) B, complex, column-major operands.
 //   GEMM_CN: A stored K x M (lda), op = conjugate transpose;  GEMM_NN: A stored M x K (lda).
@@ -25,7 +27,7 @@ enum GemmMode { GEMM_CN = 0, GEMM_NN = 1 };
 // deterministic reduction applies the epilogue; splits == 1: the epilogue is applied directly.
 template <typename T, typename EA, typename EB, typename EO>
 hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, const cx<EB>* B, long ldb,
-                const Epi<EO>& epi, int splits, c128* part, hipStream_t st);
+                const Epi<EO>& epi, int splits, c128* part, hipStream_t st, GemmRole role = ROLE_SMALL);
 
 // number of K splits the launcher would like for an (M, N, K) product on 256 CUs
 int gemm_pick_splits(int M, int N, int K);
