@@ -25,6 +25,7 @@ struct cheb_plan_s {
   // views into the persistent buffer
   int4* col = nullptr;
   int* ent = nullptr;
+  int4* xline = nullptr;
   int4* pinfo = nullptr;
   void* tw = nullptr;
   void* kin = nullptr;
@@ -124,15 +125,16 @@ struct Timed {
 
 // ---- layouts -------------------------------------------------------------------------------------------------
 struct Persist {
-  int4* col; int* ent; int4* pinfo; void* tw; void* kin; void* Vt; void* P; double* D; double* Q; c128* G; c128* Cinv;
+  int4* col; int* ent; int4* xline; int4* pinfo; void* tw; void* kin; void* Vt; void* P; double* D; double* Q; c128* G; c128* Cinv;
 };
 
-Persist persist_layout(void* base, int n, int npw, int ncol, int nproj, size_t dsize, int overlap, int prec) {
+Persist persist_layout(void* base, int n, int npw, int ncol, int rx, int nproj, size_t dsize, int overlap, int prec) {
   Bump b(base);
   Persist l{};
   const bool mixed = prec == CHEB_MIXED;
   l.col = b.take<int4>(ncol);
   l.ent = b.take<int>(npw);
+  l.xline = b.take<int4>(2 * rx + 1);
   l.pinfo = b.take<int4>(std::max(nproj, 1));
   l.tw = mixed ? (void*)b.take<c64>(n) : (void*)b.take<c128>(n);
   l.kin = mixed ? (void*)b.take<float>(npw) : (void*)b.take<double>(npw);
@@ -146,11 +148,12 @@ Persist persist_layout(void* base, int n, int npw, int ncol, int nproj, size_t d
   return l;
 }
 
-size_t persist_bytes(int n, int npw, int ncol, int nproj, size_t dsize, int overlap, int prec) {
+size_t persist_bytes(int n, int npw, int ncol, int rx, int nproj, size_t dsize, int overlap, int prec) {
   Bump b(nullptr);
   const bool mixed = prec == CHEB_MIXED;
   b.take<int4>(ncol);
   b.take<int>(npw);
+  b.take<int4>(2 * rx + 1);
   b.take<int4>(std::max(nproj, 1));
   mixed ? (void)b.take<c64>(n) : (void)b.take<c128>(n);
   mixed ? (void)b.take<float>(npw) : (void)b.take<double>(npw);
@@ -284,8 +287,15 @@ cheb_status solver_query(cheb_plan p, int op, int n, size_t* bytes) {
   if (n <= 0) return CHEB_OK;
   RBCHK(rocblas_start_device_memory_size_query(p->rb));
   if (op == CHEB_OP_RR) {
-    rocsolver_zhegvd(p->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, n, nullptr, n, nullptr, n,
-                     nullptr, nullptr, nullptr);
+    const rocblas_double_complex one = {1.0, 0.0};
+    rocsolver_zpotrf(p->rb, rocblas_fill_lower, n, nullptr, n, nullptr);
+    rocblas_ztrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, n,
+                  n, &one, nullptr, n, nullptr, n);
+    rocblas_ztrsm(p->rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
+                  rocblas_diagonal_non_unit, n, n, &one, nullptr, n, nullptr, n);
+    rocblas_ztrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
+                  rocblas_diagonal_non_unit, n, n, &one, nullptr, n, nullptr, n);
+    rocsolver_zheevd(p->rb, rocblas_evect_original, rocblas_fill_lower, n, nullptr, n, nullptr, nullptr, nullptr);
   } else {
     rocsolver_zpotrf(p->rb, rocblas_fill_lower, n, nullptr, n, nullptr);
     rocsolver_zpotri(p->rb, rocblas_fill_lower, n, nullptr, n, nullptr);
@@ -324,7 +334,7 @@ template <typename T> struct Ops {
   using C = cx<T>;
   cheb_plan p;
   hipStream_t st;
-  FftGeom geom() const { return FftGeom{p->n, p->ncol, p->npw, p->rx, p->col, p->ent}; }
+  FftGeom geom() const { return FftGeom{p->n, p->ncol, p->npw, p->rx, p->col, p->ent, p->xline}; }
   const C* P() const { return static_cast<const C*>(p->P); }
 
   // out = (K + V_loc) X, batched over bands through the disk-column buffers
@@ -532,20 +542,34 @@ template <typename T> struct Ops {
     if (flags[0]) return fail(p, CHEB_ERR_NOT_PD, "X^H S X has a non-positive diagonal (zero or non-finite column)");
     RBCHK(rocblas_set_stream(p->rb, st));
     RBCHK(rocblas_set_workspace(p->rb, w.solver, w.solver_bytes));
-    rocblas_status rs;
+    // H_X Z = S_X Z Lambda by reduction to standard form: S' = L L^H, H^ = L^-1 H' L^-H, H^ U = U Lambda,
+    // Z' = L^-H U (FP64 throughout)
+    rocblas_status rs = rocblas_status_success;
     {
       Timed t(p, st, CHEB_T_RR_EIG, 0.0, 0.0);
-      rs = rocsolver_zhegvd(p->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, nb,
-                                         reinterpret_cast<rocblas_double_complex*>(w.Hs), nb,
-                                         reinterpret_cast<rocblas_double_complex*>(w.Ss), nb, ritz, w.E, w.flags + 2);
+      rocblas_double_complex* Hd = reinterpret_cast<rocblas_double_complex*>(w.Hs);
+      rocblas_double_complex* Ld = reinterpret_cast<rocblas_double_complex*>(w.Ss);
+      const rocblas_double_complex one = {1.0, 0.0};
+      rs = rocsolver_zpotrf(p->rb, rocblas_fill_lower, nb, Ld, nb, w.flags + 2);
+      if (rs == rocblas_status_success)
+        rs = rocblas_ztrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                           rocblas_diagonal_non_unit, nb, nb, &one, Ld, nb, Hd, nb);
+      if (rs == rocblas_status_success)
+        rs = rocblas_ztrsm(p->rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
+                           rocblas_diagonal_non_unit, nb, nb, &one, Ld, nb, Hd, nb);
+      if (rs == rocblas_status_success)
+        rs = rocsolver_zheevd(p->rb, rocblas_evect_original, rocblas_fill_lower, nb, Hd, nb, ritz, w.E, w.flags + 3);
+      if (rs == rocblas_status_success)
+        rs = rocblas_ztrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
+                           rocblas_diagonal_non_unit, nb, nb, &one, Ld, nb, Hd, nb);
     }
     rocblas_set_workspace(p->rb, nullptr, 0);
     if (rs != rocblas_status_success)
-      return fail(p, CHEB_ERR_HIP, std::string("rocsolver_zhegvd: ") + rocblas_status_to_string(rs));
-    HIPCHK(hipMemcpyAsync(flags + 2, w.flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+      return fail(p, CHEB_ERR_HIP, std::string("dense eigensolver: ") + rocblas_status_to_string(rs));
+    HIPCHK(hipMemcpyAsync(flags, w.flags + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (flags[2] > nb) return fail(p, CHEB_ERR_NOT_PD, "X^H S X is not positive definite (rank-deficient block)");
-    if (flags[2] > 0) return fail(p, CHEB_ERR_EIG, "generalized eigensolver did not converge");
+    if (flags[0] != 0) return fail(p, CHEB_ERR_NOT_PD, "X^H S X is not positive definite (rank-deficient block)");
+    if (flags[1] != 0) return fail(p, CHEB_ERR_EIG, "Hermitian eigensolver did not converge");
     // Z = diag(d) Z' undoes the symmetric column scaling
     HIPCHK(scale_rows(nb, nb, w.Hs, nb, w.d, st));
     C* Ynew = static_cast<C*>(w.Ynew);
@@ -696,6 +720,7 @@ static cheb_status validate_desc(const cheb_desc* d, int* ncol_out, int* rx_out,
       if (g[2] != h[2] + 1) { *msg = "g-list column not a run of consecutive gz at entry " + std::to_string(e); return CHEB_ERR_ARG; }
     } else {
       if (g[0] < h[0] || (g[0] == h[0] && g[1] < h[1])) { *msg = "g-list not sorted by column (gx, gy) at entry " + std::to_string(e); return CHEB_ERR_ARG; }
+      if (g[0] == h[0] && g[1] != h[1] + 1) { *msg = "columns of one gx not a run of consecutive gy at entry " + std::to_string(e); return CHEB_ERR_ARG; }
       ++ncol;
     }
   }
@@ -727,7 +752,7 @@ cheb_status cheb_plan_persistent_bytes(const cheb_desc* d, size_t* bytes) {
   cheb_status s = validate_desc(d, &ncol, &rx, &dsize, &msg);
   if (s != CHEB_OK) return s;
   const int nproj = d->natom > 0 ? d->proj_off_host[d->natom] : 0;
-  *bytes = persist_bytes(d->n, d->npw, ncol, nproj, dsize, d->has_overlap ? 1 : 0, d->prec);
+  *bytes = persist_bytes(d->n, d->npw, ncol, rx, nproj, dsize, d->has_overlap ? 1 : 0, d->prec);
   return CHEB_OK;
 }
 
@@ -740,7 +765,7 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   cheb_status s = validate_desc(d, &ncol, &rx, &dsize, &msg);
   if (s != CHEB_OK) { std::fprintf(stderr, "cheb_plan_create: %s\n", msg.c_str()); return s; }
   const int nproj = d->natom > 0 ? d->proj_off_host[d->natom] : 0;
-  const size_t need = persist_bytes(d->n, d->npw, ncol, nproj, dsize, d->has_overlap ? 1 : 0, d->prec);
+  const size_t need = persist_bytes(d->n, d->npw, ncol, rx, nproj, dsize, d->has_overlap ? 1 : 0, d->prec);
   if (!persistent || bytes < need || reinterpret_cast<uintptr_t>(persistent) % kAlign) return CHEB_ERR_WORKSPACE;
 
   cheb_plan p = new (std::nothrow) cheb_plan_s;
@@ -748,8 +773,8 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   p->n = d->n; p->npw = d->npw; p->ncol = ncol; p->rx = rx; p->natom = d->natom; p->nproj = nproj;
   p->has_overlap = d->has_overlap ? 1 : 0; p->prec = d->prec; p->dsize = dsize;
   p->proj_off.assign(d->proj_off_host, d->proj_off_host + (d->natom > 0 ? d->natom + 1 : 0));
-  Persist l = persist_layout(persistent, d->n, d->npw, ncol, nproj, dsize, p->has_overlap, d->prec);
-  p->col = l.col; p->ent = l.ent; p->pinfo = l.pinfo; p->tw = l.tw; p->kin = l.kin; p->Vt = l.Vt; p->P = l.P;
+  Persist l = persist_layout(persistent, d->n, d->npw, ncol, rx, nproj, dsize, p->has_overlap, d->prec);
+  p->col = l.col; p->ent = l.ent; p->xline = l.xline; p->pinfo = l.pinfo; p->tw = l.tw; p->kin = l.kin; p->Vt = l.Vt; p->P = l.P;
   p->D = l.D; p->Q = l.Q; p->G = l.G; p->Cinv = l.Cinv;
 
   // host-side index maps
@@ -764,6 +789,14 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
     }
     col[c].w += 1;
     ent[e] = (c << 8) | ((g[2] % d->n + d->n) % d->n);
+  }
+  // x-lines: columns sharing gx are consecutive (sorted by gy, consecutive gy checked above)
+  std::vector<int4> xline(2 * rx + 1, int4{0, 0, 0, 0});
+  for (int cc = 0; cc < ncol; ++cc) {
+    const int32_t* g0 = d->gidx_host + 3 * col[cc].z;
+    int4& xl = xline[g0[0] + rx];
+    if (xl.z == 0) { xl.x = cc; xl.y = g0[1]; }
+    xl.z += 1;
   }
   std::vector<int4> pinfo(std::max(nproj, 1), int4{0, 0, 0, 0});
   size_t doff = 0;
@@ -786,6 +819,7 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   hipError_t e;
   if ((e = hipMemcpyAsync(p->col, col.data(), sizeof(int4) * ncol, hipMemcpyHostToDevice, st))) return fail_hip(e, "col");
   if ((e = hipMemcpyAsync(p->ent, ent.data(), sizeof(int) * d->npw, hipMemcpyHostToDevice, st))) return fail_hip(e, "ent");
+  if ((e = hipMemcpyAsync(p->xline, xline.data(), sizeof(int4) * xline.size(), hipMemcpyHostToDevice, st))) return fail_hip(e, "xline");
   if ((e = hipMemcpyAsync(p->pinfo, pinfo.data(), sizeof(int4) * pinfo.size(), hipMemcpyHostToDevice, st))) return fail_hip(e, "pinfo");
   if (mixed) {
     std::vector<c64> tw32(d->n);

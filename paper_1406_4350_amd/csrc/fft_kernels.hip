@@ -47,70 +47,157 @@ __global__ __launch_bounds__(NT) void k_col_inv(int ncol, const int4* __restrict
 }
 
 template <int N, typename T> constexpr int plane_rows() {
-  // rows per x-pass batch, a divisor of N; 8 for the N = 128 double-precision plane (160 KB of LDS)
-  return (N == 128 && sizeof(T) == 8) ? 8 : (N % 16 == 0 ? 16 : (N % 8 == 0 ? 8 : 4));
+  // rows of the x-pass handled together: about one task per thread in the first stage, and the N = 128
+  // double-precision plane kept inside 160 KB of LDS
+  constexpr int N2 = LineSplit<N>::N2;
+  constexpr int r = (N == 128 && sizeof(T) == 8) ? 8 : NT / N2;
+  return r < N ? r : N;
 }
 
 template <int N, typename T> constexpr size_t plane_lds(int nx) {
   return (size_t(nx + plane_rows<N, T>()) * (N + 1) + N) * sizeof(cx<T>);
 }
 
-static_assert(12 % plane_rows<12, double>() == 0 && 24 % plane_rows<24, double>() == 0, "row batch must divide N");
+// W_N^(DIR * j) from the forward table tw[j] = exp(-2 pi i j / N)
+template <int DIR, typename T> __device__ __forceinline__ cx<T> twiddle(const cx<T>* tw, int j) {
+  cx<T> w = tw[j];
+  if (DIR > 0) w.y = -w.y;
+  return w;
+}
 
+// signed frequency of FFT index k (|result| <= (N-1)/2 for the indices the sphere uses)
+template <int N> __device__ __forceinline__ int freq(int k) { return k <= (N - 1) / 2 ? k : k - N; }
+
+// One (z-plane, band) per block. With N = N1 N2 every length-N transform is two register codelets
+// (N1 and N2) around one exchange through LDS:
+//   A  inverse y on the 2R+1 x-lines, read straight from the disk-column row of this plane; the line
+//      stays in LDS in digit-reversed order (position N2 a + b holds y = a + N1 b)
+//   B  per row y: inverse x from the 2R+1 nonzero x-lines, then in registers: second inverse stage,
+//      multiply by V(r), first forward stage; one more exchange; second forward stage keeps the 2R+1
+//      x-lines
+//   C  forward y, written straight to the disk-column row of the output
 template <int N, typename T>
-__global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __restrict__ col,
+__global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __restrict__ xline,
                                               const cx<T>* __restrict__ twg, const T* __restrict__ Vt,
                                               const cx<T>* __restrict__ cin, cx<T>* __restrict__ cout) {
-  constexpr int LS = N + 1, RB = plane_rows<N, T>();
-  static_assert(N % RB == 0, "row batch must divide N");
+  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = N + 1, RB = plane_rows<N, T>();
   extern __shared__ unsigned char smem_raw[];
   const int nx = 2 * rx + 1;
-  cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw);  // [nx][LS]: x-lines along y
-  cx<T>* S = L + nx * LS;                          // [RB][LS]: rows along x
-  cx<T>* tw = S + RB * LS;
+  cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw);  // [nx][LS] y-lines of the x-lines |gx| <= rx
+  cx<T>* Sc = L + nx * LS;                         // [RB][LS] rows of the x-pass
+  cx<T>* tw = Sc + RB * LS;
   const int z = blockIdx.x, band = blockIdx.y, tid = threadIdx.x;
-  for (int t = tid; t < N; t += NT) tw[t] = twg[t];
-  for (int t = tid; t < nx * LS; t += NT) L[t] = cx<T>{T(0), T(0)};
-  __syncthreads();
   const long base = long(band) * N * ncol + long(z) * ncol;
-  for (int c = tid; c < ncol; c += NT) {
-    const int4 ci = col[c];
-    L[ci.x * LS + ci.y] = cin[base + c];
+  const cx<T>* in = cin + base;
+  cx<T>* out = cout + base;
+  const cx<T> zero = {T(0), T(0)};
+  for (int t = tid; t < N; t += NT) tw[t] = twg[t];
+  __syncthreads();
+
+  // ---- A: inverse y ----
+  for (int task = tid; task < nx * N2; task += NT) {
+    const int xi = task / N2, n2 = task - xi * N2;
+    const int4 xl = xline[xi];  // {first column, lowest gy, column count, 0}
+    cx<T> v[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int j = freq<N>(N2 * n1 + n2) - xl.y;
+      v[n1] = (j >= 0 && j < xl.z) ? in[xl.x + j] : zero;
+    }
+    Dft<N1, +1>::run(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) L[xi * LS + N2 * k1 + n2] = k1 ? cmul(v[k1], twiddle<+1>(tw, (n2 * k1) % N)) : v[0];
   }
   __syncthreads();
-  lds_fft<N, +1, T>(L, nx, 1, LS, tw);
+  for (int task = tid; task < nx * N1; task += NT) {
+    const int xi = task / N1, a = task - xi * N1;
+    cx<T>* p = L + xi * LS + N2 * a;
+    cx<T> v[N2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) v[n2] = p[n2];
+    Dft<N2, +1>::run(v);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) p[k2] = v[k2];  // y = a + N1 k2
+  }
+  __syncthreads();
+
+  // ---- B: x-pass per row ----
   const T* Vz = Vt + long(z) * N * N;
   for (int y0 = 0; y0 < N; y0 += RB) {
-    for (int t = tid; t < RB * LS; t += NT) S[t] = cx<T>{T(0), T(0)};
-    __syncthreads();
-    for (int t = tid; t < nx * RB; t += NT) {
-      const int xi = t / RB, yy = t - xi * RB;
-      int x = xi - rx;
-      x += x < 0 ? N : 0;
-      S[yy * LS + x] = L[xi * LS + y0 + yy];
+    const int nrow = min(RB, N - y0);
+    for (int task = tid; task < nrow * N2; task += NT) {
+      const int yy = task / N2, n2 = task - yy * N2;
+      const int y = y0 + yy, py = N2 * (y % N1) + y / N1;
+      cx<T> v[N1];
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) {
+        const int gx = freq<N>(N2 * n1 + n2);
+        v[n1] = (gx >= -rx && gx <= rx) ? L[(gx + rx) * LS + py] : zero;
+      }
+      Dft<N1, +1>::run(v);
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1)
+        Sc[yy * LS + N2 * k1 + n2] = k1 ? cmul(v[k1], twiddle<+1>(tw, (n2 * k1) % N)) : v[0];
     }
     __syncthreads();
-    lds_fft<N, +1, T>(S, RB, 1, LS, tw);
-    for (int t = tid; t < RB * N; t += NT) {
-      const int yy = t / N, x = t - yy * N;
-      const T v = Vz[long(y0 + yy) * N + x];
-      cx<T> s = S[yy * LS + x];
-      S[yy * LS + x] = cx<T>{s.x * v, s.y * v};
+    for (int task = tid; task < nrow * N1; task += NT) {
+      const int yy = task / N1, a = task - yy * N1;
+      cx<T>* p = Sc + yy * LS + N2 * a;
+      const T* Vrow = Vz + long(y0 + yy) * N + a;
+      cx<T> v[N2];
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) v[n2] = p[n2];
+      Dft<N2, +1>::run(v);  // v[b] = psi(x = a + N1 b)
+#pragma unroll
+      for (int b = 0; b < N2; ++b) {
+        const T vr = Vrow[N1 * b];
+        v[b] = cx<T>{v[b].x * vr, v[b].y * vr};
+      }
+      Dft<N2, -1>::run(v);
+#pragma unroll
+      for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twiddle<-1>(tw, (a * kb) % N)) : v[0];
     }
     __syncthreads();
-    lds_fft<N, -1, T>(S, RB, 1, LS, tw);
-    for (int t = tid; t < nx * RB; t += NT) {
-      const int xi = t / RB, yy = t - xi * RB;
-      int x = xi - rx;
-      x += x < 0 ? N : 0;
-      L[xi * LS + y0 + yy] = S[yy * LS + x];
+    for (int task = tid; task < nrow * N2; task += NT) {
+      const int yy = task / N2, kb = task - yy * N2;
+      const int y = y0 + yy, py = N2 * (y % N1) + y / N1;
+      cx<T> v[N1];
+#pragma unroll
+      for (int a = 0; a < N1; ++a) v[a] = Sc[yy * LS + N2 * a + kb];
+      Dft<N1, -1>::run(v);
+#pragma unroll
+      for (int ka = 0; ka < N1; ++ka) {
+        const int gx = freq<N>(kb + N2 * ka);
+        if (gx >= -rx && gx <= rx) L[(gx + rx) * LS + py] = v[ka];
+      }
     }
     __syncthreads();
   }
-  lds_fft<N, -1, T>(L, nx, 1, LS, tw);
-  for (int c = tid; c < ncol; c += NT) {
-    const int4 ci = col[c];
-    cout[base + c] = L[ci.x * LS + ci.y];
+
+  // ---- C: forward y ----
+  for (int task = tid; task < nx * N1; task += NT) {
+    const int xi = task / N1, a = task - xi * N1;
+    cx<T>* p = L + xi * LS + N2 * a;
+    cx<T> v[N2];
+#pragma unroll
+    for (int b = 0; b < N2; ++b) v[b] = p[b];
+    Dft<N2, -1>::run(v);
+#pragma unroll
+    for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twiddle<-1>(tw, (a * kb) % N)) : v[0];
+  }
+  __syncthreads();
+  for (int task = tid; task < nx * N2; task += NT) {
+    const int xi = task / N2, kb = task - xi * N2;
+    const int4 xl = xline[xi];
+    cx<T> v[N1];
+#pragma unroll
+    for (int a = 0; a < N1; ++a) v[a] = L[xi * LS + N2 * a + kb];
+    Dft<N1, -1>::run(v);
+#pragma unroll
+    for (int ka = 0; ka < N1; ++ka) {
+      const int j = freq<N>(kb + N2 * ka) - xl.y;
+      if (j >= 0 && j < xl.z) out[xl.x + j] = v[ka];
+    }
   }
 }
 
@@ -182,7 +269,7 @@ hipError_t fft_plane(const FftGeom& g, const cx<T>* tw, const T* Vt, const cx<T>
     constexpr int N = decltype(nc)::value;
     const size_t lds = plane_lds<N, T>(2 * g.rx + 1);
     if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_plane<N, T>), dim3(N, nb), dim3(NT), lds, st, g.ncol, g.rx, g.col, tw, Vt, cin, cout);
+    hipLaunchKernelGGL((k_plane<N, T>), dim3(N, nb), dim3(NT), lds, st, g.ncol, g.rx, g.xline, tw, Vt, cin, cout);
     return hipGetLastError();
   });
 }

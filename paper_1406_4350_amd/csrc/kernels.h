@@ -37,6 +37,7 @@ struct FftGeom {
   int n, ncol, npw, rx;
   const int4* col;  // per column: {x-line index gx + rx, y = gy mod n, first sphere entry, length}
   const int* ent;   // per sphere entry: (column << 8) | (gz mod n)
+  const int4* xline;  // per x-line xi = gx + rx: {first column, lowest gy, number of columns (consecutive gy), 0}
 };
 template <typename T>
 hipError_t fft_col_inverse(const FftGeom& g, const cx<T>* tw, const cx<T>* X, long ldx, int nb, cx<T>* colbuf,
