@@ -143,6 +143,23 @@ cheb_status cheb_rayleigh_quotients(cheb_plan plan, const void* X, int ldx, int 
 cheb_status cheb_upper_bound(cheb_plan plan, int k, const void* v0_dev, double* lambda_plus_host, void* ws,
                              size_t ws_bytes, hipStream_t stream);
 
+/* Adjoint of one filter + Rayleigh-Ritz pass (an addition beyond the paper: differentiation form).
+ * Runs the forward Y = T_m((S^-1 H - c)/r) X0 (Alg. 2, Sec. 4.2) and Rayleigh-Ritz, writes the nb Ritz values
+ * (ascending) to ritz_dev, and the gradients of L = sum_{i < nk} w_i lambda_i (c, r held fixed) with the
+ * convention dL = 2 Re tr(G^H dX) for the complex start block:
+ *   dX   (npw x nb, plan precision, leading dimension lddx)  dL/dX0
+ *   dV   (n^3 FP64, [x][y][z] like V)                        dL/dV(r_j)
+ *   dD   (packed like cheb_set_D, FP64; NULL iff no projectors) dL/dD, symmetric per block
+ * w_dev: nk FP64 weights (1 <= nk <= nb). The recurrence is checkpointed every ckpt_every steps (pairs
+ * psi^(t-1), psi^t) and recomputed segment by segment, so memory grows with m / ckpt_every + ckpt_every.
+ * Requires a gap lambda_nk < lambda_(nk+1) and non-degenerate wanted Ritz values. Box sizes up to 64.
+ * Synchronizes (Rayleigh-Ritz). Workspace: cheb_backward_workspace_bytes. */
+cheb_status cheb_backward_workspace_bytes(cheb_plan plan, int nb, int m, int ckpt_every, size_t* bytes);
+cheb_status cheb_filter_rr_backward(cheb_plan plan, const void* X0, int ldx, int nb, int m, double c, double r,
+                                   int nk, const double* w_dev, int ckpt_every, double* ritz_dev, void* dX,
+                                   int lddx, double* dV_dev, double* dD_dev, void* ws, size_t ws_bytes,
+                                   hipStream_t stream);
+
 /* Kernel-class timers (diagnostics). While enabled, each launch of a class below made by calls on the plan is
  * bracketed by HIP events on the call's own stream, and the algorithmic bytes and flops of the launch
  * (from its shapes: the bytes the operation must move and the flops it must do, not what the kernel
@@ -157,7 +174,8 @@ typedef enum {
   CHEB_T_RR_GRAM = 6,       /* subspace matrices X^H H X, X^H S X */
   CHEB_T_RR_EIG = 7,        /* dense generalized eigensolver */
   CHEB_T_RR_ROTATE = 8,     /* X Z rotation and residual products */
-  CHEB_T_COUNT = 9
+  CHEB_T_XDENS = 9,         /* cross densities of the adjoint */
+  CHEB_T_COUNT = 10
 } cheb_timer;
 
 /* on != 0: reset the tallies and start timing; on == 0: stop. */

@@ -29,9 +29,10 @@ CHEB_OP_H, CHEB_OP_SINV, CHEB_OP_FILTER, CHEB_OP_RR, CHEB_OP_BOUND, CHEB_OP_SETU
 SYMBOLS = ["cheb_plan_persistent_bytes", "cheb_plan_create", "cheb_plan_destroy", "cheb_set_potential",
            "cheb_set_projectors", "cheb_set_D", "cheb_workspace_bytes", "cheb_apply_H", "cheb_apply_S",
            "cheb_apply_Sinv", "cheb_filter", "cheb_rayleigh_ritz", "cheb_rayleigh_quotients", "cheb_upper_bound",
-           "cheb_profile_enable", "cheb_profile_read", "cheb_last_error"]
+           "cheb_profile_enable", "cheb_profile_read", "cheb_backward_workspace_bytes", "cheb_filter_rr_backward",
+           "cheb_last_error"]
 TIMERS = ["fft_col_inverse", "fft_plane", "fft_col_forward", "project", "backproject", "small", "rr_gram", "rr_eig",
-          "rr_rotate"]
+          "rr_rotate", "xdens"]
 
 
 class ChebError(RuntimeError):
@@ -77,6 +78,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cheb_upper_bound": [vp, i, vp, P(d), vp, sz, vp],
         "cheb_profile_enable": [vp, i],
         "cheb_profile_read": [vp, i, P(d), P(ctypes.c_int64), P(d), P(d)],
+        "cheb_backward_workspace_bytes": [vp, i, i, i, P(sz)],
+        "cheb_filter_rr_backward": [vp, vp, i, i, i, d, d, i, vp, i, vp, vp, i, vp, vp, vp, sz, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -235,6 +238,31 @@ class Plan:
         return out.value
 
 
+    def filter_rr_backward(self, X0, m: int, c: float, r: float, w, ckpt_every: int = 3):
+        """Forward filter + Rayleigh-Ritz and the adjoint of L = sum_i w_i lambda_i (lowest len(w) Ritz values).
+        Returns (ritz, dX, dV, dD) with dL = 2 Re tr(dX^H dX0), dV (n, n, n) FP64, dD packed FP64."""
+        nb, ldx = self._block(X0, "X0")
+        w = torch.as_tensor(w, dtype=torch.float64).to(self.device).contiguous()
+        nk = int(w.numel())
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.cheb_backward_workspace_bytes(self.handle, nb, int(m), int(ckpt_every),
+                                                           ctypes.byref(nbytes)), "cheb_backward_workspace_bytes")
+        key = ("bwd", nb, int(m), int(ckpt_every))
+        if key not in self._ws:
+            self._ws = {k: v for k, v in self._ws.items() if k[0] != "bwd"}
+            self._ws[key] = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
+        ws = self._ws[key]
+        ritz = torch.empty(nb, dtype=torch.float64, device=self.device)
+        dX = torch.empty_like(X0)
+        dV = torch.empty((self.n,) * 3, dtype=torch.float64, device=self.device)
+        dsize = int(sum((int(self._off[a + 1]) - int(self._off[a])) ** 2 for a in range(self.natom)))
+        dD = torch.empty(max(dsize, 1), dtype=torch.float64, device=self.device)
+        self._check(self.lib.cheb_filter_rr_backward(
+            self.handle, X0.data_ptr(), ldx, nb, int(m), float(c), float(r), nk, w.data_ptr(), int(ckpt_every),
+            ritz.data_ptr(), dX.data_ptr(), dX.stride(0), dV.data_ptr(), dD.data_ptr() if dsize else None,
+            ws.data_ptr(), ws.numel(), _stream()), "cheb_filter_rr_backward")
+        return ritz, dX, dV, dD[:dsize]
+
     def profile_enable(self, on: bool = True):
         self._check(self.lib.cheb_profile_enable(self.handle, int(bool(on))), "cheb_profile_enable")
 
@@ -296,3 +324,7 @@ def cheb_rayleigh_quotients(plan: Plan, X):
 
 def cheb_upper_bound(plan: Plan, v0, k=10):
     return plan.upper_bound(v0, k)
+
+
+def cheb_filter_rr_backward(plan: Plan, X0, m, c, r, w, ckpt_every=3):
+    return plan.filter_rr_backward(X0, m, c, r, w, ckpt_every)

@@ -27,6 +27,7 @@ struct cheb_plan_s {
   int* ent = nullptr;
   int4* xline = nullptr;
   int4* pinfo = nullptr;
+  int2* dent = nullptr;  // packed D entry -> (global row, global column)
   void* tw = nullptr;
   void* kin = nullptr;
   void* Vt = nullptr;
@@ -125,7 +126,7 @@ struct Timed {
 
 // ---- layouts -------------------------------------------------------------------------------------------------
 struct Persist {
-  int4* col; int* ent; int4* xline; int4* pinfo; void* tw; void* kin; void* Vt; void* P; double* D; double* Q; c128* G; c128* Cinv;
+  int4* col; int* ent; int4* xline; int4* pinfo; int2* dent; void* tw; void* kin; void* Vt; void* P; double* D; double* Q; c128* G; c128* Cinv;
 };
 
 Persist persist_layout(void* base, int n, int npw, int ncol, int rx, int nproj, size_t dsize, int overlap, int prec) {
@@ -136,6 +137,7 @@ Persist persist_layout(void* base, int n, int npw, int ncol, int rx, int nproj, 
   l.ent = b.take<int>(npw);
   l.xline = b.take<int4>(2 * rx + 1);
   l.pinfo = b.take<int4>(std::max(nproj, 1));
+  l.dent = b.take<int2>(std::max<size_t>(dsize, 1));
   l.tw = mixed ? (void*)b.take<c64>(n) : (void*)b.take<c128>(n);
   l.kin = mixed ? (void*)b.take<float>(npw) : (void*)b.take<double>(npw);
   l.Vt = mixed ? (void*)b.take<float>(size_t(n) * n * n) : (void*)b.take<double>(size_t(n) * n * n);
@@ -155,6 +157,7 @@ size_t persist_bytes(int n, int npw, int ncol, int rx, int nproj, size_t dsize, 
   b.take<int>(npw);
   b.take<int4>(2 * rx + 1);
   b.take<int4>(std::max(nproj, 1));
+  b.take<int2>(std::max<size_t>(dsize, 1));
   mixed ? (void)b.take<c64>(n) : (void)b.take<c128>(n);
   mixed ? (void)b.take<float>(npw) : (void)b.take<double>(npw);
   mixed ? (void)b.take<float>(size_t(n) * n * n) : (void)b.take<double>(size_t(n) * n * n);
@@ -306,6 +309,63 @@ cheb_status solver_query(cheb_plan p, int op, int n, size_t* bytes) {
   return CHEB_OK;
 }
 
+// Workspace of the adjoint: one filter workspace and one Rayleigh-Ritz workspace, plus checkpoints, the
+// recomputed segment, the adjoint vectors and the cross-density scratch.
+struct BwdWs {
+  Ws fw, rr;
+  FftWs fft{};
+  void* colc = nullptr;
+  void* F[2] = {nullptr, nullptr};
+  void* bar[3] = {nullptr, nullptr, nullptr};
+  void *a = nullptr, *loca = nullptr;
+  std::vector<void*> ck, seg;       // 2 ncp checkpoint vectors, k - 1 segment vectors
+  std::vector<c128*> ckp, segp;     // their projections
+  c128* pf[2] = {nullptr, nullptr};
+  c128 *pbar = nullptr, *qa = nullptr, *pa = nullptr, *Dpa = nullptr, *B = nullptr;
+  double *xpart = nullptr, *norms = nullptr;
+  size_t total = 0;
+};
+
+cheb_status bwd_layout(cheb_plan p, int nb, int m, int k, void* base, BwdWs* w) {
+  Bump b(base);
+  const size_t eb = elem_bytes(p->prec);
+  const size_t vec = size_t(p->npw) * std::max(nb, 1) * eb;
+  const size_t pp = size_t(std::max(p->nproj, 1)) * std::max(nb, 1);
+  Ws probe;
+  CHK(ws_layout(p, CHEB_OP_FILTER, nb, nullptr, &probe));
+  char* fwb = b.take<char>(probe.total);
+  CHK(ws_layout(p, CHEB_OP_FILTER, nb, fwb, &w->fw));
+  CHK(ws_layout(p, CHEB_OP_RR, nb, nullptr, &probe));
+  char* rrb = b.take<char>(probe.total);
+  CHK(ws_layout(p, CHEB_OP_RR, nb, rrb, &w->rr));
+  const int fb = fft_batch_for(p, nb);
+  const size_t colb = size_t(fb) * p->n * p->ncol * eb;
+  w->fft.a = b.take<char>(colb);
+  w->fft.b = b.take<char>(colb);
+  w->colc = b.take<char>(colb);
+  for (int i = 0; i < 2; ++i) w->F[i] = b.take<char>(vec);
+  for (int i = 0; i < 3; ++i) w->bar[i] = b.take<char>(vec);
+  w->a = b.take<char>(vec);
+  w->loca = b.take<char>(vec);
+  const int ncp = (m + k - 1) / k;
+  w->ck.assign(2 * ncp, nullptr);
+  w->ckp.assign(2 * ncp, nullptr);
+  for (int i = 0; i < 2 * ncp; ++i) { w->ck[i] = b.take<char>(vec); w->ckp[i] = b.take<c128>(pp); }
+  w->seg.assign(std::max(k - 1, 0), nullptr);
+  w->segp.assign(std::max(k - 1, 0), nullptr);
+  for (int i = 0; i + 1 < k; ++i) { w->seg[i] = b.take<char>(vec); w->segp[i] = b.take<c128>(pp); }
+  for (int i = 0; i < 2; ++i) w->pf[i] = b.take<c128>(pp);
+  w->pbar = b.take<c128>(pp);
+  w->qa = b.take<c128>(pp);
+  w->pa = b.take<c128>(pp);
+  w->Dpa = b.take<c128>(pp);
+  w->B = b.take<c128>(size_t(std::max(nb, 1)) * std::max(nb, 1));
+  w->xpart = b.take<double>(cross_density_part_doubles(p->n, fb));
+  w->norms = b.take<double>(std::max(nb, 1));
+  w->total = b.off;
+  return CHEB_OK;
+}
+
 cheb_status check_ws(cheb_plan p, int op, int nb, void* ws, size_t wsb, Ws* w) {
   Ws probe;
   CHK(ws_layout(p, op, nb, nullptr, &probe));
@@ -435,62 +495,69 @@ template <typename T> struct Ops {
     return backproject(w.Dp, nb, e);
   }
 
+  // One step of the recurrence (Alg. 2 inner loop): out = s1 (S^-1 H cur - c cur) - s2 prev, with the
+  // projections p = P^H psi carried alongside (reuse trick, Sec. 5.1). out may alias prev (and pout pprev);
+  // prev / pprev are unused for i = 1.
+  cheb_status filter_step(int i, const C* cur, long ldc, const C* prev, long ldp, C* out, long ldo,
+                          const c128* pcur, const c128* pprev, c128* pout, int nb, double c, double r, const Ws& w) {
+    const int np = p->nproj;
+    const long npw = p->npw;
+    C* loc = static_cast<C*>(w.loc);
+    const double s1 = (i == 1 ? 1.0 : 2.0) / r;
+    const double s2 = (i == 1 ? 0.0 : 1.0);
+    CHK(hloc(cur, ldc, nb, loc, npw, w.fft));
+    if (np == 0) {
+      HIPCHK((axpbypcz<T>(npw, nb, s1, loc, npw, -s1 * c, cur, ldc, -s2, i == 1 ? nullptr : prev, ldp, out, ldo, st)));
+      return CHEB_OK;
+    }
+    // projector space: p_loc = P^H loc; D p; p_phi = P^H H psi = p_loc + G D p
+    CHK(project(loc, npw, nb, w.ploc, w.part));
+    HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, pcur, np, w.Dp, np, st));
+    Epi<double> e1;
+    e1.out = w.pphi; e1.ldo = np; e1.L = w.ploc; e1.ldl = np; e1.bL = 1.0;
+    CHK(small(p->G, w.Dp, nb, e1, w.part));
+    const c128* wv = w.Dp;
+    if (p->has_overlap) {
+      // q = C^-1 p_phi; w = D p - q  (S^-1 H psi = loc + P w, Sec. 5.1)
+      Epi<double> e2;
+      e2.out = w.q; e2.ldo = np;
+      CHK(small(p->Cinv, w.pphi, nb, e2, w.part));
+      HIPCHK((axpbypcz<double>(np, nb, 1.0, w.Dp, np, -1.0, w.q, np, 0.0, nullptr, 0, w.w, np, st)));
+      wv = w.w;
+    }
+    // psi^i = s1 (loc + P w - c psi^(i-1)) - s2 psi^(i-2)
+    Epi<T> e;
+    e.out = out; e.ldo = ldo; e.alpha = s1;
+    e.L = loc; e.ldl = npw; e.bL = s1;
+    e.U = cur; e.ldu = ldc; e.bU = -s1 * c;
+    if (i > 1) { e.W = prev; e.ldw = ldp; e.bW = -s2; }
+    CHK(backproject(wv, nb, e));
+    // p^i = s1 (p_y - c p^(i-1)) - s2 p^(i-2), with p_y = P^H S^-1 H psi = p_phi - G q (reuse trick)
+    if (p->has_overlap) {
+      Epi<double> e3;
+      e3.out = pout; e3.ldo = np; e3.alpha = -s1;
+      e3.L = w.pphi; e3.ldl = np; e3.bL = s1;
+      e3.U = pcur; e3.ldu = np; e3.bU = -s1 * c;
+      if (i > 1) { e3.W = pprev; e3.ldw = np; e3.bW = -s2; }
+      CHK(small(p->G, w.q, nb, e3, w.part));
+    } else {
+      HIPCHK((axpbypcz<double>(np, nb, s1, w.pphi, np, -s1 * c, pcur, np, -s2, i == 1 ? nullptr : pprev, np, pout, np,
+                               st)));
+    }
+    return CHEB_OK;
+  }
+
   // Alg. 2 inner loop for the whole block. psi^i overwrites psi^(i-2); buffers alternate X, W.
   cheb_status filter(C* X, long ldx, int nb, int m, double c, double r, const Ws& w) {
     if (m == 0 || nb == 0) return CHEB_OK;
-    const int np = p->nproj;
     const long npw = p->npw;
     C* buf[2] = {X, static_cast<C*>(w.W)};
     long ld[2] = {ldx, npw};
     c128* pb[2] = {w.p0, w.p1};
-    C* loc = static_cast<C*>(w.loc);
-    if (np > 0) CHK(project(X, ldx, nb, pb[0], w.part));
+    if (p->nproj > 0) CHK(project(X, ldx, nb, pb[0], w.part));
     for (int i = 1; i <= m; ++i) {
       const int ci = (i - 1) & 1, oi = i & 1;
-      const C* cur = buf[ci];
-      C* out = buf[oi];
-      const double s1 = (i == 1 ? 1.0 : 2.0) / r;
-      const double s2 = (i == 1 ? 0.0 : 1.0);
-      CHK(hloc(cur, ld[ci], nb, loc, npw, w.fft));
-      if (np == 0) {
-        HIPCHK((axpbypcz<T>(npw, nb, s1, loc, npw, -s1 * c, cur, ld[ci], -s2, i == 1 ? nullptr : out, ld[oi], out,
-                            ld[oi], st)));
-        continue;
-      }
-      // projector space: p_loc = P^H loc; D p; p_phi = P^H H psi = p_loc + G D p
-      CHK(project(loc, npw, nb, w.ploc, w.part));
-      HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, pb[ci], np, w.Dp, np, st));
-      Epi<double> e1;
-      e1.out = w.pphi; e1.ldo = np; e1.L = w.ploc; e1.ldl = np; e1.bL = 1.0;
-      CHK(small(p->G, w.Dp, nb, e1, w.part));
-      const c128* wv = w.Dp;
-      if (p->has_overlap) {
-        // q = C^-1 p_phi; w = D p - q  (S^-1 H psi = loc + P w, Sec. 5.1)
-        Epi<double> e2;
-        e2.out = w.q; e2.ldo = np;
-        CHK(small(p->Cinv, w.pphi, nb, e2, w.part));
-        HIPCHK((axpbypcz<double>(np, nb, 1.0, w.Dp, np, -1.0, w.q, np, 0.0, nullptr, 0, w.w, np, st)));
-        wv = w.w;
-      }
-      // psi^i = s1 (loc + P w - c psi^(i-1)) - s2 psi^(i-2)
-      Epi<T> e;
-      e.out = out; e.ldo = ld[oi]; e.alpha = s1;
-      e.L = loc; e.ldl = npw; e.bL = s1;
-      e.U = cur; e.ldu = ld[ci]; e.bU = -s1 * c;
-      if (i > 1) { e.W = out; e.ldw = ld[oi]; e.bW = -s2; }
-      CHK(backproject(wv, nb, e));
-      // p^i = s1 (p_y - c p^(i-1)) - s2 p^(i-2), with p_y = P^H S^-1 H psi = p_phi - G q (reuse trick)
-      if (p->has_overlap) {
-        Epi<double> e3;
-        e3.out = pb[oi]; e3.ldo = np; e3.alpha = -s1;
-        e3.L = w.pphi; e3.ldl = np; e3.bL = s1;
-        e3.U = pb[ci]; e3.ldu = np; e3.bU = -s1 * c;
-        if (i > 1) { e3.W = pb[oi]; e3.ldw = np; e3.bW = -s2; }
-        CHK(small(p->G, w.q, nb, e3, w.part));
-      } else {
-        HIPCHK((axpbypcz<double>(np, nb, s1, w.pphi, np, -s1 * c, pb[ci], np, -s2, i == 1 ? nullptr : pb[oi], np,
-                                 pb[oi], np, st)));
-      }
+      CHK(filter_step(i, buf[ci], ld[ci], buf[oi], ld[oi], buf[oi], ld[oi], pb[ci], pb[oi], pb[oi], nb, c, r, w));
     }
     if (m & 1) HIPCHK((convert_copy<T, T>(npw, nb, buf[1], npw, X, ldx, st)));
     return CHEB_OK;
@@ -604,6 +671,170 @@ template <typename T> struct Ops {
       HIPCHK((col_resid_norms<T>(npw, nb, R, npw, Ynew, npw, ritz, resid, st)));
     }
     HIPCHK((convert_copy<T, T>(npw, nb, Ynew, npw, X, ldx, st)));
+    return CHEB_OK;
+  }
+
+  // out = (K + V) a for a block, and dV += coef n^-3 Re sum_b conj(a_b(r)) psi_b(r) from the same column pass
+  cheb_status hloc_xdens(const C* a, long lda, const C* psi, long ldp, int nb, C* out, long ldo, double coef,
+                         double* dV, const BwdWs& bw) {
+    const int fb = fft_batch_for(p, nb);
+    const FftGeom g = geom();
+    const C* tw = static_cast<const C*>(p->tw);
+    C* ca = static_cast<C*>(bw.fft.a);
+    C* cb = static_cast<C*>(bw.fft.b);
+    C* cc = static_cast<C*>(bw.colc);
+    const double b = sizeof(C), colv = double(p->n) * p->ncol, npw = p->npw;
+    for (int b0 = 0; b0 < nb; b0 += fb) {
+      const int cnt = std::min(fb, nb - b0);
+      {
+        Timed t(p, st, CHEB_T_FFT_COL_INV, 2.0 * cnt * (npw + colv) * b, 0.0);
+        HIPCHK(fft_col_inverse<T>(g, tw, a + long(b0) * lda, lda, cnt, ca, st));
+        HIPCHK(fft_col_inverse<T>(g, tw, psi + long(b0) * ldp, ldp, cnt, cc, st));
+      }
+      {
+        Timed t(p, st, CHEB_T_FFT_PLANE, cnt * 2.0 * colv * b, 0.0);
+        HIPCHK(fft_plane<T>(g, tw, static_cast<const T*>(p->Vt), ca, cb, cnt, st));
+      }
+      {
+        Timed t(p, st, CHEB_T_FFT_COL_FWD, cnt * (colv + 2.0 * npw) * b, 0.0);
+        HIPCHK(fft_col_forward<T>(g, tw, cb, a + long(b0) * lda, lda, static_cast<const T*>(p->kin),
+                                  out + long(b0) * ldo, ldo, cnt, st));
+      }
+      {
+        Timed t(p, st, CHEB_T_XDENS, cnt * 2.0 * colv * b, 0.0);
+        HIPCHK(cross_density<T>(g, tw, ca, cc, cnt, nullptr, coef, bw.xpart, dV, st));
+      }
+    }
+    return CHEB_OK;
+  }
+
+  // dV += n^-3 sum_i w_i |u_i(r)|^2 over the first nk bands of U (Hellmann-Feynman term)
+  cheb_status density(const C* U, long ldu, int nk, const double* wts, double* dV, const BwdWs& bw) {
+    const int fb = fft_batch_for(p, nk);
+    const FftGeom g = geom();
+    const C* tw = static_cast<const C*>(p->tw);
+    C* ca = static_cast<C*>(bw.fft.a);
+    for (int b0 = 0; b0 < nk; b0 += fb) {
+      const int cnt = std::min(fb, nk - b0);
+      HIPCHK(fft_col_inverse<T>(g, tw, U + long(b0) * ldu, ldu, cnt, ca, st));
+      Timed t(p, st, CHEB_T_XDENS, cnt * double(p->n) * p->ncol * sizeof(C), 0.0);
+      HIPCHK(cross_density<T>(g, tw, ca, ca, cnt, wts + b0, 1.0, bw.xpart, dV, st));
+    }
+    return CHEB_OK;
+  }
+
+  // Filter + Rayleigh-Ritz forward, then the adjoint of L = sum_{i<nk} w_i lambda_i with c, r fixed.
+  cheb_status backward(const C* X0, long ldx, int nb, int m, double c, double r, int nk, const double* wts, int k,
+                       double* ritz, C* dX, long lddx, double* dV, double* dD, const BwdWs& bw) {
+    const int np = p->nproj;
+    const long npw = p->npw;
+    const long nv = long(p->n) * p->n * p->n;
+    HIPCHK(fill_zero_real<double>(dV, nv, st));
+    if (dD && p->dsize) HIPCHK(fill_zero_real<double>(dD, long(p->dsize), st));
+    C* F[2] = {static_cast<C*>(bw.F[0]), static_cast<C*>(bw.F[1])};
+    const int ncp = (m + k - 1) / k;
+    // ---- forward with checkpoints (psi^(t-1), psi^t) at t = 0, k, 2k, ...
+    HIPCHK((convert_copy<T, T>(npw, nb, X0, ldx, F[0], npw, st)));
+    if (np > 0) CHK(project(F[0], npw, nb, bw.pf[0], bw.fw.part));
+    for (int i = 1; i <= m; ++i) {
+      const int ci = (i - 1) & 1, oi = i & 1;
+      if ((i - 1) % k == 0) {
+        const int j = (i - 1) / k;
+        HIPCHK((convert_copy<T, T>(npw, nb, F[ci], npw, static_cast<C*>(bw.ck[2 * j + 1]), npw, st)));
+        if (np > 0) HIPCHK((convert_copy<double, double>(np, nb, bw.pf[ci], np, bw.ckp[2 * j + 1], np, st)));
+        if (i >= 2) {
+          HIPCHK((convert_copy<T, T>(npw, nb, F[oi], npw, static_cast<C*>(bw.ck[2 * j]), npw, st)));
+          if (np > 0) HIPCHK((convert_copy<double, double>(np, nb, bw.pf[oi], np, bw.ckp[2 * j], np, st)));
+        }
+      }
+      CHK(filter_step(i, F[ci], npw, F[oi], npw, F[oi], npw, bw.pf[ci], bw.pf[oi], bw.pf[oi], nb, c, r, bw.fw));
+    }
+    C* Y = F[m & 1];
+    // ---- Rayleigh-Ritz with residual vectors: U = Y Z, R = H U - S U Lambda
+    CHK(rayleigh_ritz(Y, npw, nb, ritz, bw.norms, bw.rr));
+    C* R = static_cast<C*>(bw.rr.R);
+    const C* U = static_cast<const C*>(bw.rr.Ynew);
+    HIPCHK(sub_lambda_cols<T>(npw, nk, R, npw, U, npw, ritz, st));
+    // Hellmann-Feynman terms at fixed Y
+    CHK(density(U, npw, nk, wts, dV, bw));
+    if (np > 0 && dD) HIPCHK(block_grad(int(p->dsize), p->dent, nk, bw.rr.q, np, bw.rr.q, np, wts, 0.5, dD, st));
+    // Ybar = R_K W Z_K^H
+    C* bar[3] = {static_cast<C*>(bw.bar[0]), static_cast<C*>(bw.bar[1]), static_cast<C*>(bw.bar[2])};
+    HIPCHK(weighted_adjoint(nk, nb, wts, bw.rr.Hs, nb, bw.B, st));
+    {
+      Epi<T> e;
+      e.out = bar[m % 3]; e.ldo = npw;
+      HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, nk, R, npw, bw.B, nk, e, 1, nullptr, st, ROLE_SUBSPACE)));
+    }
+    HIPCHK((fill_zero<T>(bar[(m - 1) % 3], npw * nb, st)));
+    // ---- reverse sweep over segments, recomputing psi^(t0) .. psi^(t1-1) from each checkpoint
+    std::vector<C*> seg(k);
+    std::vector<c128*> segp(k);
+    for (int sgm = ncp - 1; sgm >= 0; --sgm) {
+      const int t0 = sgm * k, t1 = std::min(m, t0 + k);
+      seg[0] = static_cast<C*>(bw.ck[2 * sgm + 1]);
+      segp[0] = bw.ckp[2 * sgm + 1];
+      for (int j = t0 + 1; j < t1; ++j) {
+        const int idx = j - t0;
+        seg[idx] = static_cast<C*>(bw.seg[idx - 1]);
+        segp[idx] = bw.segp[idx - 1];
+        const C* prv = idx >= 2 ? seg[idx - 2] : static_cast<const C*>(bw.ck[2 * sgm]);
+        const c128* pprv = idx >= 2 ? segp[idx - 2] : bw.ckp[2 * sgm];
+        CHK(filter_step(j, seg[idx - 1], npw, prv, npw, seg[idx], npw, segp[idx - 1], pprv, segp[idx], nb, c, r, bw.fw));
+      }
+      for (int i = t1; i >= t0 + 1; --i) {
+        const C* psim1 = seg[i - 1 - t0];
+        const c128* pm1 = segp[i - 1 - t0];
+        CHK(adjoint_step(i, bar[i % 3], bar[(i - 1) % 3], i >= 2 ? bar[(i - 2) % 3] : nullptr, psim1, pm1, nb, c, r,
+                         dV, dD, bw));
+      }
+    }
+    HIPCHK((convert_copy<T, T>(npw, nb, bar[0], npw, dX, lddx, st)));
+    return CHEB_OK;
+  }
+
+  // psibar^(i-1) += s (H a - c psibar^i), psibar^(i-2) = -psibar^i, a = S^-1 psibar^i; gradient terms of step i
+  cheb_status adjoint_step(int i, C* Bi, C* Bm1, C* Bm2, const C* psim1, const c128* pm1, int nb, double c, double r,
+                           double* dV, double* dD, const BwdWs& bw) {
+    const int np = p->nproj;
+    const long npw = p->npw;
+    const double si = (i == 1 ? 1.0 : 2.0) / r;
+    const Ws& w = bw.fw;
+    const C* a = Bi;
+    const c128* pa = bw.pbar;
+    if (np > 0) {
+      CHK(project(Bi, npw, nb, bw.pbar, w.part));
+      if (p->has_overlap) {
+        Epi<double> eq;
+        eq.out = bw.qa; eq.ldo = np;
+        CHK(small(p->Cinv, bw.pbar, nb, eq, w.part));
+        Epi<T> ea;
+        ea.out = static_cast<C*>(bw.a); ea.ldo = npw; ea.alpha = -1.0;
+        ea.L = Bi; ea.ldl = npw; ea.bL = 1.0;
+        CHK(backproject(bw.qa, nb, ea));
+        a = static_cast<const C*>(bw.a);
+        Epi<double> ep;
+        ep.out = bw.pa; ep.ldo = np; ep.alpha = -1.0;
+        ep.L = bw.pbar; ep.ldl = np; ep.bL = 1.0;
+        CHK(small(p->G, bw.qa, nb, ep, w.part));
+        pa = bw.pa;
+      }
+    }
+    C* loca = static_cast<C*>(bw.loca);
+    CHK(hloc_xdens(a, npw, psim1, npw, nb, loca, npw, 2.0 * si, dV, bw));
+    if (np > 0) {
+      HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, pa, np, bw.Dpa, np, st));
+      Epi<T> e;
+      e.out = Bm1; e.ldo = npw; e.alpha = si;
+      e.L = loca; e.ldl = npw; e.bL = si;
+      e.U = Bi; e.ldu = npw; e.bU = -si * c;
+      e.W = Bm1; e.ldw = npw; e.bW = 1.0;
+      CHK(backproject(bw.Dpa, nb, e));
+      if (dD) HIPCHK(block_grad(int(p->dsize), p->dent, nb, pa, np, pm1, np, nullptr, si, dD, st));
+    } else {
+      HIPCHK((axpbypcz<T>(npw, nb, si, loca, npw, -si * c, Bi, npw, 1.0, Bm1, npw, Bm1, npw, st)));
+    }
+    if (Bm2) HIPCHK((axpbypcz<T>(npw, nb, -1.0, Bi, npw, 0.0, nullptr, 0, 0.0, nullptr, 0, Bm2, npw, st)));
     return CHEB_OK;
   }
 
@@ -774,7 +1005,7 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   p->has_overlap = d->has_overlap ? 1 : 0; p->prec = d->prec; p->dsize = dsize;
   p->proj_off.assign(d->proj_off_host, d->proj_off_host + (d->natom > 0 ? d->natom + 1 : 0));
   Persist l = persist_layout(persistent, d->n, d->npw, ncol, rx, nproj, dsize, p->has_overlap, d->prec);
-  p->col = l.col; p->ent = l.ent; p->xline = l.xline; p->pinfo = l.pinfo; p->tw = l.tw; p->kin = l.kin; p->Vt = l.Vt; p->P = l.P;
+  p->col = l.col; p->ent = l.ent; p->xline = l.xline; p->pinfo = l.pinfo; p->dent = l.dent; p->tw = l.tw; p->kin = l.kin; p->Vt = l.Vt; p->P = l.P;
   p->D = l.D; p->Q = l.Q; p->G = l.G; p->Cinv = l.Cinv;
 
   // host-side index maps
@@ -800,9 +1031,12 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   }
   std::vector<int4> pinfo(std::max(nproj, 1), int4{0, 0, 0, 0});
   size_t doff = 0;
+  std::vector<int2> dent(std::max<size_t>(dsize, 1), int2{0, 0});
   for (int a = 0; a < d->natom; ++a) {
     const int o = d->proj_off_host[a], na = d->proj_off_host[a + 1] - o;
     for (int i = 0; i < na; ++i) pinfo[o + i] = int4{o, na, int(doff), 0};
+    for (int i = 0; i < na; ++i)
+      for (int j = 0; j < na; ++j) dent[doff + size_t(i) * na + j] = int2{o + i, o + j};
     doff += size_t(na) * na;
   }
   const bool mixed = d->prec == CHEB_MIXED;
@@ -821,6 +1055,7 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   if ((e = hipMemcpyAsync(p->ent, ent.data(), sizeof(int) * d->npw, hipMemcpyHostToDevice, st))) return fail_hip(e, "ent");
   if ((e = hipMemcpyAsync(p->xline, xline.data(), sizeof(int4) * xline.size(), hipMemcpyHostToDevice, st))) return fail_hip(e, "xline");
   if ((e = hipMemcpyAsync(p->pinfo, pinfo.data(), sizeof(int4) * pinfo.size(), hipMemcpyHostToDevice, st))) return fail_hip(e, "pinfo");
+  if ((e = hipMemcpyAsync(p->dent, dent.data(), sizeof(int2) * dent.size(), hipMemcpyHostToDevice, st))) return fail_hip(e, "dent");
   if (mixed) {
     std::vector<c64> tw32(d->n);
     std::vector<float> kin32(d->npw);
@@ -1046,6 +1281,50 @@ cheb_status cheb_upper_bound(cheb_plan p, int k, const void* v0, double* lambda_
   return with_prec(p, st, [&](auto ops) {
     using C = typename decltype(ops)::C;
     return ops.upper_bound(k, static_cast<const C*>(v0), lambda_plus, w);
+  });
+}
+
+static cheb_status backward_check(cheb_plan p, int nb, int m, int k) {
+  if (nb < 1) return fail(p, CHEB_ERR_ARG, "nb must be >= 1");
+  if (m < 1) return fail(p, CHEB_ERR_ARG, "degree m must be >= 1");
+  if (k < 1) return fail(p, CHEB_ERR_ARG, "ckpt_every must be >= 1");
+  if (p->n > 64) return fail(p, CHEB_ERR_ARG, "the adjoint supports FFT boxes up to 64");
+  if (fft_xdens_lds_bytes(p->n, p->rx, p->prec != CHEB_MIXED) > 160 * 1024)
+    return fail(p, CHEB_ERR_ARG, "sphere too wide in x for the cross-density pass in 160 KB of LDS");
+  return CHEB_OK;
+}
+
+cheb_status cheb_backward_workspace_bytes(cheb_plan p, int nb, int m, int ckpt_every, size_t* bytes) {
+  if (!p || !bytes) return CHEB_ERR_ARG;
+  CHK(backward_check(p, nb, m, ckpt_every));
+  BwdWs w;
+  CHK(bwd_layout(p, nb, m, ckpt_every, nullptr, &w));
+  *bytes = w.total;
+  return CHEB_OK;
+}
+
+cheb_status cheb_filter_rr_backward(cheb_plan p, const void* X0, int ldx, int nb, int m, double c, double r, int nk,
+                                   const double* w_dev, int ckpt_every, double* ritz_dev, void* dX, int lddx,
+                                   double* dV_dev, double* dD_dev, void* ws, size_t wsb, hipStream_t st) {
+  if (!p) return CHEB_ERR_ARG;
+  CHK(check_ready(p));
+  CHK(backward_check(p, nb, m, ckpt_every));
+  CHK(check_block(p, X0, ldx, nb, "X0"));
+  CHK(check_block(p, dX, lddx, nb, "dX"));
+  if (nk < 1 || nk > nb) return fail(p, CHEB_ERR_ARG, "nk must be in [1, nb]");
+  if (!w_dev || !ritz_dev || !dV_dev) return fail(p, CHEB_ERR_ARG, "null w, ritz or dV");
+  if (p->dsize > 0 && !dD_dev) return fail(p, CHEB_ERR_ARG, "null dD");
+  if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite(c)) return fail(p, CHEB_ERR_ARG, "need finite c and r > 0");
+  BwdWs probe;
+  CHK(bwd_layout(p, nb, m, ckpt_every, nullptr, &probe));
+  if (wsb < probe.total) return fail(p, CHEB_ERR_WORKSPACE, "workspace too small: need " + std::to_string(probe.total));
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(p, CHEB_ERR_ARG, "workspace null or not 256-byte aligned");
+  BwdWs w;
+  CHK(bwd_layout(p, nb, m, ckpt_every, ws, &w));
+  return with_prec(p, st, [&](auto ops) {
+    using C = typename decltype(ops)::C;
+    return ops.backward(static_cast<const C*>(X0), ldx, nb, m, c, r, nk, w_dev, ckpt_every, ritz_dev,
+                        static_cast<C*>(dX), lddx, dV_dev, dD_dev, w);
   });
 }
 

@@ -201,6 +201,144 @@ __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __re
   }
 }
 
+// ---- cross density for the adjoint: part[chunk][z][y][x] = sum_b w_b Re(conj(a_b(r)) psi_b(r)) ----------
+// Inputs are the z-transformed disk columns of both blocks (as written by the column pass). Per block: one
+// z-plane and a chunk of bands; each thread keeps its (y, x) points of every row batch in FP64 registers
+// across the bands of the chunk, so the band sum is in a fixed order.
+template <int N, typename T> constexpr int xdens_rows() { return plane_rows<N, T>(); }
+template <int N, typename T> constexpr int xdens_batches() { return (N + xdens_rows<N, T>() - 1) / xdens_rows<N, T>(); }
+template <int N, typename T> constexpr size_t xdens_lds(int nx) {
+  return (size_t(2 * (nx + xdens_rows<N, T>())) * (N + 1) + N) * sizeof(cx<T>);
+}
+
+// inverse y of one x-line block (both stages), the line ends in digit-reversed order as in k_plane
+template <int N, typename T>
+__device__ __forceinline__ void y_inverse(const cx<T>* __restrict__ in, cx<T>* L, const int4* __restrict__ xline,
+                                          const cx<T>* tw, int nx) {
+  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = N + 1;
+  const int tid = threadIdx.x;
+  const cx<T> zero = {T(0), T(0)};
+  for (int task = tid; task < nx * N2; task += NT) {
+    const int xi = task / N2, n2 = task - xi * N2;
+    const int4 xl = xline[xi];
+    cx<T> v[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int j = freq<N>(N2 * n1 + n2) - xl.y;
+      v[n1] = (j >= 0 && j < xl.z) ? in[xl.x + j] : zero;
+    }
+    Dft<N1, +1>::run(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) L[xi * LS + N2 * k1 + n2] = k1 ? cmul(v[k1], twiddle<+1>(tw, (n2 * k1) % N)) : v[0];
+  }
+  __syncthreads();
+  for (int task = tid; task < nx * N1; task += NT) {
+    const int xi = task / N1, a = task - xi * N1;
+    cx<T>* p = L + xi * LS + N2 * a;
+    cx<T> v[N2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) v[n2] = p[n2];
+    Dft<N2, +1>::run(v);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) p[k2] = v[k2];
+  }
+}
+
+// first inverse-x stage of rows y0 .. y0 + nrow - 1 from the x-lines in L into the row scratch S
+template <int N, typename T>
+__device__ __forceinline__ void x_inverse_stage1(const cx<T>* L, cx<T>* S, const cx<T>* tw, int rx, int y0, int nrow) {
+  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = N + 1;
+  const cx<T> zero = {T(0), T(0)};
+  for (int task = threadIdx.x; task < nrow * N2; task += NT) {
+    const int yy = task / N2, n2 = task - yy * N2;
+    const int y = y0 + yy, py = N2 * (y % N1) + y / N1;
+    cx<T> v[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int gx = freq<N>(N2 * n1 + n2);
+      v[n1] = (gx >= -rx && gx <= rx) ? L[(gx + rx) * LS + py] : zero;
+    }
+    Dft<N1, +1>::run(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) S[yy * LS + N2 * k1 + n2] = k1 ? cmul(v[k1], twiddle<+1>(tw, (n2 * k1) % N)) : v[0];
+  }
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(NT) void k_xdens(int ncol, int rx, const int4* __restrict__ xline,
+                                              const cx<T>* __restrict__ twg, const cx<T>* __restrict__ ca,
+                                              const cx<T>* __restrict__ cb, int nband, int bpc,
+                                              const double* __restrict__ wts, double* __restrict__ part) {
+  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = N + 1;
+  constexpr int RB = xdens_rows<N, T>(), NBT = xdens_batches<N, T>();
+  static_assert(RB * N1 <= NT, "one second-stage task per thread and row batch");
+  extern __shared__ unsigned char smem_raw[];
+  const int nx = 2 * rx + 1;
+  cx<T>* La = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* Lb = La + nx * LS;
+  cx<T>* Sa = Lb + nx * LS;
+  cx<T>* Sb = Sa + RB * LS;
+  cx<T>* tw = Sb + RB * LS;
+  const int z = blockIdx.x, chunk = blockIdx.y, tid = threadIdx.x;
+  const int b0 = chunk * bpc, b1 = min(nband, b0 + bpc);
+  for (int t = tid; t < N; t += NT) tw[t] = twg[t];
+  double acc[NBT][N2];
+#pragma unroll
+  for (int t = 0; t < NBT; ++t)
+#pragma unroll
+    for (int b = 0; b < N2; ++b) acc[t][b] = 0.0;
+  const int yy = tid / N1, a = tid - (tid / N1) * N1;
+  __syncthreads();
+  for (int band = b0; band < b1; ++band) {
+    const double wt = wts ? wts[band] : 1.0;
+    const long base = long(band) * N * ncol + long(z) * ncol;
+    y_inverse<N, T>(ca + base, La, xline, tw, nx);
+    y_inverse<N, T>(cb + base, Lb, xline, tw, nx);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NBT; ++t) {
+      const int y0 = t * RB, nrow = min(RB, N - y0);
+      x_inverse_stage1<N, T>(La, Sa, tw, rx, y0, nrow);
+      x_inverse_stage1<N, T>(Lb, Sb, tw, rx, y0, nrow);
+      __syncthreads();
+      if (yy < nrow) {
+        cx<T> va[N2], vb[N2];
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) {
+          va[n2] = Sa[yy * LS + N2 * a + n2];
+          vb[n2] = Sb[yy * LS + N2 * a + n2];
+        }
+        Dft<N2, +1>::run(va);
+        Dft<N2, +1>::run(vb);
+#pragma unroll
+        for (int b = 0; b < N2; ++b)
+          acc[t][b] += wt * (double(va[b].x) * double(vb[b].x) + double(va[b].y) * double(vb[b].y));
+      }
+      __syncthreads();
+    }
+  }
+  double* out = part + (long(chunk) * N + z) * N * N;
+#pragma unroll
+  for (int t = 0; t < NBT; ++t) {
+    const int y0 = t * RB, nrow = min(RB, N - y0);
+    if (yy < nrow) {
+#pragma unroll
+      for (int b = 0; b < N2; ++b) out[long(y0 + yy) * N + a + N1 * b] = acc[t][b];
+    }
+  }
+}
+
+// dV[x][y][z] += coef * sum_chunk part[chunk][z][y][x]
+__global__ void k_xdens_reduce(int n, int nchunk, const double* __restrict__ part, double coef, double* __restrict__ dV) {
+  const long total = long(n) * n * n;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < nchunk; ++c) s += part[long(c) * total + t];
+    const long x = t % n, y = (t / n) % n, z = t / (long(n) * n);
+    dV[(x * n + y) * n + z] += coef * s;
+  }
+}
+
 template <int N, typename T>
 __global__ __launch_bounds__(NT) void k_col_fwd(int ncol, const int4* __restrict__ col, const int* __restrict__ ent,
                                                 const cx<T>* __restrict__ twg, const cx<T>* __restrict__ colbuf,
@@ -298,6 +436,51 @@ size_t fft_plane_lds_bytes(int n, int rx, bool dbl) {
   return out;
 }
 
+int xdens_chunks(int n, int nband) {
+  int c = (1024 + n - 1) / n;
+  return c < nband ? c : (nband > 0 ? nband : 1);
+}
+
+template <typename T>
+hipError_t cross_density(const FftGeom& g, const cx<T>* tw, const cx<T>* ca, const cx<T>* cb, int nband,
+                         const double* wts, double coef, double* part, double* dV, hipStream_t st) {
+  if (nband <= 0) return hipSuccess;
+  if (g.n > 64) return hipErrorInvalidValue;
+  const int nchunk = xdens_chunks(g.n, nband);
+  const int bpc = (nband + nchunk - 1) / nchunk;
+  hipError_t e = dispatch_n(g.n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    if constexpr (N <= 64) {
+      const size_t lds = xdens_lds<N, T>(2 * g.rx + 1);
+      if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+      hipLaunchKernelGGL((k_xdens<N, T>), dim3(N, nchunk), dim3(NT), lds, st, g.ncol, g.rx, g.xline, tw, ca, cb, nband,
+                         bpc, wts, part);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  });
+  if (e != hipSuccess) return e;
+  const long total = long(g.n) * g.n * g.n;
+  int blocks = int((total + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_xdens_reduce, dim3(blocks), dim3(256), 0, st, g.n, nchunk, part,
+                     coef / (double(g.n) * g.n * g.n), dV);
+  return hipGetLastError();
+}
+
+size_t cross_density_part_doubles(int n, int nband) { return size_t(xdens_chunks(n, nband)) * n * n * n; }
+
+size_t fft_xdens_lds_bytes(int n, int rx, bool dbl) {
+  size_t out = 0;
+  (void)dispatch_n(n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    out = dbl ? xdens_lds<N, double>(2 * rx + 1) : xdens_lds<N, float>(2 * rx + 1);
+    return hipSuccess;
+  });
+  return out;
+}
+
 hipError_t fft_prepare_attributes() {
   // allow the plane kernels their full dynamic LDS (up to 160 KB on gfx950)
   hipError_t err = hipSuccess;
@@ -309,12 +492,20 @@ hipError_t fft_prepare_attributes() {
     constexpr int N = decltype(nc)::value;
     set(reinterpret_cast<const void*>(&k_plane<N, double>));
     set(reinterpret_cast<const void*>(&k_plane<N, float>));
+    if constexpr (N <= 64) {
+      set(reinterpret_cast<const void*>(&k_xdens<N, double>));
+      set(reinterpret_cast<const void*>(&k_xdens<N, float>));
+    }
     return hipSuccess;
   };
   for (int n : {8, 12, 16, 24, 32, 48, 64, 96, 128}) (void)dispatch_n(n, each);
   return err;
 }
 
+template hipError_t cross_density<double>(const FftGeom&, const c128*, const c128*, const c128*, int, const double*,
+                                          double, double*, double*, hipStream_t);
+template hipError_t cross_density<float>(const FftGeom&, const c64*, const c64*, const c64*, int, const double*,
+                                         double, double*, double*, hipStream_t);
 template hipError_t fft_col_inverse<double>(const FftGeom&, const c128*, const c128*, long, int, c128*, hipStream_t);
 template hipError_t fft_col_inverse<float>(const FftGeom&, const c64*, const c64*, long, int, c64*, hipStream_t);
 template hipError_t fft_plane<double>(const FftGeom&, const c128*, const double*, const c128*, c128*, int, hipStream_t);

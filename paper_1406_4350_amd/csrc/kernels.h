@@ -49,6 +49,13 @@ template <typename T>
 hipError_t fft_col_forward(const FftGeom& g, const cx<T>* tw, const cx<T>* colbuf, const cx<T>* X, long ldx,
                            const T* kin, cx<T>* out, long ldo, int nb, hipStream_t st);
 hipError_t fft_prepare_attributes();
+// dV[x][y][z] += coef n^-3 sum_b w_b Re(conj(a_b(r)) psi_b(r)) for nband bands of z-transformed disk columns ca, cb
+// (w = null: all weights 1); n <= 64; part: cross_density_part_doubles(n, nband) doubles of scratch
+template <typename T>
+hipError_t cross_density(const FftGeom& g, const cx<T>* tw, const cx<T>* ca, const cx<T>* cb, int nband,
+                         const double* wts, double coef, double* part, double* dV, hipStream_t st);
+size_t cross_density_part_doubles(int n, int nband);
+size_t fft_xdens_lds_bytes(int n, int rx, bool dbl);
 // dynamic LDS bytes of the plane pass for box n, x-line half-width rx (0 if n unsupported)
 size_t fft_plane_lds_bytes(int n, int rx, bool dbl);
 
@@ -88,6 +95,16 @@ template <typename E> hipError_t fill_zero(cx<E>* p, long count, hipStream_t st)
 // out[:, j] = a[:, j] - lam[j] b[:, j]  (contiguous rows x nb, complex128)
 hipError_t sub_scaled_cols(int rows, int nb, const c128* a, const c128* b, const double* lam, c128* out,
                            hipStream_t st);
+// out[e] += alpha sum_b w_b Re(conj(x[k,b]) y[l,b] + conj(x[l,b]) y[k,b]) for packed block entry e = (k, l)
+hipError_t block_grad(int dsize, const int2* dent, int nb, const c128* x, long ldx, const c128* y, long ldy,
+                      const double* wts, double alpha, double* out, hipStream_t st);
+// B[i + j nk] = w_i conj(Z[j + i ldz]), i < nk, j < nb
+hipError_t weighted_adjoint(int nk, int nb, const double* w, const c128* Z, long ldz, c128* B, hipStream_t st);
+// R[:, i] -= lam[i] U[:, i] for i < ncols
+template <typename E>
+hipError_t sub_lambda_cols(long rows, int ncols, cx<E>* R, long ldr, const cx<E>* U, long ldu, const double* lam,
+                           hipStream_t st);
+template <typename E> hipError_t fill_zero_real(E* p, long count, hipStream_t st);
 // out[i] = Re a[i] / Re b[i]
 hipError_t ratio_real(int nb, const c128* a, const c128* b, double* out, hipStream_t st);
 

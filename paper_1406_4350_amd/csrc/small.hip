@@ -309,3 +309,70 @@ hipError_t ratio_real(int nb, const c128* a, const c128* b, double* out, hipStre
   return hipGetLastError();
 }
 }  // namespace chebfd
+
+namespace chebfd {
+namespace {
+__global__ void k_block_grad(int dsize, const int2* __restrict__ dent, int nb, const c128* __restrict__ x, long ldx,
+                             const c128* __restrict__ y, long ldy, const double* __restrict__ wts, double alpha,
+                             double* __restrict__ out) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < dsize; e += gridDim.x * blockDim.x) {
+    const int k = dent[e].x, l = dent[e].y;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      const c128 xk = x[b * ldx + k], xl = x[b * ldx + l], yk = y[b * ldy + k], yl = y[b * ldy + l];
+      const double v = xk.x * yl.x + xk.y * yl.y + xl.x * yk.x + xl.y * yk.y;
+      s += wts ? wts[b] * v : v;
+    }
+    out[e] += alpha * s;
+  }
+}
+__global__ void k_weighted_adjoint(int nk, int nb, const double* w, const c128* Z, long ldz, c128* B) {
+  const long total = long(nk) * nb;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const int j = int(t / nk), i = int(t - long(j) * nk);
+    const c128 z = Z[j + i * ldz];
+    B[t] = c128{w[i] * z.x, -w[i] * z.y};
+  }
+}
+template <typename E>
+__global__ void k_sub_lambda(long rows, int ncols, cx<E>* R, long ldr, const cx<E>* U, long ldu, const double* lam) {
+  const long total = rows * ncols;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long j = t / rows, i = t - j * rows;
+    const cx<E> r = R[j * ldr + i], u = U[j * ldu + i];
+    const double l = lam[j];
+    R[j * ldr + i] = cx<E>{E(double(r.x) - l * double(u.x)), E(double(r.y) - l * double(u.y))};
+  }
+}
+template <typename E> __global__ void k_zero_real(E* p, long count) {
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < count; t += long(gridDim.x) * blockDim.x) p[t] = E(0);
+}
+}  // namespace
+
+hipError_t block_grad(int dsize, const int2* dent, int nb, const c128* x, long ldx, const c128* y, long ldy,
+                      const double* wts, double alpha, double* out, hipStream_t st) {
+  if (dsize <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_grad, dim3(nblocks(dsize)), dim3(256), 0, st, dsize, dent, nb, x, ldx, y, ldy, wts, alpha, out);
+  return hipGetLastError();
+}
+hipError_t weighted_adjoint(int nk, int nb, const double* w, const c128* Z, long ldz, c128* B, hipStream_t st) {
+  if (nk <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_weighted_adjoint, dim3(nblocks(long(nk) * nb)), dim3(256), 0, st, nk, nb, w, Z, ldz, B);
+  return hipGetLastError();
+}
+template <typename E>
+hipError_t sub_lambda_cols(long rows, int ncols, cx<E>* R, long ldr, const cx<E>* U, long ldu, const double* lam,
+                           hipStream_t st) {
+  if (rows <= 0 || ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sub_lambda<E>), dim3(nblocks(rows * ncols)), dim3(256), 0, st, rows, ncols, R, ldr, U, ldu, lam);
+  return hipGetLastError();
+}
+template <typename E> hipError_t fill_zero_real(E* p, long count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_zero_real<E>), dim3(nblocks(count)), dim3(256), 0, st, p, count);
+  return hipGetLastError();
+}
+template hipError_t sub_lambda_cols<double>(long, int, c128*, long, const c128*, long, const double*, hipStream_t);
+template hipError_t sub_lambda_cols<float>(long, int, c64*, long, const c64*, long, const double*, hipStream_t);
+template hipError_t fill_zero_real<double>(double*, long, hipStream_t);
+}  // namespace chebfd
