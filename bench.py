@@ -71,6 +71,7 @@ def run_path(cf, pb, prec, lam_plus, steps, warmup):
     t1 = time.perf_counter()
     prof = plan.profile_read()
     plan.profile_enable(False)
+    rr_stats = plan.rr_stats()
 
     # filter alone, event-timed on the current stream (same block, same interval)
     c = 0.5 * (lam_plus + state["lam_minus"])
@@ -85,7 +86,7 @@ def run_path(cf, pb, prec, lam_plus, steps, warmup):
     ev1.record()
     torch.cuda.synchronize()
     filter_ms = ev0.elapsed_time(ev1) / reps
-    return dict(plan=plan, X=X, seconds=t1 - t0, prof=prof, filter_ms=filter_ms, state=state,
+    return dict(plan=plan, X=X, seconds=t1 - t0, prof=prof, filter_ms=filter_ms, state=state, rr_stats=rr_stats,
                 apps_per_s=nb * m * steps / (t1 - t0), filter_apps_per_s=nb * m / (filter_ms * 1e-3))
 
 
@@ -256,6 +257,7 @@ def main():
                    "npw": pb.npw, "nb": cfg.nb, "nproj": pb.nproj, "m": cfg.m, "n": cfg.n},
         "filter_only": {"fp64_apps_per_s": r64["filter_apps_per_s"], "fp64_ms": r64["filter_ms"]},
         "breakdown_ms_per_step": {k: v["ms"] / args.steps for k, v in r64["prof"].items()},
+        "rr_solves_refined_library": r64["rr_stats"],
         "roofline": roofline(r64["prof"], "f64", cfg.n),
     }
     if not args.no_mixed:

@@ -133,6 +133,13 @@ cheb_status cheb_filter(cheb_plan plan, void* X, int ldx, int nb, int m, double 
 cheb_status cheb_rayleigh_ritz(cheb_plan plan, void* X, int ldx, int nb, double* ritz_dev, double* resid_dev,
                                void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Dense eigensolver of cheb_rayleigh_ritz. on (default): first try a warm-started iterative refinement of
+ * Z from the identity in the column-scaled basis (n^3 products only; accepted only if X^H S_X X = I and
+ * X^H H_X X diagonal to 1e-12 are verified), else the library path. off: always the library path.
+ * cheb_rr_stats counts the Rayleigh-Ritz calls solved each way. */
+cheb_status cheb_set_rr_refine(cheb_plan plan, int on);
+cheb_status cheb_rr_stats(cheb_plan plan, int64_t* refined, int64_t* fallback);
+
 /* rq_dev[i] = (x_i^H H x_i) / (x_i^H S x_i), FP64 (first step of Alg. 2). */
 cheb_status cheb_rayleigh_quotients(cheb_plan plan, const void* X, int ldx, int nb, double* rq_dev, void* ws,
                                     size_t ws_bytes, hipStream_t stream);

@@ -30,7 +30,7 @@ SYMBOLS = ["cheb_plan_persistent_bytes", "cheb_plan_create", "cheb_plan_destroy"
            "cheb_set_projectors", "cheb_set_D", "cheb_workspace_bytes", "cheb_apply_H", "cheb_apply_S",
            "cheb_apply_Sinv", "cheb_filter", "cheb_rayleigh_ritz", "cheb_rayleigh_quotients", "cheb_upper_bound",
            "cheb_profile_enable", "cheb_profile_read", "cheb_backward_workspace_bytes", "cheb_filter_rr_backward",
-           "cheb_last_error"]
+           "cheb_set_rr_refine", "cheb_rr_stats", "cheb_last_error"]
 TIMERS = ["fft_col_inverse", "fft_plane", "fft_col_forward", "project", "backproject", "small", "rr_gram", "rr_eig",
           "rr_rotate", "xdens"]
 
@@ -80,6 +80,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cheb_profile_read": [vp, i, P(d), P(ctypes.c_int64), P(d), P(d)],
         "cheb_backward_workspace_bytes": [vp, i, i, i, P(sz)],
         "cheb_filter_rr_backward": [vp, vp, i, i, i, d, d, i, vp, i, vp, vp, i, vp, vp, vp, sz, vp],
+        "cheb_set_rr_refine": [vp, i],
+        "cheb_rr_stats": [vp, P(ctypes.c_int64), P(ctypes.c_int64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -262,6 +264,15 @@ class Plan:
             ritz.data_ptr(), dX.data_ptr(), dX.stride(0), dV.data_ptr(), dD.data_ptr() if dsize else None,
             ws.data_ptr(), ws.numel(), _stream()), "cheb_filter_rr_backward")
         return ritz, dX, dV, dD[:dsize]
+
+    def set_rr_refine(self, on: bool):
+        self._check(self.lib.cheb_set_rr_refine(self.handle, int(bool(on))), "cheb_set_rr_refine")
+
+    def rr_stats(self) -> tuple[int, int]:
+        """(Rayleigh-Ritz calls solved by the warm-started refinement, calls solved by the library path)."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.cheb_rr_stats(self.handle, ctypes.byref(a), ctypes.byref(b)), "cheb_rr_stats")
+        return a.value, b.value
 
     def profile_enable(self, on: bool = True):
         self._check(self.lib.cheb_profile_enable(self.handle, int(bool(on))), "cheb_profile_enable")

@@ -38,6 +38,8 @@ struct cheb_plan_s {
   c128* Cinv = nullptr;
   bool have_V = false, have_P = false, have_D = false;
   int fft_batch = 1;
+  bool rr_refine = true;                    // warm-started refinement before the library eigensolver
+  int64_t rr_refined = 0, rr_fallback = 0;  // how Rayleigh-Ritz steps were solved
   rocblas_handle rb = nullptr;
   std::string err;
   // kernel-class timers
@@ -186,6 +188,9 @@ struct Ws {
   c128 *Hs = nullptr, *Ss = nullptr, *part = nullptr, *dots = nullptr, *dots2 = nullptr;
   double *d = nullptr, *E = nullptr;
   int* flags = nullptr;  // [0..1] rr_prepare flags, [2] solver info
+  c128 *Xa = nullptr, *Xb = nullptr, *T = nullptr, *M1 = nullptr, *M2 = nullptr, *F = nullptr;  // refinement
+  double *absF = nullptr, *lam = nullptr, *res = nullptr;
+  int* perm = nullptr;
   void* solver = nullptr;
   size_t solver_bytes = 0;
   size_t total = 0;
@@ -249,8 +254,21 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
       w->d = b.take<double>(std::max(nb, 1));
       w->E = b.take<double>(std::max(nb, 1));
       w->flags = b.take<int>(4);
+      {
+        const size_t nn = size_t(std::max(nb, 1)) * std::max(nb, 1);
+        w->Xa = b.take<c128>(nn);
+        w->Xb = b.take<c128>(nn);
+        w->T = b.take<c128>(nn);
+        w->M1 = b.take<c128>(nn);
+        w->M2 = b.take<c128>(nn);
+        w->F = b.take<c128>(nn);
+        w->absF = b.take<double>(nn);
+        w->lam = b.take<double>(std::max(nb, 1));
+        w->res = b.take<double>(4);
+        w->perm = b.take<int>(std::max(nb, 1));
+      }
       part = std::max({part_elems(np, nb, p->npw), part_elems(nb, nb, p->npw), part_elems(nb, nb, np),
-                       part_elems(np, nb, nb)});
+                       part_elems(np, nb, nb), part_elems(nb, nb, nb)});
       CHK(solver_query(p, CHEB_OP_RR, nb, &w->solver_bytes));
       w->solver = b.take<char>(std::max<size_t>(w->solver_bytes, 1));
       break;
@@ -596,6 +614,57 @@ template <typename T> struct Ops {
     return CHEB_OK;
   }
 
+  // Warm start: after the column scaling the previous Ritz vectors make Z' close to I. Generalized iterative
+  // refinement X <- X (I + F) (first-order correction of X^H S' X = I, X^H H' X diagonal) converges
+  // quadratically from there using only n^3 products; the result is accepted only after an explicit check of
+  // both conditions. Returns false (nothing written to ritz / Hs) when it does not converge.
+  bool rr_refine(int n, double* ritz, const Ws& w, cheb_status* st_out) {
+    *st_out = CHEB_OK;
+    auto hip_fail = [&](hipError_t e) { *st_out = fail(p, CHEB_ERR_HIP, std::string("refinement: ") + hipGetErrorString(e)); return false; };
+    auto prod = [&](const c128* A, const c128* B, c128* out, GemmMode mode) {
+      Epi<double> e;
+      e.out = out; e.ldo = n;
+      return gemm<double, double, double, double>(mode, n, n, n, A, n, B, n, e, gemm_pick_splits(n, n, n), w.part, st,
+                                                  ROLE_SUBSPACE);
+    };
+    hipError_t e;
+    c128 *X = w.Xa, *Xn = w.Xb;
+    if ((e = identity_matrix(n, X, st))) return hip_fail(e);
+    const c128* M1 = w.Ss;
+    const c128* M2 = w.Hs;
+    bool conv = false;
+    double prev = 1e300;
+    for (int it = 0; it < 8; ++it) {
+      if ((e = refine_update(n, M1, M2, w.F, w.lam, w.absF, w.res + 2, st))) return hip_fail(e);
+      double maxF = 0.0;
+      if ((e = hipMemcpyAsync(&maxF, w.res + 2, sizeof(double), hipMemcpyDeviceToHost, st))) return hip_fail(e);
+      if ((e = hipStreamSynchronize(st))) return hip_fail(e);
+      if (!(maxF < 0.25) || (it >= 2 && maxF > 0.1 * prev)) return false;  // not in the quadratic regime
+      prev = maxF;
+      Epi<double> eu;
+      eu.out = Xn; eu.ldo = n; eu.L = X; eu.ldl = n; eu.bL = 1.0;
+      if ((e = gemm<double, double, double, double>(GEMM_NN, n, n, n, X, n, w.F, n, eu, gemm_pick_splits(n, n, n), w.part,
+                                                    st, ROLE_SUBSPACE))) return hip_fail(e);
+      std::swap(X, Xn);
+      if ((e = prod(w.Ss, X, w.T, GEMM_NN)) || (e = prod(X, w.T, w.M1, GEMM_CN))) return hip_fail(e);
+      if ((e = prod(w.Hs, X, w.T, GEMM_NN)) || (e = prod(X, w.T, w.M2, GEMM_CN))) return hip_fail(e);
+      M1 = w.M1;
+      M2 = w.M2;
+      if (maxF < 1e-10) { conv = true; break; }
+    }
+    if (!conv) return false;
+    double res[2] = {1.0, 1.0};
+    if ((e = refine_check(n, w.M1, w.M2, w.res, st))) return hip_fail(e);
+    if ((e = hipMemcpyAsync(res, w.res, 2 * sizeof(double), hipMemcpyDeviceToHost, st))) return hip_fail(e);
+    if ((e = hipStreamSynchronize(st))) return hip_fail(e);
+    if (!(res[0] <= 1e-12) || !(res[1] <= 1e-12)) return false;
+    // eigenvalues of the verified X, ascending; Z = d .* X[:, perm] replaces H_X in w.Hs
+    if ((e = refine_update(n, w.M1, w.M2, w.F, w.lam, w.absF, w.res + 2, st))) return hip_fail(e);
+    if ((e = sort_eigen(n, w.lam, ritz, w.perm, X, w.d, w.T, st))) return hip_fail(e);
+    if ((e = hipMemcpyAsync(w.Hs, w.T, sizeof(c128) * size_t(n) * n, hipMemcpyDeviceToDevice, st))) return hip_fail(e);
+    return true;
+  }
+
   cheb_status rayleigh_ritz(C* X, long ldx, int nb, double* ritz, double* resid, const Ws& w) {
     const int np = p->nproj;
     const long npw = p->npw;
@@ -607,38 +676,52 @@ template <typename T> struct Ops {
     HIPCHK(hipStreamSynchronize(st));
     if (flags[1]) return fail(p, CHEB_ERR_NONFINITE, "non-finite entry in the subspace matrices");
     if (flags[0]) return fail(p, CHEB_ERR_NOT_PD, "X^H S X has a non-positive diagonal (zero or non-finite column)");
-    RBCHK(rocblas_set_stream(p->rb, st));
-    RBCHK(rocblas_set_workspace(p->rb, w.solver, w.solver_bytes));
-    // H_X Z = S_X Z Lambda by reduction to standard form: S' = L L^H, H^ = L^-1 H' L^-H, H^ U = U Lambda,
-    // Z' = L^-H U (FP64 throughout)
-    rocblas_status rs = rocblas_status_success;
+    // H_X Z = S_X Z Lambda: warm-started refinement, else reduction to standard form (S' = L L^H,
+    // H^ = L^-1 H' L^-H, H^ U = U Lambda, Z' = L^-H U) with the library eigensolver, FP64 throughout
+    bool refined = false;
     {
       Timed t(p, st, CHEB_T_RR_EIG, 0.0, 0.0);
-      rocblas_double_complex* Hd = reinterpret_cast<rocblas_double_complex*>(w.Hs);
-      rocblas_double_complex* Ld = reinterpret_cast<rocblas_double_complex*>(w.Ss);
-      const rocblas_double_complex one = {1.0, 0.0};
-      rs = rocsolver_zpotrf(p->rb, rocblas_fill_lower, nb, Ld, nb, w.flags + 2);
-      if (rs == rocblas_status_success)
-        rs = rocblas_ztrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                           rocblas_diagonal_non_unit, nb, nb, &one, Ld, nb, Hd, nb);
-      if (rs == rocblas_status_success)
-        rs = rocblas_ztrsm(p->rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
-                           rocblas_diagonal_non_unit, nb, nb, &one, Ld, nb, Hd, nb);
-      if (rs == rocblas_status_success)
-        rs = rocsolver_zheevd(p->rb, rocblas_evect_original, rocblas_fill_lower, nb, Hd, nb, ritz, w.E, w.flags + 3);
-      if (rs == rocblas_status_success)
-        rs = rocblas_ztrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
-                           rocblas_diagonal_non_unit, nb, nb, &one, Ld, nb, Hd, nb);
+      if (p->rr_refine && nb <= 2048) {
+        cheb_status rs_ = CHEB_OK;
+        refined = rr_refine(nb, ritz, w, &rs_);
+        if (rs_ != CHEB_OK) return rs_;
+      }
     }
-    rocblas_set_workspace(p->rb, nullptr, 0);
-    if (rs != rocblas_status_success)
-      return fail(p, CHEB_ERR_HIP, std::string("dense eigensolver: ") + rocblas_status_to_string(rs));
-    HIPCHK(hipMemcpyAsync(flags, w.flags + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (flags[0] != 0) return fail(p, CHEB_ERR_NOT_PD, "X^H S X is not positive definite (rank-deficient block)");
-    if (flags[1] != 0) return fail(p, CHEB_ERR_EIG, "Hermitian eigensolver did not converge");
-    // Z = diag(d) Z' undoes the symmetric column scaling
-    HIPCHK(scale_rows(nb, nb, w.Hs, nb, w.d, st));
+    if (refined) {
+      p->rr_refined += 1;
+    } else {
+      p->rr_fallback += 1;
+      RBCHK(rocblas_set_stream(p->rb, st));
+      RBCHK(rocblas_set_workspace(p->rb, w.solver, w.solver_bytes));
+      rocblas_status rs = rocblas_status_success;
+      {
+        Timed t(p, st, CHEB_T_RR_EIG, 0.0, 0.0);
+        rocblas_double_complex* Hd = reinterpret_cast<rocblas_double_complex*>(w.Hs);
+        rocblas_double_complex* Ld = reinterpret_cast<rocblas_double_complex*>(w.Ss);
+        const rocblas_double_complex one = {1.0, 0.0};
+        rs = rocsolver_zpotrf(p->rb, rocblas_fill_lower, nb, Ld, nb, w.flags + 2);
+        if (rs == rocblas_status_success)
+          rs = rocblas_ztrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                             rocblas_diagonal_non_unit, nb, nb, &one, Ld, nb, Hd, nb);
+        if (rs == rocblas_status_success)
+          rs = rocblas_ztrsm(p->rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
+                             rocblas_diagonal_non_unit, nb, nb, &one, Ld, nb, Hd, nb);
+        if (rs == rocblas_status_success)
+          rs = rocsolver_zheevd(p->rb, rocblas_evect_original, rocblas_fill_lower, nb, Hd, nb, ritz, w.E, w.flags + 3);
+        if (rs == rocblas_status_success)
+          rs = rocblas_ztrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
+                             rocblas_diagonal_non_unit, nb, nb, &one, Ld, nb, Hd, nb);
+      }
+      rocblas_set_workspace(p->rb, nullptr, 0);
+      if (rs != rocblas_status_success)
+        return fail(p, CHEB_ERR_HIP, std::string("dense eigensolver: ") + rocblas_status_to_string(rs));
+      HIPCHK(hipMemcpyAsync(flags, w.flags + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (flags[0] != 0) return fail(p, CHEB_ERR_NOT_PD, "X^H S X is not positive definite (rank-deficient block)");
+      if (flags[1] != 0) return fail(p, CHEB_ERR_EIG, "Hermitian eigensolver did not converge");
+      // Z = diag(d) Z' undoes the symmetric column scaling
+      HIPCHK(scale_rows(nb, nb, w.Hs, nb, w.d, st));
+    }
     C* Ynew = static_cast<C*>(w.Ynew);
     Timed tr(p, st, CHEB_T_RR_ROTATE, (resid ? 4.0 : 2.0) * npw * nb * sizeof(C) + nb * nb * 16.0,
              (resid ? 16.0 : 8.0) * npw * nb * nb);
@@ -1282,6 +1365,19 @@ cheb_status cheb_upper_bound(cheb_plan p, int k, const void* v0, double* lambda_
     using C = typename decltype(ops)::C;
     return ops.upper_bound(k, static_cast<const C*>(v0), lambda_plus, w);
   });
+}
+
+cheb_status cheb_set_rr_refine(cheb_plan p, int on) {
+  if (!p) return CHEB_ERR_ARG;
+  p->rr_refine = on != 0;
+  return CHEB_OK;
+}
+
+cheb_status cheb_rr_stats(cheb_plan p, int64_t* refined, int64_t* fallback) {
+  if (!p) return CHEB_ERR_ARG;
+  if (refined) *refined = p->rr_refined;
+  if (fallback) *fallback = p->rr_fallback;
+  return CHEB_OK;
 }
 
 static cheb_status backward_check(cheb_plan p, int nb, int m, int k) {

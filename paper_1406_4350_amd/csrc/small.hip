@@ -376,3 +376,149 @@ template hipError_t sub_lambda_cols<double>(long, int, c128*, long, const c128*,
 template hipError_t sub_lambda_cols<float>(long, int, c64*, long, const c64*, long, const double*, hipStream_t);
 template hipError_t fill_zero_real<double>(double*, long, hipStream_t);
 }  // namespace chebfd
+
+// ---- warm-started refinement of the dense generalized eigenproblem (Rayleigh-Ritz) -----------------------
+namespace chebfd {
+namespace {
+// M1 = X^H S X, M2 = X^H H X (n x n). lam_i = Re M2_ii / Re M1_ii; F_ij = (M2_ij - lam_j M1_ij) / (lam_j - lam_i)
+// for i != j, F_ii = (1 - M1_ii) / 2. absF[t] = |F_t| (off-diagonal) for the convergence test; pairs closer
+// than the resolution threshold get F_ij = -M1_ij / 2 and a nonzero absF if their coupling is not negligible.
+__global__ void k_refine_update(int n, const c128* M1, const c128* M2, c128* F, double* lam, double* absF) {
+  const long total = long(n) * n;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const int j = int(t / n), i = int(t - long(j) * n);
+    const double li = M2[i + long(i) * n].x / M1[i + long(i) * n].x;
+    const double lj = M2[j + long(j) * n].x / M1[j + long(j) * n].x;
+    if (i == j) {
+      lam[i] = li;
+      F[t] = c128{0.5 * (1.0 - M1[t].x), 0.0};
+      absF[t] = 0.0;
+      continue;
+    }
+    const c128 m1 = M1[t], m2 = M2[t];
+    const double nr = m2.x - lj * m1.x, ni = m2.y - lj * m1.y;
+    const double gap = lj - li;
+    const double scale = fmax(1.0, fmax(fabs(li), fabs(lj)));
+    if (fabs(gap) > 1e-9 * scale) {
+      F[t] = c128{nr / gap, ni / gap};
+      absF[t] = sqrt(nr * nr + ni * ni) / fabs(gap);
+    } else {
+      F[t] = c128{-0.5 * m1.x, -0.5 * m1.y};
+      const double cpl = sqrt(nr * nr + ni * ni);
+      absF[t] = cpl > 1e-13 * scale ? 1e300 : 0.0;  // unresolvable near-degenerate coupling
+    }
+  }
+}
+
+// res[0] = max |M1 - I|, res[1] = max_{i != j} |M2_ij| / max(1, max_i |M2_ii|)  (one block, fixed order)
+__global__ __launch_bounds__(1024) void k_refine_check(int n, const c128* M1, const c128* M2, double* res) {
+  __shared__ double s1[1024], s2[1024], s3[1024];
+  double a = 0.0, b = 0.0, d = 0.0;
+  const long total = long(n) * n;
+  for (long t = threadIdx.x; t < total; t += blockDim.x) {
+    const int j = int(t / n), i = int(t - long(j) * n);
+    const c128 m1 = M1[t], m2 = M2[t];
+    const double e1 = i == j ? hypot(m1.x - 1.0, m1.y) : hypot(m1.x, m1.y);
+    a = fmax(a, e1);
+    if (i == j) d = fmax(d, fabs(m2.x)); else b = fmax(b, hypot(m2.x, m2.y));
+  }
+  s1[threadIdx.x] = a; s2[threadIdx.x] = b; s3[threadIdx.x] = d;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) {
+      s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + k]);
+      s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + k]);
+      s3[threadIdx.x] = fmax(s3[threadIdx.x], s3[threadIdx.x + k]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { res[0] = s1[0]; res[1] = s2[0] / fmax(1.0, s3[0]); }
+}
+
+// out[0] = max of x[0..count) (one block, fixed order)
+__global__ __launch_bounds__(1024) void k_max_reduce(long count, const double* x, double* out) {
+  __shared__ double s[1024];
+  double a = 0.0;
+  for (long t = threadIdx.x; t < count; t += blockDim.x) a = fmax(a, x[t]);
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + k]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
+__global__ void k_identity(int n, c128* X) {
+  const long total = long(n) * n;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long j = t / n, i = t - j * n;
+    X[t] = c128{i == j ? 1.0 : 0.0, 0.0};
+  }
+}
+
+// Ascending sort of lam (n <= 2048) with its permutation, one block, bitonic network on 2048 slots;
+// ties keep index order. Then ritz[k] = lam[perm[k]].
+__global__ __launch_bounds__(1024) void k_sort_lam(int n, const double* lam, double* ritz, int* perm) {
+  __shared__ double key[2048];
+  __shared__ int idx[2048];
+  for (int t = threadIdx.x; t < 2048; t += blockDim.x) {
+    key[t] = t < n ? lam[t] : 1e308;
+    idx[t] = t;
+  }
+  __syncthreads();
+  for (int k = 2; k <= 2048; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < 2048; t += blockDim.x) {
+        const int u = t ^ j;
+        if (u > t) {
+          const bool up = (t & k) == 0;
+          const bool gt = key[t] > key[u] || (key[t] == key[u] && idx[t] > idx[u]);
+          if (gt == up) {
+            const double kk = key[t]; key[t] = key[u]; key[u] = kk;
+            const int ii = idx[t]; idx[t] = idx[u]; idx[u] = ii;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    ritz[t] = key[t];
+    perm[t] = idx[t];
+  }
+}
+
+// Z[:, k] = d .* X[:, perm[k]]  (undoes the symmetric column scaling and applies the sort)
+__global__ void k_permute_scale(int n, const c128* X, const int* perm, const double* d, c128* Z) {
+  const long total = long(n) * n;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long k = t / n, i = t - k * n;
+    const c128 v = X[i + long(perm[k]) * n];
+    Z[t] = c128{v.x * d[i], v.y * d[i]};
+  }
+}
+}  // namespace
+
+hipError_t refine_update(int n, const c128* M1, const c128* M2, c128* F, double* lam, double* absF, double* maxF,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_update, dim3(nblocks(long(n) * n)), dim3(256), 0, st, n, M1, M2, F, lam, absF);
+  hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(1024), 0, st, long(n) * n, absF, maxF);
+  return hipGetLastError();
+}
+hipError_t refine_check(int n, const c128* M1, const c128* M2, double* res, hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(1024), 0, st, n, M1, M2, res);
+  return hipGetLastError();
+}
+hipError_t identity_matrix(int n, c128* X, hipStream_t st) {
+  hipLaunchKernelGGL(k_identity, dim3(nblocks(long(n) * n)), dim3(256), 0, st, n, X);
+  return hipGetLastError();
+}
+hipError_t sort_eigen(int n, const double* lam, double* ritz, int* perm, const c128* X, const double* d, c128* Z,
+                      hipStream_t st) {
+  if (n > 2048) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sort_lam, dim3(1), dim3(1024), 0, st, n, lam, ritz, perm);
+  hipLaunchKernelGGL(k_permute_scale, dim3(nblocks(long(n) * n)), dim3(256), 0, st, n, X, perm, d, Z);
+  return hipGetLastError();
+}
+}  // namespace chebfd

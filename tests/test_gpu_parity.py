@@ -97,3 +97,26 @@ def test_mixed_operators(case):
     Xd = cf.to_device_block(X, torch.complex64)
     assert _rel(cf.to_host_block(plan.apply_H(Xd)), ops.apply_H(X)) < 2e-5
     assert _rel(cf.to_host_block(plan.apply_Sinv(Xd)), ops.apply_Sinv(X)) < 2e-5
+
+
+def test_rr_refinement_and_library_paths_agree(case):
+    """The warm-started refinement and the library eigensolver give the same trajectory (and the oracle's)."""
+    pb, ops, plan = case
+    iters = 6
+    lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
+    hist_o = matfree.chebfsi(ops, pb.X0, pb.cfg.m, iters, lp)[3]
+    out = {}
+    for on in (True, False):
+        plan.set_rr_refine(on)
+        r0, f0 = plan.rr_stats()
+        Xd = cf.to_device_block(pb.X0, torch.complex128)
+        out[on] = chebfsi(plan, Xd, pb.cfg.m, iters, lp)[2]
+        r1, f1 = plan.rr_stats()
+        print(f"refine={on}: refined {r1 - r0}, library {f1 - f0}")
+        if not on:
+            assert r1 == r0
+    plan.set_rr_refine(True)
+    for ho, h1, h0 in zip(hist_o, out[True], out[False]):
+        tol = 1e-10 * np.maximum(np.abs(ho["ritz"]), 1.0)
+        assert np.all(np.abs(h1["ritz"] - ho["ritz"]) <= tol)
+        assert np.all(np.abs(h0["ritz"] - ho["ritz"]) <= tol)
