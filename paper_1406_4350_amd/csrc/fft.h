@@ -108,49 +108,60 @@ template <> struct LineSplit<64> { static constexpr int N1 = 8, N2 = 8; };
 template <> struct LineSplit<96> { static constexpr int N1 = 8, N2 = 12; };
 template <> struct LineSplit<128> { static constexpr int N1 = 8, N2 = 16; };
 
-// In-place length-N DFTs of `nlines` lines held in LDS: element e of line l at buf[l * ls + e * es].
-// tw[j] = exp(-2 pi i j / N) (forward table; conjugated for the inverse). Two stages of register
-// codelets (N1 then N2) with the inter-stage twiddle; all threads of the block must call it.
+// In-place length-N DFTs of `nlines` lines held in LDS: point e of line l at buf[l * ls + e], natural order in
+// and out. The stride ls must be at least N1 * (N2 + 1): between the two register-codelet stages (N1, then
+// N2, with the twiddle W_N^{n2 k1}) the line is held as N1 groups of N2 with one pad slot per group, so
+// that lanes reading a group each are spread over the LDS banks. twA[k1 N2 + n2] = exp(-2 pi i n2 k1 / N)
+// (read by lanes of consecutive n2), conjugated for the inverse. All threads of the block must call it.
 template <int N, int DIR, typename T>
-__device__ void lds_fft(cx<T>* buf, int nlines, int es, int ls, const cx<T>* tw) {
-  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2;
+__device__ void lds_fft(cx<T>* buf, int nlines, int ls, const cx<T>* twA) {
+  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, PS = N2 + 1;
   const int tid = threadIdx.x, nth = blockDim.x;
-  // stage 1: for each (line, n2): DFT over n1 of x[N2 n1 + n2], times W_N^{n2 k1}, back in place
-  for (int task = tid; task < nlines * N2; task += nth) {
-    const int l = task / N2, n2 = task - l * N2;
-    cx<T>* p = buf + l * ls + n2 * es;
+  // stage 1 per (line, n2): DFT over n1 of x[N2 n1 + n2], times W_N^{n2 k1}, to group slot PS k1 + n2
+  const int lines1 = nth / N2 > 0 ? nth / N2 : 1;
+  for (int l0 = 0; l0 < nlines; l0 += lines1) {
+    const int l1 = min(nlines, l0 + lines1);
+    const bool act = tid < (l1 - l0) * N2;
+    const int l = l0 + tid / N2, n2 = tid % N2;
     cx<T> v[N1];
+    if (act) {
+      const cx<T>* p = buf + l * ls + n2;
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) v[n1] = p[n1 * N2 * es];
-    Dft<N1, DIR>::run(v);
+      for (int n1 = 0; n1 < N1; ++n1) v[n1] = p[n1 * N2];
+      Dft<N1, DIR>::run(v);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-      cx<T> w = tw[(n2 * k1) % N];
-      if (DIR > 0) w.y = -w.y;
-      p[k1 * N2 * es] = k1 == 0 ? v[0] : cmul(v[k1], w);
+      for (int k1 = 1; k1 < N1; ++k1) {
+        cx<T> w = twA[k1 * N2 + n2];
+        if (DIR > 0) w.y = -w.y;
+        v[k1] = cmul(v[k1], w);
+      }
     }
+    __syncthreads();
+    if (act) {
+      cx<T>* p = buf + l * ls + n2;
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) p[PS * k1] = v[k1];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // stage 2: for each (line, k1): DFT over n2 of y[N2 k1 + n2] -> X[k1 + N1 k2] (natural order).
-  // Reads and writes of a line overlap, so lines are processed in rounds: read all, sync, write all.
-  const int lines_per_round = nth / N1 > 0 ? nth / N1 : 1;
-  for (int l0 = 0; l0 < nlines; l0 += lines_per_round) {
-    const int l1 = min(nlines, l0 + lines_per_round);
-    const int task = tid;
-    const bool act = task < (l1 - l0) * N1;
-    const int l = l0 + task / N1, k1 = task % N1;
+  // stage 2 per (line, k1): DFT over n2 of the group k1 -> X[k1 + N1 k2] (natural order)
+  const int lines2 = nth / N1 > 0 ? nth / N1 : 1;
+  for (int l0 = 0; l0 < nlines; l0 += lines2) {
+    const int l1 = min(nlines, l0 + lines2);
+    const bool act = tid < (l1 - l0) * N1;
+    const int l = l0 + tid / N1, k1 = tid % N1;
     cx<T> v[N2];
     if (act) {
-      const cx<T>* p = buf + l * ls + k1 * N2 * es;
+      const cx<T>* p = buf + l * ls + PS * k1;
 #pragma unroll
-      for (int n2 = 0; n2 < N2; ++n2) v[n2] = p[n2 * es];
+      for (int n2 = 0; n2 < N2; ++n2) v[n2] = p[n2];
       Dft<N2, DIR>::run(v);
     }
     __syncthreads();
     if (act) {
-      cx<T>* p = buf + l * ls + k1 * es;
+      cx<T>* p = buf + l * ls + k1;
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) p[k2 * N1 * es] = v[k2];
+      for (int k2 = 0; k2 < N2; ++k2) p[k2 * N1] = v[k2];
     }
     __syncthreads();
   }

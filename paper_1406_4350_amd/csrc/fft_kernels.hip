@@ -16,19 +16,25 @@ namespace {
 
 constexpr int NT = 256;
 
+// In LDS a line is kept as N1 groups of N2 points with one pad slot per group (group a starts at PS a,
+// PS = N2 + 1) and an odd line stride, so that lanes walking groups and lanes walking lines both spread
+// over the LDS banks.
+template <int N> constexpr int group_stride() { return LineSplit<N>::N2 + 1; }
+template <int N> constexpr int line_stride() { return (LineSplit<N>::N1 * group_stride<N>()) | 1; }
+
 template <typename T> constexpr int cpb() { return sizeof(T) == 8 ? 16 : 32; }  // columns per block
 
 template <int N, typename T>
 __global__ __launch_bounds__(NT) void k_col_inv(int ncol, const int4* __restrict__ col, const int* __restrict__ ent,
                                                 const cx<T>* __restrict__ twg, const cx<T>* __restrict__ X, long ldx,
                                                 cx<T>* __restrict__ colbuf) {
-  constexpr int CPB = cpb<T>(), LS = N + 1;
+  constexpr int CPB = cpb<T>(), LS = line_stride<N>();
   __shared__ cx<T> lines[CPB * LS];
-  __shared__ cx<T> tw[N];
+  __shared__ cx<T> twA[N];
   const int band = blockIdx.y;
   const int c0 = blockIdx.x * CPB, c1 = min(ncol, c0 + CPB), nc = c1 - c0;
   const int tid = threadIdx.x;
-  for (int t = tid; t < N; t += NT) tw[t] = twg[t];
+  for (int t = tid; t < N; t += NT) twA[t] = twg[((t % LineSplit<N>::N2) * (t / LineSplit<N>::N2)) % N];
   for (int t = tid; t < CPB * LS; t += NT) lines[t] = cx<T>{T(0), T(0)};
   __syncthreads();
   const int e0 = col[c0].z, e1 = col[c1 - 1].z + col[c1 - 1].w;
@@ -38,7 +44,7 @@ __global__ __launch_bounds__(NT) void k_col_inv(int ncol, const int4* __restrict
     lines[((code >> 8) - c0) * LS + (code & 255)] = xb[e];
   }
   __syncthreads();
-  lds_fft<N, +1, T>(lines, nc, 1, LS, tw);
+  lds_fft<N, +1, T>(lines, nc, LS, twA);
   cx<T>* out = colbuf + long(band) * N * ncol;
   for (int t = tid; t < N * nc; t += NT) {
     const int z = t / nc, c = t - z * nc;
@@ -54,9 +60,23 @@ template <int N, typename T> constexpr int plane_rows() {
   return r < N ? r : N;
 }
 
+
 template <int N, typename T> constexpr size_t plane_lds(int nx) {
-  return (size_t(nx + plane_rows<N, T>()) * (N + 1) + N) * sizeof(cx<T>);
+  return (size_t(nx + plane_rows<N, T>()) * line_stride<N>() + 3 * N) * sizeof(cx<T>);
 }
+
+// Inter-stage twiddles laid out for the lanes that use them: twA[k1 N2 + n2] = W_N^(n2 k1) is read by lanes of
+// consecutive n2, twB[kb N1 + a] = W_N^(a kb) by lanes of consecutive a (forward sign; conjugate for inverse).
+template <int N, typename T> __device__ __forceinline__ void stage_twiddles(const cx<T>* tw, cx<T>* twA, cx<T>* twB) {
+  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2;
+  for (int t = threadIdx.x; t < N; t += NT) {
+    const int k1 = t / N2, n2 = t - k1 * N2;
+    twA[t] = tw[(n2 * k1) % N];
+    const int kb = t / N1, a = t - kb * N1;
+    twB[t] = tw[(a * kb) % N];
+  }
+}
+template <typename T> __device__ __forceinline__ cx<T> conj_if(cx<T> w, bool c) { return c ? cx<T>{w.x, -w.y} : w; }
 
 // W_N^(DIR * j) from the forward table tw[j] = exp(-2 pi i j / N)
 template <int DIR, typename T> __device__ __forceinline__ cx<T> twiddle(const cx<T>* tw, int j) {
@@ -80,18 +100,24 @@ template <int N, typename T>
 __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __restrict__ xline,
                                               const cx<T>* __restrict__ twg, const T* __restrict__ Vt,
                                               const cx<T>* __restrict__ cin, cx<T>* __restrict__ cout) {
-  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = N + 1, RB = plane_rows<N, T>();
+  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = line_stride<N>(), PS = group_stride<N>();
+  constexpr int RB = plane_rows<N, T>();
+  static_assert(RB * N1 <= NT, "one second-stage task per thread and row batch");
   extern __shared__ unsigned char smem_raw[];
   const int nx = 2 * rx + 1;
   cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw);  // [nx][LS] y-lines of the x-lines |gx| <= rx
   cx<T>* Sc = L + nx * LS;                         // [RB][LS] rows of the x-pass
   cx<T>* tw = Sc + RB * LS;
+  cx<T>* twA = tw + N;
+  cx<T>* twB = twA + N;
   const int z = blockIdx.x, band = blockIdx.y, tid = threadIdx.x;
   const long base = long(band) * N * ncol + long(z) * ncol;
   const cx<T>* in = cin + base;
   cx<T>* out = cout + base;
   const cx<T> zero = {T(0), T(0)};
   for (int t = tid; t < N; t += NT) tw[t] = twg[t];
+  __syncthreads();
+  stage_twiddles<N, T>(tw, twA, twB);
   __syncthreads();
 
   // ---- A: inverse y ----
@@ -106,12 +132,12 @@ __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __re
     }
     Dft<N1, +1>::run(v);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) L[xi * LS + N2 * k1 + n2] = k1 ? cmul(v[k1], twiddle<+1>(tw, (n2 * k1) % N)) : v[0];
+    for (int k1 = 0; k1 < N1; ++k1) L[xi * LS + PS * k1 + n2] = k1 ? cmul(v[k1], conj_if(twA[k1 * N2 + n2], true)) : v[0];
   }
   __syncthreads();
   for (int task = tid; task < nx * N1; task += NT) {
     const int xi = task / N1, a = task - xi * N1;
-    cx<T>* p = L + xi * LS + N2 * a;
+    cx<T>* p = L + xi * LS + PS * a;
     cx<T> v[N2];
 #pragma unroll
     for (int n2 = 0; n2 < N2; ++n2) v[n2] = p[n2];
@@ -125,9 +151,18 @@ __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __re
   const T* Vz = Vt + long(z) * N * N;
   for (int y0 = 0; y0 < N; y0 += RB) {
     const int nrow = min(RB, N - y0);
+    // V(r) of this thread's second-stage points, loaded before the first stage so the load latency is hidden
+    T vr[N2];
+    const bool has2 = tid < nrow * N1;  // at most one second-stage task per thread (RB * N1 <= NT)
+    {
+      const int yy = tid / N1, a = tid - (tid / N1) * N1;
+      const T* Vrow = Vz + long(y0 + (has2 ? yy : 0)) * N + a;
+#pragma unroll
+      for (int b = 0; b < N2; ++b) vr[b] = has2 ? Vrow[N1 * b] : T(0);
+    }
     for (int task = tid; task < nrow * N2; task += NT) {
       const int yy = task / N2, n2 = task - yy * N2;
-      const int y = y0 + yy, py = N2 * (y % N1) + y / N1;
+      const int y = y0 + yy, py = PS * (y % N1) + y / N1;
       cx<T> v[N1];
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) {
@@ -137,33 +172,29 @@ __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __re
       Dft<N1, +1>::run(v);
 #pragma unroll
       for (int k1 = 0; k1 < N1; ++k1)
-        Sc[yy * LS + N2 * k1 + n2] = k1 ? cmul(v[k1], twiddle<+1>(tw, (n2 * k1) % N)) : v[0];
+        Sc[yy * LS + PS * k1 + n2] = k1 ? cmul(v[k1], conj_if(twA[k1 * N2 + n2], true)) : v[0];
     }
     __syncthreads();
-    for (int task = tid; task < nrow * N1; task += NT) {
-      const int yy = task / N1, a = task - yy * N1;
-      cx<T>* p = Sc + yy * LS + N2 * a;
-      const T* Vrow = Vz + long(y0 + yy) * N + a;
+    if (has2) {
+      const int yy = tid / N1, a = tid - yy * N1;
+      cx<T>* p = Sc + yy * LS + PS * a;
       cx<T> v[N2];
 #pragma unroll
       for (int n2 = 0; n2 < N2; ++n2) v[n2] = p[n2];
       Dft<N2, +1>::run(v);  // v[b] = psi(x = a + N1 b)
 #pragma unroll
-      for (int b = 0; b < N2; ++b) {
-        const T vr = Vrow[N1 * b];
-        v[b] = cx<T>{v[b].x * vr, v[b].y * vr};
-      }
+      for (int b = 0; b < N2; ++b) v[b] = cx<T>{v[b].x * vr[b], v[b].y * vr[b]};
       Dft<N2, -1>::run(v);
 #pragma unroll
-      for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twiddle<-1>(tw, (a * kb) % N)) : v[0];
+      for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twB[kb * N1 + a]) : v[0];
     }
     __syncthreads();
     for (int task = tid; task < nrow * N2; task += NT) {
       const int yy = task / N2, kb = task - yy * N2;
-      const int y = y0 + yy, py = N2 * (y % N1) + y / N1;
+      const int y = y0 + yy, py = PS * (y % N1) + y / N1;
       cx<T> v[N1];
 #pragma unroll
-      for (int a = 0; a < N1; ++a) v[a] = Sc[yy * LS + N2 * a + kb];
+      for (int a = 0; a < N1; ++a) v[a] = Sc[yy * LS + PS * a + kb];
       Dft<N1, -1>::run(v);
 #pragma unroll
       for (int ka = 0; ka < N1; ++ka) {
@@ -177,13 +208,13 @@ __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __re
   // ---- C: forward y ----
   for (int task = tid; task < nx * N1; task += NT) {
     const int xi = task / N1, a = task - xi * N1;
-    cx<T>* p = L + xi * LS + N2 * a;
+    cx<T>* p = L + xi * LS + PS * a;
     cx<T> v[N2];
 #pragma unroll
     for (int b = 0; b < N2; ++b) v[b] = p[b];
     Dft<N2, -1>::run(v);
 #pragma unroll
-    for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twiddle<-1>(tw, (a * kb) % N)) : v[0];
+    for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twB[kb * N1 + a]) : v[0];
   }
   __syncthreads();
   for (int task = tid; task < nx * N2; task += NT) {
@@ -191,7 +222,7 @@ __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __re
     const int4 xl = xline[xi];
     cx<T> v[N1];
 #pragma unroll
-    for (int a = 0; a < N1; ++a) v[a] = L[xi * LS + N2 * a + kb];
+    for (int a = 0; a < N1; ++a) v[a] = L[xi * LS + PS * a + kb];
     Dft<N1, -1>::run(v);
 #pragma unroll
     for (int ka = 0; ka < N1; ++ka) {
@@ -208,14 +239,14 @@ __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __re
 template <int N, typename T> constexpr int xdens_rows() { return plane_rows<N, T>(); }
 template <int N, typename T> constexpr int xdens_batches() { return (N + xdens_rows<N, T>() - 1) / xdens_rows<N, T>(); }
 template <int N, typename T> constexpr size_t xdens_lds(int nx) {
-  return (size_t(2 * (nx + xdens_rows<N, T>())) * (N + 1) + N) * sizeof(cx<T>);
+  return (size_t(2 * (nx + xdens_rows<N, T>())) * line_stride<N>() + 3 * N) * sizeof(cx<T>);
 }
 
 // inverse y of one x-line block (both stages), the line ends in digit-reversed order as in k_plane
 template <int N, typename T>
 __device__ __forceinline__ void y_inverse(const cx<T>* __restrict__ in, cx<T>* L, const int4* __restrict__ xline,
-                                          const cx<T>* tw, int nx) {
-  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = N + 1;
+                                          const cx<T>* twA, int nx) {
+  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = line_stride<N>(), PS = group_stride<N>();
   const int tid = threadIdx.x;
   const cx<T> zero = {T(0), T(0)};
   for (int task = tid; task < nx * N2; task += NT) {
@@ -229,12 +260,12 @@ __device__ __forceinline__ void y_inverse(const cx<T>* __restrict__ in, cx<T>* L
     }
     Dft<N1, +1>::run(v);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) L[xi * LS + N2 * k1 + n2] = k1 ? cmul(v[k1], twiddle<+1>(tw, (n2 * k1) % N)) : v[0];
+    for (int k1 = 0; k1 < N1; ++k1) L[xi * LS + PS * k1 + n2] = k1 ? cmul(v[k1], conj_if(twA[k1 * N2 + n2], true)) : v[0];
   }
   __syncthreads();
   for (int task = tid; task < nx * N1; task += NT) {
     const int xi = task / N1, a = task - xi * N1;
-    cx<T>* p = L + xi * LS + N2 * a;
+    cx<T>* p = L + xi * LS + PS * a;
     cx<T> v[N2];
 #pragma unroll
     for (int n2 = 0; n2 < N2; ++n2) v[n2] = p[n2];
@@ -246,12 +277,12 @@ __device__ __forceinline__ void y_inverse(const cx<T>* __restrict__ in, cx<T>* L
 
 // first inverse-x stage of rows y0 .. y0 + nrow - 1 from the x-lines in L into the row scratch S
 template <int N, typename T>
-__device__ __forceinline__ void x_inverse_stage1(const cx<T>* L, cx<T>* S, const cx<T>* tw, int rx, int y0, int nrow) {
-  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = N + 1;
+__device__ __forceinline__ void x_inverse_stage1(const cx<T>* L, cx<T>* S, const cx<T>* twA, int rx, int y0, int nrow) {
+  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = line_stride<N>(), PS = group_stride<N>();
   const cx<T> zero = {T(0), T(0)};
   for (int task = threadIdx.x; task < nrow * N2; task += NT) {
     const int yy = task / N2, n2 = task - yy * N2;
-    const int y = y0 + yy, py = N2 * (y % N1) + y / N1;
+    const int y = y0 + yy, py = PS * (y % N1) + y / N1;
     cx<T> v[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
@@ -260,7 +291,7 @@ __device__ __forceinline__ void x_inverse_stage1(const cx<T>* L, cx<T>* S, const
     }
     Dft<N1, +1>::run(v);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) S[yy * LS + N2 * k1 + n2] = k1 ? cmul(v[k1], twiddle<+1>(tw, (n2 * k1) % N)) : v[0];
+    for (int k1 = 0; k1 < N1; ++k1) S[yy * LS + PS * k1 + n2] = k1 ? cmul(v[k1], conj_if(twA[k1 * N2 + n2], true)) : v[0];
   }
 }
 
@@ -269,7 +300,7 @@ __global__ __launch_bounds__(NT) void k_xdens(int ncol, int rx, const int4* __re
                                               const cx<T>* __restrict__ twg, const cx<T>* __restrict__ ca,
                                               const cx<T>* __restrict__ cb, int nband, int bpc,
                                               const double* __restrict__ wts, double* __restrict__ part) {
-  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = N + 1;
+  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = line_stride<N>(), PS = group_stride<N>();
   constexpr int RB = xdens_rows<N, T>(), NBT = xdens_batches<N, T>();
   static_assert(RB * N1 <= NT, "one second-stage task per thread and row batch");
   extern __shared__ unsigned char smem_raw[];
@@ -279,9 +310,13 @@ __global__ __launch_bounds__(NT) void k_xdens(int ncol, int rx, const int4* __re
   cx<T>* Sa = Lb + nx * LS;
   cx<T>* Sb = Sa + RB * LS;
   cx<T>* tw = Sb + RB * LS;
+  cx<T>* twA = tw + N;
+  cx<T>* twB = twA + N;
   const int z = blockIdx.x, chunk = blockIdx.y, tid = threadIdx.x;
   const int b0 = chunk * bpc, b1 = min(nband, b0 + bpc);
   for (int t = tid; t < N; t += NT) tw[t] = twg[t];
+  __syncthreads();
+  stage_twiddles<N, T>(tw, twA, twB);
   double acc[NBT][N2];
 #pragma unroll
   for (int t = 0; t < NBT; ++t)
@@ -292,21 +327,21 @@ __global__ __launch_bounds__(NT) void k_xdens(int ncol, int rx, const int4* __re
   for (int band = b0; band < b1; ++band) {
     const double wt = wts ? wts[band] : 1.0;
     const long base = long(band) * N * ncol + long(z) * ncol;
-    y_inverse<N, T>(ca + base, La, xline, tw, nx);
-    y_inverse<N, T>(cb + base, Lb, xline, tw, nx);
+    y_inverse<N, T>(ca + base, La, xline, twA, nx);
+    y_inverse<N, T>(cb + base, Lb, xline, twA, nx);
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < NBT; ++t) {
       const int y0 = t * RB, nrow = min(RB, N - y0);
-      x_inverse_stage1<N, T>(La, Sa, tw, rx, y0, nrow);
-      x_inverse_stage1<N, T>(Lb, Sb, tw, rx, y0, nrow);
+      x_inverse_stage1<N, T>(La, Sa, twA, rx, y0, nrow);
+      x_inverse_stage1<N, T>(Lb, Sb, twA, rx, y0, nrow);
       __syncthreads();
       if (yy < nrow) {
         cx<T> va[N2], vb[N2];
 #pragma unroll
         for (int n2 = 0; n2 < N2; ++n2) {
-          va[n2] = Sa[yy * LS + N2 * a + n2];
-          vb[n2] = Sb[yy * LS + N2 * a + n2];
+          va[n2] = Sa[yy * LS + PS * a + n2];
+          vb[n2] = Sb[yy * LS + PS * a + n2];
         }
         Dft<N2, +1>::run(va);
         Dft<N2, +1>::run(vb);
@@ -344,20 +379,20 @@ __global__ __launch_bounds__(NT) void k_col_fwd(int ncol, const int4* __restrict
                                                 const cx<T>* __restrict__ twg, const cx<T>* __restrict__ colbuf,
                                                 const cx<T>* __restrict__ X, long ldx, const T* __restrict__ kin,
                                                 cx<T>* __restrict__ out, long ldo, T scale) {
-  constexpr int CPB = cpb<T>(), LS = N + 1;
+  constexpr int CPB = cpb<T>(), LS = line_stride<N>();
   __shared__ cx<T> lines[CPB * LS];
-  __shared__ cx<T> tw[N];
+  __shared__ cx<T> twA[N];
   const int band = blockIdx.y;
   const int c0 = blockIdx.x * CPB, c1 = min(ncol, c0 + CPB), nc = c1 - c0;
   const int tid = threadIdx.x;
-  for (int t = tid; t < N; t += NT) tw[t] = twg[t];
+  for (int t = tid; t < N; t += NT) twA[t] = twg[((t % LineSplit<N>::N2) * (t / LineSplit<N>::N2)) % N];
   const cx<T>* in = colbuf + long(band) * N * ncol;
   for (int t = tid; t < N * nc; t += NT) {
     const int z = t / nc, c = t - z * nc;
     lines[c * LS + z] = in[long(z) * ncol + c0 + c];
   }
   __syncthreads();
-  lds_fft<N, -1, T>(lines, nc, 1, LS, tw);
+  lds_fft<N, -1, T>(lines, nc, LS, twA);
   const int e0 = col[c0].z, e1 = col[c1 - 1].z + col[c1 - 1].w;
   const cx<T>* xb = X + long(band) * ldx;
   cx<T>* ob = out + long(band) * ldo;

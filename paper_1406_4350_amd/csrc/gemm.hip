@@ -58,10 +58,12 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, co
 #pragma unroll
       for (int v = 0; v < 4; ++v) { cr[i][j][v] = T(0); ci[i][j][v] = T(0); }
 
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // stage A tile as (k, m) planes
+  // global -> registers for one K tile (converted to the MFMA type), registers -> LDS planes
+  constexpr int RA = (BM * BK) / NT, RBn = (BN * BK) / NT;
+  T ra_r[RA], ra_i[RA], rb_r[RBn], rb_i[RBn];
+  auto load_tile = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < (BM * BK) / NT; ++r) {
+    for (int r = 0; r < RA; ++r) {
       const int idx = tid + r * NT;
       int kk, mm;
       if (MODE == GEMM_CN) { kk = idx % BK; mm = idx / BK; }
@@ -70,21 +72,48 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, co
       const int gk = k0 + kk;
       cx<EA> v = {EA(0), EA(0)};
       if (gm < M && gk < kend) v = (MODE == GEMM_CN) ? A[gk + gm * lda] : A[gm + long(gk) * lda];
-      Ar[kk][mm] = T(v.x);
-      Ai[kk][mm] = T(v.y);
+      ra_r[r] = T(v.x);
+      ra_i[r] = T(v.y);
     }
 #pragma unroll
-    for (int r = 0; r < (BN * BK) / NT; ++r) {
+    for (int r = 0; r < RBn; ++r) {
       const int idx = tid + r * NT;
       const int kk = idx % BK, nn = idx / BK;
       const long gn = n0 + nn;
       const int gk = k0 + kk;
       cx<EB> v = {EB(0), EB(0)};
       if (gn < N && gk < kend) v = B[gk + gn * ldb];
-      Br[kk][nn] = T(v.x);
-      Bi[kk][nn] = T(v.y);
+      rb_r[r] = T(v.x);
+      rb_i[r] = T(v.y);
     }
-    __syncthreads();
+  };
+  auto store_tile = [&]() {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const int idx = tid + r * NT;
+      int kk, mm;
+      if (MODE == GEMM_CN) { kk = idx % BK; mm = idx / BK; }
+      else { mm = idx % BM; kk = idx / BM; }
+      Ar[kk][mm] = ra_r[r];
+      Ai[kk][mm] = ra_i[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RBn; ++r) {
+      const int idx = tid + r * NT;
+      const int kk = idx % BK, nn = idx / BK;
+      Br[kk][nn] = rb_r[r];
+      Bi[kk][nn] = rb_i[r];
+    }
+  };
+
+  if (kbeg < kend) {
+    load_tile(kbeg);
+    store_tile();
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) load_tile(k0 + BK);  // in flight while this tile is multiplied
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       T ar[2], ai[2], br[2], bi[2];
@@ -114,6 +143,10 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, co
       }
     }
     __syncthreads();
+    if (more) {
+      store_tile();
+      __syncthreads();
+    }
   }
 
   // accumulator v of a lane holds column li of each 16 x 16 block, row 4*lk + v for the f32 MFMA and
@@ -157,11 +190,11 @@ __global__ __launch_bounds__(256) void k_reduce(int M, int N, int splits, const 
 int gemm_pick_splits(int M, int N, int K) {
   if (M <= 0 || N <= 0 || K <= 0) return 1;
   const long tiles = long((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  const long want = 1024;  // ~4 blocks per CU
+  const long want = 512;  // ~2 blocks per CU: enough to fill the chip, half the partial-sum traffic
   long s = (want + tiles - 1) / tiles;
   const long kblocks = (K + BK - 1) / BK;
   if (s > kblocks / 2) s = kblocks / 2;  // at least two K tiles per split
-  if (s > 64) s = 64;
+  if (s > 32) s = 32;
   if (s < 1) s = 1;
   return int(s);
 }
