@@ -168,29 +168,36 @@ def cpu_baseline(pb, target_s=15.0):
                       f"FFT with {cores} workers), {dt:.1f} s"}
 
 
-def mixed_accuracy(cf, pb, r64, rmx):
-    """Ritz values of the mixed run against the FP64 run after the same iterations from the same start block,
-    and residuals of the mixed Ritz vectors re-evaluated with the FP64 operators."""
+def mixed_accuracy(cf, pb, r64, rmx, lam_plus, extra=30):
+    """Mixed-precision eigenpairs against converged FP64 ones. The FP64 run is continued for `extra` more
+    iterations to serve as the reference; a mixed band meets the target when its residual, re-evaluated with
+    the FP64 operators, is <= 1e-5 and its Ritz value is within 1e-6 Ha of the reference."""
     import numpy as np
     import torch
 
-    lam64 = r64["state"]["ritz"].cpu().numpy()
-    res64 = r64["state"]["res"].cpu().numpy()
+    plan = r64["plan"]
+    X = r64["X"]
+    lam_minus = float(r64["state"]["ritz"].max().item())
+    for _ in range(extra):
+        c, r = 0.5 * (lam_plus + lam_minus), 0.5 * (lam_plus - lam_minus)
+        plan.filter(X, pb.cfg.m, c, r)
+        ritz, res = plan.rayleigh_ritz(X)
+        lam_minus = float(ritz.max().item())
+    lam_ref, res_ref = ritz.cpu().numpy(), res.cpu().numpy()
     lamx = rmx["state"]["ritz"].cpu().numpy()
     U = rmx["X"].to(torch.complex128)
-    plan = r64["plan"]
     HU = plan.apply_H(U)
     SU = plan.apply_S(U)
     lam_t = torch.from_numpy(lamx).to(U.device)
-    res_fp64 = torch.linalg.vector_norm(HU - SU * lam_t[:, None], dim=1).cpu().numpy()
-    conv = res64 <= 1e-5
-    nconv = int(conv.sum())
-    dlam = np.abs(lamx - lam64)
-    ok = conv & (dlam <= 1e-6) & (res_fp64 <= 1e-5)
-    return {"bands_converged_fp64": nconv, "bands_meeting_target": int(ok.sum()),
-            "max_abs_dlambda_converged_Ha": float(dlam[conv].max()) if nconv else None,
-            "max_resid_fp64_eval_converged": float(res_fp64[conv].max()) if nconv else None,
-            "max_abs_dlambda_all_Ha": float(dlam.max())}
+    res_x = torch.linalg.vector_norm(HU - SU * lam_t[:, None], dim=1).cpu().numpy()
+    ref_ok = res_ref <= 1e-8
+    conv = (res_x <= 1e-5) & ref_ok
+    dlam = np.abs(lamx - lam_ref)
+    ok = conv & (dlam <= 1e-6)
+    return {"reference": f"FP64 path continued {extra} more iterations; {int(ref_ok.sum())} bands with residual <= 1e-8",
+            "bands_converged_mixed": int(conv.sum()), "bands_meeting_target": int(ok.sum()),
+            "max_abs_dlambda_converged_Ha": float(dlam[conv].max()) if conv.any() else None,
+            "max_resid_fp64_eval_converged": float(res_x[conv].max()) if conv.any() else None}
 
 
 def main():
@@ -268,7 +275,7 @@ def main():
             "filter_apps_per_s": rmx["filter_apps_per_s"],
             "filter_ratio_vs_fp64": rmx["filter_apps_per_s"] / r64["filter_apps_per_s"],
             "dtype": "f32 (complex64 bands/FFTs, FP32-MFMA GEMMs); FP64 Rayleigh-Ritz",
-            "accuracy": mixed_accuracy(cf, pb, r64, rmx),
+            "accuracy": mixed_accuracy(cf, pb, r64, rmx, lam_plus),
             "breakdown_ms_per_step": {k: v["ms"] / args.steps for k, v in rmx["prof"].items()},
             "roofline": roofline(rmx["prof"], "f32", cfg.n),
         }

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -258,9 +259,9 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
         const size_t nn = size_t(std::max(nb, 1)) * std::max(nb, 1);
         w->Xa = b.take<c128>(nn);
         w->Xb = b.take<c128>(nn);
-        w->T = b.take<c128>(nn);
-        w->M1 = b.take<c128>(nn);
-        w->M2 = b.take<c128>(nn);
+        w->T = b.take<c128>(2 * nn);   // [S' X; H' X], 2n x n
+        w->M1 = b.take<c128>(2 * nn);  // X^H [S' X | H' X] with interleaved columns
+        w->M2 = b.take<c128>(2 * nn);  // [S'; H'] stacked, 2n x n
         w->F = b.take<c128>(nn);
         w->absF = b.take<double>(nn);
         w->lam = b.take<double>(std::max(nb, 1));
@@ -268,7 +269,8 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
         w->perm = b.take<int>(std::max(nb, 1));
       }
       part = std::max({part_elems(np, nb, p->npw), part_elems(nb, nb, p->npw), part_elems(nb, nb, np),
-                       part_elems(np, nb, nb), part_elems(nb, nb, nb)});
+                       part_elems(np, nb, nb), part_elems(nb, nb, nb), part_elems(2 * nb, nb, nb),
+                       part_elems(nb, 2 * nb, nb)});
       CHK(solver_query(p, CHEB_OP_RR, nb, &w->solver_bytes));
       w->solver = b.take<char>(std::max<size_t>(w->solver_bytes, 1));
       break;
@@ -621,47 +623,61 @@ template <typename T> struct Ops {
   bool rr_refine(int n, double* ritz, const Ws& w, cheb_status* st_out) {
     *st_out = CHEB_OK;
     auto hip_fail = [&](hipError_t e) { *st_out = fail(p, CHEB_ERR_HIP, std::string("refinement: ") + hipGetErrorString(e)); return false; };
-    auto prod = [&](const c128* A, const c128* B, c128* out, GemmMode mode) {
-      Epi<double> e;
-      e.out = out; e.ldo = n;
-      return gemm<double, double, double, double>(mode, n, n, n, A, n, B, n, e, gemm_pick_splits(n, n, n), w.part, st,
-                                                  ROLE_SUBSPACE);
-    };
     hipError_t e;
+    const long n2 = 2L * n;
     c128 *X = w.Xa, *Xn = w.Xb;
+    c128* HS = w.M2;  // [S'; H'] stacked: one product gives S' X and H' X together
+    c128* TT = w.T;   // [S' X; H' X] (2n x n); read with ld n it is n x 2n with columns S'X_j, H'X_j interleaved
+    c128* M = w.M1;   // X^H [S'X_0, H'X_0, S'X_1, ...]: X^H S' X has ld 2n at M, X^H H' X at M + n
+    if ((e = convert_copy<double, double>(n, n, w.Ss, n, HS, n2, st))) return hip_fail(e);
+    if ((e = convert_copy<double, double>(n, n, w.Hs, n, HS + n, n2, st))) return hip_fail(e);
     if ((e = identity_matrix(n, X, st))) return hip_fail(e);
     const c128* M1 = w.Ss;
     const c128* M2 = w.Hs;
+    long ld = n;
     bool conv = false;
     double prev = 1e300;
-    for (int it = 0; it < 8; ++it) {
-      if ((e = refine_update(n, M1, M2, w.F, w.lam, w.absF, w.res + 2, st))) return hip_fail(e);
+    static const bool trace = std::getenv("CHEBFD_TRACE_RR") != nullptr;  // diagnostics: correction sizes
+    auto products = [&](const c128* Xc) {
+      Epi<double> e1;
+      e1.out = TT; e1.ldo = n2;
+      hipError_t r = gemm<double, double, double, double>(GEMM_NN, 2 * n, n, n, HS, n2, Xc, n, e1,
+                                                          gemm_pick_splits(2 * n, n, n), w.part, st, ROLE_SUBSPACE);
+      if (r != hipSuccess) return r;
+      Epi<double> e2;
+      e2.out = M; e2.ldo = n;
+      return gemm<double, double, double, double>(GEMM_CN, n, 2 * n, n, Xc, n, TT, n, e2, gemm_pick_splits(n, 2 * n, n),
+                                                  w.part, st, ROLE_SUBSPACE);
+    };
+    for (int it = 0; it < 16; ++it) {
+      if ((e = refine_update(n, M1, ld, M2, ld, w.F, w.lam, w.absF, w.res + 2, st))) return hip_fail(e);
       double maxF = 0.0;
       if ((e = hipMemcpyAsync(&maxF, w.res + 2, sizeof(double), hipMemcpyDeviceToHost, st))) return hip_fail(e);
       if ((e = hipStreamSynchronize(st))) return hip_fail(e);
-      if (!(maxF < 0.25) || (it >= 2 && maxF > 0.1 * prev)) return false;  // not in the quadratic regime
+      if (trace) std::fprintf(stderr, "[rr-refine] n=%d it=%d max|F|=%.3e\n", n, it, maxF);
+      // leave when clearly outside the region of convergence
+      if (!(maxF < 1.0) || (it >= 4 && maxF > 0.7 * prev)) return false;
       prev = maxF;
       Epi<double> eu;
       eu.out = Xn; eu.ldo = n; eu.L = X; eu.ldl = n; eu.bL = 1.0;
       if ((e = gemm<double, double, double, double>(GEMM_NN, n, n, n, X, n, w.F, n, eu, gemm_pick_splits(n, n, n), w.part,
                                                     st, ROLE_SUBSPACE))) return hip_fail(e);
       std::swap(X, Xn);
-      if ((e = prod(w.Ss, X, w.T, GEMM_NN)) || (e = prod(X, w.T, w.M1, GEMM_CN))) return hip_fail(e);
-      if ((e = prod(w.Hs, X, w.T, GEMM_NN)) || (e = prod(X, w.T, w.M2, GEMM_CN))) return hip_fail(e);
-      M1 = w.M1;
-      M2 = w.M2;
+      if ((e = products(X))) return hip_fail(e);
+      M1 = M;
+      M2 = M + n;
+      ld = n2;
       if (maxF < 1e-10) { conv = true; break; }
     }
     if (!conv) return false;
     double res[2] = {1.0, 1.0};
-    if ((e = refine_check(n, w.M1, w.M2, w.res, st))) return hip_fail(e);
+    if ((e = refine_check(n, M1, ld, M2, ld, w.res, st))) return hip_fail(e);
     if ((e = hipMemcpyAsync(res, w.res, 2 * sizeof(double), hipMemcpyDeviceToHost, st))) return hip_fail(e);
     if ((e = hipStreamSynchronize(st))) return hip_fail(e);
     if (!(res[0] <= 1e-12) || !(res[1] <= 1e-12)) return false;
     // eigenvalues of the verified X, ascending; Z = d .* X[:, perm] replaces H_X in w.Hs
-    if ((e = refine_update(n, w.M1, w.M2, w.F, w.lam, w.absF, w.res + 2, st))) return hip_fail(e);
-    if ((e = sort_eigen(n, w.lam, ritz, w.perm, X, w.d, w.T, st))) return hip_fail(e);
-    if ((e = hipMemcpyAsync(w.Hs, w.T, sizeof(c128) * size_t(n) * n, hipMemcpyDeviceToDevice, st))) return hip_fail(e);
+    if ((e = refine_update(n, M1, ld, M2, ld, w.F, w.lam, w.absF, w.res + 2, st))) return hip_fail(e);
+    if ((e = sort_eigen(n, w.lam, ritz, w.perm, X, w.d, w.Hs, st))) return hip_fail(e);
     return true;
   }
 

@@ -383,19 +383,20 @@ namespace {
 // M1 = X^H S X, M2 = X^H H X (n x n). lam_i = Re M2_ii / Re M1_ii; F_ij = (M2_ij - lam_j M1_ij) / (lam_j - lam_i)
 // for i != j, F_ii = (1 - M1_ii) / 2. absF[t] = |F_t| (off-diagonal) for the convergence test; pairs closer
 // than the resolution threshold get F_ij = -M1_ij / 2 and a nonzero absF if their coupling is not negligible.
-__global__ void k_refine_update(int n, const c128* M1, const c128* M2, c128* F, double* lam, double* absF) {
+__global__ void k_refine_update(int n, const c128* M1, long ld1, const c128* M2, long ld2, c128* F, double* lam,
+                                double* absF) {
   const long total = long(n) * n;
   for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
     const int j = int(t / n), i = int(t - long(j) * n);
-    const double li = M2[i + long(i) * n].x / M1[i + long(i) * n].x;
-    const double lj = M2[j + long(j) * n].x / M1[j + long(j) * n].x;
+    const double li = M2[i + long(i) * ld2].x / M1[i + long(i) * ld1].x;
+    const double lj = M2[j + long(j) * ld2].x / M1[j + long(j) * ld1].x;
+    const c128 m1 = M1[i + long(j) * ld1], m2 = M2[i + long(j) * ld2];
     if (i == j) {
       lam[i] = li;
-      F[t] = c128{0.5 * (1.0 - M1[t].x), 0.0};
+      F[t] = c128{0.5 * (1.0 - m1.x), 0.0};
       absF[t] = 0.0;
       continue;
     }
-    const c128 m1 = M1[t], m2 = M2[t];
     const double nr = m2.x - lj * m1.x, ni = m2.y - lj * m1.y;
     const double gap = lj - li;
     const double scale = fmax(1.0, fmax(fabs(li), fabs(lj)));
@@ -411,13 +412,14 @@ __global__ void k_refine_update(int n, const c128* M1, const c128* M2, c128* F, 
 }
 
 // res[0] = max |M1 - I|, res[1] = max_{i != j} |M2_ij| / max(1, max_i |M2_ii|)  (one block, fixed order)
-__global__ __launch_bounds__(1024) void k_refine_check(int n, const c128* M1, const c128* M2, double* res) {
+__global__ __launch_bounds__(1024) void k_refine_check(int n, const c128* M1, long ld1, const c128* M2, long ld2,
+                                                      double* res) {
   __shared__ double s1[1024], s2[1024], s3[1024];
   double a = 0.0, b = 0.0, d = 0.0;
   const long total = long(n) * n;
   for (long t = threadIdx.x; t < total; t += blockDim.x) {
     const int j = int(t / n), i = int(t - long(j) * n);
-    const c128 m1 = M1[t], m2 = M2[t];
+    const c128 m1 = M1[i + long(j) * ld1], m2 = M2[i + long(j) * ld2];
     const double e1 = i == j ? hypot(m1.x - 1.0, m1.y) : hypot(m1.x, m1.y);
     a = fmax(a, e1);
     if (i == j) d = fmax(d, fabs(m2.x)); else b = fmax(b, hypot(m2.x, m2.y));
@@ -500,14 +502,14 @@ __global__ void k_permute_scale(int n, const c128* X, const int* perm, const dou
 }
 }  // namespace
 
-hipError_t refine_update(int n, const c128* M1, const c128* M2, c128* F, double* lam, double* absF, double* maxF,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_refine_update, dim3(nblocks(long(n) * n)), dim3(256), 0, st, n, M1, M2, F, lam, absF);
+hipError_t refine_update(int n, const c128* M1, long ld1, const c128* M2, long ld2, c128* F, double* lam, double* absF,
+                         double* maxF, hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_update, dim3(nblocks(long(n) * n)), dim3(256), 0, st, n, M1, ld1, M2, ld2, F, lam, absF);
   hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(1024), 0, st, long(n) * n, absF, maxF);
   return hipGetLastError();
 }
-hipError_t refine_check(int n, const c128* M1, const c128* M2, double* res, hipStream_t st) {
-  hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(1024), 0, st, n, M1, M2, res);
+hipError_t refine_check(int n, const c128* M1, long ld1, const c128* M2, long ld2, double* res, hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(1024), 0, st, n, M1, ld1, M2, ld2, res);
   return hipGetLastError();
 }
 hipError_t identity_matrix(int n, c128* X, hipStream_t st) {
