@@ -200,6 +200,44 @@ def mixed_accuracy(cf, pb, r64, rmx, lam_plus, extra=30):
             "max_resid_fp64_eval_converged": float(res_x[conv].max()) if conv.any() else None}
 
 
+def time_backward(cf, pb, lam_plus, reps=3):
+    """Forward (filter + Rayleigh-Ritz) against forward + adjoint (cheb_filter_rr_backward), both precisions."""
+    import torch
+
+    out = {}
+    m, nk = pb.cfg.m, min(pb.cfg.nk, pb.cfg.nb)
+    for prec, name in ((cf.CHEB_FP64, "fp64"), (cf.CHEB_MIXED, "mixed")):
+        plan = cf.plan_from_problem(pb, prec)
+        dtype = torch.complex64 if prec == cf.CHEB_MIXED else torch.complex128
+        X0 = cf.to_device_block(pb.X0, dtype)
+        lm = float(plan.rayleigh_quotients(X0).max().item())
+        c, r = 0.5 * (lam_plus + lm), 0.5 * (lam_plus - lm)
+        w = torch.from_numpy(pb.w[:nk])
+
+        def fwd():
+            Y = X0.clone()
+            plan.filter(Y, m, c, r)
+            plan.rayleigh_ritz(Y, with_residuals=False)
+
+        def bwd():
+            plan.filter_rr_backward(X0, m, c, r, w, 3)
+        times = {}
+        for key, fn in (("forward", fwd), ("forward_plus_adjoint", bwd)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            times[key] = (time.perf_counter() - t0) / reps * 1e3
+        times["adjoint_over_forward"] = (times["forward_plus_adjoint"] - times["forward"]) / times["forward"]
+        out[name] = {k: round(v, 4) for k, v in times.items()}
+        log(f"[bench] {name}: forward {times['forward']:.2f} ms, with adjoint {times['forward_plus_adjoint']:.2f} ms")
+        plan.close()
+    out["note"] = f"ms per call, nb={pb.cfg.nb}, m={m}, loss over the lowest {nk} Ritz values, checkpoints every 3 steps"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +246,10 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--ref-iters", type=int, default=30,
+                    help="extra FP64 iterations for the converged reference of the mixed accuracy check (0: skip)")
+    ap.add_argument("--backward", action="store_true",
+                    help="also time the adjoint of one filter + Rayleigh-Ritz pass against the forward pass")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (for scaling HBM "
                          "byte counters) and exit")
@@ -275,10 +317,12 @@ def main():
             "filter_apps_per_s": rmx["filter_apps_per_s"],
             "filter_ratio_vs_fp64": rmx["filter_apps_per_s"] / r64["filter_apps_per_s"],
             "dtype": "f32 (complex64 bands/FFTs, FP32-MFMA GEMMs); FP64 Rayleigh-Ritz",
-            "accuracy": mixed_accuracy(cf, pb, r64, rmx, lam_plus),
+            "accuracy": mixed_accuracy(cf, pb, r64, rmx, lam_plus, args.ref_iters) if args.ref_iters > 0 else None,
             "breakdown_ms_per_step": {k: v["ms"] / args.steps for k, v in rmx["prof"].items()},
             "roofline": roofline(rmx["prof"], "f32", cfg.n),
         }
+    if args.backward:
+        out["differentiation"] = time_backward(cf, pb, lam_plus)
     if not args.no_cpu:
         log("[bench] timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(pb)

@@ -54,9 +54,10 @@ __global__ __launch_bounds__(NT) void k_col_inv(int ncol, const int4* __restrict
 
 template <int N, typename T> constexpr int plane_rows() {
   // rows of the x-pass handled together: about one task per thread in the first stage, and the N = 128
-  // double-precision plane kept inside 160 KB of LDS
+  // double-precision plane (65 x-lines of 137 slots, 16-byte points, three twiddle tables) kept inside
+  // 160 KB of LDS
   constexpr int N2 = LineSplit<N>::N2;
-  constexpr int r = (N == 128 && sizeof(T) == 8) ? 8 : NT / N2;
+  constexpr int r = (N == 128 && sizeof(T) == 8) ? 4 : NT / N2;
   return r < N ? r : N;
 }
 

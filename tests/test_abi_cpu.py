@@ -91,3 +91,18 @@ def test_create_rejects_missing_buffer(lib):
     h = ctypes.c_void_p()
     assert lib.cheb_plan_create(ctypes.byref(d), None, 0, None, ctypes.byref(h)) == cf.CHEB_ERR_WORKSPACE
     assert not h.value
+
+
+def test_named_configs_validate(lib):
+    """Every named workload fits the kernels' limits (LDS of the plane pass) in both precisions."""
+    for cid in (1, 2, 3, 4, 5):
+        cfg = wl.CONFIGS[cid]
+        g = wl.sphere(cfg.radius)
+        kin = np.zeros(g.shape[0])
+        nl = wl.CHANNELS[cfg.channels]
+        off = (np.arange(cfg.natom + 1) * nl).astype(np.int32)
+        for prec in (cf.CHEB_FP64, cf.CHEB_MIXED):
+            d = cf.cheb_desc(cfg.n, g.shape[0], g.ctypes.data, kin.ctypes.data, cfg.natom, off.ctypes.data,
+                             int(cfg.overlap), prec)
+            out = ctypes.c_size_t()
+            assert lib.cheb_plan_persistent_bytes(ctypes.byref(d), ctypes.byref(out)) == cf.CHEB_OK, (cid, prec)
