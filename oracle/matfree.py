@@ -171,10 +171,12 @@ def lanczos_upper_bound(ops: Operators, v0, k: int = 10):
     return float(theta[-1] + betas[-1]), np.array(alphas), np.array(betas)
 
 
-def chebfsi(ops: Operators, X0, m: int, iters: int, lam_plus: float, callback=None):
+def chebfsi(ops: Operators, X0, m: int, iters: int, lam_plus: float, callback=None, lock_tol=None):
     """Outer loop: Rayleigh quotients -> lambda_-, filter centre and radius, filter, Rayleigh-Ritz
     (Alg. 2 repeated; lambda_- is the largest Rayleigh quotient, Sec. 5.3). After a Rayleigh-Ritz step the
-    Rayleigh quotients of the rotated block are its Ritz values, so lambda_- is then their maximum."""
+    Rayleigh quotients of the rotated block are its Ritz values, so lambda_- is then their maximum.
+    With lock_tol, from the second iteration on each band is filtered with the degree the residual estimate
+    of Sec. 5.4 (Eq. 5) asks for, at most m (0 = locked); every band stays in the Rayleigh-Ritz step."""
     X = np.asarray(X0, dtype=np.complex128)
     lam_minus = float(np.max(rayleigh_quotients(ops, X)))
     hist = []
@@ -182,9 +184,14 @@ def chebfsi(ops: Operators, X0, m: int, iters: int, lam_plus: float, callback=No
     for it in range(iters):
         c = 0.5 * (lam_plus + lam_minus)
         r = 0.5 * (lam_plus - lam_minus)
-        Y = chebyshev_filter(ops, X, m, c, r)
+        if lock_tol is not None and hist:
+            deg = locking_degrees(res, lam, c, r, m, lock_tol)
+            Y = chebyshev_filter_degrees(ops, X, deg, c, r)
+        else:
+            deg = np.full(X.shape[1], m, dtype=np.int64)
+            Y = chebyshev_filter(ops, X, m, c, r)
         lam, X, res = rayleigh_ritz(ops, Y)
-        hist.append(dict(it=it, c=c, r=r, lam_minus=lam_minus, ritz=lam.copy(), resid=res.copy()))
+        hist.append(dict(it=it, c=c, r=r, lam_minus=lam_minus, ritz=lam.copy(), resid=res.copy(), degrees=deg))
         if callback is not None:
             callback(hist[-1])
         lam_minus = float(np.max(lam))
@@ -194,3 +201,38 @@ def chebfsi(ops: Operators, X0, m: int, iters: int, lam_plus: float, callback=No
 def stability_factor(m: int, lam1: float, c: float, r: float) -> float:
     """T_m((lambda_1 - c)/r), which must stay far below 1/eps for a well-conditioned S_Y (Sec. 5.3)."""
     return float(dense.chebyshev_T(m, np.array([(lam1 - c) / r]))[0])
+
+
+# --- locking (Sec. 5.4) ------------------------------------------------------------------------------------
+def chebyshev_filter_degrees(ops: Operators, X, degrees, c: float, r: float):
+    """Band-wise filter with its own degree per band: column b becomes T_{m_b}((A - c)/r) x_b (Sec. 5.4,
+    adaptive degree per band); bands with degree 0 are left unchanged (locked)."""
+    X = np.asarray(X, dtype=np.complex128)
+    degrees = np.asarray(degrees, dtype=np.int64)
+    out = X.copy()
+    for m in np.unique(degrees):
+        if m == 0:
+            continue
+        cols = np.nonzero(degrees == m)[0]
+        out[:, cols] = chebyshev_filter(ops, X[:, cols], int(m), c, r)
+    return out
+
+
+def locking_degrees(resid, ritz, c: float, r: float, m_max: int, tol: float):
+    """Degree per band from the residual estimate of Sec. 5.4 (Eq. 5): after a degree-n filter and
+    Rayleigh-Ritz, the residual of band i is about ||r_i|| / |T_n((lambda_i - c)/r)|. The degree is the
+    smallest n <= m_max bringing it to tol; a band already at tol is locked (degree 0). The paper's formula
+    shows lambda_1 where the text speaks of each band's own lambda_i; the band's own Ritz value is used."""
+    resid = np.asarray(resid, dtype=np.float64)
+    ritz = np.asarray(ritz, dtype=np.float64)
+    deg = np.full(resid.shape, m_max, dtype=np.int64)
+    for i in range(resid.shape[0]):
+        if resid[i] <= tol:
+            deg[i] = 0
+            continue
+        x = (ritz[i] - c) / r
+        for n in range(1, m_max + 1):
+            if resid[i] / abs(float(dense.chebyshev_T(n, np.array([x]))[0])) <= tol:
+                deg[i] = n
+                break
+    return deg

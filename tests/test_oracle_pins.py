@@ -251,3 +251,76 @@ def test_planted_woodbury_error_is_caught(tiny):
     C = np.diag(pb.Q).astype(complex) + pb.P.conj().T @ pb.P  # Q instead of Q^-1
     bad = pb.X0[:, :2] - pb.P @ np.linalg.solve(C, pb.P.conj().T @ pb.X0[:, :2])
     assert not np.allclose(S @ bad, pb.X0[:, :2], atol=1e-8)
+
+
+# ---- locking (Sec. 5.4) --------------------------------------------------------------------------------------
+def test_filter_degrees_reduces_to_filter(tiny):
+    pb, H, S, ops = tiny
+    lam = dense.eig_pencil(H, S)[0]
+    c, r = 0.5 * (lam[-1] + lam[10]), 0.5 * (lam[-1] - lam[10])
+    X = pb.X0[:, :6]
+    full = matfree.chebyshev_filter(ops, X, 4, c, r)
+    assert np.allclose(matfree.chebyshev_filter_degrees(ops, X, [4] * 6, c, r), full, atol=1e-12 * np.abs(full).max())
+    deg = [0, 3, 1, 4, 0, 2]
+    out = matfree.chebyshev_filter_degrees(ops, X, deg, c, r)
+    for b, m in enumerate(deg):  # spectral form T_m(S^-1 H) x_b, band by band
+        want = X[:, b] if m == 0 else dense.filter_spectral(H, S, X[:, [b]], m, c, r)[:, 0]
+        assert np.allclose(out[:, b], want, atol=1e-11 * max(np.abs(want).max(), 1.0))
+
+
+def test_locking_degree_rule():
+    """Degree = smallest n with ||r|| / |T_n((lambda - c)/r)| <= tol (Eq. 5), 0 when already converged."""
+    c, r = 2.0, 1.0
+    # x = (lambda - c)/r = -3: |T_n(-3)| = 3, 17, 99, 577, ...
+    res = np.array([1e-9, 1e-6 * 3.5, 1e-6 * 16, 1e-6 * 600, 1.0])
+    lam = np.full(5, -1.0)
+    deg = matfree.locking_degrees(res, lam, c, r, 6, 1e-6)
+    assert list(deg) == [0, 2, 2, 5, 6]
+    assert abs(dense.chebyshev_T(2, np.array([-3.0]))[0] - 17.0) < 1e-12
+
+
+@pytest.fixture(scope="module")
+def mid_run():
+    pb = wl.make_problem("mid_paw")
+    ops = matfree.Operators.from_problem(pb)
+    lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
+    return pb, ops, lp
+
+
+def test_locking_estimate_becomes_exact(mid_run):
+    """Eq. 5 is exact at convergence: once the block has converged for a few iterations, the residual after
+    the next degree-m iteration is within a factor 2 of ||r_i|| / |T_m((lambda_i - c)/r)| for the wanted
+    bands (residuals far above rounding). Using lambda_1 for every band instead fails this."""
+    pb, ops, lp = mid_run
+    hist = matfree.chebfsi(ops, pb.X0, pb.cfg.m, 7, lp)[3]
+    nw = pb.cfg.nb - 8
+    for h0, h1 in zip(hist[4:-1], hist[5:]):
+        c, r = h1["c"], h1["r"]
+        est = h0["resid"] / np.abs(dense.chebyshev_T(pb.cfg.m, (h0["ritz"] - c) / r))
+        keep = h1["resid"][:nw] > 1e-9
+        assert keep.sum() > nw // 2
+        ratio = h1["resid"][:nw][keep] / est[:nw][keep]
+        assert np.all((ratio > 0.5) & (ratio < 2.0)), ratio
+        est1 = h0["resid"] / np.abs(dense.chebyshev_T(pb.cfg.m, (h0["ritz"][0] - c) / r))
+        assert np.any(h1["resid"][:nw][keep] / est1[:nw][keep] > 2.0)
+
+
+def test_locking_outer_loop(mid_run):
+    """With locking, the wanted eigenpairs still converge to those of the dense pencil (brute force) while
+    the filter applies fewer band-degrees than the fixed-degree loop."""
+    pb, ops, lp = mid_run
+    H = dense.hamiltonian(pb.gidx, pb.kin, pb.V, pb.P, pb.D)
+    S = dense.overlap(pb.npw, pb.P, pb.Q)
+    exact = dense.eig_pencil(H, S)[0]
+    tol = 1e-8
+    lam, X, res, hist = matfree.chebfsi(ops, pb.X0, pb.cfg.m, 12, lp, lock_tol=tol)
+    done = res <= 2 * tol  # locked bands hover just below tol
+    assert done[:20].all()
+    assert np.all(np.abs(lam[done] - exact[:pb.cfg.nb][done]) <= 1e-12 * np.maximum(np.abs(exact[:pb.cfg.nb][done]), 1))
+    # bands still far from tol got the full degree every time: same residuals as without locking
+    res_full = matfree.chebfsi(ops, pb.X0, pb.cfg.m, 12, lp)[2]
+    slow = res_full > 100 * tol
+    assert slow.sum() >= 8 and np.allclose(res[slow], res_full[slow], rtol=1e-3)
+    work = sum(int(h["degrees"].sum()) for h in hist)
+    assert work < 0.8 * pb.cfg.nb * pb.cfg.m * len(hist)
+    assert any((h["degrees"] == 0).any() for h in hist)  # some bands were locked
