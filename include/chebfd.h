@@ -63,7 +63,8 @@ typedef enum {
   CHEB_OP_FILTER = 2,   /* cheb_filter */
   CHEB_OP_RR = 3,       /* cheb_rayleigh_ritz, cheb_rayleigh_quotients */
   CHEB_OP_BOUND = 4,    /* cheb_upper_bound (nb ignored) */
-  CHEB_OP_SETUP = 5     /* cheb_set_projectors (nb ignored) */
+  CHEB_OP_SETUP = 5,    /* cheb_set_projectors (nb ignored) */
+  CHEB_OP_FILTER_DEGREES = 6 /* cheb_filter_degrees */
 } cheb_op;
 
 typedef struct {
@@ -124,6 +125,24 @@ cheb_status cheb_apply_Sinv(cheb_plan plan, const void* X, int ldx, void* Y, int
  * Sec. 5.1 (one P^H and one P product per step). m >= 0 (m = 0 leaves X unchanged), r > 0. */
 cheb_status cheb_filter(cheb_plan plan, void* X, int ldx, int nb, int m, double c, double r, void* ws,
                         size_t ws_bytes, hipStream_t stream);
+
+/* Locking (Sec. 5.4): the same filter with its own degree per band, X[:, b] <- T_{deg[b]}((S^-1 H - c)/r) X[:, b].
+ * degrees: nb host int32 values >= 0; a band of degree 0 is left unchanged (locked). Bands are gathered in
+ * order of decreasing degree into the workspace, step i of the recurrence runs on the bands of degree >= i
+ * only (a shrinking prefix, so locked and nearly converged bands cost nothing), and each band is written
+ * back from the step that finished it. Results equal cheb_filter run band by band with each band's degree.
+ * The permutation is staged through a pinned host buffer owned by the plan; calls on one plan must not
+ * overlap from several host threads. r > 0. Workspace: cheb_workspace_bytes(CHEB_OP_FILTER_DEGREES, nb). */
+cheb_status cheb_filter_degrees(cheb_plan plan, void* X, int ldx, int nb, const int32_t* degrees, double c,
+                                double r, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Degree per band from the residual estimate of Sec. 5.4 (Eq. 5): after a degree-n filter and Rayleigh-Ritz,
+ * the residual of band i is about resid[i] / |T_n((ritz[i] - c)/r)|. degrees[i] = 0 if resid[i] <= tol,
+ * else the smallest n in [1, m_max] whose estimate is <= tol, else m_max. The band's own Ritz value is
+ * used in T_n (the equation prints lambda_1 where the text speaks of band i). Host arrays, host
+ * arithmetic only; touches no GPU. Returns the number of locked bands in *nlocked (may be NULL). */
+cheb_status cheb_locking_degrees(int nb, const double* ritz, const double* resid, double c, double r, int m_max,
+                                 double tol, int32_t* degrees, int* nlocked);
 
 /* In place Rayleigh-Ritz (Alg. 2): H_X = X^H H X, S_X = X^H S X, H_X Z = S_X Z Lambda with
  * Z^H S_X Z = I (FP64 generalized Hermitian eigensolver), X <- X Z. ritz_dev: nb FP64 Ritz values,

@@ -23,14 +23,14 @@ CHEB_OK, CHEB_ERR_ARG, CHEB_ERR_HIP, CHEB_ERR_WORKSPACE, CHEB_ERR_NOT_PD, CHEB_E
 STATUS_NAMES = ["CHEB_OK", "CHEB_ERR_ARG", "CHEB_ERR_HIP", "CHEB_ERR_WORKSPACE", "CHEB_ERR_NOT_PD", "CHEB_ERR_EIG",
                 "CHEB_ERR_NONFINITE", "CHEB_ERR_STATE"]
 CHEB_FP64, CHEB_MIXED = 0, 1
-CHEB_OP_H, CHEB_OP_SINV, CHEB_OP_FILTER, CHEB_OP_RR, CHEB_OP_BOUND, CHEB_OP_SETUP = range(6)
+CHEB_OP_H, CHEB_OP_SINV, CHEB_OP_FILTER, CHEB_OP_RR, CHEB_OP_BOUND, CHEB_OP_SETUP, CHEB_OP_FILTER_DEGREES = range(7)
 
 # exported symbols, as declared in include/chebfd.h
 SYMBOLS = ["cheb_plan_persistent_bytes", "cheb_plan_create", "cheb_plan_destroy", "cheb_set_potential",
            "cheb_set_projectors", "cheb_set_D", "cheb_workspace_bytes", "cheb_apply_H", "cheb_apply_S",
            "cheb_apply_Sinv", "cheb_filter", "cheb_rayleigh_ritz", "cheb_rayleigh_quotients", "cheb_upper_bound",
            "cheb_profile_enable", "cheb_profile_read", "cheb_backward_workspace_bytes", "cheb_filter_rr_backward",
-           "cheb_set_rr_refine", "cheb_rr_stats", "cheb_last_error"]
+           "cheb_set_rr_refine", "cheb_rr_stats", "cheb_filter_degrees", "cheb_locking_degrees", "cheb_last_error"]
 TIMERS = ["fft_col_inverse", "fft_plane", "fft_col_forward", "project", "backproject", "small", "rr_gram", "rr_eig",
           "rr_rotate", "xdens"]
 
@@ -82,6 +82,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cheb_filter_rr_backward": [vp, vp, i, i, i, d, d, i, vp, i, vp, vp, i, vp, vp, vp, sz, vp],
         "cheb_set_rr_refine": [vp, i],
         "cheb_rr_stats": [vp, P(ctypes.c_int64), P(ctypes.c_int64)],
+        "cheb_filter_degrees": [vp, vp, i, i, vp, d, d, vp, sz, vp],
+        "cheb_locking_degrees": [i, vp, vp, d, d, i, d, vp, P(i)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -91,6 +93,23 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cheb_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
+
+
+def locking_degrees(ritz, resid, c: float, r: float, m_max: int, tol: float):
+    """Degrees per band from the residual estimate of Eq. 5 (cheb_locking_degrees, host arithmetic only).
+    Returns (degrees int32 array, number of locked bands)."""
+    lib = load_library()
+    ritz = np.ascontiguousarray(ritz, dtype=np.float64)
+    resid = np.ascontiguousarray(resid, dtype=np.float64)
+    if ritz.shape != resid.shape or ritz.ndim != 1:
+        raise ValueError("ritz and resid must be 1-D of equal length")
+    deg = np.empty(ritz.shape[0], dtype=np.int32)
+    nlocked = ctypes.c_int()
+    st = lib.cheb_locking_degrees(ritz.shape[0], ritz.ctypes.data, resid.ctypes.data, float(c), float(r), int(m_max),
+                                  float(tol), deg.ctypes.data, ctypes.byref(nlocked))
+    if st != CHEB_OK:
+        raise ChebError(st, "cheb_locking_degrees")
+    return deg, nlocked.value
 
 
 def _ptr(t) -> int | None:
@@ -211,6 +230,18 @@ class Plan:
         ws = self.workspace(CHEB_OP_FILTER, nb)
         self._check(self.lib.cheb_filter(self.handle, X.data_ptr(), ldx, nb, int(m), float(c), float(r),
                                          ws.data_ptr(), ws.numel(), _stream()), "cheb_filter")
+        return X
+
+    def filter_degrees(self, X, degrees, c: float, r: float):
+        """Per-band degrees (locking): X[b] <- T_{degrees[b]}((S^-1 H - c)/r) X[b]; degree 0 leaves a band as is."""
+        nb, ldx = self._block(X, "X")
+        deg = np.ascontiguousarray(degrees, dtype=np.int32)
+        if deg.shape != (nb,):
+            raise ValueError(f"degrees must have shape ({nb},), got {deg.shape}")
+        ws = self.workspace(CHEB_OP_FILTER_DEGREES, nb)
+        self._check(self.lib.cheb_filter_degrees(self.handle, X.data_ptr(), ldx, nb, deg.ctypes.data, float(c),
+                                                 float(r), ws.data_ptr(), ws.numel(), _stream()),
+                    "cheb_filter_degrees")
         return X
 
     def rayleigh_ritz(self, X, with_residuals: bool = True):
@@ -339,3 +370,11 @@ def cheb_upper_bound(plan: Plan, v0, k=10):
 
 def cheb_filter_rr_backward(plan: Plan, X0, m, c, r, w, ckpt_every=3):
     return plan.filter_rr_backward(X0, m, c, r, w, ckpt_every)
+
+
+def cheb_filter_degrees(plan: Plan, X, degrees, c, r):
+    return plan.filter_degrees(X, degrees, c, r)
+
+
+def cheb_locking_degrees(ritz, resid, c, r, m_max, tol):
+    return locking_degrees(ritz, resid, c, r, m_max, tol)

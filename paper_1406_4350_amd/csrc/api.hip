@@ -42,6 +42,10 @@ struct cheb_plan_s {
   bool rr_refine = true;                    // warm-started refinement before the library eigensolver
   int64_t rr_refined = 0, rr_fallback = 0;  // how Rayleigh-Ritz steps were solved
   rocblas_handle rb = nullptr;
+  // pinned staging of the band permutation of cheb_filter_degrees; lock_ev marks the end of its last copy
+  int* lock_host = nullptr;
+  size_t lock_cap = 0;
+  hipEvent_t lock_ev = nullptr;
   std::string err;
   // kernel-class timers
   struct TimerRec { hipEvent_t a, b; int kind; };
@@ -192,6 +196,8 @@ struct Ws {
   c128 *Xa = nullptr, *Xb = nullptr, *T = nullptr, *M1 = nullptr, *M2 = nullptr, *F = nullptr;  // refinement
   double *absF = nullptr, *lam = nullptr, *res = nullptr;
   int* perm = nullptr;
+  void* Xs = nullptr;   // band-sorted copy for the per-band degree filter
+  int* lidx = nullptr;  // its gather / scatter indices (3 nb)
   void* solver = nullptr;
   size_t solver_bytes = 0;
   size_t total = 0;
@@ -225,7 +231,8 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
       part = std::max(part_elems(np, nb, p->npw), part_elems(np, nb, np));
       break;
     }
-    case CHEB_OP_FILTER: {
+    case CHEB_OP_FILTER:
+    case CHEB_OP_FILTER_DEGREES: {
       need_fft();
       w->W = b.take<char>(vec);
       w->loc = b.take<char>(vec);
@@ -237,6 +244,12 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
       w->q = b.take<c128>(pp);
       w->w = b.take<c128>(pp);
       part = std::max(part_elems(np, nb, p->npw), part_elems(np, nb, np));
+      if (op == CHEB_OP_FILTER_DEGREES) {
+        w->Xs = b.take<char>(vec);
+        w->lidx = b.take<int>(3 * size_t(std::max(nb, 1)));
+        // the active block shrinks step by step; split-K partials are sized for every width up to nb
+        for (int k = 1; k < nb; ++k) part = std::max({part, part_elems(np, k, p->npw), part_elems(np, k, np)});
+      }
       break;
     }
     case CHEB_OP_RR: {
@@ -580,6 +593,31 @@ template <typename T> struct Ops {
       CHK(filter_step(i, buf[ci], ld[ci], buf[oi], ld[oi], buf[oi], ld[oi], pb[ci], pb[oi], pb[oi], nb, c, r, w));
     }
     if (m & 1) HIPCHK((convert_copy<T, T>(npw, nb, buf[1], npw, X, ldx, st)));
+    return CHEB_OK;
+  }
+
+  // Per-band degrees (locking, Sec. 5.4). The bands with degree > 0 are gathered into w.Xs in order of
+  // decreasing degree (idx[0, na)); step i runs the recurrence of Alg. 2 on the first active[i-1] of them,
+  // a shrinking prefix, so a band's columns are never touched after its last step. psi^i lands in buffer
+  // i & 1: even-degree bands are scattered back from w.Xs (idx[na, na + 2 ne): sources, then destinations),
+  // odd-degree bands from w.W (the next 2 no entries).
+  cheb_status filter_degrees(C* X, long ldx, const std::vector<int>& active, const int* idx, int ne, int no, double c,
+                             double r, const Ws& w) {
+    const long npw = p->npw;
+    const int na = active.empty() ? 0 : active[0];
+    if (na == 0) return CHEB_OK;
+    C* buf[2] = {static_cast<C*>(w.Xs), static_cast<C*>(w.W)};
+    c128* pb[2] = {w.p0, w.p1};
+    HIPCHK((permute_cols<T>(npw, na, X, ldx, idx, buf[0], npw, nullptr, st)));
+    if (p->nproj > 0) CHK(project(buf[0], npw, na, pb[0], w.part));
+    for (int i = 1; i <= int(active.size()); ++i) {
+      const int ci = (i - 1) & 1, oi = i & 1;
+      CHK(filter_step(i, buf[ci], npw, buf[oi], npw, buf[oi], npw, pb[ci], pb[oi], pb[oi], active[i - 1], c, r, w));
+    }
+    const int* ev = idx + na;
+    const int* od = ev + 2 * ne;
+    HIPCHK((permute_cols<T>(npw, ne, buf[0], npw, ev, X, ldx, ev + ne, st)));
+    HIPCHK((permute_cols<T>(npw, no, buf[1], npw, od, X, ldx, od + no, st)));
     return CHEB_OK;
   }
 
@@ -1183,6 +1221,8 @@ cheb_status cheb_plan_destroy(cheb_plan p) {
   for (auto& r : p->prof_pending) { (void)hipEventSynchronize(r.b); (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
   for (auto& r : p->prof_free) { (void)hipEventDestroy(r.first); (void)hipEventDestroy(r.second); }
   if (p->rb) rocblas_destroy_handle(p->rb);
+  if (p->lock_ev) { (void)hipEventSynchronize(p->lock_ev); (void)hipEventDestroy(p->lock_ev); }
+  if (p->lock_host) (void)hipHostFree(p->lock_host);
   delete p;
   return CHEB_OK;
 }
@@ -1343,6 +1383,87 @@ cheb_status cheb_filter(cheb_plan p, void* X, int ldx, int nb, int m, double c, 
     using C = typename decltype(ops)::C;
     return ops.filter(static_cast<C*>(X), ldx, nb, m, c, r, w);
   });
+}
+
+cheb_status cheb_filter_degrees(cheb_plan p, void* X, int ldx, int nb, const int32_t* degrees, double c, double r,
+                                void* ws, size_t wsb, hipStream_t st) {
+  if (!p) return CHEB_ERR_ARG;
+  CHK(check_block(p, X, ldx, nb, "X"));
+  if (nb > 0 && !degrees) return fail(p, CHEB_ERR_ARG, "degrees is null");
+  if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite(c)) return fail(p, CHEB_ERR_ARG, "need finite c and r > 0");
+  if (nb > 65535) return fail(p, CHEB_ERR_ARG, "nb > 65535");
+  int m = 0;
+  for (int b = 0; b < nb; ++b) {
+    if (degrees[b] < 0) return fail(p, CHEB_ERR_ARG, "negative degree for band " + std::to_string(b));
+    m = std::max(m, int(degrees[b]));
+  }
+  if (nb == 0 || m == 0) return CHEB_OK;
+  OP_PRELUDE(CHEB_OP_FILTER_DEGREES, nb);
+  // order of decreasing degree (stable), active counts per step, gather and scatter lists
+  std::vector<int> order(nb);
+  for (int b = 0; b < nb; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return degrees[a] > degrees[b]; });
+  std::vector<int> active(m, 0);
+  int na = 0, ne = 0, no = 0;
+  for (int j = 0; j < nb; ++j) {
+    const int d = degrees[order[j]];
+    if (d == 0) break;
+    ++na;
+    for (int i = 0; i < d; ++i) ++active[i];
+    (d & 1 ? no : ne) += 1;
+  }
+  const size_t need = 3 * size_t(na);
+  if (p->lock_ev) HIPCHK(hipEventSynchronize(p->lock_ev));  // the previous copy out of the staging buffer is done
+  else HIPCHK(hipEventCreateWithFlags(&p->lock_ev, hipEventDisableTiming));
+  if (p->lock_cap < need) {
+    if (p->lock_host) HIPCHK(hipHostFree(p->lock_host));
+    p->lock_host = nullptr;
+    p->lock_cap = 0;
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->lock_host), need * sizeof(int), hipHostMallocDefault));
+    p->lock_cap = need;
+  }
+  int* h = p->lock_host;
+  int* hev = h + na;
+  int* hod = hev + 2 * ne;
+  for (int j = 0, e = 0, o = 0; j < na; ++j) {
+    h[j] = order[j];
+    if (degrees[order[j]] & 1) { hod[o] = j; hod[no + o] = order[j]; ++o; }
+    else { hev[e] = j; hev[ne + e] = order[j]; ++e; }
+  }
+  HIPCHK(hipMemcpyAsync(w.lidx, h, need * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(p->lock_ev, st));
+  return with_prec(p, st, [&](auto ops) {
+    using C = typename decltype(ops)::C;
+    return ops.filter_degrees(static_cast<C*>(X), ldx, active, w.lidx, ne, no, c, r, w);
+  });
+}
+
+cheb_status cheb_locking_degrees(int nb, const double* ritz, const double* resid, double c, double r, int m_max,
+                                 double tol, int32_t* degrees, int* nlocked) {
+  if (nb < 0 || m_max < 1 || !(r > 0.0) || !std::isfinite(c) || !std::isfinite(r) || !(tol >= 0.0)) return CHEB_ERR_ARG;
+  if (nb > 0 && (!ritz || !resid || !degrees)) return CHEB_ERR_ARG;
+  int locked = 0;
+  for (int i = 0; i < nb; ++i) {
+    if (!std::isfinite(resid[i]) || !std::isfinite(ritz[i])) return CHEB_ERR_ARG;
+    if (resid[i] <= tol) {
+      degrees[i] = 0;
+      ++locked;
+      continue;
+    }
+    // T_n(x) by its three-term recurrence; the estimate resid / |T_n(x)| (Eq. 5)
+    const double x = (ritz[i] - c) / r;
+    double t0 = 1.0, t1 = x;
+    int deg = m_max;
+    for (int n = 1; n <= m_max; ++n) {
+      if (resid[i] <= tol * std::fabs(t1)) { deg = n; break; }
+      const double t2 = 2.0 * x * t1 - t0;
+      t0 = t1;
+      t1 = t2;
+    }
+    degrees[i] = deg;
+  }
+  if (nlocked) *nlocked = locked;
+  return CHEB_OK;
 }
 
 cheb_status cheb_rayleigh_ritz(cheb_plan p, void* X, int ldx, int nb, double* ritz, double* resid, void* ws,

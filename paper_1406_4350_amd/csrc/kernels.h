@@ -92,6 +92,10 @@ hipError_t capacitance(int n, const c128* G, const double* q, c128* C, hipStream
 // V [x][y][z] (FP64) -> Vt [z][y][x] in T
 template <typename T> hipError_t transpose_potential(int n, const double* V, T* Vt, hipStream_t st);
 template <typename E> hipError_t fill_zero(cx<E>* p, long count, hipStream_t st);
+// dst[:, didx ? didx[j] : j] = src[:, sidx ? sidx[j] : j] for j < ncols (gather / scatter of band columns)
+template <typename E>
+hipError_t permute_cols(long rows, int ncols, const cx<E>* src, long lds, const int* sidx, cx<E>* dst, long ldd,
+                        const int* didx, hipStream_t st);
 // out[:, j] = a[:, j] - lam[j] b[:, j]  (contiguous rows x nb, complex128)
 hipError_t sub_scaled_cols(int rows, int nb, const c128* a, const c128* b, const double* lam, c128* out,
                            hipStream_t st);

@@ -1,5 +1,7 @@
 // Projector-space and vector kernels: block-diagonal D (Eq. 3), the capacitance matrix of the Woodbury
 // inverse (Sec. 5.1), Rayleigh-Ritz preparation (Alg. 2), column dots and residual norms (Sec. 6.1).
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace chebfd {
@@ -62,6 +64,17 @@ __global__ void k_convert(long rows, int nb, const cx<EI>* in, long ldi, cx<EO>*
     cx<EI> v = in[col * ldi + i];
     out[col * ldo + i] = cx<EO>{EO(v.x), EO(v.y)};
   }
+}
+
+// one block column per band; rows strided so that a wave reads consecutive coefficients
+template <typename E>
+__global__ void k_permute_cols(long rows, int ncols, const cx<E>* src, long lds, const int* sidx, cx<E>* dst,
+                               long ldd, const int* didx) {
+  const int j = blockIdx.y;
+  if (j >= ncols) return;
+  const cx<E>* s = src + long(sidx ? sidx[j] : j) * lds;
+  cx<E>* d = dst + long(didx ? didx[j] : j) * ldd;
+  for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < rows; i += long(gridDim.x) * blockDim.x) d[i] = s[i];
 }
 
 // one block per column, fixed-order tree reduction (deterministic)
@@ -214,6 +227,17 @@ hipError_t convert_copy(long rows, int nb, const cx<EI>* in, long ldi, cx<EO>* o
 }
 
 template <typename E>
+hipError_t permute_cols(long rows, int ncols, const cx<E>* src, long lds, const int* sidx, cx<E>* dst, long ldd,
+                        const int* didx, hipStream_t st) {
+  if (rows <= 0 || ncols <= 0) return hipSuccess;
+  if (ncols > 65535) return hipErrorInvalidValue;
+  const long bx = std::min<long>((rows + 255) / 256, 64);
+  hipLaunchKernelGGL((k_permute_cols<E>), dim3(unsigned(bx), unsigned(ncols)), dim3(256), 0, st, rows, ncols, src, lds,
+                     sidx, dst, ldd, didx);
+  return hipGetLastError();
+}
+
+template <typename E>
 hipError_t col_dots(long rows, int nb, const cx<E>* x, long ldx, const cx<E>* y, long ldy, c128* out,
                     hipStream_t st) {
   if (nb <= 0) return hipSuccess;
@@ -278,6 +302,8 @@ template hipError_t col_resid_norms<float>(long, int, const c64*, long, const c6
 template hipError_t transpose_potential<double>(int, const double*, double*, hipStream_t);
 template hipError_t transpose_potential<float>(int, const double*, float*, hipStream_t);
 template hipError_t fill_zero<double>(c128*, long, hipStream_t);
+template hipError_t permute_cols<double>(long, int, const c128*, long, const int*, c128*, long, const int*, hipStream_t);
+template hipError_t permute_cols<float>(long, int, const c64*, long, const int*, c64*, long, const int*, hipStream_t);
 template hipError_t fill_zero<float>(c64*, long, hipStream_t);
 
 }  // namespace chebfd

@@ -9,28 +9,41 @@ import time
 
 import torch
 
-from .chebfd import Plan
+from .chebfd import Plan, locking_degrees
 
 
 def chebfsi(plan: Plan, X: torch.Tensor, m: int, iters: int, lam_plus: float, callback=None,
-            with_residuals: bool = True):
+            with_residuals: bool = True, lock_tol: float | None = None):
     """Run `iters` outer iterations in place on X (nb, npw). lambda_- is the largest Rayleigh quotient of the
     block: explicitly for the start block, the largest Ritz value afterwards (the Rayleigh quotients of a
-    Rayleigh-Ritz-rotated block are its Ritz values). Returns (ritz, residuals, history)."""
+    Rayleigh-Ritz-rotated block are its Ritz values). With lock_tol, after each Rayleigh-Ritz step every band
+    gets the degree the residual estimate of Eq. 5 asks for to reach lock_tol with the next filter (at most m,
+    0 = locked; Sec. 5.4); the first iteration uses m for all bands. Returns (ritz, residuals, history)."""
+    if lock_tol is not None and not with_residuals:
+        raise ValueError("locking needs the residuals")
     lam_minus = float(plan.rayleigh_quotients(X).max().item())
     hist = []
     ritz = res = None
+    nb = X.shape[0]
     for it in range(iters):
         if not lam_plus > lam_minus:
             raise ValueError(f"upper bound {lam_plus} not above lambda_- {lam_minus}")
         c = 0.5 * (lam_plus + lam_minus)
         r = 0.5 * (lam_plus - lam_minus)
+        degrees = nlocked = None
+        if lock_tol is not None and hist:
+            degrees, nlocked = locking_degrees(hist[-1]["ritz"], hist[-1]["resid"], c, r, m, lock_tol)
         t0 = time.perf_counter()
-        plan.filter(X, m, c, r)
+        if degrees is None:
+            plan.filter(X, m, c, r)
+        else:
+            plan.filter_degrees(X, degrees, c, r)
         ritz, res = plan.rayleigh_ritz(X, with_residuals=with_residuals)
         torch.cuda.synchronize()
         rec = dict(it=it, c=c, r=r, lam_minus=lam_minus, seconds=time.perf_counter() - t0,
-                   ritz=ritz.cpu().numpy(), resid=None if res is None else res.cpu().numpy())
+                   ritz=ritz.cpu().numpy(), resid=None if res is None else res.cpu().numpy(),
+                   band_applications=nb * m if degrees is None else int(degrees.sum()),
+                   locked=0 if degrees is None else nlocked, degrees=None if degrees is None else degrees.copy())
         hist.append(rec)
         if callback is not None:
             callback(rec)

@@ -106,3 +106,28 @@ def test_named_configs_validate(lib):
                              int(cfg.overlap), prec)
             out = ctypes.c_size_t()
             assert lib.cheb_plan_persistent_bytes(ctypes.byref(d), ctypes.byref(out)) == cf.CHEB_OK, (cid, prec)
+
+
+def test_locking_degrees_host_function(lib):
+    """cheb_locking_degrees (host arithmetic only) picks the same degree per band as the oracle's rule
+    (Eq. 5, Sec. 5.4), on random residuals spread over many decades and Ritz values inside and below the
+    damped interval; and it rejects bad arguments."""
+    from oracle import matfree
+    rng = np.random.default_rng(7)
+    nb, c, r, m, tol = 500, 3.0, 2.0, 12, 1e-7
+    ritz = rng.uniform(-6.0, 5.5, nb)
+    resid = 10.0 ** rng.uniform(-10, 1, nb)
+    deg, nlocked = cf.locking_degrees(ritz, resid, c, r, m, tol)
+    ref = matfree.locking_degrees(resid, ritz, c, r, m, tol)
+    assert np.array_equal(deg, ref)
+    assert nlocked == int((resid <= tol).sum()) and nlocked > 0
+    assert (deg == m).sum() > 0 and ((deg > 0) & (deg < m)).sum() > 0
+    with pytest.raises(cf.ChebError):
+        cf.locking_degrees(ritz, resid, c, -1.0, m, tol)
+    with pytest.raises(cf.ChebError):
+        cf.locking_degrees(ritz, resid, c, r, 0, tol)
+    bad = resid.copy()
+    bad[3] = np.nan
+    with pytest.raises(cf.ChebError):
+        cf.locking_degrees(ritz, bad, c, r, m, tol)
+    assert cf.locking_degrees(ritz[:0], resid[:0], c, r, m, tol)[0].shape == (0,)
