@@ -152,6 +152,12 @@ cheb_status cheb_locking_degrees(int nb, const double* ritz, const double* resid
 cheb_status cheb_rayleigh_ritz(cheb_plan plan, void* X, int ldx, int nb, double* ritz_dev, double* resid_dev,
                                void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Mixed plans only (no effect on FP64 plans): the projector products P^H x and P w of the filter and the
+ * operators use the FP16 hi/lo split MFMA (on = 1, the default: each operand is a sum of two FP16 numbers,
+ * about 22 significant bits, products hi*hi + hi*lo + lo*hi accumulated in FP32) or the FP32 MFMA (on = 0).
+ * The split planes of P are built by cheb_set_projectors. */
+cheb_status cheb_set_split_gemm(cheb_plan plan, int on);
+
 /* Dense eigensolver of cheb_rayleigh_ritz. on (default): first try a warm-started iterative refinement of
  * Z from the identity in the column-scaled basis (n^3 products only; accepted only if X^H S_X X = I and
  * X^H H_X X diagonal to 1e-12 are verified), else the library path. off: always the library path.

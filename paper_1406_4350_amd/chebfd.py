@@ -30,7 +30,8 @@ SYMBOLS = ["cheb_plan_persistent_bytes", "cheb_plan_create", "cheb_plan_destroy"
            "cheb_set_projectors", "cheb_set_D", "cheb_workspace_bytes", "cheb_apply_H", "cheb_apply_S",
            "cheb_apply_Sinv", "cheb_filter", "cheb_rayleigh_ritz", "cheb_rayleigh_quotients", "cheb_upper_bound",
            "cheb_profile_enable", "cheb_profile_read", "cheb_backward_workspace_bytes", "cheb_filter_rr_backward",
-           "cheb_set_rr_refine", "cheb_rr_stats", "cheb_filter_degrees", "cheb_locking_degrees", "cheb_last_error"]
+           "cheb_set_rr_refine", "cheb_rr_stats", "cheb_filter_degrees", "cheb_locking_degrees", "cheb_set_split_gemm",
+           "cheb_last_error"]
 TIMERS = ["fft_col_inverse", "fft_plane", "fft_col_forward", "project", "backproject", "small", "rr_gram", "rr_eig",
           "rr_rotate", "xdens"]
 
@@ -83,6 +84,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cheb_set_rr_refine": [vp, i],
         "cheb_rr_stats": [vp, P(ctypes.c_int64), P(ctypes.c_int64)],
         "cheb_filter_degrees": [vp, vp, i, i, vp, d, d, vp, sz, vp],
+        "cheb_set_split_gemm": [vp, i],
         "cheb_locking_degrees": [i, vp, vp, d, d, i, d, vp, P(i)],
     }
     for name, args in sig.items():
@@ -295,6 +297,10 @@ class Plan:
             ritz.data_ptr(), dX.data_ptr(), dX.stride(0), dV.data_ptr(), dD.data_ptr() if dsize else None,
             ws.data_ptr(), ws.numel(), _stream()), "cheb_filter_rr_backward")
         return ritz, dX, dV, dD[:dsize]
+
+    def set_split_gemm(self, on: bool):
+        """Mixed plans: FP16 hi/lo split MFMA (True, default) or FP32 MFMA (False) for the projector GEMMs."""
+        self._check(self.lib.cheb_set_split_gemm(self.handle, int(bool(on))), "cheb_set_split_gemm")
 
     def set_rr_refine(self, on: bool):
         self._check(self.lib.cheb_set_rr_refine(self.handle, int(bool(on))), "cheb_set_rr_refine")

@@ -39,6 +39,8 @@ struct cheb_plan_s {
   c128* Cinv = nullptr;
   bool have_V = false, have_P = false, have_D = false;
   int fft_batch = 1;
+  HalfPlanes hproj, hback;                  // mixed plans: split planes of P (set with the projectors)
+  bool split_gemm = true;                   // mixed plans: FP16 hi/lo split MFMA for P^H x and P w
   bool rr_refine = true;                    // warm-started refinement before the library eigensolver
   int64_t rr_refined = 0, rr_fallback = 0;  // how Rayleigh-Ritz steps were solved
   rocblas_handle rb = nullptr;
@@ -134,8 +136,14 @@ struct Timed {
 // ---- layouts -------------------------------------------------------------------------------------------------
 struct Persist {
   int4* col; int* ent; int4* xline; int4* pinfo; int2* dent; void* tw; void* kin; void* Vt; void* P; double* D; double* Q; c128* G; c128* Cinv;
+  _Float16* Hproj;  // mixed plans: FP16 hi/lo planes of P for P^H x (rows = projectors, k = plane waves)
+  _Float16* Hback;  // and for P w (rows = plane waves, k = projectors)
+  size_t bytes;
 };
 
+inline long pad32(long k) { return (k + 31) / 32 * 32; }
+
+// Carves the persistent buffer (base == nullptr: only measures)
 Persist persist_layout(void* base, int n, int npw, int ncol, int rx, int nproj, size_t dsize, int overlap, int prec) {
   Bump b(base);
   Persist l{};
@@ -152,28 +160,18 @@ Persist persist_layout(void* base, int n, int npw, int ncol, int rx, int nproj, 
   l.D = b.take<double>(std::max<size_t>(dsize, 1));
   l.Q = b.take<double>(std::max(nproj, 1));
   l.G = b.take<c128>(size_t(nproj) * nproj);
-  l.Cinv = overlap ? b.take<c128>(size_t(nproj) * nproj) : nullptr;
-  (void)l;
+  l.Cinv = overlap ? b.take<c128>(2 * size_t(nproj) * nproj) : nullptr;  // [C^-1 | C^-1 G]
+  l.Hproj = l.Hback = nullptr;
+  if (mixed && nproj > 0) {
+    l.Hproj = b.take<_Float16>(4 * size_t(nproj) * pad32(npw));
+    l.Hback = b.take<_Float16>(4 * size_t(npw) * pad32(nproj));
+  }
+  l.bytes = b.off;
   return l;
 }
 
 size_t persist_bytes(int n, int npw, int ncol, int rx, int nproj, size_t dsize, int overlap, int prec) {
-  Bump b(nullptr);
-  const bool mixed = prec == CHEB_MIXED;
-  b.take<int4>(ncol);
-  b.take<int>(npw);
-  b.take<int4>(2 * rx + 1);
-  b.take<int4>(std::max(nproj, 1));
-  b.take<int2>(std::max<size_t>(dsize, 1));
-  mixed ? (void)b.take<c64>(n) : (void)b.take<c128>(n);
-  mixed ? (void)b.take<float>(npw) : (void)b.take<double>(npw);
-  mixed ? (void)b.take<float>(size_t(n) * n * n) : (void)b.take<double>(size_t(n) * n * n);
-  mixed ? (void)b.take<c64>(size_t(npw) * nproj) : (void)b.take<c128>(size_t(npw) * nproj);
-  b.take<double>(std::max<size_t>(dsize, 1));
-  b.take<double>(std::max(nproj, 1));
-  b.take<c128>(size_t(nproj) * nproj);
-  if (overlap) b.take<c128>(size_t(nproj) * nproj);
-  return b.off;
+  return persist_layout(nullptr, n, npw, ncol, rx, nproj, dsize, overlap, prec).bytes;
 }
 
 size_t part_elems(int M, int N, int K) {
@@ -196,6 +194,7 @@ struct Ws {
   c128 *Xa = nullptr, *Xb = nullptr, *T = nullptr, *M1 = nullptr, *M2 = nullptr, *F = nullptr;  // refinement
   double *absF = nullptr, *lam = nullptr, *res = nullptr;
   int* perm = nullptr;
+  float* bsc = nullptr;  // per-band power-of-two scales of the split GEMMs
   void* Xs = nullptr;   // band-sorted copy for the per-band degree filter
   int* lidx = nullptr;  // its gather / scatter indices (3 nb)
   void* solver = nullptr;
@@ -238,17 +237,15 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
       w->loc = b.take<char>(vec);
       w->p0 = b.take<c128>(pp);
       w->p1 = b.take<c128>(pp);
-      w->ploc = b.take<c128>(pp);
-      w->Dp = b.take<c128>(pp);
-      w->pphi = b.take<c128>(pp);
-      w->q = b.take<c128>(pp);
+      w->ploc = b.take<c128>(2 * pp);  // [P^H loc; D p], ld 2 nproj
       w->w = b.take<c128>(pp);
-      part = std::max(part_elems(np, nb, p->npw), part_elems(np, nb, np));
+      part = std::max({part_elems(np, nb, p->npw), part_elems(np, nb, np), part_elems(np, nb, 2 * np)});
       if (op == CHEB_OP_FILTER_DEGREES) {
         w->Xs = b.take<char>(vec);
         w->lidx = b.take<int>(3 * size_t(std::max(nb, 1)));
         // the active block shrinks step by step; split-K partials are sized for every width up to nb
-        for (int k = 1; k < nb; ++k) part = std::max({part, part_elems(np, k, p->npw), part_elems(np, k, np)});
+        for (int k = 1; k < nb; ++k)
+          part = std::max({part, part_elems(np, k, p->npw), part_elems(np, k, np), part_elems(np, k, 2 * np)});
       }
       break;
     }
@@ -314,6 +311,7 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
       return fail(p, CHEB_ERR_ARG, "unknown op");
   }
   w->part = b.take<c128>(std::max<size_t>(part, 1));
+  w->bsc = b.take<float>(std::max(nb, 1));
   w->total = b.off;
   return CHEB_OK;
 }
@@ -457,47 +455,76 @@ template <typename T> struct Ops {
     return CHEB_OK;
   }
 
-  // pout (nproj x nb, c128) = P^H X
-  cheb_status project(const C* X, long ldx, int nb, c128* pout, c128* part) {
+  // pout (nproj x nb, c128) = P^H X. exact: FP64 MFMA whatever the plan precision (products of complex64
+  // inputs are exact in FP64), for the Rayleigh-Ritz matrices of a mixed plan.
+  bool use_split() const { return std::is_same<T, float>::value && p->split_gemm && p->hproj.p; }
+
+  // pout (nproj x nb, c128) = P^H X. exact: FP64 MFMA whatever the plan precision (products of complex64
+  // inputs are exact in FP64), for the Rayleigh-Ritz matrices of a mixed plan. Otherwise a mixed plan uses
+  // the FP16 hi/lo split MFMA on X scaled per band by a power of two (FP32-level accuracy).
+  cheb_status project(const C* X, long ldx, int nb, c128* pout, const Ws& w, bool exact = false, long ldo = 0) {
     Epi<double> e;
     e.out = pout;
-    e.ldo = p->nproj;
+    e.ldo = ldo > 0 ? ldo : p->nproj;
     const double b = sizeof(C), np = p->nproj, npw = p->npw;
     Timed t(p, st, CHEB_T_PROJECT, (npw * np + npw * nb) * b + np * nb * 16.0, 8.0 * np * nb * npw);
-    HIPCHK((gemm<T, T, T, double>(GEMM_CN, p->nproj, nb, p->npw, P(), p->npw, X, ldx, e,
-                                  gemm_pick_splits(p->nproj, nb, p->npw), part, st, ROLE_PROJECT)));
+    if (exact) {
+      HIPCHK((gemm<double, T, T, double>(GEMM_CN, p->nproj, nb, p->npw, P(), p->npw, X, ldx, e,
+                                         gemm_pick_splits(p->nproj, nb, p->npw), w.part, st, ROLE_PROJECT)));
+    } else if (use_split()) {
+      if constexpr (std::is_same<T, float>::value) {
+        HIPCHK(column_scales<float>(p->npw, nb, X, ldx, w.bsc, st));
+        HIPCHK((gemm_h<float, double>(GEMM_CN, p->nproj, nb, p->npw, p->hproj, X, ldx, w.bsc, e,
+                                      gemm_h_pick_splits(p->nproj, nb, p->npw), w.part, st, ROLE_PROJECT)));
+      }
+    } else {
+      HIPCHK((gemm<T, T, T, double>(GEMM_CN, p->nproj, nb, p->npw, P(), p->npw, X, ldx, e,
+                                    gemm_pick_splits(p->nproj, nb, p->npw), w.part, st, ROLE_PROJECT)));
+    }
     return CHEB_OK;
   }
 
-  // out = alpha P w + bL L (+ bU U + bW W): back-projection with the vector epilogue
-  cheb_status backproject(const c128* w, int nb, Epi<T> e) {
+  // out = alpha P wv + bL L (+ bU U + bW W): back-projection with the vector epilogue
+  cheb_status backproject(const c128* wv, int nb, Epi<T> e, const Ws& w, long ldw = 0) {
     const double b = sizeof(C), np = p->nproj, npw = p->npw;
     const double vecs = 1.0 + (e.L ? 1 : 0) + (e.U ? 1 : 0) + (e.W ? 1 : 0);
+    if (ldw <= 0) ldw = p->nproj;
     Timed t(p, st, CHEB_T_BACKPROJECT, npw * np * b + np * nb * 16.0 + vecs * npw * nb * b, 8.0 * npw * nb * np);
-    HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, p->nproj, P(), p->npw, w, p->nproj, e, 1, nullptr, st,
-                                  ROLE_BACKPROJECT)));
+    if (use_split()) {
+      if constexpr (std::is_same<T, float>::value) {
+        HIPCHK(column_scales<double>(p->nproj, nb, wv, ldw, w.bsc, st));
+        HIPCHK((gemm_h<double, float>(GEMM_NN, p->npw, nb, p->nproj, p->hback, wv, ldw, w.bsc, e, 1, nullptr, st,
+                                      ROLE_BACKPROJECT)));
+      }
+    } else {
+      HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, p->nproj, P(), p->npw, wv, ldw, e, 1, nullptr, st,
+                                    ROLE_BACKPROJECT)));
+    }
     return CHEB_OK;
   }
 
-  // small projector-space product out = alpha M x (+ epilogue), M nproj x nproj (c128)
-  cheb_status small(const c128* M, const c128* x, int nb, Epi<double> e, c128* part) {
+  // small projector-space product out = alpha A x (+ epilogue): A nproj x K (c128, ld lda), x K x nb (ld ldx)
+  cheb_status small(const c128* A, long lda, int K, const c128* x, long ldx, int nb, Epi<double> e, c128* part) {
     const int np = p->nproj;
     const double vecs = 2.0 + (e.L ? 1 : 0) + (e.U ? 1 : 0) + (e.W ? 1 : 0);
-    Timed t(p, st, CHEB_T_SMALL, double(np) * np * 16.0 + vecs * np * nb * 16.0, 8.0 * np * np * nb);
-    HIPCHK((gemm<double, double, double, double>(GEMM_NN, np, nb, np, M, np, x, np, e, gemm_pick_splits(np, nb, np),
+    Timed t(p, st, CHEB_T_SMALL, double(np) * K * 16.0 + vecs * np * nb * 16.0, 8.0 * np * double(K) * nb);
+    HIPCHK((gemm<double, double, double, double>(GEMM_NN, np, nb, K, A, lda, x, ldx, e, gemm_pick_splits(np, nb, K),
                                                  part, st)));
     return CHEB_OK;
+  }
+  cheb_status small(const c128* M, const c128* x, int nb, Epi<double> e, c128* part) {
+    return small(M, p->nproj, p->nproj, x, p->nproj, nb, e, part);
   }
 
   cheb_status apply_H(const C* X, long ldx, C* Y, long ldy, int nb, const Ws& w) {
     CHK(hloc(X, ldx, nb, Y, ldy, w.fft));
     if (p->nproj == 0) return CHEB_OK;
-    CHK(project(X, ldx, nb, w.p0, w.part));
+    CHK(project(X, ldx, nb, w.p0, w));
     HIPCHK(block_diag_apply(p->nproj, nb, p->pinfo, p->D, w.p0, p->nproj, w.Dp, p->nproj, st));
     Epi<T> e;
     e.out = Y; e.ldo = ldy; e.alpha = 1.0;
     e.L = Y; e.ldl = ldy; e.bL = 1.0;
-    return backproject(w.Dp, nb, e);
+    return backproject(w.Dp, nb, e, w);
   }
 
   cheb_status apply_S(const C* X, long ldx, C* Y, long ldy, int nb, const Ws& w) {
@@ -505,12 +532,12 @@ template <typename T> struct Ops {
       HIPCHK((convert_copy<T, T>(p->npw, nb, X, ldx, Y, ldy, st)));
       return CHEB_OK;
     }
-    CHK(project(X, ldx, nb, w.p0, w.part));
+    CHK(project(X, ldx, nb, w.p0, w));
     HIPCHK(diag_apply(p->nproj, nb, p->Q, w.p0, p->nproj, w.Dp, p->nproj, st));
     Epi<T> e;
     e.out = Y; e.ldo = ldy; e.alpha = 1.0;
     e.L = X; e.ldl = ldx; e.bL = 1.0;
-    return backproject(w.Dp, nb, e);
+    return backproject(w.Dp, nb, e, w);
   }
 
   cheb_status apply_Sinv(const C* X, long ldx, C* Y, long ldy, int nb, const Ws& w) {
@@ -518,14 +545,14 @@ template <typename T> struct Ops {
       HIPCHK((convert_copy<T, T>(p->npw, nb, X, ldx, Y, ldy, st)));
       return CHEB_OK;
     }
-    CHK(project(X, ldx, nb, w.p0, w.part));
+    CHK(project(X, ldx, nb, w.p0, w));
     Epi<double> es;
     es.out = w.Dp; es.ldo = p->nproj;
     CHK(small(p->Cinv, w.p0, nb, es, w.part));
     Epi<T> e;
     e.out = Y; e.ldo = ldy; e.alpha = -1.0;
     e.L = X; e.ldl = ldx; e.bL = 1.0;
-    return backproject(w.Dp, nb, e);
+    return backproject(w.Dp, nb, e, w);
   }
 
   // One step of the recurrence (Alg. 2 inner loop): out = s1 (S^-1 H cur - c cur) - s2 prev, with the
@@ -543,20 +570,24 @@ template <typename T> struct Ops {
       HIPCHK((axpbypcz<T>(npw, nb, s1, loc, npw, -s1 * c, cur, ldc, -s2, i == 1 ? nullptr : prev, ldp, out, ldo, st)));
       return CHEB_OK;
     }
-    // projector space: p_loc = P^H loc; D p; p_phi = P^H H psi = p_loc + G D p
-    CHK(project(loc, npw, nb, w.ploc, w.part));
-    HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, pcur, np, w.Dp, np, st));
-    Epi<double> e1;
-    e1.out = w.pphi; e1.ldo = np; e1.L = w.ploc; e1.ldl = np; e1.bL = 1.0;
-    CHK(small(p->G, w.Dp, nb, e1, w.part));
-    const c128* wv = w.Dp;
+    // projector space, stacked [p_loc; D p] (ld 2 np): p_loc = P^H loc, D p from the carried p = P^H psi.
+    // With p_phi = P^H H psi = p_loc + G D p and q = C^-1 p_phi (Sec. 5.1):
+    //   S^-1 H psi = loc + P w,  w = D p - q = D p - [C^-1 | C^-1 G] [p_loc; D p]
+    //   P^H S^-1 H psi = p_phi - G q = p_loc + G w   (reuse trick; S = I: w = D p)
+    const long l2 = 2L * np;
+    c128* pl = w.ploc;
+    c128* dp = w.ploc + np;
+    CHK(project(loc, npw, nb, pl, w, false, l2));
+    HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, pcur, np, dp, l2, st));
+    const c128* wv = dp;
+    long ldw = l2;
     if (p->has_overlap) {
-      // q = C^-1 p_phi; w = D p - q  (S^-1 H psi = loc + P w, Sec. 5.1)
       Epi<double> e2;
-      e2.out = w.q; e2.ldo = np;
-      CHK(small(p->Cinv, w.pphi, nb, e2, w.part));
-      HIPCHK((axpbypcz<double>(np, nb, 1.0, w.Dp, np, -1.0, w.q, np, 0.0, nullptr, 0, w.w, np, st)));
+      e2.out = w.w; e2.ldo = np; e2.alpha = -1.0;
+      e2.L = dp; e2.ldl = l2; e2.bL = 1.0;
+      CHK(small(p->Cinv, np, 2 * np, pl, l2, nb, e2, w.part));
       wv = w.w;
+      ldw = np;
     }
     // psi^i = s1 (loc + P w - c psi^(i-1)) - s2 psi^(i-2)
     Epi<T> e;
@@ -564,19 +595,14 @@ template <typename T> struct Ops {
     e.L = loc; e.ldl = npw; e.bL = s1;
     e.U = cur; e.ldu = ldc; e.bU = -s1 * c;
     if (i > 1) { e.W = prev; e.ldw = ldp; e.bW = -s2; }
-    CHK(backproject(wv, nb, e));
-    // p^i = s1 (p_y - c p^(i-1)) - s2 p^(i-2), with p_y = P^H S^-1 H psi = p_phi - G q (reuse trick)
-    if (p->has_overlap) {
-      Epi<double> e3;
-      e3.out = pout; e3.ldo = np; e3.alpha = -s1;
-      e3.L = w.pphi; e3.ldl = np; e3.bL = s1;
-      e3.U = pcur; e3.ldu = np; e3.bU = -s1 * c;
-      if (i > 1) { e3.W = pprev; e3.ldw = np; e3.bW = -s2; }
-      CHK(small(p->G, w.q, nb, e3, w.part));
-    } else {
-      HIPCHK((axpbypcz<double>(np, nb, s1, w.pphi, np, -s1 * c, pcur, np, -s2, i == 1 ? nullptr : pprev, np, pout, np,
-                               st)));
-    }
+    CHK(backproject(wv, nb, e, w, ldw));
+    // p^i = s1 (p_loc + G w - c p^(i-1)) - s2 p^(i-2)
+    Epi<double> e3;
+    e3.out = pout; e3.ldo = np; e3.alpha = s1;
+    e3.L = pl; e3.ldl = l2; e3.bL = s1;
+    e3.U = pcur; e3.ldu = np; e3.bU = -s1 * c;
+    if (i > 1) { e3.W = pprev; e3.ldw = np; e3.bW = -s2; }
+    CHK(small(p->G, np, np, wv, ldw, nb, e3, w.part));
     return CHEB_OK;
   }
 
@@ -587,7 +613,7 @@ template <typename T> struct Ops {
     C* buf[2] = {X, static_cast<C*>(w.W)};
     long ld[2] = {ldx, npw};
     c128* pb[2] = {w.p0, w.p1};
-    if (p->nproj > 0) CHK(project(X, ldx, nb, pb[0], w.part));
+    if (p->nproj > 0) CHK(project(X, ldx, nb, pb[0], w));
     for (int i = 1; i <= m; ++i) {
       const int ci = (i - 1) & 1, oi = i & 1;
       CHK(filter_step(i, buf[ci], ld[ci], buf[oi], ld[oi], buf[oi], ld[oi], pb[ci], pb[oi], pb[oi], nb, c, r, w));
@@ -609,7 +635,7 @@ template <typename T> struct Ops {
     C* buf[2] = {static_cast<C*>(w.Xs), static_cast<C*>(w.W)};
     c128* pb[2] = {w.p0, w.p1};
     HIPCHK((permute_cols<T>(npw, na, X, ldx, idx, buf[0], npw, nullptr, st)));
-    if (p->nproj > 0) CHK(project(buf[0], npw, na, pb[0], w.part));
+    if (p->nproj > 0) CHK(project(buf[0], npw, na, pb[0], w));
     for (int i = 1; i <= int(active.size()); ++i) {
       const int ci = (i - 1) & 1, oi = i & 1;
       CHK(filter_step(i, buf[ci], npw, buf[oi], npw, buf[oi], npw, pb[ci], pb[oi], pb[oi], active[i - 1], c, r, w));
@@ -630,14 +656,17 @@ template <typename T> struct Ops {
     Timed t(p, st, CHEB_T_RR_GRAM, 3.0 * npw * nb * sizeof(C) + 2.0 * nb * nb * 16.0, 16.0 * npw * nb * nb);
     Epi<double> eh;
     eh.out = w.Hs; eh.ldo = nb;
-    HIPCHK((gemm<T, T, T, double>(GEMM_CN, nb, nb, p->npw, X, ldx, loc, npw, eh, gemm_pick_splits(nb, nb, p->npw),
-                                  w.part, st, ROLE_SUBSPACE)));
+    // FP64 MFMA in both precisions: with complex64 blocks the products are exact and the sums over npw
+    // terms keep FP64 rounding, so the subspace matrices (and the Ritz values) are limited by the FP32
+    // rounding of H X only, not by FP32 accumulation over the sphere.
+    HIPCHK((gemm<double, T, T, double>(GEMM_CN, nb, nb, p->npw, X, ldx, loc, npw, eh,
+                                       gemm_pick_splits(nb, nb, p->npw), w.part, st, ROLE_SUBSPACE)));
     Epi<double> es;
     es.out = w.Ss; es.ldo = nb;
-    HIPCHK((gemm<T, T, T, double>(GEMM_CN, nb, nb, p->npw, X, ldx, X, ldx, es, gemm_pick_splits(nb, nb, p->npw),
-                                  w.part, st, ROLE_SUBSPACE)));
+    HIPCHK((gemm<double, T, T, double>(GEMM_CN, nb, nb, p->npw, X, ldx, X, ldx, es,
+                                       gemm_pick_splits(nb, nb, p->npw), w.part, st, ROLE_SUBSPACE)));
     if (np > 0) {
-      CHK(project(X, ldx, nb, w.p0, w.part));
+      CHK(project(X, ldx, nb, w.p0, w, true));
       HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, w.p0, np, w.Dp, np, st));
       Epi<double> e2;
       e2.out = w.Hs; e2.ldo = nb; e2.L = w.Hs; e2.ldl = nb; e2.bL = 1.0;
@@ -803,7 +832,7 @@ template <typename T> struct Ops {
         }
         Epi<T> e2;
         e2.out = R; e2.ldo = npw; e2.L = R; e2.ldl = npw; e2.bL = 1.0;
-        CHK(backproject(t, nb, e2));
+        CHK(backproject(t, nb, e2, w));
       }
       HIPCHK((col_resid_norms<T>(npw, nb, R, npw, Ynew, npw, ritz, resid, st)));
     }
@@ -872,7 +901,7 @@ template <typename T> struct Ops {
     const int ncp = (m + k - 1) / k;
     // ---- forward with checkpoints (psi^(t-1), psi^t) at t = 0, k, 2k, ...
     HIPCHK((convert_copy<T, T>(npw, nb, X0, ldx, F[0], npw, st)));
-    if (np > 0) CHK(project(F[0], npw, nb, bw.pf[0], bw.fw.part));
+    if (np > 0) CHK(project(F[0], npw, nb, bw.pf[0], bw.fw));
     for (int i = 1; i <= m; ++i) {
       const int ci = (i - 1) & 1, oi = i & 1;
       if ((i - 1) % k == 0) {
@@ -940,7 +969,7 @@ template <typename T> struct Ops {
     const C* a = Bi;
     const c128* pa = bw.pbar;
     if (np > 0) {
-      CHK(project(Bi, npw, nb, bw.pbar, w.part));
+      CHK(project(Bi, npw, nb, bw.pbar, w));
       if (p->has_overlap) {
         Epi<double> eq;
         eq.out = bw.qa; eq.ldo = np;
@@ -948,7 +977,7 @@ template <typename T> struct Ops {
         Epi<T> ea;
         ea.out = static_cast<C*>(bw.a); ea.ldo = npw; ea.alpha = -1.0;
         ea.L = Bi; ea.ldl = npw; ea.bL = 1.0;
-        CHK(backproject(bw.qa, nb, ea));
+        CHK(backproject(bw.qa, nb, ea, w));
         a = static_cast<const C*>(bw.a);
         Epi<double> ep;
         ep.out = bw.pa; ep.ldo = np; ep.alpha = -1.0;
@@ -966,7 +995,7 @@ template <typename T> struct Ops {
       e.L = loca; e.ldl = npw; e.bL = si;
       e.U = Bi; e.ldu = npw; e.bU = -si * c;
       e.W = Bm1; e.ldw = npw; e.bW = 1.0;
-      CHK(backproject(bw.Dpa, nb, e));
+      CHK(backproject(bw.Dpa, nb, e, w));
       if (dD) HIPCHK(block_grad(int(p->dsize), p->dent, nb, pa, np, pm1, np, nullptr, si, dD, st));
     } else {
       HIPCHK((axpbypcz<T>(npw, nb, si, loca, npw, -si * c, Bi, npw, 1.0, Bm1, npw, Bm1, npw, st)));
@@ -1144,6 +1173,8 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   Persist l = persist_layout(persistent, d->n, d->npw, ncol, rx, nproj, dsize, p->has_overlap, d->prec);
   p->col = l.col; p->ent = l.ent; p->xline = l.xline; p->pinfo = l.pinfo; p->dent = l.dent; p->tw = l.tw; p->kin = l.kin; p->Vt = l.Vt; p->P = l.P;
   p->D = l.D; p->Q = l.Q; p->G = l.G; p->Cinv = l.Cinv;
+  p->hproj.p = l.Hproj; p->hproj.rows = nproj; p->hproj.ld = pad32(d->npw);
+  p->hback.p = l.Hback; p->hback.rows = d->npw; p->hback.ld = pad32(nproj);
 
   // host-side index maps
   std::vector<int4> col(ncol);
@@ -1303,6 +1334,25 @@ cheb_status cheb_set_projectors(cheb_plan p, const void* P, int ldp, const doubl
   const c128* Pd = static_cast<const c128*>(P);
   if (p->prec == CHEB_MIXED) HIPCHK((convert_copy<float, double>(p->npw, np, Pd, ldp, static_cast<c64*>(p->P), p->npw, st)));
   else HIPCHK((convert_copy<double, double>(p->npw, np, Pd, ldp, static_cast<c128*>(p->P), p->npw, st)));
+  if (p->prec == CHEB_MIXED) {
+    // FP16 hi/lo planes of sA P with one power-of-two scale sA taking max |P| into [0.5, 1)
+    double* cmax = reinterpret_cast<double*>(w.Hs);
+    HIPCHK(column_maxabs(p->npw, np, Pd, ldp, cmax, st));
+    std::vector<double> hmax(np);
+    HIPCHK(hipMemcpyAsync(hmax.data(), cmax, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double mx = 0.0;
+    for (double v : hmax) {
+      if (!std::isfinite(v)) return fail(p, CHEB_ERR_NONFINITE, "projectors hold NaN or Inf");
+      mx = std::max(mx, v);
+    }
+    int e = 0;
+    if (mx > 0.0) (void)std::frexp(mx, &e);
+    const double sA = std::ldexp(1.0, -e);
+    p->hproj.inv_scale = p->hback.inv_scale = std::ldexp(1.0, e);
+    HIPCHK(split_planes(Pd, ldp, p->npw, np, false, sA, const_cast<_Float16*>(p->hproj.p), p->hproj.rows, p->hproj.ld, st));
+    HIPCHK(split_planes(Pd, ldp, p->npw, np, true, sA, const_cast<_Float16*>(p->hback.p), p->hback.rows, p->hback.ld, st));
+  }
   // G = P^H P in FP64 from the caller's complex128 projectors
   Epi<double> eg;
   eg.out = p->G; eg.ldo = np;
@@ -1325,6 +1375,11 @@ cheb_status cheb_set_projectors(cheb_plan p, const void* P, int ldp, const doubl
     HIPCHK(hipStreamSynchronize(st));
     if (info[0] != 0 || info[1] != 0) return fail(p, CHEB_ERR_NOT_PD, "capacitance matrix Q^-1 + P^H P is not positive definite");
     HIPCHK(hermitian_from_lower(np, p->Cinv, np, st));
+    // C^-1 G beside C^-1: one product then gives C^-1 p_phi = C^-1 p_loc + C^-1 G D p in the filter
+    Epi<double> ec;
+    ec.out = p->Cinv + size_t(np) * np; ec.ldo = np;
+    HIPCHK((gemm<double, double, double, double>(GEMM_NN, np, np, np, p->Cinv, np, p->G, np, ec,
+                                                 gemm_pick_splits(np, np, np), w.part, st)));
   }
   HIPCHK(hipStreamSynchronize(st));
   p->have_P = true;
@@ -1502,6 +1557,12 @@ cheb_status cheb_upper_bound(cheb_plan p, int k, const void* v0, double* lambda_
     using C = typename decltype(ops)::C;
     return ops.upper_bound(k, static_cast<const C*>(v0), lambda_plus, w);
   });
+}
+
+cheb_status cheb_set_split_gemm(cheb_plan p, int on) {
+  if (!p) return CHEB_ERR_ARG;
+  p->split_gemm = on != 0;
+  return CHEB_OK;
 }
 
 cheb_status cheb_set_rr_refine(cheb_plan p, int on) {

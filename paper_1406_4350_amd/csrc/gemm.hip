@@ -4,6 +4,8 @@
 // P w, Alg. 1; the reuse trick of Sec. 5.1 leaves one of each per filter step), for the Rayleigh-Ritz
 // subspace matrices Y^H H Y, Y^H S Y and the rotation Y Z (Alg. 2), and for the small projector-space
 // products with P^H P and the capacitance inverse (Sec. 5.1).
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace chebfd {
@@ -58,9 +60,11 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, co
 #pragma unroll
       for (int v = 0; v < 4; ++v) { cr[i][j][v] = T(0); ci[i][j][v] = T(0); }
 
-  // global -> registers for one K tile (converted to the MFMA type), registers -> LDS planes
+  // global -> registers for one K tile (raw storage type, so that the loads stay in flight while the previous
+  // tile is multiplied), registers -> LDS planes converted to the MFMA type
   constexpr int RA = (BM * BK) / NT, RBn = (BN * BK) / NT;
-  T ra_r[RA], ra_i[RA], rb_r[RBn], rb_i[RBn];
+  cx<EA> va[RA];
+  cx<EB> vb[RBn];
   auto load_tile = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
@@ -72,8 +76,7 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, co
       const int gk = k0 + kk;
       cx<EA> v = {EA(0), EA(0)};
       if (gm < M && gk < kend) v = (MODE == GEMM_CN) ? A[gk + gm * lda] : A[gm + long(gk) * lda];
-      ra_r[r] = T(v.x);
-      ra_i[r] = T(v.y);
+      va[r] = v;
     }
 #pragma unroll
     for (int r = 0; r < RBn; ++r) {
@@ -83,8 +86,7 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, co
       const int gk = k0 + kk;
       cx<EB> v = {EB(0), EB(0)};
       if (gn < N && gk < kend) v = B[gk + gn * ldb];
-      rb_r[r] = T(v.x);
-      rb_i[r] = T(v.y);
+      vb[r] = v;
     }
   };
   auto store_tile = [&]() {
@@ -94,15 +96,15 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, co
       int kk, mm;
       if (MODE == GEMM_CN) { kk = idx % BK; mm = idx / BK; }
       else { mm = idx % BM; kk = idx / BM; }
-      Ar[kk][mm] = ra_r[r];
-      Ai[kk][mm] = ra_i[r];
+      Ar[kk][mm] = T(va[r].x);
+      Ai[kk][mm] = T(va[r].y);
     }
 #pragma unroll
     for (int r = 0; r < RBn; ++r) {
       const int idx = tid + r * NT;
       const int kk = idx % BK, nn = idx / BK;
-      Br[kk][nn] = rb_r[r];
-      Bi[kk][nn] = rb_i[r];
+      Br[kk][nn] = T(vb[r].x);
+      Bi[kk][nn] = T(vb[r].y);
     }
   };
 
@@ -185,6 +187,187 @@ __global__ __launch_bounds__(256) void k_reduce(int M, int N, int splits, const 
   }
 }
 
+// ---- FP16 hi/lo split GEMM ------------------------------------------------------------------------------
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int HBK = 32, HLD = HBK + 8;  // LDS rows of 40 halves (80 bytes): 16-byte aligned, rows spread over banks
+
+__device__ __forceinline__ f4 mfma_h(h8 a, h8 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+// acc += x * y with x = xh + xl, y = yh + yl, dropping xl * yl
+__device__ __forceinline__ f4 mul3(h8 xh, h8 xl, h8 yh, h8 yl, f4 acc) {
+  acc = mfma_h(xh, yh, acc);
+  acc = mfma_h(xh, yl, acc);
+  return mfma_h(xl, yh, acc);
+}
+
+// One 64 x 64 complex output tile per block of 4 waves, wave quadrants as in k_gemm. The 16x16x32 FP16 MFMA
+// takes, in lane l, row l % 16 of A and column l % 16 of B at k = 8 (l / 16) ... 8 (l / 16) + 7, and returns
+// row 4 (l / 16) + v, column l % 16 in accumulator element v.
+template <typename EB, typename EO, int MODE, int ROLE>
+__global__ __launch_bounds__(NT) void k_gemm_h(int M, int N, int K, int kchunk, const _Float16* __restrict__ Ap,
+                                               long arows, long ald, double ainv, const cx<EB>* __restrict__ B,
+                                               long ldb, const float* __restrict__ bsc, Epi<EO> epi,
+                                               c128* __restrict__ part) {
+  __shared__ __align__(16) _Float16 As[4][BM][HLD];
+  __shared__ __align__(16) _Float16 Bs[4][BN][HLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const long m0 = long(blockIdx.x) * BM, n0 = long(blockIdx.y) * BN;
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+
+  f4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) { cr[i][j] = f4{0.f, 0.f, 0.f, 0.f}; ci[i][j] = f4{0.f, 0.f, 0.f, 0.f}; }
+
+  // loader roles: 64 rows (A) / columns (B) x 4 groups of 8 k per tile, one group per thread
+  const int lrow = tid >> 2, lgrp = tid & 3;
+  const long gm = m0 + lrow, gn = n0 + lrow;
+  const float sc = gn < N ? bsc[gn] : 1.f;
+  // raw registers of one K tile (A planes as stored, B in its storage type), converted and split only when
+  // written to LDS, so that the loads of the next tile stay in flight during the MFMAs of this one
+  h8 ra[4];
+  cx<EB> vb[8];
+  auto load_tile = [&](int k0) {
+    const int kk = k0 + 8 * lgrp;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      h8 v = {};
+      if (gm < M) v = *reinterpret_cast<const h8*>(Ap + (pl * arows + gm) * ald + kk);  // K padded to 32: in bounds
+      ra[pl] = v;
+    }
+    const cx<EB>* col = B + (gn < N ? gn : 0) * ldb;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      cx<EB> v = {EB(0), EB(0)};
+      if (gn < N && kk + j < kend) v = col[kk + j];
+      vb[j] = v;
+    }
+  };
+  auto store_tile = [&]() {
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<h8*>(&As[pl][lrow][8 * lgrp]) = ra[pl];
+    h8 rh, rl, ih, il;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float xr = float(vb[j].x * EB(sc)), xi = float(vb[j].y * EB(sc));
+      const _Float16 hr = _Float16(xr), hi = _Float16(xi);
+      rh[j] = hr;
+      ih[j] = hi;
+      rl[j] = _Float16(xr - float(hr));
+      il[j] = _Float16(xi - float(hi));
+    }
+    *reinterpret_cast<h8*>(&Bs[0][lrow][8 * lgrp]) = rh;
+    *reinterpret_cast<h8*>(&Bs[1][lrow][8 * lgrp]) = rl;
+    *reinterpret_cast<h8*>(&Bs[2][lrow][8 * lgrp]) = ih;
+    *reinterpret_cast<h8*>(&Bs[3][lrow][8 * lgrp]) = il;
+  };
+
+  if (kbeg < kend) {
+    load_tile(kbeg);
+    store_tile();
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += HBK) {
+    const bool more = k0 + HBK < kend;
+    if (more) load_tile(k0 + HBK);  // in flight while this tile is multiplied
+    h8 a[2][4], b[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) {
+        a[i][pl] = *reinterpret_cast<const h8*>(&As[pl][wm + 16 * i + li][8 * lk]);
+        b[i][pl] = *reinterpret_cast<const h8*>(&Bs[pl][wn + 16 * i + li][8 * lk]);
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const h8 nih = -a[i][2], nil = -a[i][3];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        cr[i][j] = mul3(a[i][0], a[i][1], b[j][0], b[j][1], cr[i][j]);
+        ci[i][j] = mul3(a[i][0], a[i][1], b[j][2], b[j][3], ci[i][j]);
+        if (MODE == GEMM_CN) {  // conj(a) b: re += ar br + ai bi, im += ar bi - ai br
+          cr[i][j] = mul3(a[i][2], a[i][3], b[j][2], b[j][3], cr[i][j]);
+          ci[i][j] = mul3(nih, nil, b[j][0], b[j][1], ci[i][j]);
+        } else {  // a b: re += ar br - ai bi, im += ar bi + ai br
+          cr[i][j] = mul3(nih, nil, b[j][2], b[j][3], cr[i][j]);
+          ci[i][j] = mul3(a[i][2], a[i][3], b[j][0], b[j][1], ci[i][j]);
+        }
+      }
+    }
+    __syncthreads();
+    if (more) {
+      store_tile();
+      __syncthreads();
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const long n = n0 + wn + 16 * j + li;
+      const double f = n < N ? ainv / double(bsc[n]) : 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const long m = m0 + wm + 16 * i + 4 * lk + v;
+        if (m < M && n < N) {
+          const double re = f * double(cr[i][j][v]), im = f * double(ci[i][j][v]);
+          if (part) part[(long(blockIdx.z) * N + n) * M + m] = c128{re, im};
+          else epi_store(epi, m, n, re, im);
+        }
+      }
+    }
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_colscale(long rows, const cx<E>* __restrict__ B, long ldb, float* bsc,
+                                                  double* maxout) {
+  __shared__ double red[256];
+  const cx<E>* col = B + long(blockIdx.x) * ldb;
+  double mx = 0.0;
+  for (long i = threadIdx.x; i < rows; i += blockDim.x) {
+    const cx<E> v = col[i];
+    mx = fmax(mx, fmax(fabs(double(v.x)), fabs(double(v.y))));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    mx = red[0];
+    if (maxout) maxout[blockIdx.x] = mx;
+    if (bsc) {
+      int e = 0;
+      const bool ok = mx > 0.0 && mx < 1e300;
+      if (ok) (void)frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)
+      bsc[blockIdx.x] = ok ? ldexpf(1.f, -e) : 1.f;
+    }
+  }
+}
+
+__global__ void k_split_planes(const c128* __restrict__ X, long ldx, int ksrc, bool transpose, double scale,
+                               _Float16* __restrict__ P, long prow, long pld) {
+  const long total = prow * pld;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long r = t / pld, k = t - r * pld;
+    c128 v = {0.0, 0.0};
+    if (k < ksrc) v = transpose ? X[r + k * ldx] : X[k + r * ldx];
+    const double xr = v.x * scale, xi = v.y * scale;
+    const _Float16 hr = _Float16(float(xr)), hi = _Float16(float(xi));
+    P[t] = hr;
+    P[total + t] = _Float16(float(xr - double(float(hr))));
+    P[2 * total + t] = hi;
+    P[3 * total + t] = _Float16(float(xi - double(float(hi))));
+  }
+}
+
 }  // namespace
 
 int gemm_pick_splits(int M, int N, int K) {
@@ -233,6 +416,83 @@ hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, c
   return hipGetLastError();
 }
 
+int gemm_h_pick_splits(int M, int N, int K) {
+  if (M <= 0 || N <= 0 || K <= 0) return 1;
+  const long tiles = long((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  long s = (512 + tiles - 1) / tiles;
+  const long kblocks = (K + HBK - 1) / HBK;
+  if (s > kblocks / 2) s = kblocks / 2;
+  if (s > 32) s = 32;
+  if (s < 1) s = 1;
+  return int(s);
+}
+
+template <typename EB, typename EO>
+hipError_t gemm_h(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const cx<EB>* B, long ldb,
+                  const float* bscale, const Epi<EO>& epi, int splits, c128* part, hipStream_t st, GemmRole role) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (!A.p || A.rows < M || A.ld % HBK || A.ld < ((K + HBK - 1) / HBK) * HBK) return hipErrorInvalidValue;
+  if (splits < 1) splits = 1;
+  int kchunk = (K + splits - 1) / splits;
+  kchunk = ((kchunk + HBK - 1) / HBK) * HBK;
+  if (kchunk < HBK) kchunk = HBK;
+  splits = K > 0 ? (K + kchunk - 1) / kchunk : 1;
+  const bool use_part = splits > 1;
+  if (use_part && !part) return hipErrorInvalidValue;
+  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, splits);
+  c128* pp = use_part ? part : nullptr;
+  auto launch = [&](auto modec, auto rolec) {
+    constexpr int MO = decltype(modec)::value, RO = decltype(rolec)::value;
+    hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows, A.ld,
+                       A.inv_scale, B, ldb, bscale, epi, pp);
+  };
+  using CN = std::integral_constant<int, GEMM_CN>;
+  using NNm = std::integral_constant<int, GEMM_NN>;
+  if (role == ROLE_BACKPROJECT) mode == GEMM_CN ? launch(CN{}, std::integral_constant<int, 2>{}) : launch(NNm{}, std::integral_constant<int, 2>{});
+  else mode == GEMM_CN ? launch(CN{}, std::integral_constant<int, 1>{}) : launch(NNm{}, std::integral_constant<int, 1>{});
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !use_part) return e;
+  const long total = long(M) * N;
+  int blocks = int((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((k_reduce<EO>), dim3(blocks), dim3(256), 0, st, M, N, splits, part, epi);
+  return hipGetLastError();
+}
+
+template <typename E>
+hipError_t column_scales(long rows, int ncols, const cx<E>* B, long ldb, float* bscale, hipStream_t st) {
+  if (ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_colscale<E>), dim3(ncols), dim3(256), 0, st, rows, B, ldb, bscale, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t column_maxabs(long rows, int ncols, const c128* X, long ldx, double* out, hipStream_t st) {
+  if (ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_colscale<double>), dim3(ncols), dim3(256), 0, st, rows, X, ldx, nullptr, out);
+  return hipGetLastError();
+}
+
+hipError_t split_planes(const c128* X, long ldx, int rows_x, int cols_x, bool transpose, double scale,
+                        _Float16* planes, long prow, long pld, hipStream_t st) {
+  const int ksrc = transpose ? cols_x : rows_x;
+  if (prow != (transpose ? rows_x : cols_x) || pld < ksrc) return hipErrorInvalidValue;
+  const long total = prow * pld;
+  if (total <= 0) return hipSuccess;
+  const long blocks = std::min<long>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_split_planes, dim3(unsigned(blocks)), dim3(256), 0, st, X, ldx, ksrc, transpose, scale, planes,
+                     prow, pld);
+  return hipGetLastError();
+}
+
+template hipError_t gemm_h<float, float>(GemmMode, int, int, int, const HalfPlanes&, const c64*, long, const float*,
+                                         const Epi<float>&, int, c128*, hipStream_t, GemmRole);
+template hipError_t gemm_h<float, double>(GemmMode, int, int, int, const HalfPlanes&, const c64*, long, const float*,
+                                          const Epi<double>&, int, c128*, hipStream_t, GemmRole);
+template hipError_t gemm_h<double, float>(GemmMode, int, int, int, const HalfPlanes&, const c128*, long,
+                                          const float*, const Epi<float>&, int, c128*, hipStream_t, GemmRole);
+template hipError_t column_scales<float>(long, int, const c64*, long, float*, hipStream_t);
+template hipError_t column_scales<double>(long, int, const c128*, long, float*, hipStream_t);
+
 #define INST(T, EA, EB, EO)                                                                               \
   template hipError_t gemm<T, EA, EB, EO>(GemmMode, int, int, int, const cx<EA>*, long, const cx<EB>*, long, \
                                           const Epi<EO>&, int, c128*, hipStream_t, GemmRole);
@@ -240,6 +500,7 @@ INST(double, double, double, double)
 INST(float, float, float, float)
 INST(float, float, double, float)
 INST(float, float, float, double)
+INST(double, float, float, double)
 #undef INST
 
 }  // namespace chebfd

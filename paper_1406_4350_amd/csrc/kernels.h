@@ -32,6 +32,34 @@ hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, c
 // number of K splits the launcher would like for an (M, N, K) product on 256 CUs
 int gemm_pick_splits(int M, int N, int K);
 
+// ---- FP16 hi/lo split complex GEMM (FP32 accumulation) ---------------------------------------------------
+// A is held as four FP16 planes (Re hi, Re lo, Im hi, Im lo) of sA * A, each row m holding its K values
+// contiguously (row stride ld halves, a multiple of 8; K padded with zeros to a multiple of 32). sA is a power of
+// two chosen so that max |sA A| is in [0.5, 1): hi = fp16(sA a), lo = fp16(sA a - hi), so hi + lo carries
+// about 22 significant bits (absolute error <= 2^-25 max |sA A|).
+struct HalfPlanes {
+  const _Float16* p = nullptr;  // [4][rows][ld]: Re hi, Re lo, Im hi, Im lo
+  long rows = 0, ld = 0;
+  double inv_scale = 1.0;  // 1 / sA
+};
+// out (M x N) = op(A) B with op(A)[m][k] = A[m][k] (GEMM_NN) or conj(A[m][k]) (GEMM_CN, A = the conjugate-
+// transposed operand stored row m = output row). B (K x N, column-major, ldb) is split on the fly after
+// scaling column n by bscale[n] (a power of two, see column_scales); each product is hi*hi + hi*lo + lo*hi on
+// the 16x16x32 FP16 MFMA. Splits and epilogue as for gemm().
+template <typename EB, typename EO>
+hipError_t gemm_h(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const cx<EB>* B, long ldb,
+                  const float* bscale, const Epi<EO>& epi, int splits, c128* part, hipStream_t st, GemmRole role);
+int gemm_h_pick_splits(int M, int N, int K);
+// bscale[n] = 2^-e with max_k |B[k][n]| (over Re and Im) in [2^(e-1), 2^e); 1 for a zero column
+template <typename E> hipError_t column_scales(long rows, int ncols, const cx<E>* B, long ldb, float* bscale,
+                                               hipStream_t st);
+// per-column max |Re|, |Im| of a complex128 matrix (FP64), for the global scale of the split planes
+hipError_t column_maxabs(long rows, int ncols, const c128* X, long ldx, double* out, hipStream_t st);
+// planes of sA * X for a complex128 X (rows_x x cols_x, ld ldx). transpose = false: plane row r = column r of X
+// (k runs down X's column); transpose = true: plane row r = row r of X (k runs along X's row).
+hipError_t split_planes(const c128* X, long ldx, int rows_x, int cols_x, bool transpose, double scale,
+                        _Float16* planes, long prow, long pld, hipStream_t st);
+
 // ---- FFT passes (per batch of bands) -------------------------------------------------------------------
 struct FftGeom {
   int n, ncol, npw, rx;

@@ -90,13 +90,28 @@ def test_outer_loop_trajectory(case):
         assert np.all(np.abs(hg["ritz"] - ho["ritz"]) <= 1e-10 * np.maximum(np.abs(ho["ritz"]), 1.0))
 
 
-def test_mixed_operators(case):
+@pytest.mark.parametrize("split", [True, False], ids=["fp16x2-split", "fp32-mfma"])
+def test_mixed_operators(case, split):
+    """Mixed plans with the projector GEMMs on the FP16 hi/lo split MFMA (default) or the FP32 MFMA: both
+    hold FP32-level accuracy, per band as well as over the block."""
     pb, ops, _ = case
     plan = cf.plan_from_problem(pb, cf.CHEB_MIXED)
+    plan.set_split_gemm(split)
     X = pb.X0
     Xd = cf.to_device_block(X, torch.complex64)
-    assert _rel(cf.to_host_block(plan.apply_H(Xd)), ops.apply_H(X)) < 2e-5
-    assert _rel(cf.to_host_block(plan.apply_Sinv(Xd)), ops.apply_Sinv(X)) < 2e-5
+    for got, ref in ((plan.apply_H(Xd), ops.apply_H(X)), (plan.apply_Sinv(Xd), ops.apply_Sinv(X)),
+                     (plan.apply_S(Xd), ops.apply_S(X))):
+        got = cf.to_host_block(got)
+        assert _rel(got, ref) < 2e-5
+        colerr = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        assert colerr.max() < 4e-5
+    # scaled bands: the per-band power-of-two scaling keeps huge and tiny columns as accurate
+    scale = np.logspace(-6, 6, X.shape[1])
+    Xs = X * scale[None, :]
+    got = cf.to_host_block(plan.apply_Sinv(cf.to_device_block(Xs, torch.complex64)))
+    ref = ops.apply_Sinv(Xs)
+    colerr = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert colerr.max() < 4e-5
 
 
 def test_rr_refinement_and_library_paths_agree(case):
