@@ -236,3 +236,41 @@ def locking_degrees(resid, ritz, c: float, r: float, m_max: int, tol: float):
                 deg[i] = n
                 break
     return deg
+
+
+# --- capacitance solve by preconditioned iterative refinement (Sec. 5.1) -------------------------------------
+def atom_blocks(proj_off):
+    """(start, size) of each atom's projector block, from the offsets proj_off[0..natom]."""
+    off = np.asarray(proj_off, dtype=np.int64)
+    return [(int(off[a]), int(off[a + 1] - off[a])) for a in range(off.shape[0] - 1) if off[a + 1] > off[a]]
+
+
+def block_preconditioner(C, blocks):
+    """M^-1 for M = the atom-block diagonal of C (the preconditioner of Sec. 5.1), as a dense matrix."""
+    Minv = np.zeros_like(C)
+    for s, n in blocks:
+        Minv[s:s + n, s:s + n] = np.linalg.inv(C[s:s + n, s:s + n])
+    return Minv
+
+
+def capacitance_refine(C, blocks, b, iters=None, tol=1e-15, maxit=200):
+    """Solve C q = b by iterative refinement preconditioned by the atom-block diagonal M of C (Sec. 5.1):
+    q_0 = M^-1 b; r_k = b - C q_k; q_(k+1) = q_k + M^-1 r_k. With iters given, exactly that many corrections;
+    otherwise corrections until every column has ||r_k|| <= tol ||b||. Returns (q, corrections, residual
+    history: max over columns of ||r_k|| / ||b||)."""
+    b = np.asarray(b, dtype=np.complex128)
+    b2 = b.reshape(b.shape[0], -1)
+    Minv = block_preconditioner(C, blocks)
+    q = Minv @ b2
+    bn = np.maximum(np.linalg.norm(b2, axis=0), 1e-300)
+    hist = []
+    k = 0
+    while True:
+        r = b2 - C @ q
+        rel = float(np.max(np.linalg.norm(r, axis=0) / bn))
+        hist.append(rel)
+        if (iters is not None and k >= iters) or (iters is None and (rel <= tol or k >= maxit)):
+            break
+        q = q + Minv @ r
+        k += 1
+    return q.reshape(b.shape), k, np.array(hist)

@@ -324,3 +324,39 @@ def test_locking_outer_loop(mid_run):
     work = sum(int(h["degrees"].sum()) for h in hist)
     assert work < 0.8 * pb.cfg.nb * pb.cfg.m * len(hist)
     assert any((h["degrees"] == 0).any() for h in hist)  # some bands were locked
+
+
+# ---- capacitance solve by preconditioned iterative refinement (Sec. 5.1) ---------------------------------------
+@pytest.fixture(scope="module")
+def cap_mid():
+    pb = wl.make_problem("mid_paw")
+    C = np.diag(1.0 / pb.Q).astype(complex) + pb.P.conj().T @ pb.P
+    return pb, C, matfree.atom_blocks(pb.proj_off)
+
+
+def test_capacitance_refinement_converges_to_direct_solve(cap_mid):
+    pb, C, blocks = cap_mid
+    b = np.random.default_rng(3).normal(size=(pb.nproj, 5)) + 1j * np.random.default_rng(4).normal(size=(pb.nproj, 5))
+    q, k, hist = matfree.capacitance_refine(C, blocks, b)
+    direct = scipy.linalg.cho_solve(scipy.linalg.cho_factor(C), b)
+    assert np.linalg.norm(q - direct) <= 1e-13 * np.linalg.norm(direct)
+    assert 1 <= k <= 60 and hist[-1] <= 1e-15
+
+
+def test_capacitance_refinement_contraction(cap_mid):
+    """The error shrinks by the spectral radius of I - M^-1 C per correction (the iteration's algebra: a wrong
+    sign in the update diverges), and an exactly block-diagonal C is solved by the preconditioner alone."""
+    pb, C, blocks = cap_mid
+    Minv = matfree.block_preconditioner(C, blocks)
+    rho = np.max(np.abs(np.linalg.eigvals(np.eye(pb.nproj) - Minv @ C)))
+    assert 0 < rho < 1
+    b = np.random.default_rng(5).normal(size=pb.nproj) + 0j
+    exact = np.linalg.solve(C, b)
+    errs = [np.linalg.norm(matfree.capacitance_refine(C, blocks, b, iters=k)[0] - exact) for k in range(0, 9)]
+    ratios = np.array(errs[5:]) / np.array(errs[4:-1])
+    assert np.all(ratios <= rho * 1.05) and np.all(ratios >= 0.2 * rho)
+    Cb = np.zeros_like(C)
+    for s, n in blocks:
+        Cb[s:s + n, s:s + n] = C[s:s + n, s:s + n]
+    q, k, hist = matfree.capacitance_refine(Cb, blocks, b)
+    assert k == 0 and np.allclose(q, np.linalg.solve(Cb, b), atol=1e-14 * np.linalg.norm(q))
