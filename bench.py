@@ -293,6 +293,32 @@ def locking_report(cf, pb, lam_plus, tol, iters):
     return out
 
 
+def capacitance_report(cf, pb, lam_plus, iters):
+    """FP64 filter with the capacitance solve applied directly and by `iters` corrections of the
+    block-preconditioned iterative refinement of Sec. 5.1; relative difference of S^-1 X between the two."""
+    import torch
+
+    if pb.Q is None:
+        return None
+    plan = cf.plan_from_problem(pb, cf.CHEB_FP64)
+    X = cf.to_device_block(pb.X0, torch.complex128)
+    m, nb = pb.cfg.m, pb.cfg.nb
+    lm = float(plan.rayleigh_quotients(X).max().item())
+    c, r = 0.5 * (lam_plus + lm), 0.5 * (lam_plus - lm)
+    out = {"corrections": iters}
+    direct = plan.apply_Sinv(X).clone()
+    out["direct_filter_apps_per_s"] = nb * m / (time_filter(plan, X, m, c, r, 5) * 1e-3)
+    plan.set_capacitance_solver(iters)
+    refined = plan.apply_Sinv(X)
+    out["iterative_filter_apps_per_s"] = nb * m / (time_filter(plan, X, m, c, r, 5) * 1e-3)
+    out["sinv_rel_diff"] = float(torch.linalg.norm(refined - direct) / torch.linalg.norm(direct))
+    plan.set_capacitance_solver(0)
+    plan.close()
+    log(f"[bench] capacitance: direct {out['direct_filter_apps_per_s']:.4g}/s, {iters} corrections "
+        f"{out['iterative_filter_apps_per_s']:.4g}/s, S^-1 difference {out['sinv_rel_diff']:.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +334,8 @@ def main():
     ap.add_argument("--lock-tol", type=float, default=1e-8,
                     help="residual tolerance of the locking comparison (0: skip it)")
     ap.add_argument("--lock-iters", type=int, default=40)
+    ap.add_argument("--cap-iters", type=int, default=20,
+                    help="corrections of the iterative capacitance solve to compare with the direct one (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (for scaling HBM "
                          "byte counters) and exit")
@@ -383,6 +411,8 @@ def main():
         }
     if args.lock_tol > 0:
         out["locking"] = locking_report(cf, pb, lam_plus, args.lock_tol, args.lock_iters)
+    if args.cap_iters > 0:
+        out["capacitance_solve"] = capacitance_report(cf, pb, lam_plus, args.cap_iters)
     if args.backward:
         out["differentiation"] = time_backward(cf, pb, lam_plus)
     if not args.no_cpu:

@@ -152,6 +152,14 @@ cheb_status cheb_locking_degrees(int nb, const double* ritz, const double* resid
 cheb_status cheb_rayleigh_ritz(cheb_plan plan, void* X, int ldx, int nb, double* ritz_dev, double* resid_dev,
                                void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Capacitance solve q = C^-1 b, C = Q^-1 + P^H P, inside cheb_apply_Sinv, cheb_filter(_degrees), the Lanczos
+ * bound and the adjoint (Sec. 5.1). iterations = 0 (default): the inverse formed at cheb_set_projectors is
+ * applied directly. iterations = k > 0: iterative refinement preconditioned by the atom-block diagonal M of C,
+ * q = M^-1 b then k corrections q += M^-1 (b - C q) (error shrinks by the spectral radius of I - M^-1 C per
+ * correction). Needs the projectors set and atom blocks of at most 32 projectors; the plan must have an
+ * overlap (S != I). Changes the workspace sizes: query cheb_workspace_bytes after switching. */
+cheb_status cheb_set_capacitance_solver(cheb_plan plan, int iterations);
+
 /* Mixed plans only (no effect on FP64 plans): the projector products P^H x and P w of the filter and the
  * operators use the FP16 hi/lo split MFMA (on = 1, the default: each operand is a sum of two FP16 numbers,
  * about 22 significant bits, products hi*hi + hi*lo + lo*hi accumulated in FP32) or the FP32 MFMA (on = 0).

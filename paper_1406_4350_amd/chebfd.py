@@ -31,7 +31,7 @@ SYMBOLS = ["cheb_plan_persistent_bytes", "cheb_plan_create", "cheb_plan_destroy"
            "cheb_apply_Sinv", "cheb_filter", "cheb_rayleigh_ritz", "cheb_rayleigh_quotients", "cheb_upper_bound",
            "cheb_profile_enable", "cheb_profile_read", "cheb_backward_workspace_bytes", "cheb_filter_rr_backward",
            "cheb_set_rr_refine", "cheb_rr_stats", "cheb_filter_degrees", "cheb_locking_degrees", "cheb_set_split_gemm",
-           "cheb_last_error"]
+           "cheb_set_capacitance_solver", "cheb_last_error"]
 TIMERS = ["fft_col_inverse", "fft_plane", "fft_col_forward", "project", "backproject", "small", "rr_gram", "rr_eig",
           "rr_rotate", "xdens"]
 
@@ -85,6 +85,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cheb_rr_stats": [vp, P(ctypes.c_int64), P(ctypes.c_int64)],
         "cheb_filter_degrees": [vp, vp, i, i, vp, d, d, vp, sz, vp],
         "cheb_set_split_gemm": [vp, i],
+        "cheb_set_capacitance_solver": [vp, i],
         "cheb_locking_degrees": [i, vp, vp, d, d, i, d, vp, P(i)],
     }
     for name, args in sig.items():
@@ -160,12 +161,18 @@ class Plan:
             raise ChebError(st, where, msg)
 
     def workspace(self, op: int, nb: int) -> torch.Tensor:
+        """Cached workspace for (op, nb); cheb_workspace_bytes is asked every time, since plan settings (the
+        capacitance solver) change the size."""
         key = (op, nb)
-        if key not in self._ws:
-            nbytes = ctypes.c_size_t()
-            self._check(self.lib.cheb_workspace_bytes(self.handle, op, nb, ctypes.byref(nbytes)), "cheb_workspace_bytes")
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.cheb_workspace_bytes(self.handle, op, nb, ctypes.byref(nbytes)), "cheb_workspace_bytes")
+        if key not in self._ws or self._ws[key].numel() < nbytes.value:
             self._ws[key] = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
         return self._ws[key]
+
+    def set_capacitance_solver(self, iterations: int):
+        """0: apply C^-1 directly (default); k > 0: k corrections of block-preconditioned iterative refinement."""
+        self._check(self.lib.cheb_set_capacitance_solver(self.handle, int(iterations)), "cheb_set_capacitance_solver")
 
     def _block(self, X: torch.Tensor, name: str) -> tuple[int, int]:
         if X.dtype != self.dtype or X.device.type != "cuda" or X.dim() != 2 or X.shape[1] != self.npw:

@@ -36,7 +36,11 @@ struct cheb_plan_s {
   double* D = nullptr;
   double* Q = nullptr;
   c128* G = nullptr;
-  c128* Cinv = nullptr;
+  c128* Cinv = nullptr;  // [C^-1 | C^-1 G], C = Q^-1 + P^H P
+  c128* Cmat = nullptr;  // C itself and the inverses of its atom blocks, for the iterative solve
+  c128* Minv = nullptr;
+  int cap_iters = 0;     // 0: C^-1 applied directly; k > 0: k preconditioned refinement corrections
+  bool cap_blocks_ok = false;  // atom blocks inverted (all of size <= 32)
   bool have_V = false, have_P = false, have_D = false;
   int fft_batch = 1;
   HalfPlanes hproj, hback;                  // mixed plans: split planes of P (set with the projectors)
@@ -135,7 +139,7 @@ struct Timed {
 
 // ---- layouts -------------------------------------------------------------------------------------------------
 struct Persist {
-  int4* col; int* ent; int4* xline; int4* pinfo; int2* dent; void* tw; void* kin; void* Vt; void* P; double* D; double* Q; c128* G; c128* Cinv;
+  int4* col; int* ent; int4* xline; int4* pinfo; int2* dent; void* tw; void* kin; void* Vt; void* P; double* D; double* Q; c128* G; c128* Cinv; c128* Cmat; c128* Minv;
   _Float16* Hproj;  // mixed plans: FP16 hi/lo planes of P for P^H x (rows = projectors, k = plane waves)
   _Float16* Hback;  // and for P w (rows = plane waves, k = projectors)
   size_t bytes;
@@ -161,6 +165,8 @@ Persist persist_layout(void* base, int n, int npw, int ncol, int rx, int nproj, 
   l.Q = b.take<double>(std::max(nproj, 1));
   l.G = b.take<c128>(size_t(nproj) * nproj);
   l.Cinv = overlap ? b.take<c128>(2 * size_t(nproj) * nproj) : nullptr;  // [C^-1 | C^-1 G]
+  l.Cmat = overlap ? b.take<c128>(size_t(nproj) * nproj) : nullptr;
+  l.Minv = overlap ? b.take<c128>(std::max<size_t>(dsize, 1)) : nullptr;
   l.Hproj = l.Hback = nullptr;
   if (mixed && nproj > 0) {
     l.Hproj = b.take<_Float16>(4 * size_t(nproj) * pad32(npw));
@@ -195,6 +201,7 @@ struct Ws {
   double *absF = nullptr, *lam = nullptr, *res = nullptr;
   int* perm = nullptr;
   float* bsc = nullptr;  // per-band power-of-two scales of the split GEMMs
+  c128 *cp = nullptr, *cq = nullptr, *cr = nullptr;  // iterative capacitance solve: right side, solution, residual
   void* Xs = nullptr;   // band-sorted copy for the per-band degree filter
   int* lidx = nullptr;  // its gather / scatter indices (3 nb)
   void* solver = nullptr;
@@ -312,6 +319,11 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
   }
   w->part = b.take<c128>(std::max<size_t>(part, 1));
   w->bsc = b.take<float>(std::max(nb, 1));
+  if (p->has_overlap && p->cap_iters > 0 && op != CHEB_OP_SETUP && op != CHEB_OP_RR) {
+    w->cp = b.take<c128>(pp);
+    w->cq = b.take<c128>(pp);
+    w->cr = b.take<c128>(pp);
+  }
   w->total = b.off;
   return CHEB_OK;
 }
@@ -516,6 +528,28 @@ template <typename T> struct Ops {
     return small(M, p->nproj, p->nproj, x, p->nproj, nb, e, part);
   }
 
+  // out = C^-1 b, C = Q^-1 + P^H P (Sec. 5.1): directly with the stored inverse, or by cap_iters corrections of
+  // iterative refinement preconditioned by the atom-block diagonal M of C: q = M^-1 b, then r = b - C q,
+  // q += M^-1 r. b and out must not overlap.
+  cheb_status cinv(const c128* b, long ldb, int nb, c128* out, long ldo, const Ws& w) {
+    const int np = p->nproj;
+    if (p->cap_iters <= 0) {
+      Epi<double> e;
+      e.out = out; e.ldo = ldo;
+      return small(p->Cinv, np, np, b, ldb, nb, e, w.part);
+    }
+    if (!w.cr) return fail(p, CHEB_ERR_STATE, "workspace laid out for the direct capacitance solve");
+    HIPCHK(block_diag_apply_c(np, nb, p->pinfo, p->Minv, b, ldb, out, ldo, false, st));
+    for (int k = 0; k < p->cap_iters; ++k) {
+      Epi<double> e;
+      e.out = w.cr; e.ldo = np; e.alpha = -1.0;
+      e.L = b; e.ldl = ldb; e.bL = 1.0;
+      CHK(small(p->Cmat, np, np, out, ldo, nb, e, w.part));
+      HIPCHK(block_diag_apply_c(np, nb, p->pinfo, p->Minv, w.cr, np, out, ldo, true, st));
+    }
+    return CHEB_OK;
+  }
+
   cheb_status apply_H(const C* X, long ldx, C* Y, long ldy, int nb, const Ws& w) {
     CHK(hloc(X, ldx, nb, Y, ldy, w.fft));
     if (p->nproj == 0) return CHEB_OK;
@@ -546,9 +580,7 @@ template <typename T> struct Ops {
       return CHEB_OK;
     }
     CHK(project(X, ldx, nb, w.p0, w));
-    Epi<double> es;
-    es.out = w.Dp; es.ldo = p->nproj;
-    CHK(small(p->Cinv, w.p0, nb, es, w.part));
+    CHK(cinv(w.p0, p->nproj, nb, w.Dp, p->nproj, w));
     Epi<T> e;
     e.out = Y; e.ldo = ldy; e.alpha = -1.0;
     e.L = X; e.ldl = ldx; e.bL = 1.0;
@@ -581,7 +613,16 @@ template <typename T> struct Ops {
     HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, pcur, np, dp, l2, st));
     const c128* wv = dp;
     long ldw = l2;
-    if (p->has_overlap) {
+    if (p->has_overlap && p->cap_iters > 0) {
+      // iterative capacitance solve: p_phi, q = C^-1 p_phi by refinement, w = D p - q
+      Epi<double> e1;
+      e1.out = w.cp; e1.ldo = np; e1.L = pl; e1.ldl = l2; e1.bL = 1.0;
+      CHK(small(p->G, np, np, dp, l2, nb, e1, w.part));
+      CHK(cinv(w.cp, np, nb, w.cq, np, w));
+      HIPCHK((axpbypcz<double>(np, nb, 1.0, dp, l2, -1.0, w.cq, np, 0.0, nullptr, 0, w.w, np, st)));
+      wv = w.w;
+      ldw = np;
+    } else if (p->has_overlap) {
       Epi<double> e2;
       e2.out = w.w; e2.ldo = np; e2.alpha = -1.0;
       e2.L = dp; e2.ldl = l2; e2.bL = 1.0;
@@ -971,9 +1012,7 @@ template <typename T> struct Ops {
     if (np > 0) {
       CHK(project(Bi, npw, nb, bw.pbar, w));
       if (p->has_overlap) {
-        Epi<double> eq;
-        eq.out = bw.qa; eq.ldo = np;
-        CHK(small(p->Cinv, bw.pbar, nb, eq, w.part));
+        CHK(cinv(bw.pbar, np, nb, bw.qa, np, w));
         Epi<T> ea;
         ea.out = static_cast<C*>(bw.a); ea.ldo = npw; ea.alpha = -1.0;
         ea.L = Bi; ea.ldl = npw; ea.bL = 1.0;
@@ -1172,7 +1211,7 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   p->proj_off.assign(d->proj_off_host, d->proj_off_host + (d->natom > 0 ? d->natom + 1 : 0));
   Persist l = persist_layout(persistent, d->n, d->npw, ncol, rx, nproj, dsize, p->has_overlap, d->prec);
   p->col = l.col; p->ent = l.ent; p->xline = l.xline; p->pinfo = l.pinfo; p->dent = l.dent; p->tw = l.tw; p->kin = l.kin; p->Vt = l.Vt; p->P = l.P;
-  p->D = l.D; p->Q = l.Q; p->G = l.G; p->Cinv = l.Cinv;
+  p->D = l.D; p->Q = l.Q; p->G = l.G; p->Cinv = l.Cinv; p->Cmat = l.Cmat; p->Minv = l.Minv;
   p->hproj.p = l.Hproj; p->hproj.rows = nproj; p->hproj.ld = pad32(d->npw);
   p->hback.p = l.Hback; p->hback.rows = d->npw; p->hback.ld = pad32(nproj);
 
@@ -1361,7 +1400,9 @@ cheb_status cheb_set_projectors(cheb_plan p, const void* P, int ldp, const doubl
   if (p->has_overlap) {
     HIPCHK(hipMemcpyAsync(p->Q, Q, sizeof(double) * np, hipMemcpyDeviceToDevice, st));
     HIPCHK(capacitance(np, p->G, p->Q, p->Cinv, st));
+    HIPCHK((convert_copy<double, double>(np, np, p->Cinv, np, p->Cmat, np, st)));
     HIPCHK((fill_zero<float>(reinterpret_cast<c64*>(w.flags), 2, st)));
+    HIPCHK(block_inverse(np, p->pinfo, p->Cmat, np, p->Minv, w.flags + 2, st));
     RBCHK(rocblas_set_stream(p->rb, st));
     RBCHK(rocblas_set_workspace(p->rb, w.solver, w.solver_bytes));
     rocblas_double_complex* C = reinterpret_cast<rocblas_double_complex*>(p->Cinv);
@@ -1370,10 +1411,11 @@ cheb_status cheb_set_projectors(cheb_plan p, const void* P, int ldp, const doubl
                                                      : r1;
     rocblas_set_workspace(p->rb, nullptr, 0);
     if (r2 != rocblas_status_success) return fail(p, CHEB_ERR_HIP, std::string("rocsolver potrf/potri: ") + rocblas_status_to_string(r2));
-    int info[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(info, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    int info[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(info, w.flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (info[0] != 0 || info[1] != 0) return fail(p, CHEB_ERR_NOT_PD, "capacitance matrix Q^-1 + P^H P is not positive definite");
+    p->cap_blocks_ok = info[2] == 0;
     HIPCHK(hermitian_from_lower(np, p->Cinv, np, st));
     // C^-1 G beside C^-1: one product then gives C^-1 p_phi = C^-1 p_loc + C^-1 G D p in the filter
     Epi<double> ec;
@@ -1557,6 +1599,17 @@ cheb_status cheb_upper_bound(cheb_plan p, int k, const void* v0, double* lambda_
     using C = typename decltype(ops)::C;
     return ops.upper_bound(k, static_cast<const C*>(v0), lambda_plus, w);
   });
+}
+
+cheb_status cheb_set_capacitance_solver(cheb_plan p, int iterations) {
+  if (!p) return CHEB_ERR_ARG;
+  if (iterations < 0 || iterations > 1000) return fail(p, CHEB_ERR_ARG, "iterations must be in [0, 1000]");
+  if (iterations > 0 && !p->has_overlap) return fail(p, CHEB_ERR_ARG, "the plan has S = I: no capacitance matrix");
+  if (iterations > 0 && p->nproj > 0 && !p->have_P) return fail(p, CHEB_ERR_STATE, "projectors not set");
+  if (iterations > 0 && p->nproj > 0 && !p->cap_blocks_ok)
+    return fail(p, CHEB_ERR_ARG, "atom blocks larger than 32 projectors: no block preconditioner");
+  p->cap_iters = iterations;
+  return CHEB_OK;
 }
 
 cheb_status cheb_set_split_gemm(cheb_plan p, int on) {

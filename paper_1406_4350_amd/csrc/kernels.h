@@ -92,6 +92,12 @@ size_t fft_plane_lds_bytes(int n, int rx, bool dbl);
 hipError_t block_diag_apply(int nproj, int nb, const int4* pinfo, const double* D, const c128* in, long ldi,
                             c128* out, long ldo, hipStream_t st);
 // out[i, b] = d[i] * in[i, b]
+// Minv (packed like D, complex) = inverses of the atom diagonal blocks of the HPD matrix C (blocks up to 32;
+// bad[0] = 1 otherwise). Preconditioner of the iterative capacitance solve (Sec. 5.1).
+hipError_t block_inverse(int nproj, const int4* pinfo, const c128* C, long ldc, c128* Minv, int* bad, hipStream_t st);
+// out = blockdiag(M) in (+ out if accumulate), complex packed blocks
+hipError_t block_diag_apply_c(int nproj, int nb, const int4* pinfo, const c128* M, const c128* in, long ldi, c128* out,
+                              long ldo, bool accumulate, hipStream_t st);
 hipError_t diag_apply(int nproj, int nb, const double* d, const c128* in, long ldi, c128* out, long ldo,
                       hipStream_t st);
 // out = a x + b y (+ c z), complex, any storage type

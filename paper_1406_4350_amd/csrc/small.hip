@@ -32,6 +32,77 @@ __global__ void k_block_diag(int nproj, int nb, const int4* __restrict__ pinfo, 
   }
 }
 
+// One block per atom (the block of its first projector): Gauss-Jordan inverse of the atom's diagonal block of
+// the Hermitian positive definite C, in LDS (block sizes up to 32), into Minv packed like D (row-major per atom).
+__global__ __launch_bounds__(256) void k_block_inverse(int nproj, const int4* __restrict__ pinfo,
+                                                       const c128* __restrict__ C, long ldc, c128* __restrict__ Minv,
+                                                       int* __restrict__ bad) {
+  __shared__ c128 a[32][33];
+  __shared__ c128 x[32][33];
+  const int i0 = blockIdx.x;
+  const int4 pi = pinfo[i0];
+  if (pi.x != i0) return;  // not the first projector of its atom
+  const int n = pi.y;
+  if (n > 32) {
+    if (threadIdx.x == 0) bad[0] = 1;
+    return;
+  }
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int r = t / n, c = t - r * n;
+    a[r][c] = C[(i0 + r) + long(i0 + c) * ldc];
+    x[r][c] = c128{r == c ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {  // no pivoting: the block of an HPD matrix is HPD
+    const c128 piv = a[k][k];
+    const double den = piv.x * piv.x + piv.y * piv.y;
+    const c128 inv = c128{piv.x / den, -piv.y / den};
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {  // scale row k
+      a[k][c] = cmul(a[k][c], inv);
+      x[k][c] = cmul(x[k][c], inv);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {  // eliminate column k from the other rows
+      const int r = t / n, c = t - r * n;
+      if (r == k) continue;
+      const c128 f = a[r][k];
+      if (c != k) a[r][c] = a[r][c] - cmul(f, a[k][c]);
+      x[r][c] = x[r][c] - cmul(f, x[k][c]);
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += blockDim.x)
+      if (r != k) a[r][k] = c128{0.0, 0.0};
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int r = t / n, c = t - r * n;
+    Minv[pi.z + t] = x[r][c];
+  }
+}
+
+// out = blockdiag(Minv) in (+ out when accumulate), complex packed blocks
+__global__ void k_block_diag_c(int nproj, int nb, const int4* __restrict__ pinfo, const c128* __restrict__ M,
+                               const c128* __restrict__ in, long ldi, c128* __restrict__ out, long ldo, int accumulate) {
+  const long total = long(nproj) * nb;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const int b = int(t / nproj), i = int(t - long(b) * nproj);
+    const int4 pi = pinfo[i];
+    const int r = i - pi.x;
+    const c128* Mrow = M + pi.z + long(r) * pi.y;
+    const c128* col = in + long(b) * ldi + pi.x;
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < pi.y; ++j) {
+      const c128 m = Mrow[j], v = col[j];
+      re += m.x * v.x - m.y * v.y;
+      im += m.x * v.y + m.y * v.x;
+    }
+    c128* o = out + long(b) * ldo + i;
+    if (accumulate) { re += o->x; im += o->y; }
+    *o = c128{re, im};
+  }
+}
+
 __global__ void k_diag(int nproj, int nb, const double* __restrict__ d, const c128* __restrict__ in, long ldi,
                        c128* __restrict__ out, long ldo) {
   const long total = long(nproj) * nb;
@@ -203,6 +274,18 @@ hipError_t block_diag_apply(int nproj, int nb, const int4* pinfo, const double* 
   return hipGetLastError();
 }
 
+hipError_t block_inverse(int nproj, const int4* pinfo, const c128* C, long ldc, c128* Minv, int* bad, hipStream_t st) {
+  if (nproj <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_inverse, dim3(nproj), dim3(256), 0, st, nproj, pinfo, C, ldc, Minv, bad);
+  return hipGetLastError();
+}
+hipError_t block_diag_apply_c(int nproj, int nb, const int4* pinfo, const c128* M, const c128* in, long ldi, c128* out,
+                              long ldo, bool accumulate, hipStream_t st) {
+  if (nproj <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_diag_c, dim3(nblocks(long(nproj) * nb)), dim3(256), 0, st, nproj, nb, pinfo, M, in, ldi,
+                     out, ldo, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
 hipError_t diag_apply(int nproj, int nb, const double* d, const c128* in, long ldi, c128* out, long ldo,
                       hipStream_t st) {
   if (nproj <= 0 || nb <= 0) return hipSuccess;

@@ -1,0 +1,106 @@
+"""Iterative capacitance solve (Sec. 5.1) on the GPU: C q = b by refinement preconditioned by the atom-block
+diagonal of C, inside S^-1, the filter and the outer loop, against the oracle's refinement with the same number
+of corrections and against the direct solve once converged.
+
+Tolerances as for the direct path: 1e-12 relative for S^-1, 1e-11 for the filter, Ritz values to
+1e-10 max(|lambda|, 1).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import matfree  # noqa: E402
+from paper_1406_4350_amd import chebfd as cf  # noqa: E402
+from paper_1406_4350_amd import workload as wl  # noqa: E402
+from paper_1406_4350_amd.driver import chebfsi  # noqa: E402
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module", params=["tiny_paw", "mid_paw", 2], ids=str)
+def case(request):
+    pb = wl.make_problem(request.param)
+    if pb.cfg.nb > 64:  # full-size workload: a slice of the block keeps the oracle quick
+        pb.X0 = pb.X0[:, :24]
+    print(f"[case] {pb.cfg.name} npw={pb.npw} nproj={pb.nproj}", flush=True)
+    ops = matfree.Operators.from_problem(pb)
+    C = np.diag(1.0 / pb.Q).astype(complex) + pb.P.conj().T @ pb.P
+    plan = cf.plan_from_problem(pb, cf.CHEB_FP64)
+    return pb, ops, C, matfree.atom_blocks(pb.proj_off), plan
+
+
+def _sinv_refined(pb, C, blocks, X, k):
+    q = matfree.capacitance_refine(C, blocks, pb.P.conj().T @ X, iters=k)[0]
+    return X - pb.P @ q
+
+
+@pytest.mark.parametrize("k", [1, 3, 8])
+def test_sinv_same_corrections_as_oracle(case, k):
+    pb, ops, C, blocks, plan = case
+    X = pb.X0
+    plan.set_capacitance_solver(k)
+    try:
+        got = cf.to_host_block(plan.apply_Sinv(cf.to_device_block(X, torch.complex128)))
+    finally:
+        plan.set_capacitance_solver(0)
+    assert _rel(got, _sinv_refined(pb, C, blocks, X, k)) < 1e-12
+
+
+def test_converged_refinement_equals_direct(case):
+    pb, ops, C, blocks, plan = case
+    X = pb.X0
+    k = matfree.capacitance_refine(C, blocks, pb.P.conj().T @ X)[1] + 2
+    print(f"corrections to 1e-15: {k - 2}")
+    Xd = cf.to_device_block(X, torch.complex128)
+    direct = cf.to_host_block(plan.apply_Sinv(Xd))
+    plan.set_capacitance_solver(k)
+    try:
+        it = cf.to_host_block(plan.apply_Sinv(Xd))
+        lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
+        lm = float(np.max(matfree.rayleigh_quotients(ops, X)))
+        c, r = 0.5 * (lp + lm), 0.5 * (lp - lm)
+        Y = cf.to_device_block(X, torch.complex128)
+        plan.filter(Y, 5, c, r)
+        assert _rel(cf.to_host_block(Y), matfree.chebyshev_filter(ops, X, 5, c, r)) < 1e-11
+        Yl = cf.to_device_block(X, torch.complex128)
+        deg = np.arange(X.shape[1], dtype=np.int32) % 6
+        plan.filter_degrees(Yl, deg, c, r)
+        assert _rel(cf.to_host_block(Yl), matfree.chebyshev_filter_degrees(ops, X, deg, c, r)) < 1e-11
+    finally:
+        plan.set_capacitance_solver(0)
+    assert _rel(it, direct) < 1e-12
+    assert _rel(it, ops.apply_Sinv(X)) < 1e-12
+
+
+def test_outer_loop_with_refined_capacitance(case):
+    pb, ops, C, blocks, plan = case
+    if pb.cfg.nb > 64:
+        pytest.skip("trajectory checked on the small workloads")
+    k = matfree.capacitance_refine(C, blocks, pb.P.conj().T @ pb.X0)[1] + 2
+    lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
+    hist_o = matfree.chebfsi(ops, pb.X0, pb.cfg.m, 5, lp)[3]
+    plan.set_capacitance_solver(k)
+    try:
+        hist = chebfsi(plan, cf.to_device_block(pb.X0, torch.complex128), pb.cfg.m, 5, lp)[2]
+        lp_gpu = plan.upper_bound(torch.from_numpy(pb.v0), 10)
+    finally:
+        plan.set_capacitance_solver(0)
+    assert abs(lp_gpu - lp) <= 1e-10 * max(abs(lp), 1.0)
+    for ho, hg in zip(hist_o, hist):
+        assert np.all(np.abs(hg["ritz"] - ho["ritz"]) <= 1e-10 * np.maximum(np.abs(ho["ritz"]), 1.0))
+
+
+def test_capacitance_solver_errors():
+    pb = wl.make_problem(1)  # S = I
+    plan = cf.plan_from_problem(pb, cf.CHEB_FP64)
+    with pytest.raises(cf.ChebError) as e:
+        plan.set_capacitance_solver(5)
+    assert e.value.status == cf.CHEB_ERR_ARG
+    pw = cf.plan_from_problem(wl.make_problem("tiny_paw"), cf.CHEB_FP64)
+    with pytest.raises(cf.ChebError):
+        pw.set_capacitance_solver(-1)
+    pw.set_capacitance_solver(0)
