@@ -360,3 +360,45 @@ def test_capacitance_refinement_contraction(cap_mid):
         Cb[s:s + n, s:s + n] = C[s:s + n, s:s + n]
     q, k, hist = matfree.capacitance_refine(Cb, blocks, b)
     assert k == 0 and np.allclose(q, np.linalg.solve(Cb, b), atol=1e-14 * np.linalg.norm(q))
+
+
+# ---- LOBPCG, the block method the paper compares with (Sec. 3.1) -----------------------------------------------
+from oracle import lobpcg as lobpcg_oracle  # noqa: E402
+
+
+def test_tpa_preconditioner_function():
+    """K(0) = 1, K(1) = 65/81, decreasing, K(x) 2x -> 1 for large x (damps as the inverse kinetic energy)."""
+    K = lobpcg_oracle.tpa
+    assert K(0.0) == 1.0 and abs(K(1.0) - 65.0 / 81.0) < 1e-15
+    x = np.linspace(0, 50, 1001)
+    assert np.all(np.diff(K(x)) < 0)
+    assert abs(K(1e6) * 2e6 - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("name", [1, "tiny_paw"])
+def test_lobpcg_converges_to_dense_eigenpairs(name):
+    pb = wl.make_problem(name)
+    ops = matfree.Operators.from_problem(pb)
+    H = dense.hamiltonian(pb.gidx, pb.kin, pb.V, pb.P, pb.D)
+    S = dense.overlap(pb.npw, pb.P, pb.Q)
+    exact = dense.eig_pencil(H, S)[0]
+    nw = pb.cfg.nb - pb.cfg.nb // 8
+    lam, X, res, hist = lobpcg_oracle.lobpcg(ops, pb.X0, 40)
+    assert np.all(np.abs(lam[:nw] - exact[:nw]) <= 1e-10 * np.maximum(np.abs(exact[:nw]), 1.0))
+    assert np.all(res[:nw] <= 2e-8)
+    # Courant-Fischer: X lies in every Rayleigh-Ritz space, so no Ritz value ever increases
+    for a, b in zip(hist[:-1], hist[1:]):
+        assert np.all(b["ritz"] <= a["ritz"] + 1e-10)
+    # X is S-orthonormal
+    assert np.allclose(X.conj().T @ (S @ X), np.eye(X.shape[1]), atol=1e-9)
+
+
+def test_lobpcg_preconditioner_accelerates():
+    pb = wl.make_problem("tiny_paw")
+    ops = matfree.Operators.from_problem(pb)
+    nw = pb.cfg.nb - pb.cfg.nb // 8
+
+    def iters_to(precond):
+        hist = lobpcg_oracle.lobpcg(ops, pb.X0, 60, precond=precond)[3]
+        return next(h["it"] for h in hist[1:] if h["resid"][:nw].max() <= 1e-6)
+    assert iters_to(True) < iters_to(False)
