@@ -143,8 +143,9 @@ def _potential(cfg: Config, atoms: np.ndarray, rng: np.random.Generator) -> np.n
     return V
 
 
-def _projectors(cfg: Config, gidx: np.ndarray, atoms: np.ndarray):
-    """Columns f_n(|G|) Y_lm(G/|G|) exp(-i G.R_a), each normalised to unit 2-norm."""
+def _projectors(cfg: Config, gidx: np.ndarray, atoms: np.ndarray, real_space_real: bool = False):
+    """Columns f_n(|G|) Y_lm(G/|G|) exp(-i G.R_a), each normalised to unit 2-norm. real_space_real: times
+    (-i)^l, which makes every projector a real function in real space (P(-G) = conj P(G))."""
     L = cfg.cell
     G = (2.0 * np.pi / L) * gidx.astype(np.float64)
     G2 = (G * G).sum(axis=1)
@@ -164,6 +165,9 @@ def _projectors(cfg: Config, gidx: np.ndarray, atoms: np.ndarray):
         "2s2p1d": [rad[0] * s, rad[1] * s] + [rad[0] * c for c in p] + [rad[1] * c for c in p]
         + [rad[0] * c for c in d],
     }[cfg.channels]
+    ells = {"sp": [0, 1, 1, 1], "2s2p": [0, 0] + [1] * 6, "2s2p1d": [0, 0] + [1] * 6 + [2] * 5}[cfg.channels]
+    if real_space_real:
+        shapes = [f * (-1j) ** l for f, l in zip(shapes, ells)]
     nl = len(shapes)
     npw = gidx.shape[0]
     P = np.empty((npw, cfg.natom * nl), dtype=np.complex128, order="F")
@@ -220,3 +224,71 @@ def free_electron(cfg: Config | int | str, nb: int | None = None) -> Problem:
                    np.zeros((pb.npw, 0), dtype=np.complex128, order="F"),
                    np.zeros(natom + 1, dtype=np.int32), [np.zeros((0, 0)) for _ in range(natom)],
                    None, pb.X0, pb.v0, pb.w, pb.dV)
+
+
+# --- Gamma point (real wavefunctions, Sec. 2.1) -----------------------------------------------------------------
+def half_sphere_mask(gidx: np.ndarray) -> np.ndarray:
+    """G in the half sphere H+: gx > 0, or gx = 0 and gy > 0, or gx = gy = 0 and gz >= 0. Every G != 0 of the
+    sphere has exactly one of G, -G in H+; whole (gx, gy) columns belong to H+ except the column (0, 0)."""
+    gx, gy, gz = gidx[:, 0], gidx[:, 1], gidx[:, 2]
+    return (gx > 0) | ((gx == 0) & (gy > 0)) | ((gx == 0) & (gy == 0) & (gz >= 0))
+
+
+@dataclass
+class GammaProblem:
+    """A problem with real wavefunctions: projectors real in real space, so H and S map real functions to real
+    functions. Vectors are stored on the half sphere H+ as the coefficients of an orthonormal real basis:
+    sqrt(2) c_G for G != 0 and the real c_0 at G = 0 (c_-G = conj c_G fills the other half). `full` is the
+    same problem on the whole sphere (its X0, v0 are the expansions of the Gamma ones)."""
+
+    full: Problem
+    half: np.ndarray     # (nh,) indices of H+ in full.gidx (sphere order)
+    gidx: np.ndarray     # (nh, 3)
+    kin: np.ndarray      # (nh,)
+    P: np.ndarray        # (nh, nproj) scaled like the vectors (Fortran order)
+    X0: np.ndarray       # (nh, nb) scaled coefficients, imaginary part 0 at G = 0
+    v0: np.ndarray       # (nh,)
+
+    @property
+    def npw(self) -> int:
+        return self.gidx.shape[0]
+
+    @property
+    def nproj(self) -> int:
+        return self.P.shape[1]
+
+    @property
+    def cfg(self) -> Config:
+        return self.full.cfg
+
+
+def make_gamma_problem(cfg: Config | int | str, nb: int | None = None) -> GammaProblem:
+    """The problem of make_problem with real-space-real projectors ((-i)^l factor) and real start vectors."""
+    pb = make_problem(cfg, nb=nb)
+    cfg = pb.cfg
+    P, off = _projectors(cfg, pb.gidx, pb.atoms, real_space_real=True)
+    half = np.nonzero(half_sphere_mask(pb.gidx))[0]
+    zero = np.all(pb.gidx[half] == 0, axis=1)
+    scale = np.where(zero, 1.0, np.sqrt(2.0))
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(BASE_SEED + cfg.seed_index).spawn(9)[8]))
+    nh = half.shape[0]
+    X0 = rng.normal(size=(nh, cfg.nb)) + 1j * rng.normal(size=(nh, cfg.nb))
+    X0[zero, :] = X0[zero, :].real
+    v0 = rng.normal(size=nh) + 1j * rng.normal(size=nh)
+    v0[zero] = v0[zero].real
+    Ph = np.asfortranarray(P[half] * scale[:, None])
+    # expansions of the Gamma vectors on the whole sphere, for the full problem
+    pos = {tuple(g): i for i, g in enumerate(pb.gidx)}
+    mirror = np.array([pos[tuple(-g)] for g in pb.gidx[half]])
+
+    def expand(Y):
+        Y = np.asarray(Y).reshape(nh, -1)
+        out = np.zeros((pb.npw, Y.shape[1]), dtype=np.complex128)
+        c = Y / scale[:, None]
+        out[mirror] = np.conj(c)
+        out[half] = c
+        return out
+    full = Problem(cfg, pb.gidx, pb.kin, pb.atoms, pb.V, P, off, pb.D, pb.Q, np.asfortranarray(expand(X0)),
+                   expand(v0)[:, 0], pb.w, pb.dV)
+    return GammaProblem(full, half, np.ascontiguousarray(pb.gidx[half]), pb.kin[half].copy(), Ph,
+                        np.asfortranarray(X0), v0)

@@ -402,3 +402,68 @@ def test_lobpcg_preconditioner_accelerates():
         hist = lobpcg_oracle.lobpcg(ops, pb.X0, 60, precond=precond)[3]
         return next(h["it"] for h in hist[1:] if h["resid"][:nw].max() <= 1e-6)
     assert iters_to(True) < iters_to(False)
+
+
+# ---- Gamma point: real wavefunctions on the half sphere (Sec. 2.1) -----------------------------------------------
+from oracle import gamma as gamma_oracle  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def gam():
+    gp = wl.make_gamma_problem("tiny_paw")
+    return gp, gamma_oracle.GammaOperators.from_problem(gp)
+
+
+def test_gamma_projectors_real_in_real_space(gam):
+    """With the (-i)^l factor, P(-G) = conj P(G): every projector is a real function on the grid."""
+    gp, _ = gam
+    n = gp.cfg.n
+    for j in range(gp.nproj):
+        box = np.zeros((n, n, n), complex)
+        box[tuple((gp.full.gidx % n).T)] = gp.full.P[:, j]
+        real = dense.naive_dft3(box, +1) if n <= 12 else np.fft.ifftn(box) * n**3
+        assert np.abs(real.imag).max() <= 1e-12 * np.abs(real).max()
+
+
+def test_gamma_expand_contract(gam):
+    gp, ops = gam
+    gm = ops.map
+    Y = gp.X0
+    assert np.allclose(gm.expand(Y), gp.full.X0, atol=1e-15)  # the generator's expansion agrees
+    assert np.allclose(gm.contract(gm.expand(Y)), Y, atol=1e-14)
+    # inner products: Re <y, z> on the half sphere = <expand y, expand z> on the whole sphere
+    Z = np.random.default_rng(2).normal(size=Y.shape) + 0j
+    Z[gm.zero] = Z[gm.zero].real
+    assert np.allclose(np.real(Y.conj().T @ Z), gm.expand(Y).conj().T @ gm.expand(Z), atol=1e-11)
+    # expanded vectors are real functions on the grid
+    n = gp.cfg.n
+    box = np.zeros((n, n, n), complex)
+    box[tuple((gp.full.gidx % n).T)] = gm.expand(Y[:, 0])[:, 0]
+    assert np.abs(np.fft.ifftn(box).imag).max() <= 1e-14
+
+
+def test_gamma_spectrum_equals_complex_spectrum(gam):
+    """H restricted to real functions is the real symmetric matrix of the full Hermitian H: same spectrum
+    (the complex problem with real-space-real projectors is the complexification of the real one)."""
+    gp, ops = gam
+    Hr = gamma_oracle.dense_real(ops, "H")
+    Sr = gamma_oracle.dense_real(ops, "S")
+    assert np.allclose(Hr, Hr.T, atol=1e-12) and np.allclose(Sr, Sr.T, atol=1e-13)
+    H = dense.hamiltonian(gp.full.gidx, gp.full.kin, gp.full.V, gp.full.P, gp.full.D)
+    S = dense.overlap(gp.full.npw, gp.full.P, gp.full.Q)
+    lam_c = dense.eig_pencil(H, S)[0]
+    lam_r = scipy.linalg.eigh(Hr, Sr, eigvals_only=True)
+    assert Hr.shape[0] == gp.full.npw
+    assert np.allclose(lam_r, lam_c, atol=1e-11)
+
+
+def test_gamma_outer_loop_converges(gam):
+    gp, ops = gam
+    H = dense.hamiltonian(gp.full.gidx, gp.full.kin, gp.full.V, gp.full.P, gp.full.D)
+    S = dense.overlap(gp.full.npw, gp.full.P, gp.full.Q)
+    exact = dense.eig_pencil(H, S)[0]
+    lp = matfree.lanczos_upper_bound(ops.full, gp.full.v0, 10)[0]
+    lam, X, res, hist = gamma_oracle.chebfsi(ops, gp.X0, gp.cfg.m, 30, lp)
+    nw = gp.cfg.nb - gp.cfg.nb // 8
+    assert np.all(np.abs(lam[:nw] - exact[:nw]) <= 1e-10 * np.maximum(np.abs(exact[:nw]), 1.0))
+    assert np.abs(X[ops.map.zero].imag).max() <= 1e-12 * np.abs(X).max()  # still real functions
