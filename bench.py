@@ -29,12 +29,12 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 GEMM_CLASSES = ("project", "backproject", "small", "rr_gram", "rr_rotate")
 FFT_CLASSES = ("fft_col_inverse", "fft_plane", "fft_col_forward")
 # kernel names as rocprofv3 reports them, per timer class and precision
-KERNEL_NAMES = {
-    "backproject": "k_gemm<{t}, {t}, double, {t}, 1, 2>",
-    "project": "k_gemm<{t}, {t}, {t}, double, 0, 1>",
-    "fft_plane": "k_plane<{n}, {t}>",
-    "fft_col_inverse": "k_col_inv<{n}, {t}>",
-    "fft_col_forward": "k_col_fwd<{n}, {t}>",
+KERNEL_NAMES = {  # kernel of each timer class, FP64 / mixed plan
+    "backproject": ("k_gemm<double, double, double, double, 1, 2>", "k_gemm_h<double, float, 1, 2>"),
+    "project": ("k_gemm<double, double, double, double, 0, 1>", "k_gemm_h<float, double, 0, 1>"),
+    "fft_plane": ("k_plane<{n}, double>", "k_plane<{n}, float>"),
+    "fft_col_inverse": ("k_col_inv<{n}, double>", "k_col_inv<{n}, float>"),
+    "fft_col_forward": ("k_col_fwd<{n}, double>", "k_col_fwd<{n}, float>"),
 }
 
 
@@ -124,7 +124,7 @@ def roofline(prof, kind, n):
     out["frac"] = out["achieved"] / out["peak"]
     out["kernel_class"] = dom
     tmpl = KERNEL_NAMES.get(dom)
-    out["kernel"] = tmpl.format(t="double" if kind == "f64" else "float", n=n) if tmpl else dom
+    out["kernel"] = tmpl[0 if kind == "f64" else 1].format(n=n) if tmpl else dom
     out["avg_launch_us"] = per_launch_s * 1e6
     out["algo_per_launch"] = (d["flops"] if dom in GEMM_CLASSES else d["bytes"]) / d["launches"]
     out["traffic"] = load_traffic(out["kernel"])
@@ -293,6 +293,76 @@ def locking_report(cf, pb, lam_plus, tol, iters):
     return out
 
 
+def lobpcg_report(cf, pb, tol, iters):
+    """LOBPCG (Sec. 3.1, the paper's comparison method) from the same start block, FP64: iterations, band
+    applications of H (each also applies S) and wall time until the lowest 7/8 of the bands have residuals
+    <= 2 tol, as for the Chebyshev runs of locking_report."""
+    import numpy as np
+    import torch
+
+    from paper_1406_4350_amd.driver import lobpcg
+
+    nwant = pb.cfg.nb - pb.cfg.nb // 8
+    plan = cf.plan_from_problem(pb, cf.CHEB_FP64)
+    lobpcg(plan, cf.to_device_block(pb.X0, torch.complex128), 1, tol)  # warm-up
+    X = cf.to_device_block(pb.X0, torch.complex128)
+    _, hist = lobpcg(plan, X, iters, tol)
+    plan.close()
+    secs = np.cumsum([h["seconds"] for h in hist])
+    apps = np.cumsum([pb.cfg.nb] + [h["active"] for h in hist[1:]])
+    # residuals reported at iteration k are those of the vectors after iteration k - 1
+    hit = [i for i, h in enumerate(hist) if h["resid"] is not None and np.max(h["resid"][:nwant]) <= 2 * tol]
+    k = hit[0] - 1 if hit else None
+    out = {"tol": tol, "wanted_bands": nwant, "max_iters": iters,
+           "iterations": k, "band_applications": None if k is None else int(apps[k]),
+           "seconds": None if k is None else round(float(secs[k]), 4)}
+    log(f"[bench] lobpcg: reached after {out['iterations']} iterations, {out['band_applications']} "
+        f"band-applications, {out['seconds']} s")
+    return out
+
+
+def gamma_report(cf, cfg_index, steps, warmup):
+    """The same workload at the Gamma point (real wavefunctions on the half sphere, two bands per complex
+    transform): FP64 filter + Rayleigh-Ritz steps and the filter alone, FP64 and mixed."""
+    import torch
+
+    from paper_1406_4350_amd import workload as wl
+
+    gp = wl.make_gamma_problem(cfg_index)
+    probe = cf.plan_from_problem(gp, cf.CHEB_FP64)
+    lam_plus = probe.upper_bound(torch.from_numpy(gp.v0), 10)
+    probe.close()
+    out = {"npw_half": gp.npw}
+    for prec, name in ((cf.CHEB_FP64, "fp64"), (cf.CHEB_MIXED, "mixed")):
+        r = run_path(cf, gp, prec, lam_plus, steps, warmup)
+        out[name] = {"apps_per_s": r["apps_per_s"], "filter_apps_per_s": r["filter_apps_per_s"],
+                     "ms_per_step": r["seconds"] * 1e3 / steps}
+        log(f"[bench] gamma {name}: {r['apps_per_s']:.4g} band-apps/s, filter alone {r['filter_apps_per_s']:.4g}/s")
+        r["plan"].close()
+    return out
+
+
+def device_report():
+    """The device, the software and a measured device-to-device copy rate (read + write bytes / time) for
+    context beside the 8 TB/s peak."""
+    import torch
+
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    gbps = 5 * 2 * src.numel() * 4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del src, dst
+    return {"name": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__,
+            "copy_GBps": round(gbps, 1)}
+
+
 def capacitance_report(cf, pb, lam_plus, iters):
     """FP64 filter with the capacitance solve applied directly and by `iters` corrections of the
     block-preconditioned iterative refinement of Sec. 5.1; relative difference of S^-1 X between the two."""
@@ -334,6 +404,9 @@ def main():
     ap.add_argument("--lock-tol", type=float, default=1e-8,
                     help="residual tolerance of the locking comparison (0: skip it)")
     ap.add_argument("--lock-iters", type=int, default=40)
+    ap.add_argument("--lobpcg-iters", type=int, default=60,
+                    help="iteration cap of the LOBPCG comparison at the locking tolerance (0: skip)")
+    ap.add_argument("--no-gamma", action="store_true", help="skip the Gamma-point form of the workload")
     ap.add_argument("--cap-iters", type=int, default=20,
                     help="corrections of the iterative capacitance solve to compare with the direct one (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -411,6 +484,10 @@ def main():
         }
     if args.lock_tol > 0:
         out["locking"] = locking_report(cf, pb, lam_plus, args.lock_tol, args.lock_iters)
+    if args.lobpcg_iters > 0 and args.lock_tol > 0:
+        out["lobpcg"] = lobpcg_report(cf, pb, args.lock_tol, args.lobpcg_iters)
+    if not args.no_gamma:
+        out["gamma_point"] = gamma_report(cf, args.config, args.steps, args.warmup)
     if args.cap_iters > 0:
         out["capacitance_solve"] = capacitance_report(cf, pb, lam_plus, args.cap_iters)
     if args.backward:
@@ -418,6 +495,7 @@ def main():
     if not args.no_cpu:
         log("[bench] timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(pb)
+    out["device"] = device_report()
     print(json.dumps(out), flush=True)
 
 

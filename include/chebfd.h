@@ -64,7 +64,8 @@ typedef enum {
   CHEB_OP_RR = 3,       /* cheb_rayleigh_ritz, cheb_rayleigh_quotients */
   CHEB_OP_BOUND = 4,    /* cheb_upper_bound (nb ignored) */
   CHEB_OP_SETUP = 5,    /* cheb_set_projectors (nb ignored) */
-  CHEB_OP_FILTER_DEGREES = 6 /* cheb_filter_degrees */
+  CHEB_OP_FILTER_DEGREES = 6, /* cheb_filter_degrees */
+  CHEB_OP_LOBPCG = 7          /* cheb_lobpcg_iterate */
 } cheb_op;
 
 typedef struct {
@@ -79,6 +80,14 @@ typedef struct {
   int prec;                       /* cheb_prec: CHEB_FP64 or CHEB_MIXED (complex64 bands, FFTs, recurrence
                                      and projector GEMMs; FP64 capacitance inverse, subspace matrices and
                                      dense eigensolver) */
+  int gamma;                      /* 0: complex bands on the whole sphere. 1: Gamma point, real wavefunctions
+                                     (Sec. 2.1): gidx_host / kin_host / npw describe the half sphere H+ (gx > 0,
+                                     or gx = 0 and gy > 0, or gx = gy = 0 and gz >= 0), sorted as above, and a
+                                     band holds sqrt(2) c_G for G != 0 and the real c_0 at G = 0 (c_-G = conj c_G
+                                     implied), so that Re x^H y is the inner product of the real functions.
+                                     Projectors (cheb_set_projectors) are given the same way and must be real
+                                     functions in real space. Two bands share each complex transform. Not
+                                     available: cheb_filter_rr_backward, cheb_lobpcg_iterate. */
 } cheb_desc;
 
 /* Size in bytes of the device buffer a plan keeps for its lifetime (index maps, twiddles, V(r), P, D, Q,
@@ -151,6 +160,27 @@ cheb_status cheb_locking_degrees(int nb, const double* ritz, const double* resid
  * CHEB_ERR_NONFINITE on NaN/Inf, CHEB_ERR_EIG if the eigensolver fails. */
 cheb_status cheb_rayleigh_ritz(cheb_plan plan, void* X, int ldx, int nb, double* ritz_dev, double* resid_dev,
                                void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* LOBPCG, the block method the paper compares the filter with (Sec. 3.1), on the same operators: one
+ * iteration per call. iteration = 0: Rayleigh-Ritz of X (start); 1: Rayleigh-Ritz in span[X, W]; >= 2: in
+ * span[X, W, P], with W the residuals of the bands whose residual norm exceeds tol, preconditioned by
+ * K(t_G / E_kin) with K(x) = (27 + 18x + 12x^2 + 8x^3) / (27 + 18x + 12x^2 + 8x^3 + 16x^4) and E_kin the band's
+ * kinetic energy, and P the previous directions of those bands (soft locking: converged bands stay in X and
+ * in every Rayleigh-Ritz but add no columns). At iterations 11, 21, ... H X and S X are recomputed from X and
+ * the directions dropped (restart), which bounds the drift of the products carried by linear combinations;
+ * the iteration also restarts from span[X, W] when the Rayleigh-Ritz with the directions fails. The Rayleigh-Ritz uses an S-orthonormal basis of the space from
+ * the eigendecomposition of the scaled Gram matrix (directions below 1e-14 of the largest dropped).
+ * X (npw x nb, ldx) holds the S-orthonormal Ritz vectors on return; ritz_dev the nb FP64 Ritz values
+ * (input for iterations >= 1, output always); resid_dev (NULL or nb FP64) the residual norms
+ * ||H x - lambda S x|| of the vectors that entered the iteration (iterations >= 1); *nactive (may be NULL) the
+ * number of bands above tol. state: caller-owned device buffer of cheb_lobpcg_state_bytes, carried unchanged
+ * between calls (it holds H X, S X and the directions). Requires 3 nb <= npw and an FP64 plan (the products
+ * H X, S X, H P, S P are carried by linear combinations, which drift too fast in complex64). Synchronizes.
+ * Workspace: cheb_workspace_bytes(CHEB_OP_LOBPCG, nb). */
+cheb_status cheb_lobpcg_state_bytes(cheb_plan plan, int nb, size_t* bytes);
+cheb_status cheb_lobpcg_iterate(cheb_plan plan, void* X, int ldx, int nb, int iteration, double tol, void* state,
+                                size_t state_bytes, double* ritz_dev, double* resid_dev, int* nactive, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
 
 /* Capacitance solve q = C^-1 b, C = Q^-1 + P^H P, inside cheb_apply_Sinv, cheb_filter(_degrees), the Lanczos
  * bound and the adjoint (Sec. 5.1). iterations = 0 (default): the inverse formed at cheb_set_projectors is

@@ -55,7 +55,8 @@ def _rr(V, HV, SV, nb):
     return lam[:nb], Q @ Y[:, :nb]
 
 
-def lobpcg(ops: Operators, X0, iters: int, precond: bool = True, active_tol: float = 1e-8, callback=None):
+def lobpcg(ops: Operators, X0, iters: int, precond: bool = True, active_tol: float = 1e-8, restart: int = 10,
+           callback=None):
     """Full-block LOBPCG from the start block X0 (npw x nb). Returns (ritz, X, residual norms, history).
     history[k] holds the Ritz values after iteration k, the residual norms ||H x - lambda S x|| of the vectors
     that entered iteration k (iteration 0 = the Rayleigh-Ritz of X0) and the number of active bands.
@@ -63,7 +64,10 @@ def lobpcg(ops: Operators, X0, iters: int, precond: bool = True, active_tol: flo
     Bands whose residual is <= active_tol contribute no W or P columns (soft locking at the target
     tolerance): the corrections of converged bands are nearly dependent on X, and keeping them makes the Gram
     matrix singular and the carried products H V, S V drift until the iteration diverges (observed below
-    residuals of about 1e-9 with this basis). The band itself stays in X and in every Rayleigh-Ritz."""
+    residuals of about 1e-9 with this basis). The band itself stays in X and in every Rayleigh-Ritz.
+
+    Every `restart` iterations H X and S X are recomputed from X and the directions dropped for that iteration
+    (a restart of the recurrence), which bounds the drift of the carried products."""
     X = np.asarray(X0, dtype=np.complex128)
     nb = X.shape[1]
     # start: Rayleigh-Ritz of X0
@@ -73,6 +77,9 @@ def lobpcg(ops: Operators, X0, iters: int, precond: bool = True, active_tol: flo
     hist = [dict(it=0, ritz=lam.copy(), resid=None, active=nb)]
     P = HP = SP = None
     for it in range(1, iters + 1):
+        if restart and it > 1 and (it - 1) % restart == 0:
+            HX, SX = ops.apply_H(X), ops.apply_S(X)
+            P = HP = SP = None
         R = HX - SX * lam[None, :]
         res = np.linalg.norm(R, axis=0)
         act = np.nonzero(res > active_tol)[0]

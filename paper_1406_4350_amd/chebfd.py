@@ -23,7 +23,8 @@ CHEB_OK, CHEB_ERR_ARG, CHEB_ERR_HIP, CHEB_ERR_WORKSPACE, CHEB_ERR_NOT_PD, CHEB_E
 STATUS_NAMES = ["CHEB_OK", "CHEB_ERR_ARG", "CHEB_ERR_HIP", "CHEB_ERR_WORKSPACE", "CHEB_ERR_NOT_PD", "CHEB_ERR_EIG",
                 "CHEB_ERR_NONFINITE", "CHEB_ERR_STATE"]
 CHEB_FP64, CHEB_MIXED = 0, 1
-CHEB_OP_H, CHEB_OP_SINV, CHEB_OP_FILTER, CHEB_OP_RR, CHEB_OP_BOUND, CHEB_OP_SETUP, CHEB_OP_FILTER_DEGREES = range(7)
+(CHEB_OP_H, CHEB_OP_SINV, CHEB_OP_FILTER, CHEB_OP_RR, CHEB_OP_BOUND, CHEB_OP_SETUP, CHEB_OP_FILTER_DEGREES,
+ CHEB_OP_LOBPCG) = range(8)
 
 # exported symbols, as declared in include/chebfd.h
 SYMBOLS = ["cheb_plan_persistent_bytes", "cheb_plan_create", "cheb_plan_destroy", "cheb_set_potential",
@@ -31,7 +32,7 @@ SYMBOLS = ["cheb_plan_persistent_bytes", "cheb_plan_create", "cheb_plan_destroy"
            "cheb_apply_Sinv", "cheb_filter", "cheb_rayleigh_ritz", "cheb_rayleigh_quotients", "cheb_upper_bound",
            "cheb_profile_enable", "cheb_profile_read", "cheb_backward_workspace_bytes", "cheb_filter_rr_backward",
            "cheb_set_rr_refine", "cheb_rr_stats", "cheb_filter_degrees", "cheb_locking_degrees", "cheb_set_split_gemm",
-           "cheb_set_capacitance_solver", "cheb_last_error"]
+           "cheb_set_capacitance_solver", "cheb_lobpcg_state_bytes", "cheb_lobpcg_iterate", "cheb_last_error"]
 TIMERS = ["fft_col_inverse", "fft_plane", "fft_col_forward", "project", "backproject", "small", "rr_gram", "rr_eig",
           "rr_rotate", "xdens"]
 
@@ -46,7 +47,7 @@ class ChebError(RuntimeError):
 class cheb_desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("npw", ctypes.c_int), ("gidx_host", ctypes.c_void_p),
                 ("kin_host", ctypes.c_void_p), ("natom", ctypes.c_int), ("proj_off_host", ctypes.c_void_p),
-                ("has_overlap", ctypes.c_int), ("prec", ctypes.c_int)]
+                ("has_overlap", ctypes.c_int), ("prec", ctypes.c_int), ("gamma", ctypes.c_int)]
 
 
 _lib = None
@@ -86,6 +87,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cheb_filter_degrees": [vp, vp, i, i, vp, d, d, vp, sz, vp],
         "cheb_set_split_gemm": [vp, i],
         "cheb_set_capacitance_solver": [vp, i],
+        "cheb_lobpcg_state_bytes": [vp, i, P(sz)],
+        "cheb_lobpcg_iterate": [vp, vp, i, i, i, d, vp, sz, vp, vp, P(i), vp, sz, vp],
         "cheb_locking_degrees": [i, vp, vp, d, d, i, d, vp, P(i)],
     }
     for name, args in sig.items():
@@ -127,7 +130,7 @@ class Plan:
     """A plan over one problem (sphere, box, atoms, precision); owns its persistent device buffer."""
 
     def __init__(self, gidx: np.ndarray, kin: np.ndarray, n: int, proj_off: np.ndarray, has_overlap: bool,
-                 prec: int = CHEB_FP64, device: str = "cuda"):
+                 prec: int = CHEB_FP64, device: str = "cuda", gamma: bool = False):
         self.lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("chebfd needs a GPU (torch.cuda.is_available() is False)")
@@ -140,8 +143,10 @@ class Plan:
         self.nproj = int(self._off[-1]) if self.natom > 0 else 0
         self.prec = prec
         self.dtype = torch.complex64 if prec == CHEB_MIXED else torch.complex128
+        self.gamma = bool(gamma)
         self.desc = cheb_desc(self.n, self.npw, self._gidx.ctypes.data, self._kin.ctypes.data, self.natom,
-                              self._off.ctypes.data if self.natom > 0 else None, int(bool(has_overlap)), prec)
+                              self._off.ctypes.data if self.natom > 0 else None, int(bool(has_overlap)), prec,
+                              int(self.gamma))
         nbytes = ctypes.c_size_t()
         self._check(self.lib.cheb_plan_persistent_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)),
                     "cheb_plan_persistent_bytes", plan=False)
@@ -169,6 +174,26 @@ class Plan:
         if key not in self._ws or self._ws[key].numel() < nbytes.value:
             self._ws[key] = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
         return self._ws[key]
+
+    def lobpcg_state(self, nb: int) -> torch.Tensor:
+        """Device buffer carrying H X, S X and the search directions between LOBPCG iterations."""
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.cheb_lobpcg_state_bytes(self.handle, int(nb), ctypes.byref(nbytes)),
+                    "cheb_lobpcg_state_bytes")
+        return torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+
+    def lobpcg_iterate(self, X, iteration: int, tol: float, state: torch.Tensor, ritz: torch.Tensor):
+        """One LOBPCG iteration in place on X (nb, npw); ritz (nb FP64, device) is read and updated.
+        Returns (residual norms of the vectors that entered, number of active bands)."""
+        nb, ldx = self._block(X, "X")
+        res = torch.zeros(nb, dtype=torch.float64, device=self.device)
+        ws = self.workspace(CHEB_OP_LOBPCG, nb)
+        nact = ctypes.c_int()
+        self._check(self.lib.cheb_lobpcg_iterate(self.handle, X.data_ptr(), ldx, nb, int(iteration), float(tol),
+                                                 state.data_ptr(), state.numel(), ritz.data_ptr(), res.data_ptr(),
+                                                 ctypes.byref(nact), ws.data_ptr(), ws.numel(), _stream()),
+                    "cheb_lobpcg_iterate")
+        return res, nact.value
 
     def set_capacitance_solver(self, iterations: int):
         """0: apply C^-1 directly (default); k > 0: k corrections of block-preconditioned iterative refinement."""
@@ -333,13 +358,16 @@ class Plan:
 
 
 def plan_from_problem(pb, prec: int = CHEB_FP64, device: str = "cuda") -> Plan:
-    """Plan + potential + projectors + D for a workload.Problem (inputs copied to the device)."""
-    plan = Plan(pb.gidx, pb.kin, pb.cfg.n, pb.proj_off, pb.Q is not None, prec=prec, device=device)
-    plan.set_potential(torch.from_numpy(np.ascontiguousarray(pb.V)))
+    """Plan + potential + projectors + D for a workload.Problem, or a workload.GammaProblem (half-sphere basis,
+    Gamma plan), with the inputs copied to the device."""
+    gamma = hasattr(pb, "half")
+    full = pb.full if gamma else pb
+    plan = Plan(pb.gidx, pb.kin, pb.cfg.n, full.proj_off, full.Q is not None, prec=prec, device=device, gamma=gamma)
+    plan.set_potential(torch.from_numpy(np.ascontiguousarray(full.V)))
     P = torch.from_numpy(np.ascontiguousarray(pb.P.T))  # (nproj, npw): row j = projector j
-    Q = None if pb.Q is None else torch.from_numpy(pb.Q)
+    Q = None if full.Q is None else torch.from_numpy(full.Q)
     plan.set_projectors(P, Q)
-    plan.set_D(torch.from_numpy(pb.D_packed))
+    plan.set_D(torch.from_numpy(full.D_packed))
     return plan
 
 

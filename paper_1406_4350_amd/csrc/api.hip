@@ -21,6 +21,9 @@ using namespace chebfd;
 
 struct cheb_plan_s {
   int n = 0, npw = 0, ncol = 0, rx = 0, natom = 0, nproj = 0, has_overlap = 0, prec = 0;
+  int gamma = 0, npf = 0, h0 = -1;  // Gamma point: FFT sphere of npf entries built from the npw half-sphere ones
+  int* gmap = nullptr;              // per FFT-sphere entry: half index | conj << 30
+  int2* gpair = nullptr;            // per half entry: FFT-sphere entries of G and -G
   std::vector<int> proj_off;
   size_t dsize = 0;  // number of doubles of the packed D blocks
   // views into the persistent buffer
@@ -142,18 +145,20 @@ struct Persist {
   int4* col; int* ent; int4* xline; int4* pinfo; int2* dent; void* tw; void* kin; void* Vt; void* P; double* D; double* Q; c128* G; c128* Cinv; c128* Cmat; c128* Minv;
   _Float16* Hproj;  // mixed plans: FP16 hi/lo planes of P for P^H x (rows = projectors, k = plane waves)
   _Float16* Hback;  // and for P w (rows = plane waves, k = projectors)
+  int* gmap; int2* gpair;  // Gamma point maps
   size_t bytes;
 };
 
 inline long pad32(long k) { return (k + 31) / 32 * 32; }
 
 // Carves the persistent buffer (base == nullptr: only measures)
-Persist persist_layout(void* base, int n, int npw, int ncol, int rx, int nproj, size_t dsize, int overlap, int prec) {
+Persist persist_layout(void* base, int n, int npw, int npf, int ncol, int rx, int nproj, size_t dsize, int overlap,
+                       int prec, int gamma) {
   Bump b(base);
   Persist l{};
   const bool mixed = prec == CHEB_MIXED;
   l.col = b.take<int4>(ncol);
-  l.ent = b.take<int>(npw);
+  l.ent = b.take<int>(npf);
   l.xline = b.take<int4>(2 * rx + 1);
   l.pinfo = b.take<int4>(std::max(nproj, 1));
   l.dent = b.take<int2>(std::max<size_t>(dsize, 1));
@@ -172,12 +177,15 @@ Persist persist_layout(void* base, int n, int npw, int ncol, int rx, int nproj, 
     l.Hproj = b.take<_Float16>(4 * size_t(nproj) * pad32(npw));
     l.Hback = b.take<_Float16>(4 * size_t(npw) * pad32(nproj));
   }
+  l.gmap = gamma ? b.take<int>(npf) : nullptr;
+  l.gpair = gamma ? b.take<int2>(npw) : nullptr;
   l.bytes = b.off;
   return l;
 }
 
-size_t persist_bytes(int n, int npw, int ncol, int rx, int nproj, size_t dsize, int overlap, int prec) {
-  return persist_layout(nullptr, n, npw, ncol, rx, nproj, dsize, overlap, prec).bytes;
+size_t persist_bytes(int n, int npw, int npf, int ncol, int rx, int nproj, size_t dsize, int overlap, int prec,
+                     int gamma) {
+  return persist_layout(nullptr, n, npw, npf, ncol, rx, nproj, dsize, overlap, prec, gamma).bytes;
 }
 
 size_t part_elems(int M, int N, int K) {
@@ -186,7 +194,7 @@ size_t part_elems(int M, int N, int K) {
 }
 
 // Scratch of the FFT passes: two disk-column buffers for a batch of bands.
-struct FftWs { void* a; void* b; };
+struct FftWs { void* a; void* b; void* ga = nullptr; void* gb = nullptr; };  // ga, gb: Gamma band pairs
 
 // Every op's workspace, carved in one place so that sizes and pointers agree.
 struct Ws {
@@ -227,7 +235,15 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
   const int fb = fft_batch_for(p, nb);
   const size_t colb = size_t(fb) * p->n * p->ncol * eb;
   size_t part = 0;
-  auto need_fft = [&]() { w->fft.a = b.take<char>(colb); w->fft.b = b.take<char>(colb); };
+  auto need_fft = [&]() {
+    w->fft.a = b.take<char>(colb);
+    w->fft.b = b.take<char>(colb);
+    if (p->gamma) {  // band pairs expanded to the whole sphere, before and after the transforms
+      const size_t gsz = size_t(p->npf) * ((fb + 1) / 2) * eb;
+      w->fft.ga = b.take<char>(gsz);
+      w->fft.gb = b.take<char>(gsz);
+    }
+  };
   switch (op) {
     case CHEB_OP_H:
     case CHEB_OP_SINV: {
@@ -292,6 +308,32 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
       w->solver = b.take<char>(std::max<size_t>(w->solver_bytes, 1));
       break;
     }
+    case CHEB_OP_LOBPCG: {
+      // operator applications on up to nb columns; Rayleigh-Ritz matrices for up to 3 nb columns
+      need_fft();
+      const int n3 = 3 * std::max(nb, 1);
+      const size_t nn = size_t(n3) * n3;
+      w->p0 = b.take<c128>(pp);
+      w->Dp = b.take<c128>(pp);
+      w->Hs = b.take<c128>(nn);
+      w->Ss = b.take<c128>(nn);
+      w->Xa = b.take<c128>(nn);
+      w->Xb = b.take<c128>(nn);
+      w->F = b.take<c128>(nn);
+      w->d = b.take<double>(n3);
+      w->lam = b.take<double>(n3);
+      w->E = b.take<double>(n3);
+      w->res = b.take<double>(n3);
+      w->flags = b.take<int>(4);
+      w->lidx = b.take<int>(n3);
+      // split-K partials for every width the iteration may use (active sets shrink the blocks)
+      for (int k = 1; k <= std::max(nb, 1); ++k)
+        part = std::max({part, part_elems(np, k, p->npw), part_elems(np, k, np), part_elems(np, k, 2 * np)});
+      for (int k = std::max(nb, 1); k <= n3; ++k) part = std::max(part, part_elems(k, k, p->npw));
+      CHK(solver_query(p, CHEB_OP_RR, n3, &w->solver_bytes));
+      w->solver = b.take<char>(std::max<size_t>(w->solver_bytes, 1));
+      break;
+    }
     case CHEB_OP_BOUND: {
       need_fft();
       const size_t v1 = size_t(p->npw) * eb;
@@ -342,6 +384,16 @@ cheb_status solver_query(cheb_plan p, int op, int n, size_t* bytes) {
     rocblas_ztrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
                   rocblas_diagonal_non_unit, n, n, &one, nullptr, n, nullptr, n);
     rocsolver_zheevd(p->rb, rocblas_evect_original, rocblas_fill_lower, n, nullptr, n, nullptr, nullptr, nullptr);
+    rocsolver_zheev(p->rb, rocblas_evect_original, rocblas_fill_lower, n, nullptr, n, nullptr, nullptr, nullptr);
+    if (p->gamma) {
+      const double one = 1.0;
+      rocsolver_dpotrf(p->rb, rocblas_fill_lower, n, nullptr, n, nullptr);
+      rocblas_dtrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, n,
+                    n, &one, nullptr, n, nullptr, n);
+      rocblas_dtrsm(p->rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                    rocblas_diagonal_non_unit, n, n, &one, nullptr, n, nullptr, n);
+      rocsolver_dsyevd(p->rb, rocblas_evect_original, rocblas_fill_lower, n, nullptr, n, nullptr, nullptr, nullptr);
+    }
   } else {
     rocsolver_zpotrf(p->rb, rocblas_fill_lower, n, nullptr, n, nullptr);
     rocsolver_zpotri(p->rb, rocblas_fill_lower, n, nullptr, n, nullptr);
@@ -433,6 +485,22 @@ cheb_status check_block(cheb_plan p, const void* X, int ldx, int nb, const char*
 }
 
 // ---- operator pieces, templated on the band element type --------------------------------------------------------
+// Pinned host staging of index lists copied to the device (band permutations, active sets): waits for the
+// previous copy out of it, grows it to at least `count` ints.
+cheb_status staging(cheb_plan p, size_t count) {
+  if (p->lock_ev) HIPCHK(hipEventSynchronize(p->lock_ev));
+  else HIPCHK(hipEventCreateWithFlags(&p->lock_ev, hipEventDisableTiming));
+  if (p->lock_cap < count) {
+    if (p->lock_host) HIPCHK(hipHostFree(p->lock_host));
+    p->lock_host = nullptr;
+    p->lock_cap = 0;
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->lock_host), std::max<size_t>(count, 1) * sizeof(int),
+                         hipHostMallocDefault));
+    p->lock_cap = count;
+  }
+  return CHEB_OK;
+}
+
 template <typename T> struct Ops {
   using C = cx<T>;
   cheb_plan p;
@@ -442,6 +510,7 @@ template <typename T> struct Ops {
 
   // out = (K + V_loc) X, batched over bands through the disk-column buffers
   cheb_status hloc(const C* X, long ldx, int nb, C* out, long ldo, const FftWs& fw) {
+    if (p->gamma) return hloc_gamma(X, ldx, nb, out, ldo, fw);
     const int fb = fft_batch_for(p, nb);
     const FftGeom g = geom();
     const C* tw = static_cast<const C*>(p->tw);
@@ -467,6 +536,39 @@ template <typename T> struct Ops {
     return CHEB_OK;
   }
 
+  // Gamma point: bands 2j and 2j+1 go through one complex transform as psi_2j + i psi_2j+1 (both real in
+  // real space, V real), then are separated from the values at G and -G.
+  cheb_status hloc_gamma(const C* X, long ldx, int nb, C* out, long ldo, const FftWs& fw) {
+    const int fb = fft_batch_for(p, nb);
+    const FftGeom g = geom();
+    const C* tw = static_cast<const C*>(p->tw);
+    C* ga = static_cast<C*>(fw.ga);
+    C* gb = static_cast<C*>(fw.gb);
+    const long npf = p->npf;
+    for (int b0 = 0; b0 < nb; b0 += fb) {
+      const int cnt = std::min(fb, nb - b0), npair = (cnt + 1) / 2;
+      C* ca = static_cast<C*>(fw.a);
+      C* cb = static_cast<C*>(fw.b);
+      const double b = sizeof(C), colv = double(p->n) * p->ncol, npw = p->npw;
+      {
+        Timed t(p, st, CHEB_T_FFT_COL_INV, (cnt * npw + npair * (2.0 * npf + colv)) * b, 0.0);
+        HIPCHK((gamma_pack<T>(p->npf, cnt, p->gmap, p->h0, X + long(b0) * ldx, ldx, ga, npf, st)));
+        HIPCHK(fft_col_inverse<T>(g, tw, ga, npf, npair, ca, st));
+      }
+      {
+        Timed t(p, st, CHEB_T_FFT_PLANE, npair * 2.0 * colv * b, 0.0);
+        HIPCHK(fft_plane<T>(g, tw, static_cast<const T*>(p->Vt), ca, cb, npair, st));
+      }
+      {
+        Timed t(p, st, CHEB_T_FFT_COL_FWD, (npair * (colv + 2.0 * npf) + 2.0 * cnt * npw) * b, 0.0);
+        HIPCHK(fft_col_forward<T>(g, tw, cb, nullptr, 0, nullptr, gb, npf, npair, st));
+        HIPCHK((gamma_split<T>(p->npw, cnt, p->gpair, p->h0, gb, npf, static_cast<const T*>(p->kin),
+                               X + long(b0) * ldx, ldx, out + long(b0) * ldo, ldo, st)));
+      }
+    }
+    return CHEB_OK;
+  }
+
   // pout (nproj x nb, c128) = P^H X. exact: FP64 MFMA whatever the plan precision (products of complex64
   // inputs are exact in FP64), for the Rayleigh-Ritz matrices of a mixed plan.
   bool use_split() const { return std::is_same<T, float>::value && p->split_gemm && p->hproj.p; }
@@ -478,6 +580,7 @@ template <typename T> struct Ops {
     Epi<double> e;
     e.out = pout;
     e.ldo = ldo > 0 ? ldo : p->nproj;
+    e.real_only = p->gamma != 0;  // projections of real functions are real
     const double b = sizeof(C), np = p->nproj, npw = p->npw;
     Timed t(p, st, CHEB_T_PROJECT, (npw * np + npw * nb) * b + np * nb * 16.0, 8.0 * np * nb * npw);
     if (exact) {
@@ -696,14 +799,14 @@ template <typename T> struct Ops {
     CHK(hloc(X, ldx, nb, loc, npw, w.fft));
     Timed t(p, st, CHEB_T_RR_GRAM, 3.0 * npw * nb * sizeof(C) + 2.0 * nb * nb * 16.0, 16.0 * npw * nb * nb);
     Epi<double> eh;
-    eh.out = w.Hs; eh.ldo = nb;
+    eh.out = w.Hs; eh.ldo = nb; eh.real_only = p->gamma != 0;
     // FP64 MFMA in both precisions: with complex64 blocks the products are exact and the sums over npw
     // terms keep FP64 rounding, so the subspace matrices (and the Ritz values) are limited by the FP32
     // rounding of H X only, not by FP32 accumulation over the sphere.
     HIPCHK((gemm<double, T, T, double>(GEMM_CN, nb, nb, p->npw, X, ldx, loc, npw, eh,
                                        gemm_pick_splits(nb, nb, p->npw), w.part, st, ROLE_SUBSPACE)));
     Epi<double> es;
-    es.out = w.Ss; es.ldo = nb;
+    es.out = w.Ss; es.ldo = nb; es.real_only = p->gamma != 0;
     HIPCHK((gemm<double, T, T, double>(GEMM_CN, nb, nb, p->npw, X, ldx, X, ldx, es,
                                        gemm_pick_splits(nb, nb, p->npw), w.part, st, ROLE_SUBSPACE)));
     if (np > 0) {
@@ -818,7 +921,29 @@ template <typename T> struct Ops {
       RBCHK(rocblas_set_stream(p->rb, st));
       RBCHK(rocblas_set_workspace(p->rb, w.solver, w.solver_bytes));
       rocblas_status rs = rocblas_status_success;
-      {
+      if (p->gamma) {
+        // real symmetric pencil (Gamma point): real factorization and eigensolver keep Z real, so the rotated
+        // bands stay real functions
+        Timed t(p, st, CHEB_T_RR_EIG, 0.0, 0.0);
+        double* Hr = reinterpret_cast<double*>(w.Xa);
+        double* Sr = reinterpret_cast<double*>(w.Xb);
+        HIPCHK(real_part(nb, nb, w.Hs, nb, Hr, nb, st));
+        HIPCHK(real_part(nb, nb, w.Ss, nb, Sr, nb, st));
+        const double one = 1.0;
+        rs = rocsolver_dpotrf(p->rb, rocblas_fill_lower, nb, Sr, nb, w.flags + 2);
+        if (rs == rocblas_status_success)
+          rs = rocblas_dtrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                             rocblas_diagonal_non_unit, nb, nb, &one, Sr, nb, Hr, nb);
+        if (rs == rocblas_status_success)
+          rs = rocblas_dtrsm(p->rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                             rocblas_diagonal_non_unit, nb, nb, &one, Sr, nb, Hr, nb);
+        if (rs == rocblas_status_success)
+          rs = rocsolver_dsyevd(p->rb, rocblas_evect_original, rocblas_fill_lower, nb, Hr, nb, ritz, w.E, w.flags + 3);
+        if (rs == rocblas_status_success)
+          rs = rocblas_dtrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
+                             rocblas_diagonal_non_unit, nb, nb, &one, Sr, nb, Hr, nb);
+        if (rs == rocblas_status_success) HIPCHK(complex_from_real(nb, nb, Hr, nb, w.Hs, nb, st));
+      } else {
         Timed t(p, st, CHEB_T_RR_EIG, 0.0, 0.0);
         rocblas_double_complex* Hd = reinterpret_cast<rocblas_double_complex*>(w.Hs);
         rocblas_double_complex* Ld = reinterpret_cast<rocblas_double_complex*>(w.Ss);
@@ -879,6 +1004,195 @@ template <typename T> struct Ops {
     }
     HIPCHK((convert_copy<T, T>(npw, nb, Ynew, npw, X, ldx, st)));
     return CHEB_OK;
+  }
+
+  // ---- LOBPCG (the block method the paper compares with, Sec. 3.1) ----------------------------------------
+  // Caller-owned state: V = [X | W | P] (3 nb columns), H V, S V, then the full P, H P, S P and the new X,
+  // H X, S X (nb columns each); every block has leading dimension npw.
+  struct LobState { C *V, *HV, *SV, *Pf, *HPf, *SPf, *tX, *tHX, *tSX; };
+  LobState lob_state(void* base, int nb) const {
+    C* b = static_cast<C*>(base);
+    const long k = long(p->npw) * nb;
+    return {b, b + 3 * k, b + 6 * k, b + 9 * k, b + 10 * k, b + 11 * k, b + 12 * k, b + 13 * k, b + 14 * k};
+  }
+
+  // Rayleigh-Ritz of (V^H H V, V^H S V) over the first n columns, in an S-orthonormal basis of span(V) taken
+  // from the eigendecomposition of the diagonally scaled Gram matrix, directions with eigenvalue below
+  // trunc * largest dropped (SVQB basis). Lowest nb Ritz values to lamout (device), coefficients C with
+  // V C = Ritz vectors to w.F (n x nb, ld n). Synchronizes. FP64 throughout.
+  cheb_status svqb_rr(const C* V, const C* HV, const C* SV, int n, int nb, double trunc, double* lamout,
+                      const Ws& w) {
+    const long npw = p->npw;
+    {
+      Timed t(p, st, CHEB_T_RR_GRAM, 3.0 * npw * n * sizeof(C) + 2.0 * n * n * 16.0, 16.0 * npw * n * n);
+      Epi<double> ea;
+      ea.out = w.Hs; ea.ldo = n;
+      HIPCHK((gemm<double, T, T, double>(GEMM_CN, n, n, p->npw, V, npw, HV, npw, ea, gemm_pick_splits(n, n, p->npw),
+                                         w.part, st, ROLE_SUBSPACE)));
+      Epi<double> eb;
+      eb.out = w.Ss; eb.ldo = n;
+      HIPCHK((gemm<double, T, T, double>(GEMM_CN, n, n, p->npw, V, npw, SV, npw, eb, gemm_pick_splits(n, n, p->npw),
+                                         w.part, st, ROLE_SUBSPACE)));
+    }
+    Timed t(p, st, CHEB_T_RR_EIG, 0.0, 0.0);
+    HIPCHK((fill_zero<float>(reinterpret_cast<c64*>(w.flags), 2, st)));
+    HIPCHK(rr_prepare(n, w.Hs, w.Ss, w.d, w.flags, st));
+    CHK(heev_checked(n, w.Ss, w.Xb, w.lam, w, "scaled Gram matrix"));
+    std::vector<double> sig(n);
+    int flags[3] = {0, 0, 0};
+    HIPCHK(hipMemcpyAsync(flags, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(sig.data(), w.lam, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (flags[1]) return fail(p, CHEB_ERR_NONFINITE, "non-finite entry in the LOBPCG Gram matrices");
+    if (flags[0]) return fail(p, CHEB_ERR_NOT_PD, "zero or non-finite column in the LOBPCG basis");
+    int r = 0;
+    for (int i = 0; i < n; ++i) r += sig[i] > trunc * sig[n - 1];
+    if (r < nb) return fail(p, CHEB_ERR_NOT_PD, "LOBPCG basis of rank below the block size");
+    const int k0 = n - r;
+    c128* Q = w.Ss + long(k0) * n;  // kept eigenvectors, scaled to an S'-orthonormal basis
+    HIPCHK(scale_cols_isqrt(n, r, Q, n, w.lam + k0, st));
+    Epi<double> e1;
+    e1.out = w.Xa; e1.ldo = n;
+    HIPCHK((gemm<double, double, double, double>(GEMM_NN, n, r, n, w.Hs, n, Q, n, e1, 1, nullptr, st)));
+    Epi<double> e2;
+    e2.out = w.Xb; e2.ldo = r;
+    HIPCHK((gemm<double, double, double, double>(GEMM_CN, r, r, n, Q, n, w.Xa, n, e2, 1, nullptr, st)));
+    {  // which of the basis, H' Q and the projected matrix carries a NaN or Inf, if any
+      HIPCHK((fill_zero<float>(reinterpret_cast<c64*>(w.flags), 2, st)));
+      HIPCHK(flag_nonfinite(n, r, Q, n, w.flags, st));
+      HIPCHK(flag_nonfinite(n, r, w.Xa, n, w.flags + 1, st));
+      HIPCHK(flag_nonfinite(r, r, w.Xb, r, w.flags + 2, st));
+      int nf[3] = {0, 0, 0};
+      HIPCHK(hipMemcpyAsync(nf, w.flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (nf[0] || nf[1] || nf[2])
+        return fail(p, CHEB_ERR_NONFINITE, "non-finite LOBPCG " + std::string(nf[0] ? "basis" : nf[1] ? "H' Q" : "projected matrix") +
+                                               " (n = " + std::to_string(n) + ", r = " + std::to_string(r) + ")");
+    }
+    CHK(heev_checked(r, w.Xb, w.Xa, w.res, w, "projected matrix"));
+    Epi<double> e3;
+    e3.out = w.F; e3.ldo = n;
+    HIPCHK((gemm<double, double, double, double>(GEMM_NN, n, nb, r, Q, n, w.Xb, r, e3, 1, nullptr, st)));
+    HIPCHK(scale_rows(n, nb, w.F, n, w.d, st));  // coefficients of the unscaled V
+    HIPCHK(hipMemcpyAsync(lamout, w.res, nb * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return CHEB_OK;
+  }
+
+  // Eigendecomposition of the Hermitian n x n matrix A (ld n, lower triangle used) in place, eigenvalues to lam
+  // ascending: divide and conquer, and if that reports no convergence the QR algorithm from a copy of A kept
+  // in spare (n x n). Synchronizes to read the status.
+  cheb_status heev_checked(int n, c128* A, c128* spare, double* lam, const Ws& w, const char* what) {
+    HIPCHK((convert_copy<double, double>(n, n, A, n, spare, n, st)));
+    RBCHK(rocblas_set_stream(p->rb, st));
+    RBCHK(rocblas_set_workspace(p->rb, w.solver, w.solver_bytes));
+    rocblas_status rs = rocsolver_zheevd(p->rb, rocblas_evect_original, rocblas_fill_lower, n,
+                                         reinterpret_cast<rocblas_double_complex*>(A), n, lam, w.E, w.flags + 2);
+    rocblas_set_workspace(p->rb, nullptr, 0);
+    if (rs != rocblas_status_success) return fail(p, CHEB_ERR_HIP, std::string("zheevd: ") + rocblas_status_to_string(rs));
+    int info = 0;
+    HIPCHK(hipMemcpyAsync(&info, w.flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (info == 0) return CHEB_OK;
+    HIPCHK((convert_copy<double, double>(n, n, spare, n, A, n, st)));
+    RBCHK(rocblas_set_workspace(p->rb, w.solver, w.solver_bytes));
+    rs = rocsolver_zheev(p->rb, rocblas_evect_original, rocblas_fill_lower, n, reinterpret_cast<rocblas_double_complex*>(A),
+                         n, lam, w.E, w.flags + 2);
+    rocblas_set_workspace(p->rb, nullptr, 0);
+    if (rs != rocblas_status_success) return fail(p, CHEB_ERR_HIP, std::string("zheev: ") + rocblas_status_to_string(rs));
+    HIPCHK(hipMemcpyAsync(&info, w.flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (info != 0)
+      return fail(p, CHEB_ERR_EIG, std::string("Hermitian eigensolver did not converge on the LOBPCG ") + what + " (n = " +
+                                       std::to_string(n) + ", info " + std::to_string(info) + ")");
+    return CHEB_OK;
+  }
+
+  // X <- V[:, :nb] Cx + P with P = V[:, nb:n] Cr (C = [Cx; Cr] in w.F), the same combinations of H V and S V;
+  // the new P, H P, S P are kept in full (nb columns) for the next iteration.
+  cheb_status lob_update(const LobState& s, int n, int nb, C* X, long ldx, const Ws& w) {
+    const long npw = p->npw;
+    Timed t(p, st, CHEB_T_RR_ROTATE, 6.0 * npw * nb * sizeof(C) + double(n) * nb * 16.0, 3.0 * 8.0 * npw * n * nb);
+    const C* src[3] = {s.V, s.HV, s.SV};
+    C* pf[3] = {s.Pf, s.HPf, s.SPf};
+    C* tn[3] = {s.tX, s.tHX, s.tSX};
+    for (int k = 0; k < 3; ++k) {
+      Epi<T> e;
+      e.out = tn[k]; e.ldo = npw;
+      if (n > nb) {
+        Epi<T> ep;
+        ep.out = pf[k]; ep.ldo = npw;
+        HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, n - nb, src[k] + long(nb) * npw, npw, w.F + nb, n, ep, 1,
+                                      nullptr, st, ROLE_SUBSPACE)));
+        e.L = pf[k]; e.ldl = npw; e.bL = 1.0;
+      } else {
+        HIPCHK((fill_zero<T>(pf[k], npw * nb, st)));
+      }
+      HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, nb, src[k], npw, w.F, n, e, 1, nullptr, st, ROLE_SUBSPACE)));
+    }
+    HIPCHK((convert_copy<T, T>(npw, nb, s.tX, npw, s.V, npw, st)));
+    HIPCHK((convert_copy<T, T>(npw, nb, s.tHX, npw, s.HV, npw, st)));
+    HIPCHK((convert_copy<T, T>(npw, nb, s.tSX, npw, s.SV, npw, st)));
+    HIPCHK((convert_copy<T, T>(npw, nb, s.tX, npw, X, ldx, st)));
+    return CHEB_OK;
+  }
+
+  // One LOBPCG iteration. it = 0: Rayleigh-Ritz of X alone (start). it = 1: space [X, W]. it >= 2: [X, W, P].
+  // W are the preconditioned residuals of the bands whose residual exceeds tol, P their previous directions.
+  cheb_status lobpcg(C* X, long ldx, int nb, int it, double tol, void* state, double* ritz, double* resid,
+                     int* nactive, const Ws& w) {
+    const long npw = p->npw;
+    const LobState s = lob_state(state, nb);
+    constexpr double trunc = 1e-14;
+    if (it == 0) {
+      HIPCHK((convert_copy<T, T>(npw, nb, X, ldx, s.V, npw, st)));
+      CHK(apply_H(s.V, npw, s.HV, npw, nb, w));
+      CHK(apply_S(s.V, npw, s.SV, npw, nb, w));
+      CHK(svqb_rr(s.V, s.HV, s.SV, nb, nb, trunc, ritz, w));
+      CHK(lob_update(s, nb, nb, X, ldx, w));
+      if (nactive) *nactive = nb;
+      return CHEB_OK;
+    }
+    // every kRestart iterations: H X and S X recomputed from X, and no directions this iteration (bounds the
+    // drift of the carried products)
+    constexpr int kRestart = 10;
+    const bool restart = it > 1 && (it - 1) % kRestart == 0;
+    if (restart) {
+      CHK(apply_H(s.V, npw, s.HV, npw, nb, w));
+      CHK(apply_S(s.V, npw, s.SV, npw, nb, w));
+    }
+    double* res = resid ? resid : w.d;
+    HIPCHK((col_resid_norms<T>(npw, nb, s.HV, npw, s.SV, npw, ritz, res, st)));
+    std::vector<double> hres(nb);
+    HIPCHK(hipMemcpyAsync(hres.data(), res, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    CHK(staging(p, size_t(nb)));
+    int nact = 0;
+    for (int i = 0; i < nb; ++i)
+      if (!(hres[i] <= tol)) p->lock_host[nact++] = i;
+    if (nactive) *nactive = nact;
+    if (nact == 0) return CHEB_OK;
+    HIPCHK(hipMemcpyAsync(w.lidx, p->lock_host, nact * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(p->lock_ev, st));
+    C* Wc = s.V + long(nb) * npw;
+    HIPCHK((lobpcg_precondition<T>(npw, nact, static_cast<const T*>(p->kin), s.V, s.HV, s.SV, npw, ritz, w.lidx, Wc,
+                                   npw, st)));
+    CHK(apply_H(Wc, npw, s.HV + long(nb) * npw, npw, nact, w));
+    CHK(apply_S(Wc, npw, s.SV + long(nb) * npw, npw, nact, w));
+    int n = nb + nact;
+    if (it >= 2 && !restart) {
+      HIPCHK((permute_cols<T>(npw, nact, s.Pf, npw, w.lidx, s.V + long(n) * npw, npw, nullptr, st)));
+      HIPCHK((permute_cols<T>(npw, nact, s.HPf, npw, w.lidx, s.HV + long(n) * npw, npw, nullptr, st)));
+      HIPCHK((permute_cols<T>(npw, nact, s.SPf, npw, w.lidx, s.SV + long(n) * npw, npw, nullptr, st)));
+      n += nact;
+    }
+    cheb_status rs = svqb_rr(s.V, s.HV, s.SV, n, nb, trunc, ritz, w);
+    if (rs != CHEB_OK && n > nb + nact) {
+      // the space with the directions is numerically singular: restart from [X, W] this iteration
+      n = nb + nact;
+      rs = svqb_rr(s.V, s.HV, s.SV, n, nb, trunc, ritz, w);
+    }
+    if (rs != CHEB_OK) return rs;
+    return lob_update(s, n, nb, X, ldx, w);
   }
 
   // out = (K + V) a for a block, and dV += coef n^-3 Re sum_b conj(a_b(r)) psi_b(r) from the same column pass
@@ -1134,21 +1448,77 @@ template <typename F> cheb_status with_prec(cheb_plan p, hipStream_t st, F&& f) 
 // ======================================= C ABI ==================================================================
 extern "C" {
 
+// The sphere of the FFTs for a Gamma plan: the half sphere plus the mirror -G of every G != 0, in the sorted
+// column order; gmap / pair / h0 as kept in the plan.
+struct FullSphere {
+  std::vector<int32_t> g;
+  std::vector<int> gmap;
+  std::vector<int2> pair;
+  int h0 = -1;
+};
+
+static cheb_status build_full_sphere(const cheb_desc* d, FullSphere* fs, std::string* msg) {
+  struct Ent { int gx, gy, gz, h, cj; };
+  const int nh = d->npw;
+  std::vector<Ent> v;
+  v.reserve(2 * size_t(nh));
+  fs->h0 = -1;
+  for (int h = 0; h < nh; ++h) {
+    const int32_t* g = d->gidx_host + 3 * h;
+    const bool in_half = g[0] > 0 || (g[0] == 0 && g[1] > 0) || (g[0] == 0 && g[1] == 0 && g[2] >= 0);
+    if (!in_half) { *msg = "Gamma plan: entry " + std::to_string(h) + " is not in the half sphere"; return CHEB_ERR_ARG; }
+    if (h > 0) {
+      const int32_t* q = g - 3;
+      if (!(q[0] < g[0] || (q[0] == g[0] && (q[1] < g[1] || (q[1] == g[1] && q[2] < g[2]))))) {
+        *msg = "Gamma plan: half-sphere list not strictly increasing at entry " + std::to_string(h);
+        return CHEB_ERR_ARG;
+      }
+    }
+    v.push_back({g[0], g[1], g[2], h, 0});
+    if (g[0] == 0 && g[1] == 0 && g[2] == 0) fs->h0 = h;
+    else v.push_back({-g[0], -g[1], -g[2], h, 1});
+  }
+  std::sort(v.begin(), v.end(), [](const Ent& a, const Ent& b) {
+    return a.gx != b.gx ? a.gx < b.gx : (a.gy != b.gy ? a.gy < b.gy : a.gz < b.gz);
+  });
+  fs->g.resize(3 * v.size());
+  fs->gmap.resize(v.size());
+  fs->pair.assign(nh, int2{-1, -1});
+  for (size_t e = 0; e < v.size(); ++e) {
+    fs->g[3 * e] = v[e].gx; fs->g[3 * e + 1] = v[e].gy; fs->g[3 * e + 2] = v[e].gz;
+    fs->gmap[e] = v[e].h | (v[e].cj << 30);
+    if (v[e].cj) fs->pair[v[e].h].y = int(e);
+    else fs->pair[v[e].h].x = int(e);
+  }
+  if (fs->h0 >= 0) fs->pair[fs->h0].y = fs->pair[fs->h0].x;
+  return CHEB_OK;
+}
+
+// Checks the descriptor; ncol, rx from the sphere of the FFTs (the whole sphere of a Gamma plan, built into fs).
 static cheb_status validate_desc(const cheb_desc* d, int* ncol_out, int* rx_out, size_t* dsize_out,
-                                 std::string* msg) {
+                                 std::string* msg, FullSphere* fs) {
   if (!d) { *msg = "desc is null"; return CHEB_ERR_ARG; }
   if (!supported_n(d->n)) { *msg = "unsupported FFT box size " + std::to_string(d->n); return CHEB_ERR_ARG; }
   if (d->npw <= 0) { *msg = "npw must be positive"; return CHEB_ERR_ARG; }
   if (!d->gidx_host || !d->kin_host) { *msg = "gidx_host / kin_host is null"; return CHEB_ERR_ARG; }
   if (d->prec != CHEB_FP64 && d->prec != CHEB_MIXED) { *msg = "unknown precision"; return CHEB_ERR_ARG; }
+  if (d->gamma != 0 && d->gamma != 1) { *msg = "gamma must be 0 or 1"; return CHEB_ERR_ARG; }
   if (d->natom < 0 || (d->natom > 0 && !d->proj_off_host)) { *msg = "bad natom / proj_off_host"; return CHEB_ERR_ARG; }
+  for (int e = 0; e < d->npw; ++e)
+    if (!std::isfinite(d->kin_host[e])) { *msg = "non-finite kinetic entry"; return CHEB_ERR_ARG; }
+  const int32_t* G = d->gidx_host;
+  int npf = d->npw;
+  if (d->gamma) {
+    CHK(build_full_sphere(d, fs, msg));
+    G = fs->g.data();
+    npf = int(fs->gmap.size());
+  }
   const int hmax = (d->n - 1) / 2;
   int ncol = 0, rx = 0;
-  for (int e = 0; e < d->npw; ++e) {
-    const int32_t* g = d->gidx_host + 3 * e;
+  for (int e = 0; e < npf; ++e) {
+    const int32_t* g = G + 3 * e;
     for (int c = 0; c < 3; ++c)
       if (g[c] < -hmax || g[c] > hmax) { *msg = "Miller index outside the FFT box at entry " + std::to_string(e); return CHEB_ERR_ARG; }
-    if (!std::isfinite(d->kin_host[e])) { *msg = "non-finite kinetic entry"; return CHEB_ERR_ARG; }
     rx = std::max(rx, std::abs(g[0]));
     if (e == 0) { ncol = 1; continue; }
     const int32_t* h = g - 3;
@@ -1185,10 +1555,12 @@ cheb_status cheb_plan_persistent_bytes(const cheb_desc* d, size_t* bytes) {
   int ncol = 0, rx = 0;
   size_t dsize = 0;
   std::string msg;
-  cheb_status s = validate_desc(d, &ncol, &rx, &dsize, &msg);
+  FullSphere fs;
+  cheb_status s = validate_desc(d, &ncol, &rx, &dsize, &msg, &fs);
   if (s != CHEB_OK) return s;
   const int nproj = d->natom > 0 ? d->proj_off_host[d->natom] : 0;
-  *bytes = persist_bytes(d->n, d->npw, ncol, rx, nproj, dsize, d->has_overlap ? 1 : 0, d->prec);
+  const int npf = d->gamma ? int(fs.gmap.size()) : d->npw;
+  *bytes = persist_bytes(d->n, d->npw, npf, ncol, rx, nproj, dsize, d->has_overlap ? 1 : 0, d->prec, d->gamma);
   return CHEB_OK;
 }
 
@@ -1198,18 +1570,24 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   int ncol = 0, rx = 0;
   size_t dsize = 0;
   std::string msg;
-  cheb_status s = validate_desc(d, &ncol, &rx, &dsize, &msg);
+  FullSphere fs;
+  cheb_status s = validate_desc(d, &ncol, &rx, &dsize, &msg, &fs);
   if (s != CHEB_OK) { std::fprintf(stderr, "cheb_plan_create: %s\n", msg.c_str()); return s; }
   const int nproj = d->natom > 0 ? d->proj_off_host[d->natom] : 0;
-  const size_t need = persist_bytes(d->n, d->npw, ncol, rx, nproj, dsize, d->has_overlap ? 1 : 0, d->prec);
+  const int npf = d->gamma ? int(fs.gmap.size()) : d->npw;
+  const int32_t* G = d->gamma ? fs.g.data() : d->gidx_host;  // the sphere of the FFTs
+  const size_t need = persist_bytes(d->n, d->npw, npf, ncol, rx, nproj, dsize, d->has_overlap ? 1 : 0, d->prec,
+                                    d->gamma);
   if (!persistent || bytes < need || reinterpret_cast<uintptr_t>(persistent) % kAlign) return CHEB_ERR_WORKSPACE;
 
   cheb_plan p = new (std::nothrow) cheb_plan_s;
   if (!p) return CHEB_ERR_ARG;
   p->n = d->n; p->npw = d->npw; p->ncol = ncol; p->rx = rx; p->natom = d->natom; p->nproj = nproj;
   p->has_overlap = d->has_overlap ? 1 : 0; p->prec = d->prec; p->dsize = dsize;
+  p->gamma = d->gamma; p->npf = npf; p->h0 = fs.h0;
   p->proj_off.assign(d->proj_off_host, d->proj_off_host + (d->natom > 0 ? d->natom + 1 : 0));
-  Persist l = persist_layout(persistent, d->n, d->npw, ncol, rx, nproj, dsize, p->has_overlap, d->prec);
+  Persist l = persist_layout(persistent, d->n, d->npw, npf, ncol, rx, nproj, dsize, p->has_overlap, d->prec, d->gamma);
+  p->gmap = l.gmap; p->gpair = l.gpair;
   p->col = l.col; p->ent = l.ent; p->xline = l.xline; p->pinfo = l.pinfo; p->dent = l.dent; p->tw = l.tw; p->kin = l.kin; p->Vt = l.Vt; p->P = l.P;
   p->D = l.D; p->Q = l.Q; p->G = l.G; p->Cinv = l.Cinv; p->Cmat = l.Cmat; p->Minv = l.Minv;
   p->hproj.p = l.Hproj; p->hproj.rows = nproj; p->hproj.ld = pad32(d->npw);
@@ -1217,10 +1595,10 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
 
   // host-side index maps
   std::vector<int4> col(ncol);
-  std::vector<int> ent(d->npw);
+  std::vector<int> ent(npf);
   int c = -1;
-  for (int e = 0; e < d->npw; ++e) {
-    const int32_t* g = d->gidx_host + 3 * e;
+  for (int e = 0; e < npf; ++e) {
+    const int32_t* g = G + 3 * e;
     if (e == 0 || g[0] != g[-3] || g[1] != g[-2]) {
       ++c;
       col[c] = int4{g[0] + rx, (g[1] % d->n + d->n) % d->n, e, 0};
@@ -1231,7 +1609,7 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   // x-lines: columns sharing gx are consecutive (sorted by gy, consecutive gy checked above)
   std::vector<int4> xline(2 * rx + 1, int4{0, 0, 0, 0});
   for (int cc = 0; cc < ncol; ++cc) {
-    const int32_t* g0 = d->gidx_host + 3 * col[cc].z;
+    const int32_t* g0 = G + 3 * col[cc].z;
     int4& xl = xline[g0[0] + rx];
     if (xl.z == 0) { xl.x = cc; xl.y = g0[1]; }
     xl.z += 1;
@@ -1259,7 +1637,11 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   };
   hipError_t e;
   if ((e = hipMemcpyAsync(p->col, col.data(), sizeof(int4) * ncol, hipMemcpyHostToDevice, st))) return fail_hip(e, "col");
-  if ((e = hipMemcpyAsync(p->ent, ent.data(), sizeof(int) * d->npw, hipMemcpyHostToDevice, st))) return fail_hip(e, "ent");
+  if ((e = hipMemcpyAsync(p->ent, ent.data(), sizeof(int) * npf, hipMemcpyHostToDevice, st))) return fail_hip(e, "ent");
+  if (d->gamma) {
+    if ((e = hipMemcpyAsync(p->gmap, fs.gmap.data(), sizeof(int) * npf, hipMemcpyHostToDevice, st))) return fail_hip(e, "gmap");
+    if ((e = hipMemcpyAsync(p->gpair, fs.pair.data(), sizeof(int2) * d->npw, hipMemcpyHostToDevice, st))) return fail_hip(e, "gpair");
+  }
   if ((e = hipMemcpyAsync(p->xline, xline.data(), sizeof(int4) * xline.size(), hipMemcpyHostToDevice, st))) return fail_hip(e, "xline");
   if ((e = hipMemcpyAsync(p->pinfo, pinfo.data(), sizeof(int4) * pinfo.size(), hipMemcpyHostToDevice, st))) return fail_hip(e, "pinfo");
   if ((e = hipMemcpyAsync(p->dent, dent.data(), sizeof(int2) * dent.size(), hipMemcpyHostToDevice, st))) return fail_hip(e, "dent");
@@ -1394,7 +1776,7 @@ cheb_status cheb_set_projectors(cheb_plan p, const void* P, int ldp, const doubl
   }
   // G = P^H P in FP64 from the caller's complex128 projectors
   Epi<double> eg;
-  eg.out = p->G; eg.ldo = np;
+  eg.out = p->G; eg.ldo = np; eg.real_only = p->gamma != 0;
   HIPCHK((gemm<double, double, double, double>(GEMM_CN, np, np, p->npw, Pd, ldp, Pd, ldp, eg,
                                                gemm_pick_splits(np, np, p->npw), w.part, st)));
   if (p->has_overlap) {
@@ -1510,15 +1892,7 @@ cheb_status cheb_filter_degrees(cheb_plan p, void* X, int ldx, int nb, const int
     (d & 1 ? no : ne) += 1;
   }
   const size_t need = 3 * size_t(na);
-  if (p->lock_ev) HIPCHK(hipEventSynchronize(p->lock_ev));  // the previous copy out of the staging buffer is done
-  else HIPCHK(hipEventCreateWithFlags(&p->lock_ev, hipEventDisableTiming));
-  if (p->lock_cap < need) {
-    if (p->lock_host) HIPCHK(hipHostFree(p->lock_host));
-    p->lock_host = nullptr;
-    p->lock_cap = 0;
-    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->lock_host), need * sizeof(int), hipHostMallocDefault));
-    p->lock_cap = need;
-  }
+  CHK(staging(p, need));
   int* h = p->lock_host;
   int* hev = h + na;
   int* hod = hev + 2 * ne;
@@ -1601,6 +1975,39 @@ cheb_status cheb_upper_bound(cheb_plan p, int k, const void* v0, double* lambda_
   });
 }
 
+cheb_status cheb_lobpcg_state_bytes(cheb_plan p, int nb, size_t* bytes) {
+  if (!p || !bytes) return CHEB_ERR_ARG;
+  if (nb < 1) return fail(p, CHEB_ERR_ARG, "nb must be >= 1");
+  *bytes = 15 * size_t(p->npw) * nb * elem_bytes(p->prec);
+  return CHEB_OK;
+}
+
+cheb_status cheb_lobpcg_iterate(cheb_plan p, void* X, int ldx, int nb, int iteration, double tol, void* state,
+                                size_t state_bytes, double* ritz_dev, double* resid_dev, int* nactive, void* ws,
+                                size_t wsb, hipStream_t st) {
+  if (!p) return CHEB_ERR_ARG;
+  CHK(check_ready(p));
+  CHK(check_block(p, X, ldx, nb, "X"));
+  if (nb < 1) return fail(p, CHEB_ERR_ARG, "nb must be >= 1");
+  if (3 * nb > p->npw) return fail(p, CHEB_ERR_ARG, "3 nb must not exceed npw");
+  if (p->prec != CHEB_FP64)
+    return fail(p, CHEB_ERR_ARG, "LOBPCG runs on FP64 plans (its carried products drift in complex64)");
+  if (p->gamma) return fail(p, CHEB_ERR_ARG, "LOBPCG is not available for Gamma plans");
+  if (iteration < 0) return fail(p, CHEB_ERR_ARG, "iteration < 0");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(p, CHEB_ERR_ARG, "tol must be finite and >= 0");
+  if (!ritz_dev) return fail(p, CHEB_ERR_ARG, "ritz is null");
+  size_t need = 0;
+  CHK(cheb_lobpcg_state_bytes(p, nb, &need));
+  if (!state || state_bytes < need) return fail(p, CHEB_ERR_WORKSPACE, "LOBPCG state too small: need " + std::to_string(need));
+  if (reinterpret_cast<uintptr_t>(state) % 16) return fail(p, CHEB_ERR_ARG, "state not 16-byte aligned");
+  Ws w;
+  CHK(check_ws(p, CHEB_OP_LOBPCG, nb, ws, wsb, &w));
+  return with_prec(p, st, [&](auto ops) {
+    using C = typename decltype(ops)::C;
+    return ops.lobpcg(static_cast<C*>(X), ldx, nb, iteration, tol, state, ritz_dev, resid_dev, nactive, w);
+  });
+}
+
 cheb_status cheb_set_capacitance_solver(cheb_plan p, int iterations) {
   if (!p) return CHEB_ERR_ARG;
   if (iterations < 0 || iterations > 1000) return fail(p, CHEB_ERR_ARG, "iterations must be in [0, 1000]");
@@ -1636,6 +2043,7 @@ static cheb_status backward_check(cheb_plan p, int nb, int m, int k) {
   if (m < 1) return fail(p, CHEB_ERR_ARG, "degree m must be >= 1");
   if (k < 1) return fail(p, CHEB_ERR_ARG, "ckpt_every must be >= 1");
   if (p->n > 64) return fail(p, CHEB_ERR_ARG, "the adjoint supports FFT boxes up to 64");
+  if (p->gamma) return fail(p, CHEB_ERR_ARG, "the adjoint is not available for Gamma plans");
   if (fft_xdens_lds_bytes(p->n, p->rx, p->prec != CHEB_MIXED) > 160 * 1024)
     return fail(p, CHEB_ERR_ARG, "sphere too wide in x for the cross-density pass in 160 KB of LDS");
   return CHEB_OK;

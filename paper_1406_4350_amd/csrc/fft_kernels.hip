@@ -8,6 +8,8 @@
 //   column pass   : forward FFT along z, gather the sphere, scale by n^-3, add K psi      (fft_col_forward)
 // The disk-column buffer is laid out [band][z][column] so that plane passes read and write it
 // contiguously and column passes stage z-lines of CPB columns in LDS.
+#include <algorithm>
+
 #include "fft.h"
 #include "kernels.h"
 
@@ -400,9 +402,57 @@ __global__ __launch_bounds__(NT) void k_col_fwd(int ncol, const int4* __restrict
   for (int e = e0 + tid; e < e1; e += NT) {
     const int code = ent[e];
     const cx<T> v = lines[((code >> 8) - c0) * LS + (code & 255)];
-    const cx<T> x = xb[e];
-    const T k = kin[e];
-    ob[e] = cx<T>{v.x * scale + k * x.x, v.y * scale + k * x.y};
+    if (kin) {
+      const cx<T> x = xb[e];
+      const T k = kin[e];
+      ob[e] = cx<T>{v.x * scale + k * x.x, v.y * scale + k * x.y};
+    } else {
+      ob[e] = cx<T>{v.x * scale, v.y * scale};
+    }
+  }
+}
+
+// ---- Gamma point: two real bands per complex transform --------------------------------------------------------
+// Stored Gamma vectors hold sqrt(2) c_G on the half sphere (c_0 at G = 0). gmap[e] = h | (conj << 30) gives, for
+// entry e of the whole sphere, the half-sphere entry h with G_e = G_h (conj = 0) or G_e = -G_h (conj = 1).
+// u(G_e) = c_2j(G_e) + i c_2j+1(G_e): the inverse transform is then psi_2j(r) + i psi_2j+1(r).
+template <typename T>
+__global__ void k_gamma_pack(int npf, int nb, int npair, const int* __restrict__ gmap, int h0,
+                             const cx<T>* __restrict__ X, long ldx, cx<T>* __restrict__ U, long ldu) {
+  const long total = long(npf) * npair;
+  const T r2 = T(0.70710678118654752440);
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const int j = int(t / npf), e = int(t - long(j) * npf);
+    const int code = gmap[e];
+    const int h = code & 0x3fffffff;
+    const bool cj = (code >> 30) & 1;
+    const T s = h == h0 ? T(1) : r2;
+    cx<T> v0 = X[h + long(2 * j) * ldx];
+    cx<T> v1 = 2 * j + 1 < nb ? X[h + long(2 * j + 1) * ldx] : cx<T>{T(0), T(0)};
+    if (cj) { v0.y = -v0.y; v1.y = -v1.y; }
+    U[e + long(j) * ldu] = cx<T>{s * (v0.x - v1.y), s * (v0.y + v1.x)};
+  }
+}
+
+// Separates the transformed pair: with w = W(G), m = W(-G) (pair[h] = entries of G_h and -G_h),
+// band 2j gets (w + conj m) / 2, band 2j+1 gets (w - conj m) / (2i); scaled back to the stored form, plus K x.
+template <typename T>
+__global__ void k_gamma_split(int nh, int nb, const int2* __restrict__ pair, int h0, const cx<T>* __restrict__ W,
+                              long ldw, const T* __restrict__ kin, const cx<T>* __restrict__ X, long ldx,
+                              cx<T>* __restrict__ out, long ldo) {
+  const long total = long(nh) * nb;
+  const T sq2 = T(1.41421356237309504880);
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const int b = int(t / nh), h = int(t - long(b) * nh);
+    const int j = b >> 1;
+    const int2 pe = pair[h];
+    const cx<T> w = W[pe.x + long(j) * ldw], m = W[pe.y + long(j) * ldw];
+    cx<T> y = (b & 1) ? cx<T>{T(0.5) * (w.y + m.y), T(-0.5) * (w.x - m.x)}
+                      : cx<T>{T(0.5) * (w.x + m.x), T(0.5) * (w.y - m.y)};
+    const T s = h == h0 ? T(1) : sq2;
+    const cx<T> x = X[h + long(b) * ldx];
+    const T k = kin[h];
+    out[h + long(b) * ldo] = cx<T>{s * y.x + k * x.x, s * y.y + k * x.y};
   }
 }
 
@@ -422,6 +472,35 @@ template <typename F> hipError_t dispatch_n(int n, F&& f) {
 }
 
 }  // namespace
+
+template <typename T>
+hipError_t gamma_pack(int npf, int nb, const int* gmap, int h0, const cx<T>* X, long ldx, cx<T>* U, long ldu,
+                      hipStream_t st) {
+  const int npair = (nb + 1) / 2;
+  if (npf <= 0 || nb <= 0) return hipSuccess;
+  const long total = long(npf) * npair;
+  const long blocks = std::min<long>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_gamma_pack<T>), dim3(unsigned(blocks)), dim3(256), 0, st, npf, nb, npair, gmap, h0, X, ldx, U,
+                     ldu);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t gamma_split(int nh, int nb, const int2* pair, int h0, const cx<T>* W, long ldw, const T* kin,
+                       const cx<T>* X, long ldx, cx<T>* out, long ldo, hipStream_t st) {
+  if (nh <= 0 || nb <= 0) return hipSuccess;
+  const long total = long(nh) * nb;
+  const long blocks = std::min<long>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_gamma_split<T>), dim3(unsigned(blocks)), dim3(256), 0, st, nh, nb, pair, h0, W, ldw, kin, X,
+                     ldx, out, ldo);
+  return hipGetLastError();
+}
+template hipError_t gamma_pack<double>(int, int, const int*, int, const c128*, long, c128*, long, hipStream_t);
+template hipError_t gamma_pack<float>(int, int, const int*, int, const c64*, long, c64*, long, hipStream_t);
+template hipError_t gamma_split<double>(int, int, const int2*, int, const c128*, long, const double*, const c128*, long,
+                                        c128*, long, hipStream_t);
+template hipError_t gamma_split<float>(int, int, const int2*, int, const c64*, long, const float*, const c64*, long,
+                                       c64*, long, hipStream_t);
+
 
 template <typename T>
 hipError_t fft_col_inverse(const FftGeom& g, const cx<T>* tw, const cx<T>* X, long ldx, int nb, cx<T>* colbuf,

@@ -33,7 +33,7 @@ __device__ __forceinline__ void epi_store(const Epi<E>& e, long m, long n, doubl
   if (e.L) { cx<E> v = e.L[m + n * e.ldl]; xr += e.bL * double(v.x); xi += e.bL * double(v.y); }
   if (e.U) { cx<E> v = e.U[m + n * e.ldu]; xr += e.bU * double(v.x); xi += e.bU * double(v.y); }
   if (e.W) { cx<E> v = e.W[m + n * e.ldw]; xr += e.bW * double(v.x); xi += e.bW * double(v.y); }
-  e.out[m + n * e.ldo] = cx<E>{E(xr), E(xi)};
+  e.out[m + n * e.ldo] = cx<E>{E(xr), e.real_only ? E(0) : E(xi)};
 }
 
 // One 64 x 64 complex output tile per block of 4 waves; wave w owns the 32 x 32 quadrant

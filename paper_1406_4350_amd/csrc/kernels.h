@@ -13,6 +13,7 @@ template <typename E> struct Epi {
   const cx<E>* L = nullptr; long ldl = 0; double bL = 0.0;
   const cx<E>* U = nullptr; long ldu = 0; double bU = 0.0;
   const cx<E>* W = nullptr; long ldw = 0; double bW = 0.0;
+  bool real_only = false;  // keep the real part (inner products of real functions, Gamma point)
 };
 
 enum GemmMode { GEMM_CN = 0, GEMM_NN = 1 };
@@ -86,6 +87,14 @@ size_t cross_density_part_doubles(int n, int nband);
 size_t fft_xdens_lds_bytes(int n, int rx, bool dbl);
 // dynamic LDS bytes of the plane pass for box n, x-line half-width rx (0 if n unsupported)
 size_t fft_plane_lds_bytes(int n, int rx, bool dbl);
+// Gamma point: U[:, j] = bands 2j + i 2j+1 expanded to the whole sphere (gmap: half index | conj << 30, h0 the
+// half index of G = 0 or -1); out = the two bands separated from the transformed W, scaled back, + K X
+template <typename T>
+hipError_t gamma_pack(int npf, int nb, const int* gmap, int h0, const cx<T>* X, long ldx, cx<T>* U, long ldu,
+                      hipStream_t st);
+template <typename T>
+hipError_t gamma_split(int nh, int nb, const int2* pair, int h0, const cx<T>* W, long ldw, const T* kin,
+                       const cx<T>* X, long ldx, cx<T>* out, long ldo, hipStream_t st);
 
 // ---- small projector-space and vector kernels -------------------------------------------------------------
 // out[:, b] = blockdiag(D) in[:, b]; pinfo[i] = {first row of i's atom, block size, offset of the block in D}
@@ -154,6 +163,18 @@ hipError_t identity_matrix(int n, c128* X, hipStream_t st);
 // ascending sort of lam (n <= 2048) -> ritz, perm; Z[:, k] = d .* X[:, perm[k]]
 hipError_t sort_eigen(int n, const double* lam, double* ritz, int* perm, const c128* X, const double* d, c128* Z,
                       hipStream_t st);
+// LOBPCG: W[:, j] = K(t / E_kin(x_a)) (HX - lambda_a SX)[:, a], a = act[j], with the rational kinetic
+// preconditioner K(x) = (27 + 18x + 12x^2 + 8x^3) / (27 + 18x + 12x^2 + 8x^3 + 16x^4)
+template <typename E>
+hipError_t lobpcg_precondition(long rows, int nact, const E* kin, const cx<E>* X, const cx<E>* HX, const cx<E>* SX,
+                               long ld, const double* lam, const int* act, cx<E>* W, long ldw, hipStream_t st);
+// R = Re A; A = R + 0 i (real symmetric eigenproblems of the Gamma point)
+hipError_t real_part(long rows, int cols, const c128* A, long lda, double* R, long ldr, hipStream_t st);
+hipError_t complex_from_real(long rows, int cols, const double* R, long ldr, c128* A, long lda, hipStream_t st);
+// flag[0] = 1 if any entry of A (rows x cols, ld lda) is NaN or Inf (plain stores of 1, no atomics)
+hipError_t flag_nonfinite(long rows, int cols, const c128* A, long lda, int* flag, hipStream_t st);
+// Z[:, j] *= 1 / sqrt(s[j])
+hipError_t scale_cols_isqrt(int n, int ncols, c128* Z, long ldz, const double* s, hipStream_t st);
 // out[i] = Re a[i] / Re b[i]
 hipError_t ratio_real(int nb, const c128* a, const c128* b, double* out, hipStream_t st);
 

@@ -148,6 +148,55 @@ __global__ void k_permute_cols(long rows, int ncols, const cx<E>* src, long lds,
   for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < rows; i += long(gridDim.x) * blockDim.x) d[i] = s[i];
 }
 
+// LOBPCG preconditioned residuals, one block per active band a = act[j]: E = sum_g t_g |x_g|^2 / sum_g |x_g|^2,
+// then W[:, j] = K(t_g / E) (HX - lambda_a SX)[:, a] with K(x) = (27 + 18x + 12x^2 + 8x^3) / (... + 16x^4).
+template <typename E>
+__global__ __launch_bounds__(256) void k_lobpcg_precond(long rows, const E* __restrict__ kin, const cx<E>* X,
+                                                        const cx<E>* HX, const cx<E>* SX, long ld,
+                                                        const double* __restrict__ lam, const int* __restrict__ act,
+                                                        cx<E>* W, long ldw) {
+  __shared__ double s1[256], s2[256];
+  const int j = blockIdx.x, a = act[j];
+  const cx<E>* x = X + long(a) * ld;
+  double num = 0.0, den = 0.0;
+  for (long i = threadIdx.x; i < rows; i += blockDim.x) {
+    const cx<E> v = x[i];
+    const double m = double(v.x) * double(v.x) + double(v.y) * double(v.y);
+    num += double(kin[i]) * m;
+    den += m;
+  }
+  s1[threadIdx.x] = num;
+  s2[threadIdx.x] = den;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) { s1[threadIdx.x] += s1[threadIdx.x + k]; s2[threadIdx.x] += s2[threadIdx.x + k]; }
+    __syncthreads();
+  }
+  const double ekin = s2[0] > 0.0 ? s1[0] / s2[0] : 1.0;
+  const double l = lam[a];
+  const cx<E>* h = HX + long(a) * ld;
+  const cx<E>* sx = SX + long(a) * ld;
+  cx<E>* w = W + long(j) * ldw;
+  for (long i = threadIdx.x; i < rows; i += blockDim.x) {
+    const double xx = ekin > 0.0 ? double(kin[i]) / ekin : 0.0;
+    const double num4 = 27.0 + xx * (18.0 + xx * (12.0 + 8.0 * xx));
+    const double K = num4 / (num4 + 16.0 * xx * xx * xx * xx);
+    const cx<E> hv = h[i], sv = sx[i];
+    w[i] = cx<E>{E(K * (double(hv.x) - l * double(sv.x))), E(K * (double(hv.y) - l * double(sv.y)))};
+  }
+}
+
+// Z[:, j] *= 1 / sqrt(s[j]) for j < ncols
+__global__ void k_scale_cols_isqrt(int n, int ncols, c128* Z, long ldz, const double* s) {
+  const long total = long(n) * ncols;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long j = t / n, i = t - j * n;
+    const double f = 1.0 / sqrt(s[j]);
+    c128 v = Z[i + j * ldz];
+    Z[i + j * ldz] = c128{v.x * f, v.y * f};
+  }
+}
+
 // one block per column, fixed-order tree reduction (deterministic)
 template <typename E>
 __global__ __launch_bounds__(256) void k_col_dots(long rows, const cx<E>* x, long ldx, const cx<E>* y, long ldy,
@@ -333,6 +382,62 @@ hipError_t col_resid_norms(long rows, int nb, const cx<E>* R, long ldr, const cx
                            const double* lam, double* out, hipStream_t st) {
   if (nb <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_col_resid<E>), dim3(nb), dim3(256), 0, st, rows, R, ldr, U, ldu, lam, out);
+  return hipGetLastError();
+}
+
+template <typename E>
+hipError_t lobpcg_precondition(long rows, int nact, const E* kin, const cx<E>* X, const cx<E>* HX, const cx<E>* SX,
+                               long ld, const double* lam, const int* act, cx<E>* W, long ldw, hipStream_t st) {
+  if (nact <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_lobpcg_precond<E>), dim3(nact), dim3(256), 0, st, rows, kin, X, HX, SX, ld, lam, act, W, ldw);
+  return hipGetLastError();
+}
+template hipError_t lobpcg_precondition<double>(long, int, const double*, const c128*, const c128*, const c128*, long,
+                                                const double*, const int*, c128*, long, hipStream_t);
+template hipError_t lobpcg_precondition<float>(long, int, const float*, const c64*, const c64*, const c64*, long,
+                                               const double*, const int*, c64*, long, hipStream_t);
+hipError_t scale_cols_isqrt(int n, int ncols, c128* Z, long ldz, const double* s, hipStream_t st) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_cols_isqrt, dim3(nblocks(long(n) * ncols)), dim3(256), 0, st, n, ncols, Z, ldz, s);
+  return hipGetLastError();
+}
+
+__global__ void k_real_part(long rows, int cols, const c128* A, long lda, double* R, long ldr) {
+  const long total = rows * cols;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long j = t / rows, i = t - j * rows;
+    R[i + j * ldr] = A[i + j * lda].x;
+  }
+}
+__global__ void k_from_real(long rows, int cols, const double* R, long ldr, c128* A, long lda) {
+  const long total = rows * cols;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long j = t / rows, i = t - j * rows;
+    A[i + j * lda] = c128{R[i + j * ldr], 0.0};
+  }
+}
+hipError_t real_part(long rows, int cols, const c128* A, long lda, double* R, long ldr, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_real_part, dim3(nblocks(rows * cols)), dim3(256), 0, st, rows, cols, A, lda, R, ldr);
+  return hipGetLastError();
+}
+hipError_t complex_from_real(long rows, int cols, const double* R, long ldr, c128* A, long lda, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_from_real, dim3(nblocks(rows * cols)), dim3(256), 0, st, rows, cols, R, ldr, A, lda);
+  return hipGetLastError();
+}
+
+__global__ void k_flag_nonfinite(long rows, int cols, const c128* A, long lda, int* flag) {
+  const long total = rows * cols;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long j = t / rows, i = t - j * rows;
+    const c128 v = A[i + j * lda];
+    if (!isfinite(v.x) || !isfinite(v.y)) flag[0] = 1;
+  }
+}
+hipError_t flag_nonfinite(long rows, int cols, const c128* A, long lda, int* flag, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_flag_nonfinite, dim3(nblocks(rows * cols)), dim3(256), 0, st, rows, cols, A, lda, flag);
   return hipGetLastError();
 }
 

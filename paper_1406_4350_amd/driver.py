@@ -49,3 +49,25 @@ def chebfsi(plan: Plan, X: torch.Tensor, m: int, iters: int, lam_plus: float, ca
             callback(rec)
         lam_minus = float(rec["ritz"].max())
     return ritz, res, hist
+
+
+def lobpcg(plan: Plan, X: torch.Tensor, iters: int, tol: float = 1e-8, callback=None):
+    """Full-block LOBPCG (Sec. 3.1) in place on X (nb, npw): the start Rayleigh-Ritz and `iters` iterations.
+    Bands with residual <= tol add no correction (soft locking). Returns (ritz, history); history[k] has the
+    Ritz values after iteration k and the residuals of the vectors that entered it (None for k = 0)."""
+    nb = X.shape[0]
+    state = plan.lobpcg_state(nb)
+    ritz = torch.zeros(nb, dtype=torch.float64, device=X.device)
+    hist = []
+    for it in range(iters + 1):
+        t0 = time.perf_counter()
+        res, nact = plan.lobpcg_iterate(X, it, tol, state, ritz)
+        torch.cuda.synchronize()
+        rec = dict(it=it, ritz=ritz.cpu().numpy(), resid=None if it == 0 else res.cpu().numpy(), active=nact,
+                   seconds=time.perf_counter() - t0)
+        hist.append(rec)
+        if callback is not None:
+            callback(rec)
+        if it > 0 and nact == 0:
+            break
+    return ritz, hist

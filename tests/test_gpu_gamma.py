@@ -1,0 +1,132 @@
+"""Gamma-point plans (real wavefunctions on the half sphere, two bands per complex transform) against the Gamma
+oracle on the same seeded inputs. Tolerances as for complex plans: operators 1e-12, filter 1e-11 relative,
+Ritz values 1e-10 max(|lambda|, 1); mixed operators 2e-5.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import gamma as go  # noqa: E402
+from oracle import matfree  # noqa: E402
+from paper_1406_4350_amd import chebfd as cf  # noqa: E402
+from paper_1406_4350_amd import workload as wl  # noqa: E402
+from paper_1406_4350_amd.driver import chebfsi  # noqa: E402
+
+CASES = [1, "tiny_paw", "mid_paw", "mid_nc"]
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module", params=CASES, ids=str)
+def case(request):
+    gp = wl.make_gamma_problem(request.param)
+    print(f"[case] gamma {gp.cfg.name} npw_half={gp.npw} npw={gp.full.npw} nb={gp.cfg.nb}", flush=True)
+    ops = go.GammaOperators.from_problem(gp)
+    plan = cf.plan_from_problem(gp, cf.CHEB_FP64)
+    lp = matfree.lanczos_upper_bound(ops.full, gp.full.v0, 10)[0]
+    return gp, ops, plan, lp
+
+
+def test_gamma_operators(case):
+    gp, ops, plan, _ = case
+    X = gp.X0
+    Xd = cf.to_device_block(X, torch.complex128)
+    assert _rel(cf.to_host_block(plan.apply_H(Xd)), ops.apply_H(X)) < 1e-12
+    assert _rel(cf.to_host_block(plan.apply_S(Xd)), ops.apply_S(X)) < 1e-12
+    assert _rel(cf.to_host_block(plan.apply_Sinv(Xd)), ops.apply_Sinv(X)) < 1e-12
+    # odd band counts: the last band shares its transform with a zero band
+    Xo = X[:, :3]
+    assert _rel(cf.to_host_block(plan.apply_H(cf.to_device_block(Xo, torch.complex128))), ops.apply_H(Xo)) < 1e-12
+
+
+@pytest.mark.parametrize("m", [0, 1, 2, 5])
+def test_gamma_filter(case, m):
+    gp, ops, plan, lp = case
+    lm = float(np.max(go.rayleigh_quotients(ops, gp.X0)))
+    c, r = 0.5 * (lp + lm), 0.5 * (lp - lm)
+    Xd = cf.to_device_block(gp.X0, torch.complex128)
+    plan.filter(Xd, m, c, r)
+    assert _rel(cf.to_host_block(Xd), go.chebyshev_filter(ops, gp.X0, m, c, r)) < 1e-11
+
+
+@pytest.mark.parametrize("refine", [True, False], ids=["refinement", "library"])
+def test_gamma_rayleigh_ritz(case, refine):
+    gp, ops, plan, _ = case
+    Y = go.chebyshev_filter(ops, gp.X0, 3, 1.0, 2.0)
+    lam, U, res = go.rayleigh_ritz(ops, Y)
+    plan.set_rr_refine(refine)
+    try:
+        Yd = cf.to_device_block(Y, torch.complex128)
+        ritz, rd = plan.rayleigh_ritz(Yd)
+    finally:
+        plan.set_rr_refine(True)
+    ritz = ritz.cpu().numpy()
+    assert np.all(np.abs(ritz - lam) <= 1e-10 * np.maximum(np.abs(lam), 1.0))
+    assert np.allclose(rd.cpu().numpy(), res, rtol=1e-6, atol=1e-9)
+    Ug = cf.to_host_block(Yd)
+    assert np.allclose(np.real(Ug.conj().T @ ops.apply_S(Ug)), np.eye(Ug.shape[1]), atol=1e-9)
+    assert np.abs(Ug[ops.map.zero].imag).max() <= 1e-12 * np.abs(Ug).max()  # still real functions
+
+
+def test_gamma_trajectory_and_bound(case):
+    gp, ops, plan, lp = case
+    lp_gpu = plan.upper_bound(torch.from_numpy(gp.v0), 10)
+    lp_o = matfree.lanczos_upper_bound(ops.full, gp.full.v0, 10)[0]
+    assert abs(lp_gpu - lp_o) <= 1e-10 * max(abs(lp_o), 1.0)
+    hist_o = go.chebfsi(ops, gp.X0, gp.cfg.m, 6, lp)[3]
+    hist = chebfsi(plan, cf.to_device_block(gp.X0, torch.complex128), gp.cfg.m, 6, lp)[2]
+    for ho, hg in zip(hist_o, hist):
+        assert np.all(np.abs(hg["ritz"] - ho["ritz"]) <= 1e-10 * np.maximum(np.abs(ho["ritz"]), 1.0))
+
+
+def test_gamma_mixed_and_locking(case):
+    gp, ops, plan, lp = case
+    pm = cf.plan_from_problem(gp, cf.CHEB_MIXED)
+    X = gp.X0
+    Xm = cf.to_device_block(X, torch.complex64)
+    assert _rel(cf.to_host_block(pm.apply_H(Xm)), ops.apply_H(X)) < 2e-5
+    assert _rel(cf.to_host_block(pm.apply_Sinv(Xm)), ops.apply_Sinv(X)) < 2e-5
+    lm = float(np.max(go.rayleigh_quotients(ops, X)))
+    c, r = 0.5 * (lp + lm), 0.5 * (lp - lm)
+    deg = (np.arange(X.shape[1]) % 5).astype(np.int32)
+    Xd = cf.to_device_block(X, torch.complex128)
+    plan.filter_degrees(Xd, deg, c, r)
+    got = cf.to_host_block(Xd)
+    for d in range(5):
+        cols = np.nonzero(deg == d)[0]
+        assert _rel(got[:, cols], go.chebyshev_filter(ops, X[:, cols], d, c, r)) < 1e-11
+
+
+def test_gamma_unavailable_and_bad_half_sphere(case):
+    gp, ops, plan, _ = case
+    Xd = cf.to_device_block(gp.X0, torch.complex128)
+    with pytest.raises(cf.ChebError):
+        plan.lobpcg_iterate(Xd, 0, 1e-8, plan.lobpcg_state(gp.cfg.nb),
+                            torch.zeros(gp.cfg.nb, dtype=torch.float64, device="cuda"))
+    with pytest.raises(cf.ChebError):
+        plan.filter_rr_backward(Xd, 2, 1.0, 2.0, torch.ones(2, dtype=torch.float64), 1)
+    bad = gp.gidx.copy()
+    bad[-1] = -bad[-1]  # an entry outside the half sphere
+    with pytest.raises(cf.ChebError):
+        cf.Plan(bad, gp.kin, gp.cfg.n, gp.full.proj_off, gp.full.Q is not None, gamma=True)
+
+
+def test_gamma_paw48_sampled():
+    """The paw48 shape as a Gamma plan: sampled bands of the filter against the oracle, one band at a time."""
+    gp = wl.make_gamma_problem(2)
+    plan = cf.plan_from_problem(gp, cf.CHEB_FP64)
+    ops = go.GammaOperators.from_problem(gp)
+    lp = plan.upper_bound(torch.from_numpy(gp.v0), 10)
+    Xd = cf.to_device_block(gp.X0, torch.complex128)
+    lm = float(plan.rayleigh_quotients(Xd).max())
+    c, r = 0.5 * (lp + lm), 0.5 * (lp - lm)
+    plan.filter(Xd, gp.cfg.m, c, r)
+    cols = [0, 131, 255]
+    ref = go.chebyshev_filter(ops, gp.X0[:, cols], gp.cfg.m, c, r)
+    got = cf.to_host_block(Xd[cols])
+    for k in range(len(cols)):
+        assert _rel(got[:, k], ref[:, k]) < 1e-11
