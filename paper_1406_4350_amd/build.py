@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchebfd.so")
-SOURCES = ["api.hip", "gemm.hip", "fft_kernels.hip", "small.hip"]
+SOURCES = ["api.hip", "gemm.hip", "fft_kernels.hip", "small.hip", "cluster.hip"]
 ARCH = os.environ.get("CHEBFD_ARCH", "gfx950")
 
 

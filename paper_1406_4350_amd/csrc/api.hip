@@ -208,6 +208,8 @@ struct Ws {
   c128 *Xa = nullptr, *Xb = nullptr, *T = nullptr, *M1 = nullptr, *M2 = nullptr, *F = nullptr;  // refinement
   double *absF = nullptr, *lam = nullptr, *res = nullptr;
   int* perm = nullptr;
+  unsigned* bits = nullptr;  // coupling graph of the refinement (n x ceil(n / 32) words)
+  int *cidx = nullptr, *coff = nullptr;  // its clusters: members (n), offsets (n + 1)
   float* bsc = nullptr;  // per-band power-of-two scales of the split GEMMs
   c128 *cp = nullptr, *cq = nullptr, *cr = nullptr;  // iterative capacitance solve: right side, solution, residual
   void* Xs = nullptr;   // band-sorted copy for the per-band degree filter
@@ -300,6 +302,9 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
         w->lam = b.take<double>(std::max(nb, 1));
         w->res = b.take<double>(4);
         w->perm = b.take<int>(std::max(nb, 1));
+        w->bits = b.take<unsigned>(size_t(std::max(nb, 1)) * ((std::max(nb, 1) + 31) / 32));
+        w->cidx = b.take<int>(std::max(nb, 1));
+        w->coff = b.take<int>(std::max(nb, 1) + 1);
       }
       part = std::max({part_elems(np, nb, p->npw), part_elems(nb, nb, p->npw), part_elems(nb, nb, np),
                        part_elems(np, nb, nb), part_elems(nb, nb, nb), part_elems(2 * nb, nb, nb),
@@ -829,8 +834,44 @@ template <typename T> struct Ops {
 
   // Warm start: after the column scaling the previous Ritz vectors make Z' close to I. Generalized iterative
   // refinement X <- X (I + F) (first-order correction of X^H S' X = I, X^H H' X diagonal) converges
-  // quadratically from there using only n^3 products; the result is accepted only after an explicit check of
-  // both conditions. Returns false (nothing written to ritz / Hs) when it does not converge.
+  // quadratically from there using only n^3 products. Where close Ritz values are strongly coupled (max |F| >
+  // kClusterStep), the pairs with |F_ij| > kClusterTie are grouped into clusters whose pencils are solved
+  // exactly, X <- X Q, before the first-order steps resume. The result is accepted only after an explicit
+  // check of both conditions. Returns false (nothing written to ritz / Hs) when it does not converge.
+  static constexpr double kClusterStep = 0.5, kClusterTie = 0.2;
+  static constexpr int kRefineIters = 40, kStallWindow = 5;
+
+  // connected components of the coupling graph (host union-find over the bit matrix); false if one has more
+  // than kClusterMax members
+  bool clusters_from_bits(int n, const std::vector<unsigned>& bits, std::vector<int>& idx, std::vector<int>& off) {
+    const int W = (n + 31) / 32;
+    std::vector<int> parent(n);
+    for (int i = 0; i < n; ++i) parent[i] = i;
+    auto find = [&](int x) {
+      while (parent[x] != x) { parent[x] = parent[parent[x]]; x = parent[x]; }
+      return x;
+    };
+    for (int i = 0; i < n; ++i)
+      for (int wd = 0; wd < W; ++wd)
+        for (unsigned m = bits[size_t(i) * W + wd]; m; m &= m - 1) {
+          const int j = 32 * wd + __builtin_ctz(m);
+          const int a = find(i), b = find(j);
+          if (a != b) parent[std::max(a, b)] = std::min(a, b);
+        }
+    std::vector<int> count(n, 0);
+    for (int i = 0; i < n; ++i) count[find(i)] += 1;
+    idx.clear();
+    off.assign(1, 0);
+    for (int r = 0; r < n; ++r) {
+      if (find(r) != r || count[r] < 2) continue;
+      if (count[r] > kClusterMax) return false;
+      for (int i = r; i < n; ++i)
+        if (find(i) == r) idx.push_back(i);
+      off.push_back(int(idx.size()));
+    }
+    return true;
+  }
+
   bool rr_refine(int n, double* ritz, const Ws& w, cheb_status* st_out) {
     *st_out = CHEB_OK;
     auto hip_fail = [&](hipError_t e) { *st_out = fail(p, CHEB_ERR_HIP, std::string("refinement: ") + hipGetErrorString(e)); return false; };
@@ -840,6 +881,7 @@ template <typename T> struct Ops {
     c128* HS = w.M2;  // [S'; H'] stacked: one product gives S' X and H' X together
     c128* TT = w.T;   // [S' X; H' X] (2n x n); read with ld n it is n x 2n with columns S'X_j, H'X_j interleaved
     c128* M = w.M1;   // X^H [S'X_0, H'X_0, S'X_1, ...]: X^H S' X has ld 2n at M, X^H H' X at M + n
+    int* cflag = w.flags + 3;  // cleared with the other flags before rr_prepare
     if ((e = convert_copy<double, double>(n, n, w.Ss, n, HS, n2, st))) return hip_fail(e);
     if ((e = convert_copy<double, double>(n, n, w.Hs, n, HS + n, n2, st))) return hip_fail(e);
     if ((e = identity_matrix(n, X, st))) return hip_fail(e);
@@ -847,7 +889,9 @@ template <typename T> struct Ops {
     const c128* M2 = w.Hs;
     long ld = n;
     bool conv = false;
-    double prev = 1e300;
+    std::vector<double> hist;
+    std::vector<unsigned> bits;
+    std::vector<int> cidx, coff;
     static const bool trace = std::getenv("CHEBFD_TRACE_RR") != nullptr;  // diagnostics: correction sizes
     auto products = [&](const c128* Xc) {
       Epi<double> e1;
@@ -860,25 +904,57 @@ template <typename T> struct Ops {
       return gemm<double, double, double, double>(GEMM_CN, n, 2 * n, n, Xc, n, TT, n, e2, gemm_pick_splits(n, 2 * n, n),
                                                   w.part, st, ROLE_SUBSPACE);
     };
-    for (int it = 0; it < 16; ++it) {
+    for (int it = 0; it < kRefineIters; ++it) {
       if ((e = refine_update(n, M1, ld, M2, ld, w.F, w.lam, w.absF, w.res + 2, st))) return hip_fail(e);
       double maxF = 0.0;
+      int bad = 0;
       if ((e = hipMemcpyAsync(&maxF, w.res + 2, sizeof(double), hipMemcpyDeviceToHost, st))) return hip_fail(e);
+      if ((e = hipMemcpyAsync(&bad, cflag, sizeof(int), hipMemcpyDeviceToHost, st))) return hip_fail(e);
       if ((e = hipStreamSynchronize(st))) return hip_fail(e);
       if (trace) std::fprintf(stderr, "[rr-refine] n=%d it=%d max|F|=%.3e\n", n, it, maxF);
-      // leave when clearly outside the region of convergence
-      if (!(maxF < 1.0) || (it >= 4 && maxF > 0.7 * prev)) return false;
-      prev = maxF;
-      Epi<double> eu;
-      eu.out = Xn; eu.ldo = n; eu.L = X; eu.ldl = n; eu.bL = 1.0;
-      if ((e = gemm<double, double, double, double>(GEMM_NN, n, n, n, X, n, w.F, n, eu, gemm_pick_splits(n, n, n), w.part,
-                                                    st, ROLE_SUBSPACE))) return hip_fail(e);
+      if (bad || std::isnan(maxF)) return false;
+      // leave when no longer converging: no halving against the best value before the last kStallWindow
+      hist.push_back(maxF);
+      if (int(hist.size()) > kStallWindow &&
+          maxF > 0.5 * *std::min_element(hist.begin(), hist.end() - kStallWindow))
+        return false;
+      bool cluster = false;
+      if (maxF > kClusterStep) {
+        const int W = (n + 31) / 32;
+        bits.resize(size_t(n) * W);
+        if ((e = coupling_bits(n, w.absF, kClusterTie, w.bits, st))) return hip_fail(e);
+        if ((e = hipMemcpyAsync(bits.data(), w.bits, bits.size() * sizeof(unsigned), hipMemcpyDeviceToHost, st)))
+          return hip_fail(e);
+        if ((e = hipStreamSynchronize(st))) return hip_fail(e);
+        if (!clusters_from_bits(n, bits, cidx, coff)) return false;
+        cluster = coff.size() > 1;
+        if (trace && cluster) std::fprintf(stderr, "[rr-refine]   %zu clusters, %zu bands\n", coff.size() - 1, cidx.size());
+      }
+      if (cluster) {
+        if ((e = hipMemcpyAsync(w.cidx, cidx.data(), cidx.size() * sizeof(int), hipMemcpyHostToDevice, st)) ||
+            (e = hipMemcpyAsync(w.coff, coff.data(), coff.size() * sizeof(int), hipMemcpyHostToDevice, st)) ||
+            (e = identity_matrix(n, w.F, st)) ||
+            (e = cluster_eig(int(coff.size()) - 1, M1, ld, M2, ld, w.cidx, w.coff, w.F, n, cflag, st)))
+          return hip_fail(e);
+        // the host vectors are reused next iteration: the copies above must have left them
+        if ((e = hipStreamSynchronize(st))) return hip_fail(e);
+        Epi<double> eq;
+        eq.out = Xn; eq.ldo = n;
+        if ((e = gemm<double, double, double, double>(GEMM_NN, n, n, n, X, n, w.F, n, eq, gemm_pick_splits(n, n, n),
+                                                      w.part, st, ROLE_SUBSPACE))) return hip_fail(e);
+      } else {
+        if (!(maxF < 1.0)) return false;  // outside the region where first-order steps converge
+        Epi<double> eu;
+        eu.out = Xn; eu.ldo = n; eu.L = X; eu.ldl = n; eu.bL = 1.0;
+        if ((e = gemm<double, double, double, double>(GEMM_NN, n, n, n, X, n, w.F, n, eu, gemm_pick_splits(n, n, n),
+                                                      w.part, st, ROLE_SUBSPACE))) return hip_fail(e);
+      }
       std::swap(X, Xn);
       if ((e = products(X))) return hip_fail(e);
       M1 = M;
       M2 = M + n;
       ld = n2;
-      if (maxF < 1e-10) { conv = true; break; }
+      if (!cluster && maxF < 1e-10) { conv = true; break; }
     }
     if (!conv) return false;
     double res[2] = {1.0, 1.0};

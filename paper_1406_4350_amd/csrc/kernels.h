@@ -178,4 +178,13 @@ hipError_t scale_cols_isqrt(int n, int ncols, c128* Z, long ldz, const double* s
 // out[i] = Re a[i] / Re b[i]
 hipError_t ratio_real(int nb, const c128* a, const c128* b, double* out, hipStream_t st);
 
+// Clusters of the Rayleigh-Ritz refinement: bits[i W + w] bit b set when |F_ij| > tau, j = 32 w + b, i != j
+// (W = ceil(n / 32)). cluster_eig solves each cluster's pencil (M2_CC, M1_CC), members idx[off[c] ..
+// off[c+1]) with 2 <= size <= kClusterMax, and writes its eigenvectors into the block (C, C) of Q, which must
+// hold the identity elsewhere; flag[0] = 1 if an M1_CC is not positive definite.
+constexpr int kClusterMax = 48;
+hipError_t coupling_bits(int n, const double* absF, double tau, unsigned* bits, hipStream_t st);
+hipError_t cluster_eig(int nclusters, const c128* M1, long ld1, const c128* M2, long ld2, const int* idx, const int* off,
+                       c128* Q, long ldq, int* flag, hipStream_t st);
+
 }  // namespace chebfd
