@@ -49,6 +49,7 @@ struct cheb_plan_s {
   HalfPlanes hproj, hback;                  // mixed plans: split planes of P (set with the projectors)
   bool split_gemm = true;                   // mixed plans: FP16 hi/lo split MFMA for P^H x and P w
   bool rr_refine = true;                    // warm-started refinement before the library eigensolver
+  double* rr_host = nullptr;                // pinned staging of the refinement's block maxima and flag
   int64_t rr_refined = 0, rr_fallback = 0;  // how Rayleigh-Ritz steps were solved
   rocblas_handle rb = nullptr;
   // pinned staging of the band permutation of cheb_filter_degrees; lock_ev marks the end of its last copy
@@ -210,6 +211,7 @@ struct Ws {
   int* perm = nullptr;
   unsigned* bits = nullptr;  // coupling graph of the refinement (n x ceil(n / 32) words)
   int *cidx = nullptr, *coff = nullptr;  // its clusters: members (n), offsets (n + 1)
+  double* bmax = nullptr;                // per-block maxima of |F|
   float* bsc = nullptr;  // per-band power-of-two scales of the split GEMMs
   c128 *cp = nullptr, *cq = nullptr, *cr = nullptr;  // iterative capacitance solve: right side, solution, residual
   void* Xs = nullptr;   // band-sorted copy for the per-band degree filter
@@ -305,6 +307,7 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
         w->bits = b.take<unsigned>(size_t(std::max(nb, 1)) * ((std::max(nb, 1) + 31) / 32));
         w->cidx = b.take<int>(std::max(nb, 1));
         w->coff = b.take<int>(std::max(nb, 1) + 1);
+        w->bmax = b.take<double>(kRefineBlocksMax);
       }
       part = std::max({part_elems(np, nb, p->npw), part_elems(nb, nb, p->npw), part_elems(nb, nb, np),
                        part_elems(np, nb, nb), part_elems(nb, nb, nb), part_elems(2 * nb, nb, nb),
@@ -882,6 +885,12 @@ template <typename T> struct Ops {
     c128* TT = w.T;   // [S' X; H' X] (2n x n); read with ld n it is n x 2n with columns S'X_j, H'X_j interleaved
     c128* M = w.M1;   // X^H [S'X_0, H'X_0, S'X_1, ...]: X^H S' X has ld 2n at M, X^H H' X at M + n
     int* cflag = w.flags + 3;  // cleared with the other flags before rr_prepare
+    if (!p->rr_host) {
+      const hipError_t ea = hipHostMalloc(reinterpret_cast<void**>(&p->rr_host), (kRefineBlocksMax + 1) * sizeof(double),
+                                          hipHostMallocDefault);
+      if (ea != hipSuccess) { p->rr_host = nullptr; return hip_fail(ea); }
+    }
+    double* const hst = p->rr_host;
     if ((e = convert_copy<double, double>(n, n, w.Ss, n, HS, n2, st))) return hip_fail(e);
     if ((e = convert_copy<double, double>(n, n, w.Hs, n, HS + n, n2, st))) return hip_fail(e);
     if ((e = identity_matrix(n, X, st))) return hip_fail(e);
@@ -905,12 +914,16 @@ template <typename T> struct Ops {
                                                   w.part, st, ROLE_SUBSPACE);
     };
     for (int it = 0; it < kRefineIters; ++it) {
-      if ((e = refine_update(n, M1, ld, M2, ld, w.F, w.lam, w.absF, w.res + 2, st))) return hip_fail(e);
-      double maxF = 0.0;
-      int bad = 0;
-      if ((e = hipMemcpyAsync(&maxF, w.res + 2, sizeof(double), hipMemcpyDeviceToHost, st))) return hip_fail(e);
-      if ((e = hipMemcpyAsync(&bad, cflag, sizeof(int), hipMemcpyDeviceToHost, st))) return hip_fail(e);
+      if ((e = refine_update(n, M1, ld, M2, ld, w.F, w.lam, w.absF, w.bmax, st))) return hip_fail(e);
+      // block maxima and the cluster flag in one pinned staging buffer, one synchronization
+      const int nbm = refine_blocks(n);
+      if ((e = hipMemcpyAsync(hst, w.bmax, nbm * sizeof(double), hipMemcpyDeviceToHost, st))) return hip_fail(e);
+      if ((e = hipMemcpyAsync(hst + kRefineBlocksMax, cflag, sizeof(int), hipMemcpyDeviceToHost, st))) return hip_fail(e);
       if ((e = hipStreamSynchronize(st))) return hip_fail(e);
+      double maxF = 0.0;
+      for (int b = 0; b < nbm; ++b) maxF = std::isnan(hst[b]) ? hst[b] : std::max(maxF, hst[b]);
+      int bad = 0;
+      std::memcpy(&bad, hst + kRefineBlocksMax, sizeof(int));
       if (trace) std::fprintf(stderr, "[rr-refine] n=%d it=%d max|F|=%.3e\n", n, it, maxF);
       if (bad || std::isnan(maxF)) return false;
       // leave when no longer converging: no halving against the best value before the last kStallWindow
@@ -963,7 +976,7 @@ template <typename T> struct Ops {
     if ((e = hipStreamSynchronize(st))) return hip_fail(e);
     if (!(res[0] <= 1e-12) || !(res[1] <= 1e-12)) return false;
     // eigenvalues of the verified X, ascending; Z = d .* X[:, perm] replaces H_X in w.Hs
-    if ((e = refine_update(n, M1, ld, M2, ld, w.F, w.lam, w.absF, w.res + 2, st))) return hip_fail(e);
+    if ((e = refine_update(n, M1, ld, M2, ld, w.F, w.lam, w.absF, w.bmax, st))) return hip_fail(e);
     if ((e = sort_eigen(n, w.lam, ritz, w.perm, X, w.d, w.Hs, st))) return hip_fail(e);
     return true;
   }
@@ -1751,6 +1764,7 @@ cheb_status cheb_plan_destroy(cheb_plan p) {
   if (p->rb) rocblas_destroy_handle(p->rb);
   if (p->lock_ev) { (void)hipEventSynchronize(p->lock_ev); (void)hipEventDestroy(p->lock_ev); }
   if (p->lock_host) (void)hipHostFree(p->lock_host);
+  if (p->rr_host) (void)hipHostFree(p->rr_host);
   delete p;
   return CHEB_OK;
 }

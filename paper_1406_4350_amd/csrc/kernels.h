@@ -154,9 +154,12 @@ hipError_t sub_lambda_cols(long rows, int ncols, cx<E>* R, long ldr, const cx<E>
 template <typename E> hipError_t fill_zero_real(E* p, long count, hipStream_t st);
 // Warm-started refinement of H X = S X Lambda (n x n, FP64): given M1 = X^H S X, M2 = X^H H X, the correction
 // X <- X (I + F) with F_ij = (M2_ij - lam_j M1_ij)/(lam_j - lam_i), F_ii = (1 - M1_ii)/2, lam_i = M2_ii/M1_ii;
-// maxF[0] = max off-diagonal |F| (1e300 for an unresolvable near-degenerate pair)
+// absF = off-diagonal |F| (1e300 for an unresolvable near-degenerate pair); bmax[b] = the maximum of block b's
+// entries (NaN if one is NaN) for b < refine_blocks(n) <= kRefineBlocksMax
+constexpr int kRefineBlocksMax = 256;
+int refine_blocks(int n);
 hipError_t refine_update(int n, const c128* M1, long ld1, const c128* M2, long ld2, c128* F, double* lam, double* absF,
-                         double* maxF, hipStream_t st);
+                         double* bmax, hipStream_t st);
 // res[0] = max |M1 - I|, res[1] = max off-diagonal |M2| / max(1, max |diag M2|)
 hipError_t refine_check(int n, const c128* M1, long ld1, const c128* M2, long ld2, double* res, hipStream_t st);
 hipError_t identity_matrix(int n, c128* X, hipStream_t st);

@@ -597,8 +597,13 @@ namespace {
 // M1 = X^H S X, M2 = X^H H X (n x n). lam_i = Re M2_ii / Re M1_ii; F_ij = (M2_ij - lam_j M1_ij) / (lam_j - lam_i)
 // for i != j, F_ii = (1 - M1_ii) / 2. absF[t] = |F_t| (off-diagonal) for the convergence test; pairs closer
 // than the resolution threshold get F_ij = -M1_ij / 2 and a nonzero absF if their coupling is not negligible.
-__global__ void k_refine_update(int n, const c128* M1, long ld1, const c128* M2, long ld2, c128* F, double* lam,
-                                double* absF) {
+// maximum that keeps a NaN (fmax would drop it)
+__device__ __forceinline__ double max_nan(double a, double b) { return (a != a || b != b) ? a + b : fmax(a, b); }
+
+__global__ __launch_bounds__(256) void k_refine_update(int n, const c128* M1, long ld1, const c128* M2, long ld2, c128* F,
+                                                      double* lam, double* absF, double* bmax) {
+  __shared__ double red[256];
+  double mx = 0.0;
   const long total = long(n) * n;
   for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
     const int j = int(t / n), i = int(t - long(j) * n);
@@ -617,12 +622,22 @@ __global__ void k_refine_update(int n, const c128* M1, long ld1, const c128* M2,
     if (fabs(gap) > 1e-9 * scale) {
       F[t] = c128{nr / gap, ni / gap};
       absF[t] = sqrt(nr * nr + ni * ni) / fabs(gap);
+      mx = max_nan(mx, absF[t]);
     } else {
       F[t] = c128{-0.5 * m1.x, -0.5 * m1.y};
       const double cpl = sqrt(nr * nr + ni * ni);
       absF[t] = cpl > 1e-13 * scale ? 1e300 : 0.0;  // unresolvable near-degenerate coupling
+      mx = max_nan(mx, absF[t]);
     }
   }
+  // per-block maximum, fixed-order tree
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] = max_nan(red[threadIdx.x], red[threadIdx.x + k]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bmax[blockIdx.x] = red[0];
 }
 
 // res[0] = max |M1 - I|, res[1] = max_{i != j} |M2_ij| / max(1, max_i |M2_ii|)  (one block, fixed order)
@@ -652,19 +667,6 @@ __global__ __launch_bounds__(1024) void k_refine_check(int n, const c128* M1, lo
 }
 
 // out[0] = max of x[0..count) (one block, fixed order)
-__global__ __launch_bounds__(1024) void k_max_reduce(long count, const double* x, double* out) {
-  __shared__ double s[1024];
-  double a = 0.0;
-  for (long t = threadIdx.x; t < count; t += blockDim.x) a = fmax(a, x[t]);
-  s[threadIdx.x] = a;
-  __syncthreads();
-  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
-    if (threadIdx.x < k) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + k]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = s[0];
-}
-
 __global__ void k_identity(int n, c128* X) {
   const long total = long(n) * n;
   for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
@@ -716,10 +718,11 @@ __global__ void k_permute_scale(int n, const c128* X, const int* perm, const dou
 }
 }  // namespace
 
+int refine_blocks(int n) { return nblocks(long(n) * n, 256, kRefineBlocksMax); }
+
 hipError_t refine_update(int n, const c128* M1, long ld1, const c128* M2, long ld2, c128* F, double* lam, double* absF,
-                         double* maxF, hipStream_t st) {
-  hipLaunchKernelGGL(k_refine_update, dim3(nblocks(long(n) * n)), dim3(256), 0, st, n, M1, ld1, M2, ld2, F, lam, absF);
-  hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(1024), 0, st, long(n) * n, absF, maxF);
+                         double* bmax, hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_update, dim3(refine_blocks(n)), dim3(256), 0, st, n, M1, ld1, M2, ld2, F, lam, absF, bmax);
   return hipGetLastError();
 }
 hipError_t refine_check(int n, const c128* M1, long ld1, const c128* M2, long ld2, double* res, hipStream_t st) {
