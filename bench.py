@@ -480,6 +480,7 @@ def main():
                      "accumulation); FP64 projector space and Rayleigh-Ritz",
             "accuracy": mixed_accuracy(cf, pb, r64, rmx, lam_plus, args.ref_iters) if args.ref_iters > 0 else None,
             "breakdown_ms_per_step": {k: v["ms"] / args.steps for k, v in rmx["prof"].items()},
+            "rr_solves_refined_library": rmx["rr_stats"],
             "roofline": roofline(rmx["prof"], "f32", cfg.n),
         }
     if args.lock_tol > 0:

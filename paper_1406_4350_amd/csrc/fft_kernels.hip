@@ -117,7 +117,6 @@ __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __re
   const long base = long(band) * N * ncol + long(z) * ncol;
   const cx<T>* in = cin + base;
   cx<T>* out = cout + base;
-  const cx<T> zero = {T(0), T(0)};
   for (int t = tid; t < N; t += NT) tw[t] = twg[t];
   __syncthreads();
   stage_twiddles<N, T>(tw, twA, twB);
@@ -131,7 +130,7 @@ __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __re
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
       const int j = freq<N>(N2 * n1 + n2) - xl.y;
-      v[n1] = (j >= 0 && j < xl.z) ? in[xl.x + j] : zero;
+      v[n1] = (j >= 0 && j < xl.z) ? cx<T>(in[xl.x + j]) : cx<T>{T(0), T(0)};
     }
     Dft<N1, +1>::run(v);
 #pragma unroll
@@ -170,7 +169,7 @@ __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __re
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) {
         const int gx = freq<N>(N2 * n1 + n2);
-        v[n1] = (gx >= -rx && gx <= rx) ? L[(gx + rx) * LS + py] : zero;
+        v[n1] = (gx >= -rx && gx <= rx) ? cx<T>(L[(gx + rx) * LS + py]) : cx<T>{T(0), T(0)};
       }
       Dft<N1, +1>::run(v);
 #pragma unroll
@@ -251,7 +250,6 @@ __device__ __forceinline__ void y_inverse(const cx<T>* __restrict__ in, cx<T>* L
                                           const cx<T>* twA, int nx) {
   constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = line_stride<N>(), PS = group_stride<N>();
   const int tid = threadIdx.x;
-  const cx<T> zero = {T(0), T(0)};
   for (int task = tid; task < nx * N2; task += NT) {
     const int xi = task / N2, n2 = task - xi * N2;
     const int4 xl = xline[xi];
@@ -259,7 +257,7 @@ __device__ __forceinline__ void y_inverse(const cx<T>* __restrict__ in, cx<T>* L
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
       const int j = freq<N>(N2 * n1 + n2) - xl.y;
-      v[n1] = (j >= 0 && j < xl.z) ? in[xl.x + j] : zero;
+      v[n1] = (j >= 0 && j < xl.z) ? cx<T>(in[xl.x + j]) : cx<T>{T(0), T(0)};
     }
     Dft<N1, +1>::run(v);
 #pragma unroll
@@ -282,7 +280,6 @@ __device__ __forceinline__ void y_inverse(const cx<T>* __restrict__ in, cx<T>* L
 template <int N, typename T>
 __device__ __forceinline__ void x_inverse_stage1(const cx<T>* L, cx<T>* S, const cx<T>* twA, int rx, int y0, int nrow) {
   constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = line_stride<N>(), PS = group_stride<N>();
-  const cx<T> zero = {T(0), T(0)};
   for (int task = threadIdx.x; task < nrow * N2; task += NT) {
     const int yy = task / N2, n2 = task - yy * N2;
     const int y = y0 + yy, py = PS * (y % N1) + y / N1;
@@ -290,7 +287,7 @@ __device__ __forceinline__ void x_inverse_stage1(const cx<T>* L, cx<T>* S, const
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
       const int gx = freq<N>(N2 * n1 + n2);
-      v[n1] = (gx >= -rx && gx <= rx) ? L[(gx + rx) * LS + py] : zero;
+      v[n1] = (gx >= -rx && gx <= rx) ? cx<T>(L[(gx + rx) * LS + py]) : cx<T>{T(0), T(0)};
     }
     Dft<N1, +1>::run(v);
 #pragma unroll
