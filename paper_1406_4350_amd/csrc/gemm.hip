@@ -37,13 +37,19 @@ __device__ __forceinline__ void epi_store(const Epi<E>& e, long m, long n, doubl
 }
 
 // One 64 x 64 complex output tile per block of 4 waves; wave w owns the 32 x 32 quadrant
-// (w & 1, w >> 1) as 2 x 2 MFMA blocks with separate real and imaginary accumulators.
+// (w & 1, w >> 1) as 2 x 2 MFMA blocks. FP64 tiles take three real products per complex product
+// (P1 = a_r b_r, P2 = a_i b_i, P3 = (a_r + s a_i)(b_r + b_i) with s = 1 for a b and s = -1 for conj(a) b:
+// re = P1 - s P2, im = P3 - P1 - s P2); FP32 tiles keep the four-product form, whose rounding does not
+// grow with the magnitude of the other component.
 // ROLE only separates kernel names per use (projection, back-projection, small, subspace) for profiling.
 template <typename T, typename EA, typename EB, typename EO, int MODE, int ROLE>
-__global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, const cx<EA>* __restrict__ A,
+__global__ __launch_bounds__(NT, 2) void k_gemm(int M, int N, int K, int kchunk, const cx<EA>* __restrict__ A,
                                              long lda, const cx<EB>* __restrict__ B, long ldb, Epi<EO> epi,
                                              c128* __restrict__ part) {
+  constexpr bool G3 = sizeof(T) == 8;
+  constexpr int SP = G3 ? BK : 1;  // the sum planes exist only for the three-product form
   __shared__ T Ar[BK][BM + PAD], Ai[BK][BM + PAD], Br[BK][BN + PAD], Bi[BK][BN + PAD];
+  __shared__ T As[SP][BM + PAD], Bs[SP][BN + PAD];
   using acc_t = typename Mfma<T>::acc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -52,13 +58,13 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, co
   const int kbeg = blockIdx.z * kchunk;
   const int kend = min(K, kbeg + kchunk);
 
-  acc_t cr[2][2], ci[2][2];
+  acc_t cr[2][2], ci[2][2], c3[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) { cr[i][j][v] = T(0); ci[i][j][v] = T(0); }
+      for (int v = 0; v < 4; ++v) { cr[i][j][v] = T(0); ci[i][j][v] = T(0); c3[i][j][v] = T(0); }
 
   // global -> registers for one K tile (raw storage type, so that the loads stay in flight while the previous
   // tile is multiplied), registers -> LDS planes converted to the MFMA type
@@ -98,6 +104,7 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, co
       else { mm = idx % BM; kk = idx / BM; }
       Ar[kk][mm] = T(va[r].x);
       Ai[kk][mm] = T(va[r].y);
+      if constexpr (G3) As[kk][mm] = MODE == GEMM_CN ? T(va[r].x) - T(va[r].y) : T(va[r].x) + T(va[r].y);
     }
 #pragma unroll
     for (int r = 0; r < RBn; ++r) {
@@ -105,6 +112,7 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, co
       const int kk = idx % BK, nn = idx / BK;
       Br[kk][nn] = T(vb[r].x);
       Bi[kk][nn] = T(vb[r].y);
+      if constexpr (G3) Bs[kk][nn] = T(vb[r].x) + T(vb[r].y);
     }
   };
 
@@ -126,20 +134,39 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, co
         br[i] = Br[ks + lk][wn + 16 * i + li];
         bi[i] = Bi[ks + lk][wn + 16 * i + li];
       }
+      if constexpr (G3) {
+        // cr <- P1, ci <- P2, c3 <- P3
+        T as[2], bs[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < 2; ++i) {
+          as[i] = As[ks + lk][wm + 16 * i + li];
+          bs[i] = Bs[ks + lk][wn + 16 * i + li];
+        }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          if (MODE == GEMM_CN) {  // conj(a) b
+        for (int i = 0; i < 2; ++i) {
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
             cr[i][j] = Mfma<T>::run(ar[i], br[j], cr[i][j]);
-            cr[i][j] = Mfma<T>::run(ai[i], bi[j], cr[i][j]);
-            ci[i][j] = Mfma<T>::run(ar[i], bi[j], ci[i][j]);
-            ci[i][j] = Mfma<T>::run(-ai[i], br[j], ci[i][j]);
-          } else {  // a b
-            cr[i][j] = Mfma<T>::run(ar[i], br[j], cr[i][j]);
-            cr[i][j] = Mfma<T>::run(-ai[i], bi[j], cr[i][j]);
-            ci[i][j] = Mfma<T>::run(ar[i], bi[j], ci[i][j]);
-            ci[i][j] = Mfma<T>::run(ai[i], br[j], ci[i][j]);
+            ci[i][j] = Mfma<T>::run(ai[i], bi[j], ci[i][j]);
+            c3[i][j] = Mfma<T>::run(as[i], bs[j], c3[i][j]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            if (MODE == GEMM_CN) {  // conj(a) b
+              cr[i][j] = Mfma<T>::run(ar[i], br[j], cr[i][j]);
+              cr[i][j] = Mfma<T>::run(ai[i], bi[j], cr[i][j]);
+              ci[i][j] = Mfma<T>::run(ar[i], bi[j], ci[i][j]);
+              ci[i][j] = Mfma<T>::run(-ai[i], br[j], ci[i][j]);
+            } else {  // a b
+              cr[i][j] = Mfma<T>::run(ar[i], br[j], cr[i][j]);
+              cr[i][j] = Mfma<T>::run(-ai[i], bi[j], cr[i][j]);
+              ci[i][j] = Mfma<T>::run(ar[i], bi[j], ci[i][j]);
+              ci[i][j] = Mfma<T>::run(ai[i], br[j], ci[i][j]);
+            }
           }
         }
       }
@@ -151,6 +178,19 @@ __global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, co
     }
   }
 
+  if constexpr (G3) {
+    constexpr T sg = MODE == GEMM_CN ? T(-1) : T(1);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const T p1 = cr[i][j][v], p2 = ci[i][j][v], p3 = c3[i][j][v];
+          cr[i][j][v] = p1 - sg * p2;
+          ci[i][j][v] = p3 - p1 - sg * p2;
+        }
+  }
   // accumulator v of a lane holds column li of each 16 x 16 block, row 4*lk + v for the f32 MFMA and
   // row lk + 4*v for the f64 MFMA (lane layouts of the two 16x16x4 instructions differ)
 #pragma unroll
@@ -373,7 +413,9 @@ __global__ void k_split_planes(const c128* __restrict__ X, long ldx, int ksrc, b
 int gemm_pick_splits(int M, int N, int K) {
   if (M <= 0 || N <= 0 || K <= 0) return 1;
   const long tiles = long((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  const long want = 512;  // ~2 blocks per CU: enough to fill the chip, half the partial-sum traffic
+  // about one block per CU: measured on the paw48 projector shapes, the tall NN products (448 tiles) run best
+  // without split-K and the 256 x 256 x 7153 reductions with 16 splits
+  const long want = 256;
   long s = (want + tiles - 1) / tiles;
   const long kblocks = (K + BK - 1) / BK;
   if (s > kblocks / 2) s = kblocks / 2;  // at least two K tiles per split
@@ -414,6 +456,20 @@ hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, c
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL((k_reduce<EO>), dim3(blocks), dim3(256), 0, st, M, N, splits, part, epi);
   return hipGetLastError();
+}
+
+// upper bound of the split counts any GEMM kernel here picks for an M x N x K product (partial-buffer sizing):
+// 512 target blocks, two K tiles of 16 per split, at most 32 splits; gemm_pick_splits and gemm_h_pick_splits
+// never exceed it
+int gemm_split_bound(int M, int N, int K) {
+  if (M <= 0 || N <= 0 || K <= 0) return 1;
+  const long tiles = long((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  long s = (512 + tiles - 1) / tiles;
+  const long kblocks = (K + BK - 1) / BK;
+  if (s > kblocks / 2) s = kblocks / 2;
+  if (s > 32) s = 32;
+  if (s < 1) s = 1;
+  return int(std::max<long>(s, std::max(gemm_pick_splits(M, N, K), gemm_h_pick_splits(M, N, K))));
 }
 
 int gemm_h_pick_splits(int M, int N, int K) {

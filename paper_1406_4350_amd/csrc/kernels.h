@@ -51,6 +51,8 @@ template <typename EB, typename EO>
 hipError_t gemm_h(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const cx<EB>* B, long ldb,
                   const float* bscale, const Epi<EO>& epi, int splits, c128* part, hipStream_t st, GemmRole role);
 int gemm_h_pick_splits(int M, int N, int K);
+// upper bound of both split rules, for sizing split-K partial buffers
+int gemm_split_bound(int M, int N, int K);
 // bscale[n] = 2^-e with max_k |B[k][n]| (over Re and Im) in [2^(e-1), 2^e); 1 for a zero column
 template <typename E> hipError_t column_scales(long rows, int ncols, const cx<E>* B, long ldb, float* bscale,
                                                hipStream_t st);
