@@ -27,6 +27,21 @@ template <> struct Mfma<float> {
 
 constexpr int BM = 64, BN = 64, BK = 16, PAD = 2, NT = 256;
 
+// Block placement. The hardware deals the blocks of a launch to the 8 XCDs in turn (block i to XCD i mod 8),
+// each XCD with its own L2. Logical work items are numbered (split, M tile, N tile) with the N tile fastest,
+// so items that share a slice of A (same split and M tile) or of B (same split) are neighbours; physical block
+// i takes the logical item that gives each XCD one contiguous run of items, and the shared slices are read
+// from HBM once per XCD instead of once per block.
+__host__ __device__ inline void gemm_tile_of(int i, int total, int tm, int tn, int& bx, int& by, int& bz) {
+  const int q = total / 8, rem = total % 8, k = i % 8, j = i / 8;
+  const int L = (k < rem ? k * (q + 1) : rem * (q + 1) + (k - rem) * q) + j;
+  const int per = tm * tn;
+  bz = L / per;
+  const int t = L - bz * per;
+  bx = t / tn;
+  by = t - bx * tn;
+}
+
 template <typename E>
 __device__ __forceinline__ void epi_store(const Epi<E>& e, long m, long n, double re, double im) {
   double xr = e.alpha * re, xi = e.alpha * im;
@@ -54,8 +69,10 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(int M, int N, int K, int kchunk,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  const long m0 = long(blockIdx.x) * BM, n0 = long(blockIdx.y) * BN;
-  const int kbeg = blockIdx.z * kchunk;
+  int bx, by, bz;
+  gemm_tile_of(blockIdx.x, gridDim.x, (M + BM - 1) / BM, (N + BN - 1) / BN, bx, by, bz);
+  const long m0 = long(bx) * BM, n0 = long(by) * BN;
+  const int kbeg = bz * kchunk;
   const int kend = min(K, kbeg + kchunk);
 
   acc_t cr[2][2], ci[2][2], c3[2][2];
@@ -204,7 +221,7 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(int M, int N, int K, int kchunk,
         const long n = n0 + wn + 16 * j + li;
         if (m < M && n < N) {
           if (part) {
-            part[(long(blockIdx.z) * N + n) * M + m] = c128{double(cr[i][j][v]), double(ci[i][j][v])};
+            part[(long(bz) * N + n) * M + m] = c128{double(cr[i][j][v]), double(ci[i][j][v])};
           } else {
             epi_store(epi, m, n, double(cr[i][j][v]), double(ci[i][j][v]));
           }
@@ -254,8 +271,10 @@ __global__ __launch_bounds__(NT) void k_gemm_h(int M, int N, int K, int kchunk, 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  const long m0 = long(blockIdx.x) * BM, n0 = long(blockIdx.y) * BN;
-  const int kbeg = blockIdx.z * kchunk;
+  int bx, by, bz;
+  gemm_tile_of(blockIdx.x, gridDim.x, (M + BM - 1) / BM, (N + BN - 1) / BN, bx, by, bz);
+  const long m0 = long(bx) * BM, n0 = long(by) * BN;
+  const int kbeg = bz * kchunk;
   const int kend = min(K, kbeg + kchunk);
 
   f4 cr[2][2], ci[2][2];
@@ -357,7 +376,7 @@ __global__ __launch_bounds__(NT) void k_gemm_h(int M, int N, int K, int kchunk, 
         const long m = m0 + wm + 16 * i + 4 * lk + v;
         if (m < M && n < N) {
           const double re = f * double(cr[i][j][v]), im = f * double(ci[i][j][v]);
-          if (part) part[(long(blockIdx.z) * N + n) * M + m] = c128{re, im};
+          if (part) part[(long(bz) * N + n) * M + m] = c128{re, im};
           else epi_store(epi, m, n, re, im);
         }
       }
@@ -435,7 +454,7 @@ hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, c
   splits = K > 0 ? (K + kchunk - 1) / kchunk : 1;
   const bool use_part = splits > 1;
   if (use_part && !part) return hipErrorInvalidValue;
-  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, splits);
+  dim3 grid(((M + BM - 1) / BM) * ((N + BN - 1) / BN) * splits);
   c128* pp = use_part ? part : nullptr;
   auto launch = [&](auto modec, auto rolec) {
     constexpr int MO = decltype(modec)::value, RO = decltype(rolec)::value;
@@ -495,7 +514,7 @@ hipError_t gemm_h(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const
   splits = K > 0 ? (K + kchunk - 1) / kchunk : 1;
   const bool use_part = splits > 1;
   if (use_part && !part) return hipErrorInvalidValue;
-  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, splits);
+  dim3 grid(((M + BM - 1) / BM) * ((N + BN - 1) / BN) * splits);
   c128* pp = use_part ? part : nullptr;
   auto launch = [&](auto modec, auto rolec) {
     constexpr int MO = decltype(modec)::value, RO = decltype(rolec)::value;
