@@ -403,6 +403,7 @@ cheb_status solver_query(cheb_plan p, int op, int n, size_t* bytes) {
       rocblas_dtrsm(p->rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
                     rocblas_diagonal_non_unit, n, n, &one, nullptr, n, nullptr, n);
       rocsolver_dsyevd(p->rb, rocblas_evect_original, rocblas_fill_lower, n, nullptr, n, nullptr, nullptr, nullptr);
+      rocsolver_dsyev(p->rb, rocblas_evect_original, rocblas_fill_lower, n, nullptr, n, nullptr, nullptr, nullptr);
     }
   } else {
     rocsolver_zpotrf(p->rb, rocblas_fill_lower, n, nullptr, n, nullptr);
@@ -1016,12 +1017,22 @@ template <typename T> struct Ops {
       RBCHK(rocblas_set_stream(p->rb, st));
       RBCHK(rocblas_set_workspace(p->rb, w.solver, w.solver_bytes));
       rocblas_status rs = rocblas_status_success;
+      // divide and conquer, checked for non-finite vectors (returned with info 0 on some inputs whose tridiagonal
+      // splits into many deflated pieces); then the QR algorithm from a copy of the standard-form matrix
+      int ef[3] = {0, 0, 0};  // factorization info, eigensolver info, non-finite vectors
+      auto read_flags = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(ef, w.flags + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+        if (!e) e = hipMemcpyAsync(ef + 2, w.flags, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (!e) e = hipStreamSynchronize(st);
+        return e;
+      };
       if (p->gamma) {
         // real symmetric pencil (Gamma point): real factorization and eigensolver keep Z real, so the rotated
         // bands stay real functions
         Timed t(p, st, CHEB_T_RR_EIG, 0.0, 0.0);
         double* Hr = reinterpret_cast<double*>(w.Xa);
         double* Sr = reinterpret_cast<double*>(w.Xb);
+        double* Hc = reinterpret_cast<double*>(w.T);  // copy of the standard-form matrix
         HIPCHK(real_part(nb, nb, w.Hs, nb, Hr, nb, st));
         HIPCHK(real_part(nb, nb, w.Ss, nb, Sr, nb, st));
         const double one = 1.0;
@@ -1032,9 +1043,25 @@ template <typename T> struct Ops {
         if (rs == rocblas_status_success)
           rs = rocblas_dtrsm(p->rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
                              rocblas_diagonal_non_unit, nb, nb, &one, Sr, nb, Hr, nb);
-        if (rs == rocblas_status_success)
+        if (rs == rocblas_status_success) {
+          HIPCHK(hipMemcpyAsync(Hc, Hr, size_t(nb) * nb * sizeof(double), hipMemcpyDeviceToDevice, st));
           rs = rocsolver_dsyevd(p->rb, rocblas_evect_original, rocblas_fill_lower, nb, Hr, nb, ritz, w.E, w.flags + 3);
-        if (rs == rocblas_status_success)
+        }
+        if (rs == rocblas_status_success) {
+          HIPCHK(fill_zero_real<int>(w.flags, 1, st));
+          HIPCHK(flag_nonfinite_real(long(nb) * nb, Hr, w.flags, st));
+          HIPCHK(read_flags());
+          if (ef[0] == 0 && (ef[1] != 0 || ef[2] != 0)) {
+            HIPCHK(hipMemcpyAsync(Hr, Hc, size_t(nb) * nb * sizeof(double), hipMemcpyDeviceToDevice, st));
+            rs = rocsolver_dsyev(p->rb, rocblas_evect_original, rocblas_fill_lower, nb, Hr, nb, ritz, w.E, w.flags + 3);
+            if (rs == rocblas_status_success) {
+              HIPCHK(fill_zero_real<int>(w.flags, 1, st));
+              HIPCHK(flag_nonfinite_real(long(nb) * nb, Hr, w.flags, st));
+              HIPCHK(read_flags());
+            }
+          }
+        }
+        if (rs == rocblas_status_success && ef[0] == 0)
           rs = rocblas_dtrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
                              rocblas_diagonal_non_unit, nb, nb, &one, Sr, nb, Hr, nb);
         if (rs == rocblas_status_success) HIPCHK(complex_from_real(nb, nb, Hr, nb, w.Hs, nb, st));
@@ -1042,6 +1069,7 @@ template <typename T> struct Ops {
         Timed t(p, st, CHEB_T_RR_EIG, 0.0, 0.0);
         rocblas_double_complex* Hd = reinterpret_cast<rocblas_double_complex*>(w.Hs);
         rocblas_double_complex* Ld = reinterpret_cast<rocblas_double_complex*>(w.Ss);
+        c128* Hc = w.Xa;  // copy of the standard-form matrix
         const rocblas_double_complex one = {1.0, 0.0};
         rs = rocsolver_zpotrf(p->rb, rocblas_fill_lower, nb, Ld, nb, w.flags + 2);
         if (rs == rocblas_status_success)
@@ -1050,19 +1078,34 @@ template <typename T> struct Ops {
         if (rs == rocblas_status_success)
           rs = rocblas_ztrsm(p->rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
                              rocblas_diagonal_non_unit, nb, nb, &one, Ld, nb, Hd, nb);
-        if (rs == rocblas_status_success)
+        if (rs == rocblas_status_success) {
+          HIPCHK((convert_copy<double, double>(nb, nb, w.Hs, nb, Hc, nb, st)));
           rs = rocsolver_zheevd(p->rb, rocblas_evect_original, rocblas_fill_lower, nb, Hd, nb, ritz, w.E, w.flags + 3);
-        if (rs == rocblas_status_success)
+        }
+        if (rs == rocblas_status_success) {
+          HIPCHK(fill_zero_real<int>(w.flags, 1, st));
+          HIPCHK(flag_nonfinite(nb, nb, w.Hs, nb, w.flags, st));
+          HIPCHK(read_flags());
+          if (ef[0] == 0 && (ef[1] != 0 || ef[2] != 0)) {
+            HIPCHK((convert_copy<double, double>(nb, nb, Hc, nb, w.Hs, nb, st)));
+            rs = rocsolver_zheev(p->rb, rocblas_evect_original, rocblas_fill_lower, nb, Hd, nb, ritz, w.E, w.flags + 3);
+            if (rs == rocblas_status_success) {
+              HIPCHK(fill_zero_real<int>(w.flags, 1, st));
+              HIPCHK(flag_nonfinite(nb, nb, w.Hs, nb, w.flags, st));
+              HIPCHK(read_flags());
+            }
+          }
+        }
+        if (rs == rocblas_status_success && ef[0] == 0)
           rs = rocblas_ztrsm(p->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
                              rocblas_diagonal_non_unit, nb, nb, &one, Ld, nb, Hd, nb);
       }
       rocblas_set_workspace(p->rb, nullptr, 0);
       if (rs != rocblas_status_success)
         return fail(p, CHEB_ERR_HIP, std::string("dense eigensolver: ") + rocblas_status_to_string(rs));
-      HIPCHK(hipMemcpyAsync(flags, w.flags + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (flags[0] != 0) return fail(p, CHEB_ERR_NOT_PD, "X^H S X is not positive definite (rank-deficient block)");
-      if (flags[1] != 0) return fail(p, CHEB_ERR_EIG, "Hermitian eigensolver did not converge");
+      if (ef[0] != 0) return fail(p, CHEB_ERR_NOT_PD, "X^H S X is not positive definite (rank-deficient block)");
+      if (ef[1] != 0) return fail(p, CHEB_ERR_EIG, "Hermitian eigensolver did not converge");
+      if (ef[2] != 0) return fail(p, CHEB_ERR_EIG, "Hermitian eigensolver returned non-finite vectors");
       // Z = diag(d) Z' undoes the symmetric column scaling
       HIPCHK(scale_rows(nb, nb, w.Hs, nb, w.d, st));
     }
@@ -1174,8 +1217,9 @@ template <typename T> struct Ops {
   }
 
   // Eigendecomposition of the Hermitian n x n matrix A (ld n, lower triangle used) in place, eigenvalues to lam
-  // ascending: divide and conquer, and if that reports no convergence the QR algorithm from a copy of A kept
-  // in spare (n x n). Synchronizes to read the status.
+  // ascending: divide and conquer, and if that reports no convergence or returns non-finite vectors (seen with
+  // info 0 on scaled Gram matrices whose leading block is the identity, where the tridiagonal splits into many
+  // deflated pieces) the QR algorithm from a copy of A kept in spare (n x n). Synchronizes to read the status.
   cheb_status heev_checked(int n, c128* A, c128* spare, double* lam, const Ws& w, const char* what) {
     HIPCHK((convert_copy<double, double>(n, n, A, n, spare, n, st)));
     RBCHK(rocblas_set_stream(p->rb, st));
@@ -1184,21 +1228,26 @@ template <typename T> struct Ops {
                                          reinterpret_cast<rocblas_double_complex*>(A), n, lam, w.E, w.flags + 2);
     rocblas_set_workspace(p->rb, nullptr, 0);
     if (rs != rocblas_status_success) return fail(p, CHEB_ERR_HIP, std::string("zheevd: ") + rocblas_status_to_string(rs));
-    int info = 0;
-    HIPCHK(hipMemcpyAsync(&info, w.flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK((fill_zero_real<int>(w.flags + 3, 1, st)));
+    HIPCHK(flag_nonfinite(n, n, A, n, w.flags + 3, st));
+    int info[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(info, w.flags + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (info == 0) return CHEB_OK;
+    if (info[0] == 0 && info[1] == 0) return CHEB_OK;
     HIPCHK((convert_copy<double, double>(n, n, spare, n, A, n, st)));
     RBCHK(rocblas_set_workspace(p->rb, w.solver, w.solver_bytes));
     rs = rocsolver_zheev(p->rb, rocblas_evect_original, rocblas_fill_lower, n, reinterpret_cast<rocblas_double_complex*>(A),
                          n, lam, w.E, w.flags + 2);
     rocblas_set_workspace(p->rb, nullptr, 0);
     if (rs != rocblas_status_success) return fail(p, CHEB_ERR_HIP, std::string("zheev: ") + rocblas_status_to_string(rs));
-    HIPCHK(hipMemcpyAsync(&info, w.flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK((fill_zero_real<int>(w.flags + 3, 1, st)));
+    HIPCHK(flag_nonfinite(n, n, A, n, w.flags + 3, st));
+    HIPCHK(hipMemcpyAsync(info, w.flags + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (info != 0)
-      return fail(p, CHEB_ERR_EIG, std::string("Hermitian eigensolver did not converge on the LOBPCG ") + what + " (n = " +
-                                       std::to_string(n) + ", info " + std::to_string(info) + ")");
+    if (info[0] != 0 || info[1] != 0)
+      return fail(p, CHEB_ERR_EIG, std::string("Hermitian eigensolver failed on the LOBPCG ") + what + " (n = " +
+                                       std::to_string(n) + ", info " + std::to_string(info[0]) +
+                                       (info[1] ? ", non-finite vectors)" : ")"));
     return CHEB_OK;
   }
 

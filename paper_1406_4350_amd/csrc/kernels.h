@@ -178,6 +178,8 @@ hipError_t real_part(long rows, int cols, const c128* A, long lda, double* R, lo
 hipError_t complex_from_real(long rows, int cols, const double* R, long ldr, c128* A, long lda, hipStream_t st);
 // flag[0] = 1 if any entry of A (rows x cols, ld lda) is NaN or Inf (plain stores of 1, no atomics)
 hipError_t flag_nonfinite(long rows, int cols, const c128* A, long lda, int* flag, hipStream_t st);
+// flag[0] = 1 if any of x[0 .. count) is NaN or Inf (plain stores of 1, no atomics)
+hipError_t flag_nonfinite_real(long count, const double* x, int* flag, hipStream_t st);
 // Z[:, j] *= 1 / sqrt(s[j])
 hipError_t scale_cols_isqrt(int n, int ncols, c128* Z, long ldz, const double* s, hipStream_t st);
 // out[i] = Re a[i] / Re b[i]

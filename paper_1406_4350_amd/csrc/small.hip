@@ -441,6 +441,16 @@ hipError_t flag_nonfinite(long rows, int cols, const c128* A, long lda, int* fla
   return hipGetLastError();
 }
 
+__global__ void k_flag_nonfinite_real(long count, const double* x, int* flag) {
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < count; t += long(gridDim.x) * blockDim.x)
+    if (!isfinite(x[t])) flag[0] = 1;
+}
+hipError_t flag_nonfinite_real(long count, const double* x, int* flag, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_flag_nonfinite_real, dim3(nblocks(count)), dim3(256), 0, st, count, x, flag);
+  return hipGetLastError();
+}
+
 hipError_t rr_prepare(int n, c128* H, c128* S, double* d, int* bad, hipStream_t st) {
   hipLaunchKernelGGL(k_rr_scale, dim3(nblocks(n)), dim3(256), 0, st, n, S, d, bad);
   hipLaunchKernelGGL(k_rr_sym, dim3(nblocks(long(n) * n)), dim3(256), 0, st, n, H, S, d, bad);
@@ -589,6 +599,7 @@ template <typename E> hipError_t fill_zero_real(E* p, long count, hipStream_t st
 template hipError_t sub_lambda_cols<double>(long, int, c128*, long, const c128*, long, const double*, hipStream_t);
 template hipError_t sub_lambda_cols<float>(long, int, c64*, long, const c64*, long, const double*, hipStream_t);
 template hipError_t fill_zero_real<double>(double*, long, hipStream_t);
+template hipError_t fill_zero_real<int>(int*, long, hipStream_t);
 }  // namespace chebfd
 
 // ---- warm-started refinement of the dense generalized eigenproblem (Rayleigh-Ritz) -----------------------
