@@ -1,10 +1,12 @@
-// Complex GEMM on CDNA4 matrix cores: four real 16x16x4 MFMAs per complex product block.
+// Complex GEMM on CDNA4 matrix cores: three (FP64) or four (FP32) real 16x16x4 MFMAs per complex product block,
+// and a hi/lo split FP16 form for the projector products of the mixed-precision filter.
 //
 // Used for every O(Npw x Nprojs) contraction of the filter (projections P^H psi and back-projection
 // P w, Alg. 1; the reuse trick of Sec. 5.1 leaves one of each per filter step), for the Rayleigh-Ritz
 // subspace matrices Y^H H Y, Y^H S Y and the rotation Y Z (Alg. 2), and for the small projector-space
 // products with P^H P and the capacitance inverse (Sec. 5.1).
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -244,6 +246,110 @@ __global__ __launch_bounds__(256) void k_reduce(int M, int N, int splits, const 
   }
 }
 
+// ---- small complex FP64 GEMM ----------------------------------------------------------------------------
+// Products with at most a few hundred 16 x 16 output blocks and K of at most a thousand (the projector-space
+// matrices of Sec. 5.1 and the subspace matrices of the Rayleigh-Ritz step) fill only a few dozen 64 x 64 tiles:
+// the tiled kernel above then runs one wave per SIMD and needs split-K with a second reduction launch. Here one
+// block of 4 waves computes one 16 x 16 output block. Wave w takes the w-th quarter of K and reads its operand
+// fragments straight from global memory (a few MB that stay in L2), the next load group in flight during the
+// MFMAs of the current one; the four partial blocks meet in LDS and are summed in a fixed order, so that the result does not depend on timing.
+//
+// Within a load group of 16 k, lane (li, lk) holds k = k0 + 4 s + lk for MFMA step s (the instruction's own k
+// order): the 4 lanes of one B column (and of one A column for conj(A)^T) read 64 contiguous bytes per load.
+constexpr int SKG = 16, SKMAX = 1024, SBLKMAX = 1024, SLD = 17, SW = 4;  // 8 waves per block measured slower
+static_assert(SW >= 4, "the epilogue takes one thread per element of the 16 x 16 block");
+
+template <typename EO, int MODE>
+__global__ __launch_bounds__(64 * SW) void k_gemm_s(int M, int N, int K, int kchunk, const c128* __restrict__ A,
+                                                long lda, const c128* __restrict__ B, long ldb, Epi<EO> epi) {
+  __shared__ c128 red[SW][16 * SLD];
+  using acc_t = Mfma<double>::acc;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  int bx, by, bz;
+  gemm_tile_of(blockIdx.x, gridDim.x, (M + 15) / 16, (N + 15) / 16, bx, by, bz);
+  const long m0 = long(bx) * 16, n0 = long(by) * 16;
+  // rows of A past M and columns of B past N are read clamped: they feed only output rows and columns that are
+  // never stored
+  const long amc = min(m0 + li, long(M) - 1), bnc = min(n0 + li, long(N) - 1);
+  const c128* __restrict__ Ab = MODE == GEMM_CN ? A + amc * lda : A + amc;
+  const long ask = MODE == GEMM_CN ? 1 : lda;  // A stride along k
+  const c128* __restrict__ Bb = B + bnc * ldb;
+  const int kb = wave * kchunk, ke = min(K, kb + kchunk);
+  const int kfull = kb + (max(ke - kb, 0) / SKG) * SKG;  // end of the whole load groups
+
+  acc_t p1, p2, p3;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) { p1[v] = 0.0; p2[v] = 0.0; p3[v] = 0.0; }
+
+  // whole groups load without conditions (a load under a branch would make the compiler wait for every load
+  // in flight before the MFMAs); only the last partial group zeroes k >= ke by value
+  c128 a0[4], b0[4], a1[4], b1[4];
+  auto load = [&](int k0, c128(&a)[4], c128(&b)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * s + lk;
+      a[s] = Ab[long(k) * ask];
+      b[s] = Bb[k];
+    }
+  };
+  auto load_tail = [&](int k0, c128(&a)[4], c128(&b)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * s + lk;
+      const bool kok = k < ke;
+      const int kc = kok ? k : ke - 1;
+      const c128 va = Ab[long(kc) * ask], vb = Bb[kc];
+      a[s] = kok ? va : c128{0.0, 0.0};
+      b[s] = kok ? vb : c128{0.0, 0.0};
+    }
+  };
+  // P1 = a_r b_r, P2 = a_i b_i, P3 = (a_r + s a_i)(b_r + b_i), s = -1 for conj(a) b
+  auto mul = [&](const c128(&a)[4], const c128(&b)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double as = MODE == GEMM_CN ? a[s].x - a[s].y : a[s].x + a[s].y;
+      p1 = Mfma<double>::run(a[s].x, b[s].x, p1);
+      p2 = Mfma<double>::run(a[s].y, b[s].y, p2);
+      p3 = Mfma<double>::run(as, b[s].x + b[s].y, p3);
+    }
+  };
+  // the next group is always requested (clamped to the last whole group, which the final pass reads twice) and
+  // rotated into place after the MFMAs of this one: a request under a condition, or one consumed only past a
+  // branch, is waited for or moved by the compiler before the MFMAs
+  int k0 = kb;
+  if (k0 < kfull) load(k0, a0, b0);
+  for (; k0 < kfull; k0 += SKG) {
+    load(min(k0 + SKG, kfull - SKG), a1, b1);
+    mul(a0, b0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) { a0[s] = a1[s]; b0[s] = b1[s]; }
+  }
+  if (k0 < ke) {
+    load_tail(k0, a0, b0);
+    mul(a0, b0);
+  }
+
+  // accumulator v of a lane holds row lk + 4 v, column li of the 16 x 16 block
+  constexpr double sg = MODE == GEMM_CN ? -1.0 : 1.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    red[wave][(lk + 4 * v) + SLD * li] = c128{p1[v] - sg * p2[v], p3[v] - p1[v] - sg * p2[v]};
+  __syncthreads();
+  if (tid < 256) {
+    const int r = tid & 15, c = tid >> 4;
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int w = 0; w < SW; ++w) {
+      const c128 x = red[w][r + SLD * c];
+      re += x.x;
+      im += x.y;
+    }
+    const long m = m0 + r, n = n0 + c;
+    if (m < M && n < N) epi_store(epi, m, n, re, im);
+  }
+}
+
 // ---- FP16 hi/lo split GEMM ------------------------------------------------------------------------------
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -447,6 +553,20 @@ template <typename T, typename EA, typename EB, typename EO>
 hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, const cx<EB>* B, long ldb,
                 const Epi<EO>& epi, int splits, c128* part, hipStream_t st, GemmRole role) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if constexpr (std::is_same<T, double>::value && std::is_same<EA, double>::value && std::is_same<EB, double>::value) {
+    const long blocks = long((M + 15) / 16) * ((N + 15) / 16);
+    if (K <= SKMAX && blocks <= SBLKMAX) {  // splits and part are not used
+      int kc = (std::max(K, 0) + SW - 1) / SW;
+      kc = std::max(SKG, ((kc + SKG - 1) / SKG) * SKG);
+      if (mode == GEMM_CN)
+        hipLaunchKernelGGL((k_gemm_s<EO, GEMM_CN>), dim3(unsigned(blocks)), dim3(64 * SW), 0, st, M, N, K, kc, A, lda, B,
+                           ldb, epi);
+      else
+        hipLaunchKernelGGL((k_gemm_s<EO, GEMM_NN>), dim3(unsigned(blocks)), dim3(64 * SW), 0, st, M, N, K, kc, A, lda, B,
+                           ldb, epi);
+      return hipGetLastError();
+    }
+  }
   if (splits < 1) splits = 1;
   int kchunk = (K + splits - 1) / splits;
   kchunk = ((kchunk + BK - 1) / BK) * BK;
