@@ -27,7 +27,9 @@ template <> struct Mfma<float> {
   }
 };
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 2, NT = 256;
+// K tiles of 32 and rows padded by one element: measured best on the paw48 projector shapes among K tiles of 16
+// and 32 and paddings of 1 to 16 (a padding of 16 puts the transposed tile stores on one bank)
+constexpr int BM = 64, BN = 64, BK = 32, PAD = 1, NT = 256;
 
 // Block placement. The hardware deals the blocks of a launch to the 8 XCDs in turn (block i to XCD i mod 8),
 // each XCD with its own L2. Logical work items are numbered (split, M tile, N tile) with the N tile fastest,
@@ -53,20 +55,90 @@ __device__ __forceinline__ void epi_store(const Epi<E>& e, long m, long n, doubl
   e.out[m + n * e.ldo] = cx<E>{E(xr), e.real_only ? E(0) : E(xi)};
 }
 
+// Epilogue operands moved into the leading slots (L, then U, then W) and counted: 0, 1 or 3 slots in use, a
+// second operand without a third repeated in the third slot with weight 0 (it is a finite input). The tiled
+// kernels take the count as a template parameter and read every used slot without a branch.
+template <typename E> int epi_slots(Epi<E>& e) {
+  const cx<E>* p[3] = {e.L, e.U, e.W};
+  long l[3] = {e.ldl, e.ldu, e.ldw};
+  double b[3] = {e.bL, e.bU, e.bW};
+  int c = 0;
+  for (int s = 0; s < 3; ++s)
+    if (p[s]) { p[c] = p[s]; l[c] = l[s]; b[c] = b[s]; ++c; }
+  for (int s = c; s < 3; ++s) { p[s] = nullptr; l[s] = 0; b[s] = 0.0; }
+  if (c == 2) { p[2] = p[1]; l[2] = l[1]; b[2] = 0.0; c = 3; }
+  e.L = p[0]; e.ldl = l[0]; e.bL = b[0];
+  e.U = p[1]; e.ldu = l[1]; e.bU = b[1];
+  e.W = p[2]; e.ldw = l[2]; e.bW = b[2];
+  return c;
+}
+
+// Epilogue of one wave's 2 x 2 MFMA blocks (T accumulators, the combined real and imaginary parts in cr, ci;
+// rows of accumulator v given by row_of(v)). The NE operands of block b + 1 are requested, at clamped in-range
+// indices, before the stores of block b, so that every thread keeps a block of loads in flight instead of
+// waiting on each element in turn.
+template <int NE, typename E, typename Acc, typename RowOf>
+__device__ __forceinline__ void epi_blocks(const Epi<E>& epi, int M, int N, long mb, long nb, int li, const Acc (&cr)[2][2],
+                                           const Acc (&ci)[2][2], double scale_n0, double scale_n1, RowOf row_of) {
+  constexpr int NS = NE > 0 ? NE : 1;
+  const cx<E>* src[3] = {epi.L, epi.U, epi.W};
+  const long lds[3] = {epi.ldl, epi.ldu, epi.ldw};
+  const double bet[3] = {epi.bL, epi.bU, epi.bW};
+  cx<E> buf[2][NS][4];
+  auto eload = [&](int b, cx<E>(&dst)[NS][4]) {
+    const int i = b >> 1, j = b & 1;
+    const long n = min(nb + 16 * j + li, long(N) - 1);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const long m = min(mb + 16 * i + row_of(v), long(M) - 1);
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if constexpr (NE > 0) dst[s][v] = src[s][m + n * lds[s]];
+    }
+  };
+  if constexpr (NE > 0) eload(0, buf[0]);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    if constexpr (NE > 0)
+      if (b < 3) eload(b + 1, buf[(b + 1) & 1]);
+    const int i = b >> 1, j = b & 1;
+    const long n = nb + 16 * j + li;
+    const double f = epi.alpha * (j ? scale_n1 : scale_n0);
+    // values of all four elements first, then the guarded stores: a value computed only under the guard would
+    // let the compiler move its loads there and wait on them
+    cx<E> val[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double xr = f * double(cr[i][j][v]), xi = f * double(ci[i][j][v]);
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if constexpr (NE > 0) {
+          xr += bet[s] * double(buf[b & 1][s][v].x);
+          xi += bet[s] * double(buf[b & 1][s][v].y);
+        }
+      val[v] = cx<E>{E(xr), epi.real_only ? E(0) : E(xi)};
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const long m = mb + 16 * i + row_of(v);
+      if (m < M && n < N) epi.out[m + n * epi.ldo] = val[v];
+    }
+  }
+}
+
 // One 64 x 64 complex output tile per block of 4 waves; wave w owns the 32 x 32 quadrant
 // (w & 1, w >> 1) as 2 x 2 MFMA blocks. FP64 tiles take three real products per complex product
 // (P1 = a_r b_r, P2 = a_i b_i, P3 = (a_r + s a_i)(b_r + b_i) with s = 1 for a b and s = -1 for conj(a) b:
-// re = P1 - s P2, im = P3 - P1 - s P2); FP32 tiles keep the four-product form, whose rounding does not
-// grow with the magnitude of the other component.
+// re = P1 - s P2, im = P3 - P1 - s P2), the sums formed in registers from the real and imaginary planes
+// (storing them as two more LDS planes measured 9% slower); FP32 tiles keep the four-product form, whose
+// rounding does not grow with the magnitude of the other component.
 // ROLE only separates kernel names per use (projection, back-projection, small, subspace) for profiling.
-template <typename T, typename EA, typename EB, typename EO, int MODE, int ROLE>
+template <typename T, typename EA, typename EB, typename EO, int MODE, int ROLE, int NE>
 __global__ __launch_bounds__(NT, 2) void k_gemm(int M, int N, int K, int kchunk, const cx<EA>* __restrict__ A,
                                              long lda, const cx<EB>* __restrict__ B, long ldb, Epi<EO> epi,
                                              c128* __restrict__ part) {
   constexpr bool G3 = sizeof(T) == 8;
-  constexpr int SP = G3 ? BK : 1;  // the sum planes exist only for the three-product form
   __shared__ T Ar[BK][BM + PAD], Ai[BK][BM + PAD], Br[BK][BN + PAD], Bi[BK][BN + PAD];
-  __shared__ T As[SP][BM + PAD], Bs[SP][BN + PAD];
   using acc_t = typename Mfma<T>::acc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -123,7 +195,6 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(int M, int N, int K, int kchunk,
       else { mm = idx % BM; kk = idx / BM; }
       Ar[kk][mm] = T(va[r].x);
       Ai[kk][mm] = T(va[r].y);
-      if constexpr (G3) As[kk][mm] = MODE == GEMM_CN ? T(va[r].x) - T(va[r].y) : T(va[r].x) + T(va[r].y);
     }
 #pragma unroll
     for (int r = 0; r < RBn; ++r) {
@@ -131,7 +202,6 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(int M, int N, int K, int kchunk,
       const int kk = idx % BK, nn = idx / BK;
       Br[kk][nn] = T(vb[r].x);
       Bi[kk][nn] = T(vb[r].y);
-      if constexpr (G3) Bs[kk][nn] = T(vb[r].x) + T(vb[r].y);
     }
   };
 
@@ -158,8 +228,8 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(int M, int N, int K, int kchunk,
         T as[2], bs[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          as[i] = As[ks + lk][wm + 16 * i + li];
-          bs[i] = Bs[ks + lk][wn + 16 * i + li];
+          as[i] = MODE == GEMM_CN ? ar[i] - ai[i] : ar[i] + ai[i];
+          bs[i] = br[i] + bi[i];
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -212,23 +282,21 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(int M, int N, int K, int kchunk,
   }
   // accumulator v of a lane holds column li of each 16 x 16 block, row 4*lk + v for the f32 MFMA and
   // row lk + 4*v for the f64 MFMA (lane layouts of the two 16x16x4 instructions differ)
+  auto row_of = [&](int v) { return sizeof(T) == 8 ? lk + 4 * v : 4 * lk + v; };
+  if (part) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = sizeof(T) == 8 ? lk + 4 * v : 4 * lk + v;
-        const long m = m0 + wm + 16 * i + row;
-        const long n = n0 + wn + 16 * j + li;
-        if (m < M && n < N) {
-          if (part) {
-            part[(long(bz) * N + n) * M + m] = c128{double(cr[i][j][v]), double(ci[i][j][v])};
-          } else {
-            epi_store(epi, m, n, double(cr[i][j][v]), double(ci[i][j][v]));
-          }
+        for (int v = 0; v < 4; ++v) {
+          const long m = m0 + wm + 16 * i + row_of(v);
+          const long n = n0 + wn + 16 * j + li;
+          if (m < M && n < N) part[(long(bz) * N + n) * M + m] = c128{double(cr[i][j][v]), double(ci[i][j][v])};
         }
-      }
+  } else {
+    epi_blocks<NE>(epi, M, N, m0 + wm, n0 + wn, li, cr, ci, 1.0, 1.0, row_of);
+  }
 }
 
 template <typename EO>
@@ -367,7 +435,7 @@ __device__ __forceinline__ f4 mul3(h8 xh, h8 xl, h8 yh, h8 yl, f4 acc) {
 // One 64 x 64 complex output tile per block of 4 waves, wave quadrants as in k_gemm. The 16x16x32 FP16 MFMA
 // takes, in lane l, row l % 16 of A and column l % 16 of B at k = 8 (l / 16) ... 8 (l / 16) + 7, and returns
 // row 4 (l / 16) + v, column l % 16 in accumulator element v.
-template <typename EB, typename EO, int MODE, int ROLE>
+template <typename EB, typename EO, int MODE, int ROLE, int NE>
 __global__ __launch_bounds__(NT) void k_gemm_h(int M, int N, int K, int kchunk, const _Float16* __restrict__ Ap,
                                                long arows, long ald, double ainv, const cx<EB>* __restrict__ B,
                                                long ldb, const float* __restrict__ bsc, Epi<EO> epi,
@@ -471,22 +539,30 @@ __global__ __launch_bounds__(NT) void k_gemm_h(int M, int N, int K, int kchunk, 
     }
   }
 
+  // column scales of the lane's two columns (undo the per-band power-of-two scaling of B and the A scale)
+  double fs[2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < 2; ++j) {
+    const long n = n0 + wn + 16 * j + li;
+    fs[j] = n < N ? ainv / double(bsc[n]) : 0.0;
+  }
+  auto row_of = [&](int v) { return 4 * lk + v; };
+  if (part) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const long n = n0 + wn + 16 * j + li;
-      const double f = n < N ? ainv / double(bsc[n]) : 0.0;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const long m = m0 + wm + 16 * i + 4 * lk + v;
-        if (m < M && n < N) {
-          const double re = f * double(cr[i][j][v]), im = f * double(ci[i][j][v]);
-          if (part) part[(long(bz) * N + n) * M + m] = c128{re, im};
-          else epi_store(epi, m, n, re, im);
+      for (int j = 0; j < 2; ++j) {
+        const long n = n0 + wn + 16 * j + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const long m = m0 + wm + 16 * i + row_of(v);
+          if (m < M && n < N)
+            part[(long(bz) * N + n) * M + m] = c128{fs[j] * double(cr[i][j][v]), fs[j] * double(ci[i][j][v])};
         }
       }
-    }
+  } else {
+    epi_blocks<NE>(epi, M, N, m0 + wm, n0 + wn, li, cr, ci, fs[0], fs[1], row_of);
+  }
 }
 
 template <typename E>
@@ -539,7 +615,7 @@ int gemm_pick_splits(int M, int N, int K) {
   if (M <= 0 || N <= 0 || K <= 0) return 1;
   const long tiles = long((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   // about one block per CU: measured on the paw48 projector shapes, the tall NN products (448 tiles) run best
-  // without split-K and the 256 x 256 x 7153 reductions with 16 splits
+  // without split-K and the 256 x 256 x 7153 reductions with 16 splits (28 and 56 slower)
   const long want = 256;
   long s = (want + tiles - 1) / tiles;
   const long kblocks = (K + BK - 1) / BK;
@@ -576,9 +652,16 @@ hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, c
   if (use_part && !part) return hipErrorInvalidValue;
   dim3 grid(((M + BM - 1) / BM) * ((N + BN - 1) / BN) * splits);
   c128* pp = use_part ? part : nullptr;
+  Epi<EO> en = epi;
+  const int ne = epi_slots(en);
   auto launch = [&](auto modec, auto rolec) {
     constexpr int MO = decltype(modec)::value, RO = decltype(rolec)::value;
-    hipLaunchKernelGGL((k_gemm<T, EA, EB, EO, MO, RO>), grid, dim3(NT), 0, st, M, N, K, kchunk, A, lda, B, ldb, epi, pp);
+    if (ne == 0 || use_part)
+      hipLaunchKernelGGL((k_gemm<T, EA, EB, EO, MO, RO, 0>), grid, dim3(NT), 0, st, M, N, K, kchunk, A, lda, B, ldb, en, pp);
+    else if (ne == 1)
+      hipLaunchKernelGGL((k_gemm<T, EA, EB, EO, MO, RO, 1>), grid, dim3(NT), 0, st, M, N, K, kchunk, A, lda, B, ldb, en, pp);
+    else
+      hipLaunchKernelGGL((k_gemm<T, EA, EB, EO, MO, RO, 3>), grid, dim3(NT), 0, st, M, N, K, kchunk, A, lda, B, ldb, en, pp);
   };
   using CN = std::integral_constant<int, GEMM_CN>;
   using NNm = std::integral_constant<int, GEMM_NN>;
@@ -598,7 +681,7 @@ hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, c
 }
 
 // upper bound of the split counts any GEMM kernel here picks for an M x N x K product (partial-buffer sizing):
-// 512 target blocks, two K tiles of 16 per split, at most 32 splits; gemm_pick_splits and gemm_h_pick_splits
+// 512 target blocks, two K tiles of 32 per split, at most 32 splits; gemm_pick_splits and gemm_h_pick_splits
 // never exceed it
 int gemm_split_bound(int M, int N, int K) {
   if (M <= 0 || N <= 0 || K <= 0) return 1;
@@ -636,10 +719,19 @@ hipError_t gemm_h(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const
   if (use_part && !part) return hipErrorInvalidValue;
   dim3 grid(((M + BM - 1) / BM) * ((N + BN - 1) / BN) * splits);
   c128* pp = use_part ? part : nullptr;
+  Epi<EO> en = epi;
+  const int ne = epi_slots(en);
   auto launch = [&](auto modec, auto rolec) {
     constexpr int MO = decltype(modec)::value, RO = decltype(rolec)::value;
-    hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows, A.ld,
-                       A.inv_scale, B, ldb, bscale, epi, pp);
+    if (ne == 0 || use_part)
+      hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO, 0>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows, A.ld,
+                         A.inv_scale, B, ldb, bscale, en, pp);
+    else if (ne == 1)
+      hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO, 1>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows, A.ld,
+                         A.inv_scale, B, ldb, bscale, en, pp);
+    else
+      hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO, 3>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows, A.ld,
+                         A.inv_scale, B, ldb, bscale, en, pp);
   };
   using CN = std::integral_constant<int, GEMM_CN>;
   using NNm = std::integral_constant<int, GEMM_NN>;
