@@ -49,7 +49,8 @@ struct cheb_plan_s {
   HalfPlanes hproj, hback;                  // mixed plans: split planes of P (set with the projectors)
   bool split_gemm = true;                   // mixed plans: FP16 hi/lo split MFMA for P^H x and P w
   bool rr_refine = true;                    // warm-started refinement before the library eigensolver
-  double* rr_host = nullptr;                // pinned staging of the refinement's block maxima and flag
+  double* rr_host = nullptr;                // pinned staging of the refinement's block maxima and flag (2 slots)
+  hipEvent_t rr_ev[2] = {nullptr, nullptr}; // end of the staging copy into each slot
   int64_t rr_refined = 0, rr_fallback = 0;  // how Rayleigh-Ritz steps were solved
   rocblas_handle rb = nullptr;
   // pinned staging of the band permutation of cheb_filter_degrees; lock_ev marks the end of its last copy
@@ -209,6 +210,7 @@ struct Ws {
   double *d = nullptr, *E = nullptr;
   int* flags = nullptr;  // [0..1] rr_prepare flags, [2] solver info
   c128 *Xa = nullptr, *Xb = nullptr, *T = nullptr, *M1 = nullptr, *M2 = nullptr, *F = nullptr;  // refinement
+  c128* M1b = nullptr;  // second product buffer of the refinement (speculative step)
   double *absF = nullptr, *lam = nullptr, *res = nullptr;
   int* perm = nullptr;
   unsigned* bits = nullptr;  // coupling graph of the refinement (n x ceil(n / 32) words)
@@ -300,6 +302,7 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
         w->Xb = b.take<c128>(nn);
         w->T = b.take<c128>(2 * nn);   // [S' X; H' X], 2n x n
         w->M1 = b.take<c128>(2 * nn);  // X^H [S' X | H' X] with interleaved columns
+        w->M1b = b.take<c128>(2 * nn);  // the same for the speculative step
         w->M2 = b.take<c128>(2 * nn);  // [S'; H'] stacked, 2n x n
         w->F = b.take<c128>(nn);
         w->absF = b.take<double>(nn);
@@ -887,13 +890,18 @@ template <typename T> struct Ops {
     c128 *X = w.Xa, *Xn = w.Xb;
     c128* HS = w.M2;  // [S'; H'] stacked: one product gives S' X and H' X together
     c128* TT = w.T;   // [S' X; H' X] (2n x n); read with ld n it is n x 2n with columns S'X_j, H'X_j interleaved
-    c128* M = w.M1;   // X^H [S'X_0, H'X_0, S'X_1, ...]: X^H S' X has ld 2n at M, X^H H' X at M + n
+    // X^H [S'X_0, H'X_0, S'X_1, ...] in one of two buffers: X^H S' X has ld 2n at M, X^H H' X at M + n
+    c128* Mbuf[2] = {w.M1, w.M1b};
+    int mb = 0;
     int* cflag = w.flags + 3;  // cleared with the other flags before rr_prepare
+    constexpr int kSlot = kRefineBlocksMax + 1;  // staging slot: block maxima, then the cluster flag
     if (!p->rr_host) {
-      const hipError_t ea = hipHostMalloc(reinterpret_cast<void**>(&p->rr_host), (kRefineBlocksMax + 1) * sizeof(double),
+      const hipError_t ea = hipHostMalloc(reinterpret_cast<void**>(&p->rr_host), 2 * kSlot * sizeof(double),
                                           hipHostMallocDefault);
       if (ea != hipSuccess) { p->rr_host = nullptr; return hip_fail(ea); }
     }
+    for (hipEvent_t& ev : p->rr_ev)
+      if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming))) { ev = nullptr; return hip_fail(e); }
     double* const hst = p->rr_host;
     if ((e = convert_copy<double, double>(n, n, w.Ss, n, HS, n2, st))) return hip_fail(e);
     if ((e = convert_copy<double, double>(n, n, w.Hs, n, HS + n, n2, st))) return hip_fail(e);
@@ -906,28 +914,53 @@ template <typename T> struct Ops {
     std::vector<unsigned> bits;
     std::vector<int> cidx, coff;
     static const bool trace = std::getenv("CHEBFD_TRACE_RR") != nullptr;  // diagnostics: correction sizes
-    auto products = [&](const c128* Xc) {
+    const int nbm = refine_blocks(n);
+    auto products = [&](const c128* Xc, c128* Mo) {
       Epi<double> e1;
       e1.out = TT; e1.ldo = n2;
       hipError_t r = gemm<double, double, double, double>(GEMM_NN, 2 * n, n, n, HS, n2, Xc, n, e1,
                                                           gemm_pick_splits(2 * n, n, n), w.part, st, ROLE_SUBSPACE);
       if (r != hipSuccess) return r;
       Epi<double> e2;
-      e2.out = M; e2.ldo = n;
+      e2.out = Mo; e2.ldo = n;
       return gemm<double, double, double, double>(GEMM_CN, n, 2 * n, n, Xc, n, TT, n, e2, gemm_pick_splits(n, 2 * n, n),
                                                   w.part, st, ROLE_SUBSPACE);
     };
+    // corrections F of the X whose products are (m1, m2) and their block maxima and the cluster flag staged in
+    // slot s, the slot's event recorded after the copies
+    auto corrections = [&](const c128* m1, const c128* m2, long l, int s) {
+      hipError_t r = refine_update(n, m1, l, m2, l, w.F, w.lam, w.absF, w.bmax, st);
+      if (!r) r = hipMemcpyAsync(hst + s * kSlot, w.bmax, nbm * sizeof(double), hipMemcpyDeviceToHost, st);
+      if (!r) r = hipMemcpyAsync(hst + s * kSlot + kRefineBlocksMax, cflag, sizeof(int), hipMemcpyDeviceToHost, st);
+      if (!r) r = hipEventRecord(p->rr_ev[s], st);
+      return r;
+    };
+    auto first_order = [&]() {  // Xn = X (I + F)
+      Epi<double> eu;
+      eu.out = Xn; eu.ldo = n; eu.L = X; eu.ldl = n; eu.bL = 1.0;
+      return gemm<double, double, double, double>(GEMM_NN, n, n, n, X, n, w.F, n, eu, gemm_pick_splits(n, n, n), w.part,
+                                                  st, ROLE_SUBSPACE);
+    };
+    // Invariant at the top of an iteration: the corrections of the current X are staged in slot `slot`.
+    int slot = 0;
+    if ((e = corrections(M1, M2, ld, slot))) return hip_fail(e);
     for (int it = 0; it < kRefineIters; ++it) {
-      if ((e = refine_update(n, M1, ld, M2, ld, w.F, w.lam, w.absF, w.bmax, st))) return hip_fail(e);
-      // block maxima and the cluster flag in one pinned staging buffer, one synchronization
-      const int nbm = refine_blocks(n);
-      if ((e = hipMemcpyAsync(hst, w.bmax, nbm * sizeof(double), hipMemcpyDeviceToHost, st))) return hip_fail(e);
-      if ((e = hipMemcpyAsync(hst + kRefineBlocksMax, cflag, sizeof(int), hipMemcpyDeviceToHost, st))) return hip_fail(e);
-      if ((e = hipStreamSynchronize(st))) return hip_fail(e);
+      // From the second iteration on (corrections below the cluster threshold are then the rule) the first-order
+      // step, its products and the next corrections are queued before this iteration's max|F| is read, so that
+      // the device works while the host waits; they touch only the spare X, the other product buffer, F and the
+      // other staging slot, and are dropped if the step turns out to need clusters.
+      const bool spec = it > 0;
+      if (spec) {
+        if ((e = first_order()) || (e = products(Xn, Mbuf[mb ^ 1])) ||
+            (e = corrections(Mbuf[mb ^ 1], Mbuf[mb ^ 1] + n, n2, slot ^ 1)))
+          return hip_fail(e);
+      }
+      if ((e = hipEventSynchronize(p->rr_ev[slot]))) return hip_fail(e);
       double maxF = 0.0;
-      for (int b = 0; b < nbm; ++b) maxF = std::isnan(hst[b]) ? hst[b] : std::max(maxF, hst[b]);
+      const double* hs = hst + slot * kSlot;
+      for (int b = 0; b < nbm; ++b) maxF = std::isnan(hs[b]) ? hs[b] : std::max(maxF, hs[b]);
       int bad = 0;
-      std::memcpy(&bad, hst + kRefineBlocksMax, sizeof(int));
+      std::memcpy(&bad, hs + kRefineBlocksMax, sizeof(int));
       if (trace) std::fprintf(stderr, "[rr-refine] n=%d it=%d max|F|=%.3e\n", n, it, maxF);
       if (bad || std::isnan(maxF)) return false;
       // leave when no longer converging: no halving against the best value before the last kStallWindow
@@ -935,6 +968,18 @@ template <typename T> struct Ops {
       if (int(hist.size()) > kStallWindow &&
           maxF > 0.5 * *std::min_element(hist.begin(), hist.end() - kStallWindow))
         return false;
+      if (spec && maxF <= kClusterStep) {  // the queued first-order step stands
+        std::swap(X, Xn);
+        mb ^= 1;
+        M1 = Mbuf[mb];
+        M2 = Mbuf[mb] + n;
+        ld = n2;
+        slot ^= 1;
+        if (maxF < 1e-10) { conv = true; break; }
+        continue;
+      }
+      // the speculative step (if any) is dropped: recompute the corrections of the current X
+      if (spec && (e = refine_update(n, M1, ld, M2, ld, w.F, w.lam, w.absF, w.bmax, st))) return hip_fail(e);
       bool cluster = false;
       if (maxF > kClusterStep) {
         const int W = (n + 31) / 32;
@@ -945,7 +990,11 @@ template <typename T> struct Ops {
         if ((e = hipStreamSynchronize(st))) return hip_fail(e);
         if (!clusters_from_bits(n, bits, cidx, coff)) return false;
         cluster = coff.size() > 1;
-        if (trace && cluster) std::fprintf(stderr, "[rr-refine]   %zu clusters, %zu bands\n", coff.size() - 1, cidx.size());
+        if (trace && cluster) {
+          int big = 0;
+          for (size_t c = 0; c + 1 < coff.size(); ++c) big = std::max(big, coff[c + 1] - coff[c]);
+          std::fprintf(stderr, "[rr-refine]   %zu clusters, %zu bands, largest %d\n", coff.size() - 1, cidx.size(), big);
+        }
       }
       if (cluster) {
         if ((e = hipMemcpyAsync(w.cidx, cidx.data(), cidx.size() * sizeof(int), hipMemcpyHostToDevice, st)) ||
@@ -961,21 +1010,21 @@ template <typename T> struct Ops {
                                                       w.part, st, ROLE_SUBSPACE))) return hip_fail(e);
       } else {
         if (!(maxF < 1.0)) return false;  // outside the region where first-order steps converge
-        Epi<double> eu;
-        eu.out = Xn; eu.ldo = n; eu.L = X; eu.ldl = n; eu.bL = 1.0;
-        if ((e = gemm<double, double, double, double>(GEMM_NN, n, n, n, X, n, w.F, n, eu, gemm_pick_splits(n, n, n),
-                                                      w.part, st, ROLE_SUBSPACE))) return hip_fail(e);
+        if ((e = first_order())) return hip_fail(e);
       }
       std::swap(X, Xn);
-      if ((e = products(X))) return hip_fail(e);
-      M1 = M;
-      M2 = M + n;
+      if ((e = products(X, Mbuf[mb ^ 1]))) return hip_fail(e);
+      mb ^= 1;
+      M1 = Mbuf[mb];
+      M2 = Mbuf[mb] + n;
       ld = n2;
       if (!cluster && maxF < 1e-10) { conv = true; break; }
+      slot ^= 1;
+      if ((e = corrections(M1, M2, ld, slot))) return hip_fail(e);
     }
     if (!conv) return false;
     double res[2] = {1.0, 1.0};
-    if ((e = refine_check(n, M1, ld, M2, ld, w.res, st))) return hip_fail(e);
+    if ((e = refine_check(n, M1, ld, M2, ld, w.bmax, w.res, st))) return hip_fail(e);
     if ((e = hipMemcpyAsync(res, w.res, 2 * sizeof(double), hipMemcpyDeviceToHost, st))) return hip_fail(e);
     if ((e = hipStreamSynchronize(st))) return hip_fail(e);
     if (trace) std::fprintf(stderr, "[rr-refine] check |X^H S' X - I| = %.2e, off-diagonal X^H H' X = %.2e\n", res[0], res[1]);
@@ -1819,6 +1868,8 @@ cheb_status cheb_plan_destroy(cheb_plan p) {
   if (p->rb) rocblas_destroy_handle(p->rb);
   if (p->lock_ev) { (void)hipEventSynchronize(p->lock_ev); (void)hipEventDestroy(p->lock_ev); }
   if (p->lock_host) (void)hipHostFree(p->lock_host);
+  for (hipEvent_t& ev : p->rr_ev)
+    if (ev) { (void)hipEventSynchronize(ev); (void)hipEventDestroy(ev); }
   if (p->rr_host) (void)hipHostFree(p->rr_host);
   delete p;
   return CHEB_OK;

@@ -13,8 +13,9 @@
 namespace chebfd {
 namespace {
 
-constexpr int CNT = 256;
+constexpr int CNT = 512;  // one pass over the 2 x 2 blocks and V rows of a round up to clusters of about 30
 constexpr int CLD = kClusterMax + 1;  // LDS leading dimension (odd in 16-byte units)
+static_assert(kClusterMax <= 64, "the Cholesky diagonal sums one term per lane of a wave");
 
 // bits[i * W + w] bit b: |F_ij| > tau for j = 32 w + b, i != j (W = ceil(n / 32))
 __global__ void k_coupling_bits(int n, const double* __restrict__ absF, double tau, unsigned* __restrict__ bits) {
@@ -59,8 +60,9 @@ __global__ __launch_bounds__(CNT) void k_cluster_eig(const c128* __restrict__ M1
   c128* const A = reinterpret_cast<c128*>(smem_raw);  // [s][CLD] column-major
   c128* const L = A + kClusterMax * CLD;
   c128* const V = L + kClusterMax * CLD;
-  double* const rot = reinterpret_cast<double*>(V + kClusterMax * CLD);  // [kClusterMax / 2][5]: c, s, cos phi, sin phi, on
-  int* const pq = reinterpret_cast<int*>(rot + 5 * (kClusterMax / 2));    // [kClusterMax / 2][2]
+  c128* const A2 = V + kClusterMax * CLD;  // second buffer of the Jacobi rounds
+  double* const rot = reinterpret_cast<double*>(A2 + kClusterMax * CLD);  // [kClusterMax / 2][4]: c, s, e^{i phi}
+  int* const pq = reinterpret_cast<int*>(rot + 4 * (kClusterMax / 2));      // [kClusterMax / 2][3]: p, q, on
   __shared__ int bad;
   __shared__ double sums[2 * (CNT / 64)];
   const int c0 = off[blockIdx.x], s = off[blockIdx.x + 1] - c0;
@@ -76,11 +78,16 @@ __global__ __launch_bounds__(CNT) void k_cluster_eig(const c128* __restrict__ M1
 
   // ---- Cholesky M1_CC = L L^H (lower, left-looking) ----
   for (int j = 0; j < s; ++j) {
-    if (tid == 0) {
-      double dj = L[j + j * CLD].x;
-      for (int k = 0; k < j; ++k) dj -= L[j + k * CLD].x * L[j + k * CLD].x + L[j + k * CLD].y * L[j + k * CLD].y;
-      if (!(dj > 0.0)) { bad = 1; dj = 1.0; }
-      L[j + j * CLD] = c128{sqrt(dj), 0.0};
+    if (tid < 64) {  // d_j = M1_jj - sum_k<j |L_jk|^2: one term per lane (s <= 64), fixed-order shuffle sum
+      double q = 0.0;
+      if (tid < j) q = L[j + tid * CLD].x * L[j + tid * CLD].x + L[j + tid * CLD].y * L[j + tid * CLD].y;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+      if (tid == 0) {
+        double dj = L[j + j * CLD].x - q;
+        if (!(dj > 0.0)) { bad = 1; dj = 1.0; }
+        L[j + j * CLD] = c128{sqrt(dj), 0.0};
+      }
     }
     __syncthreads();
     const double ljj = L[j + j * CLD].x;
@@ -117,13 +124,19 @@ __global__ __launch_bounds__(CNT) void k_cluster_eig(const c128* __restrict__ M1
   __syncthreads();
 
   // ---- cyclic Jacobi, round-robin pairs (circle method over sp = s rounded up to even players) ----
+  // A round applies A <- U^H A U and V <- V U for the sp / 2 disjoint rotations of the round, all computed from
+  // the round's input matrix: the update splits into independent 2 x 2 blocks (rows of one rotation, columns of
+  // another) read from one buffer and written to the other. Two barriers per round: after the rotations, after
+  // the update.
   const int sp = s + (s & 1), np = sp / 2;
+  c128* Ac = A;
+  c128* An = A2;
   for (int sweep = 0; sweep < 16; ++sweep) {
     // off-diagonal and diagonal mass (fixed-order reduction)
     double off2 = 0.0, dia2 = 0.0;
     for (int t = tid; t < s * s; t += CNT) {
       const int j = t / s, i = t - j * s;
-      const c128 a = A[i + j * CLD];
+      const c128 a = Ac[i + j * CLD];
       if (i == j) dia2 += a.x * a.x; else off2 += a.x * a.x + a.y * a.y;
     }
 #pragma unroll
@@ -136,71 +149,94 @@ __global__ __launch_bounds__(CNT) void k_cluster_eig(const c128* __restrict__ M1
     // relative 1e-12 suffices: the first-order steps that follow converge quadratically from there
     if (off2 <= 1e-24 * fmax(off2 + dia2, 1e-300)) break;  // uniform
     for (int r = 0; r < sp - 1; ++r) {
+      // rotation k of this round: U = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] zeroing (p, q); q == s is the idle
+      // player of an odd s
       if (tid < np) {
         int a, b;
         if (tid == 0) { a = sp - 1; b = r; }
         else { a = (r + tid) % (sp - 1); b = (r - tid + (sp - 1)) % (sp - 1); }
         const int p = min(a, b), q = max(a, b);
-        double* R = rot + 5 * tid;
-        pq[2 * tid] = p;
-        pq[2 * tid + 1] = q;
-        R[4] = 0.0;
+        double* R = rot + 4 * tid;
+        int on = 0;
         if (q < s) {
-          const c128 apq = A[p + q * CLD];
-          const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
-          const double app = A[p + p * CLD].x, aqq = A[q + q * CLD].x;
-          if (mag > 1e-300 && mag > 1e-18 * sqrt(fabs(app * aqq))) {
-            const double tau = (aqq - app) / (2.0 * mag);
+          const c128 apq = Ac[p + q * CLD];
+          const double m2 = apq.x * apq.x + apq.y * apq.y;
+          const double app = Ac[p + p * CLD].x, aqq = Ac[q + q * CLD].x;
+          // |a_pq| above 1e-150 and 1e-18 sqrt|a_pp a_qq| (squared comparisons)
+          if (m2 > 1e-300 && m2 > 1e-36 * fabs(app * aqq)) {
+            const double ri = rsqrt(m2);  // 1 / |a_pq|
+            const double tau = 0.5 * (aqq - app) * ri;
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            const double cc = 1.0 / sqrt(1.0 + t * t);
+            const double cc = rsqrt(1.0 + t * t);
             R[0] = cc;
             R[1] = t * cc;
-            R[2] = apq.x / mag;  // e^{i phi} = a_pq / |a_pq|
-            R[3] = apq.y / mag;
-            R[4] = 1.0;
+            R[2] = apq.x * ri;  // e^{i phi} = a_pq / |a_pq|
+            R[3] = apq.y * ri;
+            on = 1;
+          }
+        }
+        pq[3 * tid] = p;
+        pq[3 * tid + 1] = q;
+        pq[3 * tid + 2] = on;
+      }
+      __syncthreads();
+      for (int t = tid; t < np * np + s * np; t += CNT) {
+        if (t < np * np) {
+          // block rows {p, q} (rotation k), columns {p2, q2} (rotation k2); rows or columns >= s do not exist
+          const int k = t / np, k2 = t - k * np;
+          const int p = pq[3 * k], q = pq[3 * k + 1], p2 = pq[3 * k2], q2 = pq[3 * k2 + 1];
+          const bool qr = q < s, qc = q2 < s;
+          // loads at clamped in-range indices and selects of the loaded values (a conditional between two
+          // lvalues would select addresses instead)
+          const int qq = qr ? q : p, qq2 = qc ? q2 : p2;
+          const c128 l01 = Ac[p + qq2 * CLD], l10 = Ac[qq + p2 * CLD], l11 = Ac[qq + qq2 * CLD];
+          c128 b00 = Ac[p + p2 * CLD];
+          c128 b01 = qc ? l01 : c128{0.0, 0.0};
+          c128 b10 = qr ? l10 : c128{0.0, 0.0};
+          c128 b11 = qr && qc ? l11 : c128{0.0, 0.0};
+          if (pq[3 * k2 + 2]) {  // columns: B <- B U
+            const double* C = rot + 4 * k2;
+            const c128 em = {C[2], -C[3]};
+            const c128 y0 = cmul(b01, em), y1 = cmul(b11, em);
+            const c128 n00 = b00 * C[0] - y0 * C[1], n01 = b00 * C[1] + y0 * C[0];
+            const c128 n10 = b10 * C[0] - y1 * C[1], n11 = b10 * C[1] + y1 * C[0];
+            b00 = n00; b01 = n01; b10 = n10; b11 = n11;
+          }
+          if (pq[3 * k + 2]) {  // rows: B <- U^H B, U^H = [[c, -s e^{i phi}], [s, c e^{i phi}]]
+            const double* R = rot + 4 * k;
+            const c128 ep = {R[2], R[3]};
+            const c128 y0 = cmul(ep, b10), y1 = cmul(ep, b11);
+            const c128 n00 = b00 * R[0] - y0 * R[1], n10 = b00 * R[1] + y0 * R[0];
+            const c128 n01 = b01 * R[0] - y1 * R[1], n11 = b01 * R[1] + y1 * R[0];
+            b00 = n00; b01 = n01; b10 = n10; b11 = n11;
+            if (k == k2) {  // the rotated pair: exact zeros off the diagonal, real diagonal
+              b01 = c128{0.0, 0.0};
+              b10 = c128{0.0, 0.0};
+              b00.y = 0.0;
+              b11.y = 0.0;
+            }
+          }
+          An[p + p2 * CLD] = b00;
+          if (qc) An[p + q2 * CLD] = b01;
+          if (qr) An[q + p2 * CLD] = b10;
+          if (qr && qc) An[q + q2 * CLD] = b11;
+        } else {
+          // V <- V U on columns (p, q) of rotation k, row i
+          const int u = t - np * np, k = u / s, i = u - k * s;
+          if (pq[3 * k + 2]) {
+            const int p = pq[3 * k], q = pq[3 * k + 1];
+            const double* R = rot + 4 * k;
+            const c128 em = {R[2], -R[3]};
+            const c128 x = V[i + p * CLD], y = cmul(V[i + q * CLD], em);
+            V[i + p * CLD] = x * R[0] - y * R[1];
+            V[i + q * CLD] = x * R[1] + y * R[0];
           }
         }
       }
       __syncthreads();
-      // columns: A <- A U, V <- V U with U = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] on (p, q)
-      for (int t = tid; t < s * np; t += CNT) {
-        const int k = t / s, i = t - k * s;
-        const double* R = rot + 5 * k;
-        if (R[4] == 0.0) continue;
-        const int p = pq[2 * k], q = pq[2 * k + 1];
-        const c128 em = c128{R[2], -R[3]};
-        {
-          const c128 x = A[i + p * CLD], y = cmul(A[i + q * CLD], em);
-          A[i + p * CLD] = x * R[0] - y * R[1];
-          A[i + q * CLD] = x * R[1] + y * R[0];
-        }
-        {
-          const c128 x = V[i + p * CLD], y = cmul(V[i + q * CLD], em);
-          V[i + p * CLD] = x * R[0] - y * R[1];
-          V[i + q * CLD] = x * R[1] + y * R[0];
-        }
-      }
-      __syncthreads();
-      // rows: A <- U^H A, U^H = [[c, -s e^{i phi}], [s, c e^{i phi}]]
-      for (int t = tid; t < s * np; t += CNT) {
-        const int k = t / s, j = t - k * s;
-        const double* R = rot + 5 * k;
-        if (R[4] == 0.0) continue;
-        const int p = pq[2 * k], q = pq[2 * k + 1];
-        const c128 ep = c128{R[2], R[3]};
-        const c128 x = A[p + j * CLD], y = cmul(ep, A[q + j * CLD]);
-        A[p + j * CLD] = x * R[0] - y * R[1];
-        A[q + j * CLD] = x * R[1] + y * R[0];
-      }
-      __syncthreads();
-      if (tid < np && rot[5 * tid + 4] != 0.0) {
-        const int p = pq[2 * tid], q = pq[2 * tid + 1];
-        A[p + q * CLD] = c128{0.0, 0.0};
-        A[q + p * CLD] = c128{0.0, 0.0};
-        A[p + p * CLD].y = 0.0;
-        A[q + q * CLD].y = 0.0;
-      }
-      __syncthreads();
+      c128* const tmp = Ac;
+      Ac = An;
+      An = tmp;
     }
   }
 
@@ -222,7 +258,7 @@ __global__ __launch_bounds__(CNT) void k_cluster_eig(const c128* __restrict__ M1
 }
 
 size_t cluster_lds() {
-  return size_t(3) * kClusterMax * CLD * sizeof(c128) + (kClusterMax / 2) * (5 * sizeof(double) + 2 * sizeof(int));
+  return size_t(4) * kClusterMax * CLD * sizeof(c128) + (kClusterMax / 2) * (4 * sizeof(double) + 3 * sizeof(int));
 }
 
 }  // namespace

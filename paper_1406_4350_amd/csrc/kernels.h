@@ -162,8 +162,12 @@ constexpr int kRefineBlocksMax = 256;
 int refine_blocks(int n);
 hipError_t refine_update(int n, const c128* M1, long ld1, const c128* M2, long ld2, c128* F, double* lam, double* absF,
                          double* bmax, hipStream_t st);
-// res[0] = max |M1 - I|, res[1] = max off-diagonal |M2| / max(1, max |diag M2|)
-hipError_t refine_check(int n, const c128* M1, long ld1, const c128* M2, long ld2, double* res, hipStream_t st);
+// res[0] = max |M1 - I|, res[1] = max off-diagonal |M2| / max(1, max |diag M2|) (NaN if an entry is NaN); part
+// holds 3 kRefineCheckBlocks doubles of per-block maxima
+constexpr int kRefineCheckBlocks = 64;
+static_assert(3 * kRefineCheckBlocks <= kRefineBlocksMax, "the block maxima of the check fit the refinement's");
+hipError_t refine_check(int n, const c128* M1, long ld1, const c128* M2, long ld2, double* part, double* res,
+                        hipStream_t st);
 hipError_t identity_matrix(int n, c128* X, hipStream_t st);
 // ascending sort of lam (n <= 2048) -> ritz, perm; Z[:, k] = d .* X[:, perm[k]]
 hipError_t sort_eigen(int n, const double* lam, double* ritz, int* perm, const c128* X, const double* d, c128* Z,

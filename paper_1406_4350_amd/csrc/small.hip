@@ -652,29 +652,45 @@ __global__ __launch_bounds__(256) void k_refine_update(int n, const c128* M1, lo
 }
 
 // res[0] = max |M1 - I|, res[1] = max_{i != j} |M2_ij| / max(1, max_i |M2_ii|)  (one block, fixed order)
-__global__ __launch_bounds__(1024) void k_refine_check(int n, const c128* M1, long ld1, const c128* M2, long ld2,
-                                                      double* res) {
-  __shared__ double s1[1024], s2[1024], s3[1024];
+// Per-block maxima of |M1 - I|^2, of |M2_ij|^2 off the diagonal and of |M2_ii|, three per block (NaN kept)
+__global__ __launch_bounds__(256) void k_refine_check(int n, const c128* M1, long ld1, const c128* M2, long ld2,
+                                                     double* part) {
+  __shared__ double s1[256], s2[256], s3[256];
   double a = 0.0, b = 0.0, d = 0.0;
   const long total = long(n) * n;
-  for (long t = threadIdx.x; t < total; t += blockDim.x) {
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
     const int j = int(t / n), i = int(t - long(j) * n);
     const c128 m1 = M1[i + long(j) * ld1], m2 = M2[i + long(j) * ld2];
-    const double e1 = i == j ? hypot(m1.x - 1.0, m1.y) : hypot(m1.x, m1.y);
-    a = fmax(a, e1);
-    if (i == j) d = fmax(d, fabs(m2.x)); else b = fmax(b, hypot(m2.x, m2.y));
+    const double r1 = i == j ? m1.x - 1.0 : m1.x;
+    a = max_nan(a, r1 * r1 + m1.y * m1.y);
+    if (i == j) d = max_nan(d, fabs(m2.x)); else b = max_nan(b, m2.x * m2.x + m2.y * m2.y);
   }
   s1[threadIdx.x] = a; s2[threadIdx.x] = b; s3[threadIdx.x] = d;
   __syncthreads();
   for (int k = blockDim.x / 2; k > 0; k >>= 1) {
     if (threadIdx.x < k) {
-      s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + k]);
-      s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + k]);
-      s3[threadIdx.x] = fmax(s3[threadIdx.x], s3[threadIdx.x + k]);
+      s1[threadIdx.x] = max_nan(s1[threadIdx.x], s1[threadIdx.x + k]);
+      s2[threadIdx.x] = max_nan(s2[threadIdx.x], s2[threadIdx.x + k]);
+      s3[threadIdx.x] = max_nan(s3[threadIdx.x], s3[threadIdx.x + k]);
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) { res[0] = s1[0]; res[1] = s2[0] / fmax(1.0, s3[0]); }
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = s1[0];
+    part[3 * blockIdx.x + 1] = s2[0];
+    part[3 * blockIdx.x + 2] = s3[0];
+  }
+}
+__global__ void k_refine_check_final(int nblk, const double* part, double* res) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0, d = 0.0;
+  for (int k = 0; k < nblk; ++k) {
+    a = max_nan(a, part[3 * k]);
+    b = max_nan(b, part[3 * k + 1]);
+    d = max_nan(d, part[3 * k + 2]);
+  }
+  res[0] = sqrt(a);
+  res[1] = sqrt(b) / fmax(1.0, d);
 }
 
 // out[0] = max of x[0..count) (one block, fixed order)
@@ -686,35 +702,18 @@ __global__ void k_identity(int n, c128* X) {
   }
 }
 
-// Ascending sort of lam (n <= 2048) with its permutation, one block, bitonic network on 2048 slots;
-// ties keep index order. Then ritz[k] = lam[perm[k]].
+// Ascending sort of lam (n <= 2048) with its permutation, one block: element i goes to rank #{j : key_j < key_i
+// or key_j = key_i and j < i}, so ties keep index order (NaN keys count as +Inf). Then ritz[k] = lam[perm[k]].
 __global__ __launch_bounds__(1024) void k_sort_lam(int n, const double* lam, double* ritz, int* perm) {
   __shared__ double key[2048];
-  __shared__ int idx[2048];
-  for (int t = threadIdx.x; t < 2048; t += blockDim.x) {
-    key[t] = t < n ? lam[t] : 1e308;
-    idx[t] = t;
-  }
+  for (int t = threadIdx.x; t < n; t += blockDim.x) key[t] = isnan(lam[t]) ? INFINITY : lam[t];
   __syncthreads();
-  for (int k = 2; k <= 2048; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = threadIdx.x; t < 2048; t += blockDim.x) {
-        const int u = t ^ j;
-        if (u > t) {
-          const bool up = (t & k) == 0;
-          const bool gt = key[t] > key[u] || (key[t] == key[u] && idx[t] > idx[u]);
-          if (gt == up) {
-            const double kk = key[t]; key[t] = key[u]; key[u] = kk;
-            const int ii = idx[t]; idx[t] = idx[u]; idx[u] = ii;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (int t = threadIdx.x; t < n; t += blockDim.x) {
-    ritz[t] = key[t];
-    perm[t] = idx[t];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double ki = key[i];
+    int r = 0;
+    for (int j = 0; j < n; ++j) r += key[j] < ki || (key[j] == ki && j < i);
+    ritz[r] = lam[i];
+    perm[r] = i;
   }
 }
 
@@ -736,8 +735,11 @@ hipError_t refine_update(int n, const c128* M1, long ld1, const c128* M2, long l
   hipLaunchKernelGGL(k_refine_update, dim3(refine_blocks(n)), dim3(256), 0, st, n, M1, ld1, M2, ld2, F, lam, absF, bmax);
   return hipGetLastError();
 }
-hipError_t refine_check(int n, const c128* M1, long ld1, const c128* M2, long ld2, double* res, hipStream_t st) {
-  hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(1024), 0, st, n, M1, ld1, M2, ld2, res);
+hipError_t refine_check(int n, const c128* M1, long ld1, const c128* M2, long ld2, double* part, double* res,
+                        hipStream_t st) {
+  const int nblk = nblocks(long(n) * n, 256, kRefineCheckBlocks);
+  hipLaunchKernelGGL(k_refine_check, dim3(nblk), dim3(256), 0, st, n, M1, ld1, M2, ld2, part);
+  hipLaunchKernelGGL(k_refine_check_final, dim3(1), dim3(64), 0, st, nblk, part, res);
   return hipGetLastError();
 }
 hipError_t identity_matrix(int n, c128* X, hipStream_t st) {
