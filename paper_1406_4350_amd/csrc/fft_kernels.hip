@@ -99,10 +99,26 @@ template <int N> __device__ __forceinline__ int freq(int k) { return k <= (N - 1
 //      multiply by V(r), first forward stage; one more exchange; second forward stage keeps the 2R+1
 //      x-lines
 //   C  forward y, written straight to the disk-column row of the output
+// compute units of the current device (queried once per device)
+int compute_units() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cached[dev] <= 0) {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+    cached[dev] = cu;
+  }
+  return cached[dev];
+}
+
+// Items (z-plane, band) with stride gridDim.x: FP64 launches a persistent grid of the resident blocks, which
+// stage the twiddles once and load each thread's first stage-A inputs of the next item during this one; FP32
+// launches one block per item.
 template <int N, typename T>
 __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __restrict__ xline,
                                               const cx<T>* __restrict__ twg, const T* __restrict__ Vt,
-                                              const cx<T>* __restrict__ cin, cx<T>* __restrict__ cout) {
+                                              const cx<T>* __restrict__ cin, cx<T>* __restrict__ cout, int nitems) {
   constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = line_stride<N>(), PS = group_stride<N>();
   constexpr int RB = plane_rows<N, T>();
   static_assert(RB * N1 <= NT, "one second-stage task per thread and row batch");
@@ -113,124 +129,169 @@ __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __re
   cx<T>* tw = Sc + RB * LS;
   cx<T>* twA = tw + N;
   cx<T>* twB = twA + N;
-  const int z = blockIdx.x, band = blockIdx.y, tid = threadIdx.x;
-  const long base = long(band) * N * ncol + long(z) * ncol;
-  const cx<T>* in = cin + base;
-  cx<T>* out = cout + base;
+  const int tid = threadIdx.x;
   for (int t = tid; t < N; t += NT) tw[t] = twg[t];
   __syncthreads();
   stage_twiddles<N, T>(tw, twA, twB);
   __syncthreads();
 
-  // ---- A: inverse y ----
-  for (int task = tid; task < nx * N2; task += NT) {
-    const int xi = task / N2, n2 = task - xi * N2;
+  // FP64: this thread's first stage-A task (task = tid) has its inputs for the next item loaded during this
+  // one, from row offsets clamped to 0 where the input is zero (loaded anyway and replaced by zero, so that the
+  // loads need no branch). FP32 planes load in place: the extra registers cost them a resident block per CU.
+  constexpr bool PF = sizeof(T) == 8;
+  int aoff[N1];
+  bool aon[N1];
+  if constexpr (PF) {
+    const bool has = tid < nx * N2;
+    const int xi = has ? tid / N2 : 0, n2 = tid - (tid / N2) * N2;
     const int4 xl = xline[xi];  // {first column, lowest gy, column count, 0}
-    cx<T> v[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
       const int j = freq<N>(N2 * n1 + n2) - xl.y;
-      v[n1] = (j >= 0 && j < xl.z) ? cx<T>(in[xl.x + j]) : cx<T>{T(0), T(0)};
+      aon[n1] = has && j >= 0 && j < xl.z;
+      aoff[n1] = aon[n1] ? xl.x + j : 0;
     }
-    Dft<N1, +1>::run(v);
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) L[xi * LS + PS * k1 + n2] = k1 ? cmul(v[k1], conj_if(twA[k1 * N2 + n2], true)) : v[0];
   }
-  __syncthreads();
-  for (int task = tid; task < nx * N1; task += NT) {
-    const int xi = task / N1, a = task - xi * N1;
-    cx<T>* p = L + xi * LS + PS * a;
-    cx<T> v[N2];
+  cx<T> pre[N1];
+  auto fetch = [&](int item) {
+    const cx<T>* src = cin + long(item / N) * N * ncol + long(item % N) * ncol;
 #pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) v[n2] = p[n2];
-    Dft<N2, +1>::run(v);
-#pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) p[k2] = v[k2];  // y = a + N1 k2
-  }
-  __syncthreads();
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const cx<T> x = src[aoff[n1]];
+      pre[n1] = aon[n1] ? x : cx<T>{T(0), T(0)};
+    }
+  };
+  if constexpr (PF)
+    if (int(blockIdx.x) < nitems) fetch(blockIdx.x);
 
-  // ---- B: x-pass per row ----
-  const T* Vz = Vt + long(z) * N * N;
-  for (int y0 = 0; y0 < N; y0 += RB) {
-    const int nrow = min(RB, N - y0);
-    // V(r) of this thread's second-stage points, loaded before the first stage so the load latency is hidden
-    T vr[N2];
-    const bool has2 = tid < nrow * N1;  // at most one second-stage task per thread (RB * N1 <= NT)
-    {
-      const int yy = tid / N1, a = tid - (tid / N1) * N1;
-      const T* Vrow = Vz + long(y0 + (has2 ? yy : 0)) * N + a;
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int z = item % N, band = item / N;
+    const long base = long(band) * N * ncol + long(z) * ncol;
+    const cx<T>* in = cin + base;
+    cx<T>* out = cout + base;
+    cx<T> v0[N1];
+    if constexpr (PF) {
 #pragma unroll
-      for (int b = 0; b < N2; ++b) vr[b] = has2 ? Vrow[N1 * b] : T(0);
+      for (int n1 = 0; n1 < N1; ++n1) v0[n1] = pre[n1];
+      if (item + int(gridDim.x) < nitems) fetch(item + gridDim.x);  // in flight during this item
     }
-    for (int task = tid; task < nrow * N2; task += NT) {
-      const int yy = task / N2, n2 = task - yy * N2;
-      const int y = y0 + yy, py = PS * (y % N1) + y / N1;
+
+    // ---- A: inverse y ----
+    for (int task = tid; task < nx * N2; task += NT) {
+      const int xi = task / N2, n2 = task - xi * N2;
       cx<T> v[N1];
+      if (PF && task == tid) {
 #pragma unroll
-      for (int n1 = 0; n1 < N1; ++n1) {
-        const int gx = freq<N>(N2 * n1 + n2);
-        v[n1] = (gx >= -rx && gx <= rx) ? cx<T>(L[(gx + rx) * LS + py]) : cx<T>{T(0), T(0)};
+        for (int n1 = 0; n1 < N1; ++n1) v[n1] = v0[n1];
+      } else {
+        const int4 xl = xline[xi];  // {first column, lowest gy, column count, 0}
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+          const int j = freq<N>(N2 * n1 + n2) - xl.y;
+          v[n1] = (j >= 0 && j < xl.z) ? cx<T>(in[xl.x + j]) : cx<T>{T(0), T(0)};
+        }
       }
       Dft<N1, +1>::run(v);
 #pragma unroll
-      for (int k1 = 0; k1 < N1; ++k1)
-        Sc[yy * LS + PS * k1 + n2] = k1 ? cmul(v[k1], conj_if(twA[k1 * N2 + n2], true)) : v[0];
+      for (int k1 = 0; k1 < N1; ++k1) L[xi * LS + PS * k1 + n2] = k1 ? cmul(v[k1], conj_if(twA[k1 * N2 + n2], true)) : v[0];
     }
     __syncthreads();
-    if (has2) {
-      const int yy = tid / N1, a = tid - yy * N1;
-      cx<T>* p = Sc + yy * LS + PS * a;
+    for (int task = tid; task < nx * N1; task += NT) {
+      const int xi = task / N1, a = task - xi * N1;
+      cx<T>* p = L + xi * LS + PS * a;
       cx<T> v[N2];
 #pragma unroll
       for (int n2 = 0; n2 < N2; ++n2) v[n2] = p[n2];
-      Dft<N2, +1>::run(v);  // v[b] = psi(x = a + N1 b)
+      Dft<N2, +1>::run(v);
 #pragma unroll
-      for (int b = 0; b < N2; ++b) v[b] = cx<T>{v[b].x * vr[b], v[b].y * vr[b]};
+      for (int k2 = 0; k2 < N2; ++k2) p[k2] = v[k2];  // y = a + N1 k2
+    }
+    __syncthreads();
+
+    // ---- B: x-pass per row ----
+    const T* Vz = Vt + long(z) * N * N;
+    for (int y0 = 0; y0 < N; y0 += RB) {
+      const int nrow = min(RB, N - y0);
+      // V(r) of this thread's second-stage points, loaded before the first stage so the load latency is hidden
+      T vr[N2];
+      const bool has2 = tid < nrow * N1;  // at most one second-stage task per thread (RB * N1 <= NT)
+      {
+        const int yy = tid / N1, a = tid - (tid / N1) * N1;
+        const T* Vrow = Vz + long(y0 + (has2 ? yy : 0)) * N + a;
+#pragma unroll
+        for (int b = 0; b < N2; ++b) vr[b] = has2 ? Vrow[N1 * b] : T(0);
+      }
+      for (int task = tid; task < nrow * N2; task += NT) {
+        const int yy = task / N2, n2 = task - yy * N2;
+        const int y = y0 + yy, py = PS * (y % N1) + y / N1;
+        cx<T> v[N1];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+          const int gx = freq<N>(N2 * n1 + n2);
+          v[n1] = (gx >= -rx && gx <= rx) ? cx<T>(L[(gx + rx) * LS + py]) : cx<T>{T(0), T(0)};
+        }
+        Dft<N1, +1>::run(v);
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1)
+          Sc[yy * LS + PS * k1 + n2] = k1 ? cmul(v[k1], conj_if(twA[k1 * N2 + n2], true)) : v[0];
+      }
+      __syncthreads();
+      if (has2) {
+        const int yy = tid / N1, a = tid - yy * N1;
+        cx<T>* p = Sc + yy * LS + PS * a;
+        cx<T> v[N2];
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) v[n2] = p[n2];
+        Dft<N2, +1>::run(v);  // v[b] = psi(x = a + N1 b)
+#pragma unroll
+        for (int b = 0; b < N2; ++b) v[b] = cx<T>{v[b].x * vr[b], v[b].y * vr[b]};
+        Dft<N2, -1>::run(v);
+#pragma unroll
+        for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twB[kb * N1 + a]) : v[0];
+      }
+      __syncthreads();
+      for (int task = tid; task < nrow * N2; task += NT) {
+        const int yy = task / N2, kb = task - yy * N2;
+        const int y = y0 + yy, py = PS * (y % N1) + y / N1;
+        cx<T> v[N1];
+#pragma unroll
+        for (int a = 0; a < N1; ++a) v[a] = Sc[yy * LS + PS * a + kb];
+        Dft<N1, -1>::run(v);
+#pragma unroll
+        for (int ka = 0; ka < N1; ++ka) {
+          const int gx = freq<N>(kb + N2 * ka);
+          if (gx >= -rx && gx <= rx) L[(gx + rx) * LS + py] = v[ka];
+        }
+      }
+      __syncthreads();
+    }
+
+    // ---- C: forward y ----
+    for (int task = tid; task < nx * N1; task += NT) {
+      const int xi = task / N1, a = task - xi * N1;
+      cx<T>* p = L + xi * LS + PS * a;
+      cx<T> v[N2];
+#pragma unroll
+      for (int b = 0; b < N2; ++b) v[b] = p[b];
       Dft<N2, -1>::run(v);
 #pragma unroll
       for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twB[kb * N1 + a]) : v[0];
     }
     __syncthreads();
-    for (int task = tid; task < nrow * N2; task += NT) {
-      const int yy = task / N2, kb = task - yy * N2;
-      const int y = y0 + yy, py = PS * (y % N1) + y / N1;
+    for (int task = tid; task < nx * N2; task += NT) {
+      const int xi = task / N2, kb = task - xi * N2;
+      const int4 xl = xline[xi];
       cx<T> v[N1];
 #pragma unroll
-      for (int a = 0; a < N1; ++a) v[a] = Sc[yy * LS + PS * a + kb];
+      for (int a = 0; a < N1; ++a) v[a] = L[xi * LS + PS * a + kb];
       Dft<N1, -1>::run(v);
 #pragma unroll
       for (int ka = 0; ka < N1; ++ka) {
-        const int gx = freq<N>(kb + N2 * ka);
-        if (gx >= -rx && gx <= rx) L[(gx + rx) * LS + py] = v[ka];
+        const int j = freq<N>(kb + N2 * ka) - xl.y;
+        if (j >= 0 && j < xl.z) out[xl.x + j] = v[ka];
       }
     }
-    __syncthreads();
-  }
-
-  // ---- C: forward y ----
-  for (int task = tid; task < nx * N1; task += NT) {
-    const int xi = task / N1, a = task - xi * N1;
-    cx<T>* p = L + xi * LS + PS * a;
-    cx<T> v[N2];
-#pragma unroll
-    for (int b = 0; b < N2; ++b) v[b] = p[b];
-    Dft<N2, -1>::run(v);
-#pragma unroll
-    for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twB[kb * N1 + a]) : v[0];
-  }
-  __syncthreads();
-  for (int task = tid; task < nx * N2; task += NT) {
-    const int xi = task / N2, kb = task - xi * N2;
-    const int4 xl = xline[xi];
-    cx<T> v[N1];
-#pragma unroll
-    for (int a = 0; a < N1; ++a) v[a] = L[xi * LS + PS * a + kb];
-    Dft<N1, -1>::run(v);
-#pragma unroll
-    for (int ka = 0; ka < N1; ++ka) {
-      const int j = freq<N>(kb + N2 * ka) - xl.y;
-      if (j >= 0 && j < xl.z) out[xl.x + j] = v[ka];
-    }
+    __syncthreads();  // the next item overwrites the x-lines
   }
 }
 
@@ -519,7 +580,20 @@ hipError_t fft_plane(const FftGeom& g, const cx<T>* tw, const T* Vt, const cx<T>
     constexpr int N = decltype(nc)::value;
     const size_t lds = plane_lds<N, T>(2 * g.rx + 1);
     if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_plane<N, T>), dim3(N, nb), dim3(NT), lds, st, g.ncol, g.rx, g.xline, tw, Vt, cin, cout);
+    // FP64: as many blocks as stay resident (LDS and registers), so that no block starts its share of items
+    // late; FP32 (measured 2% slower persistent): one block per item
+    const int nitems = N * nb;
+    int grid = nitems;
+    if (sizeof(T) == 8) {
+      int per_cu = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_plane<N, T>), NT,
+                                                       lds) != hipSuccess ||
+          per_cu <= 0)
+        per_cu = 1;
+      grid = int(std::min<long>(nitems, long(compute_units()) * per_cu));
+    }
+    hipLaunchKernelGGL((k_plane<N, T>), dim3(grid), dim3(NT), lds, st, g.ncol, g.rx, g.xline, tw, Vt, cin, cout,
+                       nitems);
     return hipGetLastError();
   });
 }
