@@ -217,6 +217,8 @@ struct Ws {
   int *cidx = nullptr, *coff = nullptr;  // its clusters: members (n), offsets (n + 1)
   double* bmax = nullptr;                // per-block maxima of |F|
   float* bsc = nullptr;  // per-band power-of-two scales of the split GEMMs
+  _Float16* hb = nullptr;  // mixed plans: the back-projection's projector-space operand split into FP16 planes
+  long hb_ld = 0;
   c128 *cp = nullptr, *cq = nullptr, *cr = nullptr;  // iterative capacitance solve: right side, solution, residual
   void* Xs = nullptr;   // band-sorted copy for the per-band degree filter
   int* lidx = nullptr;  // its gather / scatter indices (3 nb)
@@ -374,6 +376,10 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
   }
   w->part = b.take<c128>(std::max<size_t>(part, 1));
   w->bsc = b.take<float>(std::max(nb, 1));
+  if (p->prec == CHEB_MIXED && np > 0) {
+    w->hb_ld = ((np + 31) / 32) * 32;
+    w->hb = b.take<_Float16>(4 * size_t(std::max(nb, 1)) * w->hb_ld);
+  }
   if (p->has_overlap && p->cap_iters > 0 && op != CHEB_OP_SETUP && op != CHEB_OP_RR) {
     w->cp = b.take<c128>(pp);
     w->cq = b.take<c128>(pp);
@@ -621,9 +627,15 @@ template <typename T> struct Ops {
     Timed t(p, st, CHEB_T_BACKPROJECT, npw * np * b + np * nb * 16.0 + vecs * npw * nb * b, 8.0 * npw * nb * np);
     if (use_split()) {
       if constexpr (std::is_same<T, float>::value) {
+        // the small projector-space operand split once into FP16 planes (not once per block and K tile)
+        if (!w.hb) return fail(p, CHEB_ERR_STATE, "workspace laid out without the split back-projection operand");
         HIPCHK(column_scales<double>(p->nproj, nb, wv, ldw, w.bsc, st));
-        HIPCHK((gemm_h<double, float>(GEMM_NN, p->npw, nb, p->nproj, p->hback, wv, ldw, w.bsc, e, 1, nullptr, st,
-                                      ROLE_BACKPROJECT)));
+        HIPCHK(split_columns(p->nproj, nb, wv, ldw, w.bsc, w.hb, w.hb_ld, st));
+        HalfPlanes bp;
+        bp.p = w.hb;
+        bp.rows = nb;
+        bp.ld = w.hb_ld;
+        HIPCHK((gemm_h_pre<float>(GEMM_NN, p->npw, nb, p->nproj, p->hback, bp, w.bsc, e, st, ROLE_BACKPROJECT)));
       }
     } else {
       HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, p->nproj, P(), p->npw, wv, ldw, e, 1, nullptr, st,

@@ -435,11 +435,12 @@ __device__ __forceinline__ f4 mul3(h8 xh, h8 xl, h8 yh, h8 yl, f4 acc) {
 // One 64 x 64 complex output tile per block of 4 waves, wave quadrants as in k_gemm. The 16x16x32 FP16 MFMA
 // takes, in lane l, row l % 16 of A and column l % 16 of B at k = 8 (l / 16) ... 8 (l / 16) + 7, and returns
 // row 4 (l / 16) + v, column l % 16 in accumulator element v.
-template <typename EB, typename EO, int MODE, int ROLE, int NE>
+// BPRE: B arrives as pre-split planes Bp [4][brows][bld] (see split_columns) and is copied to LDS as it is.
+template <typename EB, typename EO, int MODE, int ROLE, int NE, bool BPRE>
 __global__ __launch_bounds__(NT) void k_gemm_h(int M, int N, int K, int kchunk, const _Float16* __restrict__ Ap,
                                                long arows, long ald, double ainv, const cx<EB>* __restrict__ B,
-                                               long ldb, const float* __restrict__ bsc, Epi<EO> epi,
-                                               c128* __restrict__ part) {
+                                               long ldb, const _Float16* __restrict__ Bp, long brows, long bld,
+                                               const float* __restrict__ bsc, Epi<EO> epi, c128* __restrict__ part) {
   __shared__ __align__(16) _Float16 As[4][BM][HLD];
   __shared__ __align__(16) _Float16 Bs[4][BN][HLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(NT) void k_gemm_h(int M, int N, int K, int kchunk, 
   const float sc = gn < N ? bsc[gn] : 1.f;
   // raw registers of one K tile (A planes as stored, B in its storage type), converted and split only when
   // written to LDS, so that the loads of the next tile stay in flight during the MFMAs of this one
-  h8 ra[4];
+  h8 ra[4], rb[4];
   cx<EB> vb[8];
   auto load_tile = [&](int k0) {
     const int kk = k0 + 8 * lgrp;
@@ -473,17 +474,31 @@ __global__ __launch_bounds__(NT) void k_gemm_h(int M, int N, int K, int kchunk, 
       if (gm < M) v = *reinterpret_cast<const h8*>(Ap + (pl * arows + gm) * ald + kk);  // K padded to 32: in bounds
       ra[pl] = v;
     }
-    const cx<EB>* col = B + (gn < N ? gn : 0) * ldb;
+    if constexpr (BPRE) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      cx<EB> v = {EB(0), EB(0)};
-      if (gn < N && kk + j < kend) v = col[kk + j];
-      vb[j] = v;
+      for (int pl = 0; pl < 4; ++pl) {
+        h8 v = {};
+        if (gn < N) v = *reinterpret_cast<const h8*>(Bp + (pl * brows + gn) * bld + kk);  // padded with zeros
+        rb[pl] = v;
+      }
+    } else {
+      const cx<EB>* col = B + (gn < N ? gn : 0) * ldb;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        cx<EB> v = {EB(0), EB(0)};
+        if (gn < N && kk + j < kend) v = col[kk + j];
+        vb[j] = v;
+      }
     }
   };
   auto store_tile = [&]() {
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<h8*>(&As[pl][lrow][8 * lgrp]) = ra[pl];
+    if constexpr (BPRE) {
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<h8*>(&Bs[pl][lrow][8 * lgrp]) = rb[pl];
+      return;
+    }
     h8 rh, rl, ih, il;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -609,6 +624,23 @@ __global__ void k_split_planes(const c128* __restrict__ X, long ldx, int ksrc, b
   }
 }
 
+__global__ void k_split_columns(int K, int N, const c128* __restrict__ B, long ldb, const float* __restrict__ bsc,
+                                _Float16* __restrict__ P, long pld) {
+  const long total = long(N) * pld;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long n = t / pld, k = t - n * pld;
+    c128 v = {0.0, 0.0};
+    if (k < K) v = B[k + n * ldb];
+    const double sc = double(bsc[n]);  // the same operations as the on-the-fly split in k_gemm_h
+    const float xr = float(v.x * sc), xi = float(v.y * sc);
+    const _Float16 hr = _Float16(xr), hi = _Float16(xi);
+    P[t] = hr;
+    P[total + t] = _Float16(xr - float(hr));
+    P[2 * total + t] = hi;
+    P[3 * total + t] = _Float16(xi - float(hi));
+  }
+}
+
 }  // namespace
 
 int gemm_pick_splits(int M, int N, int K) {
@@ -723,15 +755,16 @@ hipError_t gemm_h(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const
   const int ne = epi_slots(en);
   auto launch = [&](auto modec, auto rolec) {
     constexpr int MO = decltype(modec)::value, RO = decltype(rolec)::value;
+    const _Float16* nb16 = nullptr;
     if (ne == 0 || use_part)
-      hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO, 0>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows, A.ld,
-                         A.inv_scale, B, ldb, bscale, en, pp);
+      hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO, 0, false>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows,
+                         A.ld, A.inv_scale, B, ldb, nb16, 0L, 0L, bscale, en, pp);
     else if (ne == 1)
-      hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO, 1>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows, A.ld,
-                         A.inv_scale, B, ldb, bscale, en, pp);
+      hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO, 1, false>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows,
+                         A.ld, A.inv_scale, B, ldb, nb16, 0L, 0L, bscale, en, pp);
     else
-      hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO, 3>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows, A.ld,
-                         A.inv_scale, B, ldb, bscale, en, pp);
+      hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO, 3, false>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows,
+                         A.ld, A.inv_scale, B, ldb, nb16, 0L, 0L, bscale, en, pp);
   };
   using CN = std::integral_constant<int, GEMM_CN>;
   using NNm = std::integral_constant<int, GEMM_NN>;
@@ -743,6 +776,48 @@ hipError_t gemm_h(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const
   int blocks = int((total + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL((k_reduce<EO>), dim3(blocks), dim3(256), 0, st, M, N, splits, part, epi);
+  return hipGetLastError();
+}
+
+hipError_t split_columns(int K, int N, const c128* B, long ldb, const float* bscale, _Float16* planes, long pld,
+                         hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  if (K < 0 || pld < K || pld % HBK || ldb < K) return hipErrorInvalidValue;
+  const long total = long(N) * pld;
+  const long blocks = std::min<long>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_split_columns, dim3(unsigned(blocks)), dim3(256), 0, st, K, N, B, ldb, bscale, planes, pld);
+  return hipGetLastError();
+}
+
+template <typename EO>
+hipError_t gemm_h_pre(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const HalfPlanes& Bp,
+                      const float* bscale, const Epi<EO>& epi, hipStream_t st, GemmRole role) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const long kp = ((std::max(K, 0) + HBK - 1) / HBK) * HBK;
+  if (!A.p || A.rows < M || A.ld % HBK || A.ld < kp) return hipErrorInvalidValue;
+  if (!Bp.p || Bp.rows != N || Bp.ld % HBK || Bp.ld < kp) return hipErrorInvalidValue;
+  int kchunk = std::max<int>(HBK, int(kp));
+  dim3 grid(((M + BM - 1) / BM) * ((N + BN - 1) / BN));
+  Epi<EO> en = epi;
+  const int ne = epi_slots(en);
+  const cx<double>* nb64 = nullptr;
+  c128* np = nullptr;
+  auto launch = [&](auto modec, auto rolec) {
+    constexpr int MO = decltype(modec)::value, RO = decltype(rolec)::value;
+    if (ne == 0)
+      hipLaunchKernelGGL((k_gemm_h<double, EO, MO, RO, 0, true>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows,
+                         A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np);
+    else if (ne == 1)
+      hipLaunchKernelGGL((k_gemm_h<double, EO, MO, RO, 1, true>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows,
+                         A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np);
+    else
+      hipLaunchKernelGGL((k_gemm_h<double, EO, MO, RO, 3, true>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows,
+                         A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np);
+  };
+  using CN = std::integral_constant<int, GEMM_CN>;
+  using NNm = std::integral_constant<int, GEMM_NN>;
+  if (role == ROLE_BACKPROJECT) mode == GEMM_CN ? launch(CN{}, std::integral_constant<int, 2>{}) : launch(NNm{}, std::integral_constant<int, 2>{});
+  else mode == GEMM_CN ? launch(CN{}, std::integral_constant<int, 1>{}) : launch(NNm{}, std::integral_constant<int, 1>{});
   return hipGetLastError();
 }
 
@@ -777,6 +852,8 @@ template hipError_t gemm_h<float, double>(GemmMode, int, int, int, const HalfPla
                                           const Epi<double>&, int, c128*, hipStream_t, GemmRole);
 template hipError_t gemm_h<double, float>(GemmMode, int, int, int, const HalfPlanes&, const c128*, long,
                                           const float*, const Epi<float>&, int, c128*, hipStream_t, GemmRole);
+template hipError_t gemm_h_pre<float>(GemmMode, int, int, int, const HalfPlanes&, const HalfPlanes&, const float*,
+                                       const Epi<float>&, hipStream_t, GemmRole);
 template hipError_t column_scales<float>(long, int, const c64*, long, float*, hipStream_t);
 template hipError_t column_scales<double>(long, int, const c128*, long, float*, hipStream_t);
 
