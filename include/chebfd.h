@@ -255,6 +255,17 @@ cheb_status cheb_profile_enable(cheb_plan plan, int on);
 cheb_status cheb_profile_read(cheb_plan plan, int timer, double* ms, int64_t* launches, double* algo_bytes,
                               double* algo_flops);
 
+/* Tiling rules of the complex GEMMs, host arithmetic only (no device call; usable without a GPU). For an
+ * M x N x K product: *fp64 = the split-K count of the tiled FP64/FP32 kernel, *fp16 = that of the FP16 split
+ * kernel of mixed plans, *bound = the count every workspace sizes its split-K partials by (each partial buffer
+ * holds bound x M x N complex FP64 values; bound >= fp64 and bound >= fp16). CHEB_ERR_ARG for a null pointer. */
+cheb_status cheb_gemm_splits(int M, int N, int K, int* fp64, int* fp16, int* bound);
+/* Work item of block i in a tiled GEMM launch of `total` blocks over (split, M tile, N tile) items with
+ * tm x tn tiles per split: the blocks are dealt to the 8 XCDs in turn and each XCD receives one contiguous run
+ * of items, so that blocks sharing an operand slice share an L2. Host arithmetic only. CHEB_ERR_ARG unless
+ * 0 <= i < total, total a multiple of tm * tn > 0 and the pointers non-null. */
+cheb_status cheb_gemm_block_item(int i, int total, int tm, int tn, int* bx, int* by, int* bz);
+
 /* Message of the last failing call on `plan` ("" if none). Valid until the next call on the plan. */
 const char* cheb_last_error(cheb_plan plan);
 

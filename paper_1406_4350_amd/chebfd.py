@@ -32,7 +32,8 @@ SYMBOLS = ["cheb_plan_persistent_bytes", "cheb_plan_create", "cheb_plan_destroy"
            "cheb_apply_Sinv", "cheb_filter", "cheb_rayleigh_ritz", "cheb_rayleigh_quotients", "cheb_upper_bound",
            "cheb_profile_enable", "cheb_profile_read", "cheb_backward_workspace_bytes", "cheb_filter_rr_backward",
            "cheb_set_rr_refine", "cheb_rr_stats", "cheb_filter_degrees", "cheb_locking_degrees", "cheb_set_split_gemm",
-           "cheb_set_capacitance_solver", "cheb_lobpcg_state_bytes", "cheb_lobpcg_iterate", "cheb_last_error"]
+           "cheb_set_capacitance_solver", "cheb_lobpcg_state_bytes", "cheb_lobpcg_iterate", "cheb_gemm_splits",
+           "cheb_gemm_block_item", "cheb_last_error"]
 TIMERS = ["fft_col_inverse", "fft_plane", "fft_col_forward", "project", "backproject", "small", "rr_gram", "rr_eig",
           "rr_rotate", "xdens"]
 
@@ -90,6 +91,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cheb_lobpcg_state_bytes": [vp, i, P(sz)],
         "cheb_lobpcg_iterate": [vp, vp, i, i, i, d, vp, sz, vp, vp, P(i), vp, sz, vp],
         "cheb_locking_degrees": [i, vp, vp, d, d, i, d, vp, P(i)],
+        "cheb_gemm_splits": [i, i, i, P(i), P(i), P(i)],
+        "cheb_gemm_block_item": [i, i, i, i, P(i), P(i), P(i)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

@@ -2117,6 +2117,21 @@ cheb_status cheb_filter_degrees(cheb_plan p, void* X, int ldx, int nb, const int
   });
 }
 
+cheb_status cheb_gemm_splits(int M, int N, int K, int* fp64, int* fp16, int* bound) {
+  if (!fp64 || !fp16 || !bound) return CHEB_ERR_ARG;
+  *fp64 = gemm_pick_splits(M, N, K);
+  *fp16 = gemm_h_pick_splits(M, N, K);
+  *bound = gemm_split_bound(M, N, K);
+  return CHEB_OK;
+}
+
+cheb_status cheb_gemm_block_item(int i, int total, int tm, int tn, int* bx, int* by, int* bz) {
+  if (!bx || !by || !bz || tm <= 0 || tn <= 0 || total <= 0 || i < 0 || i >= total) return CHEB_ERR_ARG;
+  if (total % (long(tm) * tn)) return CHEB_ERR_ARG;
+  gemm_block_item(i, total, tm, tn, *bx, *by, *bz);
+  return CHEB_OK;
+}
+
 cheb_status cheb_locking_degrees(int nb, const double* ritz, const double* resid, double c, double r, int m_max,
                                  double tol, int32_t* degrees, int* nlocked) {
   if (nb < 0 || m_max < 1 || !(r > 0.0) || !std::isfinite(c) || !std::isfinite(r) || !(tol >= 0.0)) return CHEB_ERR_ARG;

@@ -722,6 +722,10 @@ hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, c
   return hipGetLastError();
 }
 
+void gemm_block_item(int i, int total, int tm, int tn, int& bx, int& by, int& bz) {
+  gemm_tile_of(i, total, tm, tn, bx, by, bz);
+}
+
 // upper bound of the split counts any GEMM kernel here picks for an M x N x K product (partial-buffer sizing):
 // 512 target blocks, two K tiles of 32 per split, at most 32 splits; gemm_pick_splits and gemm_h_pick_splits
 // never exceed it

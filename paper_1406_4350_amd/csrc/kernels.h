@@ -61,6 +61,8 @@ hipError_t gemm_h_pre(GemmMode mode, int M, int N, int K, const HalfPlanes& A, c
 int gemm_h_pick_splits(int M, int N, int K);
 // upper bound of both split rules, for sizing split-K partial buffers
 int gemm_split_bound(int M, int N, int K);
+// the work item (M tile bx, N tile by, split bz) the tiled kernels give block i of a `total`-block launch
+void gemm_block_item(int i, int total, int tm, int tn, int& bx, int& by, int& bz);
 // bscale[n] = 2^-e with max_k |B[k][n]| (over Re and Im) in [2^(e-1), 2^e); 1 for a zero column
 template <typename E> hipError_t column_scales(long rows, int ncols, const cx<E>* B, long ldb, float* bscale,
                                                hipStream_t st);

@@ -131,3 +131,41 @@ def test_locking_degrees_host_function(lib):
     with pytest.raises(cf.ChebError):
         cf.locking_degrees(ritz, bad, c, r, m, tol)
     assert cf.locking_degrees(ritz[:0], resid[:0], c, r, m, tol)[0].shape == (0,)
+
+
+def test_gemm_split_bound_covers_both_kernels(lib):
+    """Split-K partial buffers hold bound x M x N values: the bound must cover the split count either GEMM
+    kernel picks, for every shape (host arithmetic of the C ABI, no GPU). Shapes around the tile sizes (64, 16)
+    and K tiles (32), the paw48 projector and subspace shapes and large K."""
+    f64, f16, bd = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    mn = [1, 2, 15, 16, 17, 63, 64, 65, 127, 128, 129, 200, 255, 256, 257, 300, 448, 511, 512, 513, 1000, 2109, 7153]
+    ks = [1, 2, 3, 16, 31, 32, 33, 63, 64, 65, 100, 256, 257, 1000, 1024, 1025, 2109, 7153, 20000, 137065]
+    for M in mn:
+        for N in mn:
+            for K in ks:
+                assert lib.cheb_gemm_splits(M, N, K, ctypes.byref(f64), ctypes.byref(f16), ctypes.byref(bd)) == cf.CHEB_OK
+                assert 1 <= f64.value <= 32 and 1 <= f16.value <= 32, (M, N, K, f64.value, f16.value)
+                assert bd.value >= max(f64.value, f16.value), (M, N, K, f64.value, f16.value, bd.value)
+    assert lib.cheb_gemm_splits(4, 4, 4, None, ctypes.byref(f16), ctypes.byref(bd)) == cf.CHEB_ERR_ARG
+
+
+def test_gemm_block_item_is_a_bijection_with_one_run_per_xcd(lib):
+    """Block i of a tiled GEMM launch takes work item (split, M tile, N tile) so that every item is taken once
+    and the blocks dealt to each of the 8 XCDs (i mod 8) hold one contiguous run of items (host arithmetic)."""
+    bx, by, bz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    for tm, tn, s in [(1, 1, 1), (1, 1, 7), (2, 3, 1), (4, 4, 16), (7, 5, 3), (112, 4, 1), (4, 4, 32), (9, 9, 2),
+                      (3, 1, 13), (16, 16, 1)]:
+        total = tm * tn * s
+        seen = {}
+        for i in range(total):
+            assert lib.cheb_gemm_block_item(i, total, tm, tn, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == 0
+            item = (bz.value * tm + bx.value) * tn + by.value  # (split, M tile, N tile), N tile fastest
+            assert 0 <= bx.value < tm and 0 <= by.value < tn and 0 <= bz.value < s
+            assert item not in seen.values()
+            seen[i] = item
+        assert sorted(seen.values()) == list(range(total))
+        for x in range(8):
+            items = sorted(seen[i] for i in range(x, total, 8))
+            assert items == list(range(items[0], items[0] + len(items))) if items else True, (tm, tn, s, x)
+    assert lib.cheb_gemm_block_item(5, 5, 1, 1, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == cf.CHEB_ERR_ARG
+    assert lib.cheb_gemm_block_item(0, 7, 2, 2, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == cf.CHEB_ERR_ARG
