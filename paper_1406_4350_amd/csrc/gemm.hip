@@ -590,24 +590,25 @@ __global__ __launch_bounds__(NT) void k_gemm_h(int M, int N, int K, int kchunk, 
   }
 }
 
+// one 1024-thread block per column (16 waves per CU keep enough loads in flight), max over lanes by shuffles
+constexpr int CST = 1024;
 template <typename E>
-__global__ __launch_bounds__(256) void k_colscale(long rows, const cx<E>* __restrict__ B, long ldb, float* bsc,
+__global__ __launch_bounds__(CST) void k_colscale(long rows, const cx<E>* __restrict__ B, long ldb, float* bsc,
                                                   double* maxout) {
-  __shared__ double red[256];
+  __shared__ double red[CST / 64];
   const cx<E>* col = B + long(blockIdx.x) * ldb;
   double mx = 0.0;
   for (long i = threadIdx.x; i < rows; i += blockDim.x) {
     const cx<E> v = col[i];
     mx = fmax(mx, fmax(fabs(double(v.x)), fabs(double(v.y))));
   }
-  red[threadIdx.x] = mx;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
     mx = red[0];
+    for (int w = 1; w < CST / 64; ++w) mx = fmax(mx, red[w]);
     if (maxout) maxout[blockIdx.x] = mx;
     if (bsc) {
       int e = 0;
@@ -840,13 +841,13 @@ hipError_t gemm_h_pre(GemmMode mode, int M, int N, int K, const HalfPlanes& A, c
 template <typename E>
 hipError_t column_scales(long rows, int ncols, const cx<E>* B, long ldb, float* bscale, hipStream_t st) {
   if (ncols <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_colscale<E>), dim3(ncols), dim3(256), 0, st, rows, B, ldb, bscale, nullptr);
+  hipLaunchKernelGGL((k_colscale<E>), dim3(ncols), dim3(CST), 0, st, rows, B, ldb, bscale, nullptr);
   return hipGetLastError();
 }
 
 hipError_t column_maxabs(long rows, int ncols, const c128* X, long ldx, double* out, hipStream_t st) {
   if (ncols <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_colscale<double>), dim3(ncols), dim3(256), 0, st, rows, X, ldx, nullptr, out);
+  hipLaunchKernelGGL((k_colscale<double>), dim3(ncols), dim3(CST), 0, st, rows, X, ldx, nullptr, out);
   return hipGetLastError();
 }
 
