@@ -52,7 +52,8 @@ typedef enum {
   CHEB_ERR_NOT_PD = 4,       /* a matrix that must be Hermitian positive definite is not (S_X, capacitance) */
   CHEB_ERR_EIG = 5,          /* the dense eigensolver did not converge */
   CHEB_ERR_NONFINITE = 6,    /* NaN or Inf met in a subspace matrix */
-  CHEB_ERR_STATE = 7         /* potential, projectors or D not set yet */
+  CHEB_ERR_STATE = 7,        /* potential, projectors or D not set yet */
+  CHEB_ERR_HOST = 8          /* host-side failure (host memory exhausted); any call may return it */
 } cheb_status;
 
 typedef enum { CHEB_FP64 = 0, CHEB_MIXED = 1 } cheb_prec;

@@ -19,9 +19,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libchebfd.so")
 
 CHEB_OK, CHEB_ERR_ARG, CHEB_ERR_HIP, CHEB_ERR_WORKSPACE, CHEB_ERR_NOT_PD, CHEB_ERR_EIG, CHEB_ERR_NONFINITE, \
-    CHEB_ERR_STATE = range(8)
+    CHEB_ERR_STATE, CHEB_ERR_HOST = range(9)
 STATUS_NAMES = ["CHEB_OK", "CHEB_ERR_ARG", "CHEB_ERR_HIP", "CHEB_ERR_WORKSPACE", "CHEB_ERR_NOT_PD", "CHEB_ERR_EIG",
-                "CHEB_ERR_NONFINITE", "CHEB_ERR_STATE"]
+                "CHEB_ERR_NONFINITE", "CHEB_ERR_STATE", "CHEB_ERR_HOST"]
 CHEB_FP64, CHEB_MIXED = 0, 1
 (CHEB_OP_H, CHEB_OP_SINV, CHEB_OP_FILTER, CHEB_OP_RR, CHEB_OP_BOUND, CHEB_OP_SETUP, CHEB_OP_FILTER_DEGREES,
  CHEB_OP_LOBPCG) = range(8)

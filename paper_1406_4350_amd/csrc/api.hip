@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -95,6 +96,18 @@ cheb_status fail(cheb_plan p, cheb_status s, const std::string& msg) {
   return s;
 }
 
+// Every status-returning entry point is a function-try-block: a C++ exception (host memory exhausted in a
+// std::vector or std::string) must not cross the C ABI, so it ends the call with CHEB_ERR_HOST instead.
+cheb_status host_fail(cheb_plan p) noexcept {
+  if (p) {
+    try {
+      p->err = "host-side failure (out of host memory or an internal exception)";
+    } catch (...) {
+    }
+  }
+  return CHEB_ERR_HOST;
+}
+
 #define HIPCHK(expr)                                                                                   \
   do {                                                                                                 \
     hipError_t e_ = (expr);                                                                            \
@@ -127,10 +140,16 @@ struct Timed {
     if (!p->prof_free.empty()) {
       ev = p->prof_free.back();
       p->prof_free.pop_back();
-    } else if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+    } else if (hipEventCreate(&ev.first) != hipSuccess) {
+      return;
+    } else if (hipEventCreate(&ev.second) != hipSuccess) {
+      (void)hipEventDestroy(ev.first);
       return;
     }
-    if (hipEventRecord(ev.first, st) != hipSuccess) return;
+    if (hipEventRecord(ev.first, st) != hipSuccess) {
+      p->prof_free.push_back(ev);  // unused pair: back to the pool, released with the plan
+      return;
+    }
     end = ev.second;
     p->prof_pending.push_back({ev.first, ev.second, kind});
     p->prof_bytes[kind] += bytes;
@@ -1755,7 +1774,7 @@ static cheb_status validate_desc(const cheb_desc* d, int* ncol_out, int* rx_out,
   return CHEB_OK;
 }
 
-cheb_status cheb_plan_persistent_bytes(const cheb_desc* d, size_t* bytes) {
+cheb_status cheb_plan_persistent_bytes(const cheb_desc* d, size_t* bytes) try {
   if (!bytes) return CHEB_ERR_ARG;
   int ncol = 0, rx = 0;
   size_t dsize = 0;
@@ -1767,9 +1786,11 @@ cheb_status cheb_plan_persistent_bytes(const cheb_desc* d, size_t* bytes) {
   const int npf = d->gamma ? int(fs.gmap.size()) : d->npw;
   *bytes = persist_bytes(d->n, d->npw, npf, ncol, rx, nproj, dsize, d->has_overlap ? 1 : 0, d->prec, d->gamma);
   return CHEB_OK;
+} catch (...) {
+  return host_fail(nullptr);
 }
 
-cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes, hipStream_t st, cheb_plan* out) {
+cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes, hipStream_t st, cheb_plan* out) try {
   if (!out) return CHEB_ERR_ARG;
   *out = nullptr;
   int ncol = 0, rx = 0;
@@ -1785,8 +1806,8 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
                                     d->gamma);
   if (!persistent || bytes < need || reinterpret_cast<uintptr_t>(persistent) % kAlign) return CHEB_ERR_WORKSPACE;
 
-  cheb_plan p = new (std::nothrow) cheb_plan_s;
-  if (!p) return CHEB_ERR_ARG;
+  std::unique_ptr<cheb_plan_s> owner(new cheb_plan_s);  // handed to the caller only on success
+  cheb_plan p = owner.get();
   p->n = d->n; p->npw = d->npw; p->ncol = ncol; p->rx = rx; p->natom = d->natom; p->nproj = nproj;
   p->has_overlap = d->has_overlap ? 1 : 0; p->prec = d->prec; p->dsize = dsize;
   p->gamma = d->gamma; p->npf = npf; p->h0 = fs.h0;
@@ -1837,9 +1858,12 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   }
   auto fail_hip = [&](hipError_t e, const char* what) {
     std::fprintf(stderr, "cheb_plan_create: %s: %s\n", what, hipGetErrorString(e));
-    delete p;
     return CHEB_ERR_HIP;
   };
+  // every host table exists before the first copy is issued, so that nothing thrown later frees a source
+  // buffer under a copy in flight
+  std::vector<c64> tw32(mixed ? d->n : 0);
+  std::vector<float> kin32(mixed ? d->npw : 0);
   hipError_t e;
   if ((e = hipMemcpyAsync(p->col, col.data(), sizeof(int4) * ncol, hipMemcpyHostToDevice, st))) return fail_hip(e, "col");
   if ((e = hipMemcpyAsync(p->ent, ent.data(), sizeof(int) * npf, hipMemcpyHostToDevice, st))) return fail_hip(e, "ent");
@@ -1851,8 +1875,6 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   if ((e = hipMemcpyAsync(p->pinfo, pinfo.data(), sizeof(int4) * pinfo.size(), hipMemcpyHostToDevice, st))) return fail_hip(e, "pinfo");
   if ((e = hipMemcpyAsync(p->dent, dent.data(), sizeof(int2) * dent.size(), hipMemcpyHostToDevice, st))) return fail_hip(e, "dent");
   if (mixed) {
-    std::vector<c64> tw32(d->n);
-    std::vector<float> kin32(d->npw);
     for (int j = 0; j < d->n; ++j) tw32[j] = c64{float(tw[j].x), float(tw[j].y)};
     for (int i = 0; i < d->npw; ++i) kin32[i] = float(d->kin_host[i]);
     if ((e = hipMemcpyAsync(p->tw, tw32.data(), sizeof(c64) * d->n, hipMemcpyHostToDevice, st))) return fail_hip(e, "tw");
@@ -1866,14 +1888,15 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   if ((e = fft_prepare_attributes())) return fail_hip(e, "kernel attributes");
   if (rocblas_create_handle(&p->rb) != rocblas_status_success) {
     std::fprintf(stderr, "cheb_plan_create: rocblas_create_handle failed\n");
-    delete p;
     return CHEB_ERR_HIP;
   }
-  *out = p;
+  *out = owner.release();
   return CHEB_OK;
+} catch (...) {
+  return host_fail(nullptr);
 }
 
-cheb_status cheb_plan_destroy(cheb_plan p) {
+cheb_status cheb_plan_destroy(cheb_plan p) try {
   if (!p) return CHEB_OK;
   for (auto& r : p->prof_pending) { (void)hipEventSynchronize(r.b); (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
   for (auto& r : p->prof_free) { (void)hipEventDestroy(r.first); (void)hipEventDestroy(r.second); }
@@ -1885,6 +1908,8 @@ cheb_status cheb_plan_destroy(cheb_plan p) {
   if (p->rr_host) (void)hipHostFree(p->rr_host);
   delete p;
   return CHEB_OK;
+} catch (...) {
+  return host_fail(nullptr);  // the plan may already be released
 }
 
 const char* cheb_last_error(cheb_plan p) { return p ? p->err.c_str() : "null plan"; }
@@ -1901,7 +1926,7 @@ static cheb_status prof_collect(cheb_plan p) {
   return CHEB_OK;
 }
 
-cheb_status cheb_profile_enable(cheb_plan p, int on) {
+cheb_status cheb_profile_enable(cheb_plan p, int on) try {
   if (!p) return CHEB_ERR_ARG;
   CHK(prof_collect(p));
   if (on) {
@@ -1909,9 +1934,11 @@ cheb_status cheb_profile_enable(cheb_plan p, int on) {
   }
   p->prof_on = on != 0;
   return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
 }
 
-cheb_status cheb_profile_read(cheb_plan p, int timer, double* ms, int64_t* launches, double* bytes, double* flops) {
+cheb_status cheb_profile_read(cheb_plan p, int timer, double* ms, int64_t* launches, double* bytes, double* flops) try {
   if (!p) return CHEB_ERR_ARG;
   if (timer < 0 || timer >= CHEB_T_COUNT) return fail(p, CHEB_ERR_ARG, "unknown timer");
   CHK(prof_collect(p));
@@ -1920,37 +1947,45 @@ cheb_status cheb_profile_read(cheb_plan p, int timer, double* ms, int64_t* launc
   if (bytes) *bytes = p->prof_bytes[timer];
   if (flops) *flops = p->prof_flops[timer];
   return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
 }
 
-cheb_status cheb_set_potential(cheb_plan p, const double* V, hipStream_t st) {
+cheb_status cheb_set_potential(cheb_plan p, const double* V, hipStream_t st) try {
   if (!p) return CHEB_ERR_ARG;
   if (!V) return fail(p, CHEB_ERR_ARG, "V is null");
   if (p->prec == CHEB_MIXED) HIPCHK(transpose_potential<float>(p->n, V, static_cast<float*>(p->Vt), st));
   else HIPCHK(transpose_potential<double>(p->n, V, static_cast<double*>(p->Vt), st));
   p->have_V = true;
   return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
 }
 
-cheb_status cheb_set_D(cheb_plan p, const double* D, hipStream_t st) {
+cheb_status cheb_set_D(cheb_plan p, const double* D, hipStream_t st) try {
   if (!p) return CHEB_ERR_ARG;
   if (p->dsize == 0) { p->have_D = true; return CHEB_OK; }
   if (!D) return fail(p, CHEB_ERR_ARG, "D is null");
   HIPCHK(hipMemcpyAsync(p->D, D, sizeof(double) * p->dsize, hipMemcpyDeviceToDevice, st));
   p->have_D = true;
   return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
 }
 
-cheb_status cheb_workspace_bytes(cheb_plan p, int op, int nb, size_t* bytes) {
+cheb_status cheb_workspace_bytes(cheb_plan p, int op, int nb, size_t* bytes) try {
   if (!p || !bytes) return CHEB_ERR_ARG;
   if (nb < 0) return fail(p, CHEB_ERR_ARG, "nb < 0");
   Ws w;
   CHK(ws_layout(p, op, op == CHEB_OP_BOUND ? 1 : nb, nullptr, &w));
   *bytes = w.total;
   return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
 }
 
 cheb_status cheb_set_projectors(cheb_plan p, const void* P, int ldp, const double* Q, void* ws, size_t wsb,
-                                hipStream_t st) {
+                                hipStream_t st) try {
   if (!p) return CHEB_ERR_ARG;
   const int np = p->nproj;
   if (np == 0) { p->have_P = true; return CHEB_OK; }
@@ -2016,6 +2051,8 @@ cheb_status cheb_set_projectors(cheb_plan p, const void* P, int ldp, const doubl
   HIPCHK(hipStreamSynchronize(st));
   p->have_P = true;
   return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
 }
 
 #define OP_PRELUDE(op, nbv)                  \
@@ -2046,20 +2083,26 @@ static cheb_status apply_common(cheb_plan p, int which, const void* X, int ldx, 
 }
 
 cheb_status cheb_apply_H(cheb_plan p, const void* X, int ldx, void* Y, int ldy, int nb, void* ws, size_t wsb,
-                         hipStream_t st) {
+                         hipStream_t st) try {
   return apply_common(p, 0, X, ldx, Y, ldy, nb, ws, wsb, st);
+} catch (...) {
+  return host_fail(p);
 }
 cheb_status cheb_apply_S(cheb_plan p, const void* X, int ldx, void* Y, int ldy, int nb, void* ws, size_t wsb,
-                         hipStream_t st) {
+                         hipStream_t st) try {
   return apply_common(p, 1, X, ldx, Y, ldy, nb, ws, wsb, st);
+} catch (...) {
+  return host_fail(p);
 }
 cheb_status cheb_apply_Sinv(cheb_plan p, const void* X, int ldx, void* Y, int ldy, int nb, void* ws, size_t wsb,
-                            hipStream_t st) {
+                            hipStream_t st) try {
   return apply_common(p, 2, X, ldx, Y, ldy, nb, ws, wsb, st);
+} catch (...) {
+  return host_fail(p);
 }
 
 cheb_status cheb_filter(cheb_plan p, void* X, int ldx, int nb, int m, double c, double r, void* ws, size_t wsb,
-                        hipStream_t st) {
+                        hipStream_t st) try {
   if (!p) return CHEB_ERR_ARG;
   CHK(check_block(p, X, ldx, nb, "X"));
   if (m < 0) return fail(p, CHEB_ERR_ARG, "degree m < 0");
@@ -2070,10 +2113,12 @@ cheb_status cheb_filter(cheb_plan p, void* X, int ldx, int nb, int m, double c, 
     using C = typename decltype(ops)::C;
     return ops.filter(static_cast<C*>(X), ldx, nb, m, c, r, w);
   });
+} catch (...) {
+  return host_fail(p);
 }
 
 cheb_status cheb_filter_degrees(cheb_plan p, void* X, int ldx, int nb, const int32_t* degrees, double c, double r,
-                                void* ws, size_t wsb, hipStream_t st) {
+                                void* ws, size_t wsb, hipStream_t st) try {
   if (!p) return CHEB_ERR_ARG;
   CHK(check_block(p, X, ldx, nb, "X"));
   if (nb > 0 && !degrees) return fail(p, CHEB_ERR_ARG, "degrees is null");
@@ -2115,25 +2160,31 @@ cheb_status cheb_filter_degrees(cheb_plan p, void* X, int ldx, int nb, const int
     using C = typename decltype(ops)::C;
     return ops.filter_degrees(static_cast<C*>(X), ldx, active, w.lidx, ne, no, c, r, w);
   });
+} catch (...) {
+  return host_fail(p);
 }
 
-cheb_status cheb_gemm_splits(int M, int N, int K, int* fp64, int* fp16, int* bound) {
+cheb_status cheb_gemm_splits(int M, int N, int K, int* fp64, int* fp16, int* bound) try {
   if (!fp64 || !fp16 || !bound) return CHEB_ERR_ARG;
   *fp64 = gemm_pick_splits(M, N, K);
   *fp16 = gemm_h_pick_splits(M, N, K);
   *bound = gemm_split_bound(M, N, K);
   return CHEB_OK;
+} catch (...) {
+  return host_fail(nullptr);
 }
 
-cheb_status cheb_gemm_block_item(int i, int total, int tm, int tn, int* bx, int* by, int* bz) {
+cheb_status cheb_gemm_block_item(int i, int total, int tm, int tn, int* bx, int* by, int* bz) try {
   if (!bx || !by || !bz || tm <= 0 || tn <= 0 || total <= 0 || i < 0 || i >= total) return CHEB_ERR_ARG;
   if (total % (long(tm) * tn)) return CHEB_ERR_ARG;
   gemm_block_item(i, total, tm, tn, *bx, *by, *bz);
   return CHEB_OK;
+} catch (...) {
+  return host_fail(nullptr);
 }
 
 cheb_status cheb_locking_degrees(int nb, const double* ritz, const double* resid, double c, double r, int m_max,
-                                 double tol, int32_t* degrees, int* nlocked) {
+                                 double tol, int32_t* degrees, int* nlocked) try {
   if (nb < 0 || m_max < 1 || !(r > 0.0) || !std::isfinite(c) || !std::isfinite(r) || !(tol >= 0.0)) return CHEB_ERR_ARG;
   if (nb > 0 && (!ritz || !resid || !degrees)) return CHEB_ERR_ARG;
   int locked = 0;
@@ -2158,10 +2209,12 @@ cheb_status cheb_locking_degrees(int nb, const double* ritz, const double* resid
   }
   if (nlocked) *nlocked = locked;
   return CHEB_OK;
+} catch (...) {
+  return host_fail(nullptr);
 }
 
 cheb_status cheb_rayleigh_ritz(cheb_plan p, void* X, int ldx, int nb, double* ritz, double* resid, void* ws,
-                               size_t wsb, hipStream_t st) {
+                               size_t wsb, hipStream_t st) try {
   if (!p) return CHEB_ERR_ARG;
   CHK(check_block(p, X, ldx, nb, "X"));
   if (nb > 0 && !ritz) return fail(p, CHEB_ERR_ARG, "ritz is null");
@@ -2171,10 +2224,12 @@ cheb_status cheb_rayleigh_ritz(cheb_plan p, void* X, int ldx, int nb, double* ri
     using C = typename decltype(ops)::C;
     return ops.rayleigh_ritz(static_cast<C*>(X), ldx, nb, ritz, resid, w);
   });
+} catch (...) {
+  return host_fail(p);
 }
 
 cheb_status cheb_rayleigh_quotients(cheb_plan p, const void* X, int ldx, int nb, double* rq, void* ws, size_t wsb,
-                                    hipStream_t st) {
+                                    hipStream_t st) try {
   if (!p) return CHEB_ERR_ARG;
   CHK(check_block(p, X, ldx, nb, "X"));
   if (nb > 0 && !rq) return fail(p, CHEB_ERR_ARG, "rq is null");
@@ -2184,10 +2239,12 @@ cheb_status cheb_rayleigh_quotients(cheb_plan p, const void* X, int ldx, int nb,
     using C = typename decltype(ops)::C;
     return ops.rayleigh_quotients(static_cast<const C*>(X), ldx, nb, rq, w);
   });
+} catch (...) {
+  return host_fail(p);
 }
 
 cheb_status cheb_upper_bound(cheb_plan p, int k, const void* v0, double* lambda_plus, void* ws, size_t wsb,
-                             hipStream_t st) {
+                             hipStream_t st) try {
   if (!p) return CHEB_ERR_ARG;
   if (k < 1 || k > 64) return fail(p, CHEB_ERR_ARG, "k must be in [1, 64]");
   if (!v0 || !lambda_plus) return fail(p, CHEB_ERR_ARG, "null v0 or output");
@@ -2196,18 +2253,22 @@ cheb_status cheb_upper_bound(cheb_plan p, int k, const void* v0, double* lambda_
     using C = typename decltype(ops)::C;
     return ops.upper_bound(k, static_cast<const C*>(v0), lambda_plus, w);
   });
+} catch (...) {
+  return host_fail(p);
 }
 
-cheb_status cheb_lobpcg_state_bytes(cheb_plan p, int nb, size_t* bytes) {
+cheb_status cheb_lobpcg_state_bytes(cheb_plan p, int nb, size_t* bytes) try {
   if (!p || !bytes) return CHEB_ERR_ARG;
   if (nb < 1) return fail(p, CHEB_ERR_ARG, "nb must be >= 1");
   *bytes = 15 * size_t(p->npw) * nb * elem_bytes(p->prec);
   return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
 }
 
 cheb_status cheb_lobpcg_iterate(cheb_plan p, void* X, int ldx, int nb, int iteration, double tol, void* state,
                                 size_t state_bytes, double* ritz_dev, double* resid_dev, int* nactive, void* ws,
-                                size_t wsb, hipStream_t st) {
+                                size_t wsb, hipStream_t st) try {
   if (!p) return CHEB_ERR_ARG;
   CHK(check_ready(p));
   CHK(check_block(p, X, ldx, nb, "X"));
@@ -2229,9 +2290,11 @@ cheb_status cheb_lobpcg_iterate(cheb_plan p, void* X, int ldx, int nb, int itera
     using C = typename decltype(ops)::C;
     return ops.lobpcg(static_cast<C*>(X), ldx, nb, iteration, tol, state, ritz_dev, resid_dev, nactive, w);
   });
+} catch (...) {
+  return host_fail(p);
 }
 
-cheb_status cheb_set_capacitance_solver(cheb_plan p, int iterations) {
+cheb_status cheb_set_capacitance_solver(cheb_plan p, int iterations) try {
   if (!p) return CHEB_ERR_ARG;
   if (iterations < 0 || iterations > 1000) return fail(p, CHEB_ERR_ARG, "iterations must be in [0, 1000]");
   if (iterations > 0 && !p->has_overlap) return fail(p, CHEB_ERR_ARG, "the plan has S = I: no capacitance matrix");
@@ -2240,25 +2303,33 @@ cheb_status cheb_set_capacitance_solver(cheb_plan p, int iterations) {
     return fail(p, CHEB_ERR_ARG, "atom blocks larger than 32 projectors: no block preconditioner");
   p->cap_iters = iterations;
   return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
 }
 
-cheb_status cheb_set_split_gemm(cheb_plan p, int on) {
+cheb_status cheb_set_split_gemm(cheb_plan p, int on) try {
   if (!p) return CHEB_ERR_ARG;
   p->split_gemm = on != 0;
   return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
 }
 
-cheb_status cheb_set_rr_refine(cheb_plan p, int on) {
+cheb_status cheb_set_rr_refine(cheb_plan p, int on) try {
   if (!p) return CHEB_ERR_ARG;
   p->rr_refine = on != 0;
   return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
 }
 
-cheb_status cheb_rr_stats(cheb_plan p, int64_t* refined, int64_t* fallback) {
+cheb_status cheb_rr_stats(cheb_plan p, int64_t* refined, int64_t* fallback) try {
   if (!p) return CHEB_ERR_ARG;
   if (refined) *refined = p->rr_refined;
   if (fallback) *fallback = p->rr_fallback;
   return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
 }
 
 static cheb_status backward_check(cheb_plan p, int nb, int m, int k) {
@@ -2272,18 +2343,20 @@ static cheb_status backward_check(cheb_plan p, int nb, int m, int k) {
   return CHEB_OK;
 }
 
-cheb_status cheb_backward_workspace_bytes(cheb_plan p, int nb, int m, int ckpt_every, size_t* bytes) {
+cheb_status cheb_backward_workspace_bytes(cheb_plan p, int nb, int m, int ckpt_every, size_t* bytes) try {
   if (!p || !bytes) return CHEB_ERR_ARG;
   CHK(backward_check(p, nb, m, ckpt_every));
   BwdWs w;
   CHK(bwd_layout(p, nb, m, ckpt_every, nullptr, &w));
   *bytes = w.total;
   return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
 }
 
 cheb_status cheb_filter_rr_backward(cheb_plan p, const void* X0, int ldx, int nb, int m, double c, double r, int nk,
                                    const double* w_dev, int ckpt_every, double* ritz_dev, void* dX, int lddx,
-                                   double* dV_dev, double* dD_dev, void* ws, size_t wsb, hipStream_t st) {
+                                   double* dV_dev, double* dD_dev, void* ws, size_t wsb, hipStream_t st) try {
   if (!p) return CHEB_ERR_ARG;
   CHK(check_ready(p));
   CHK(backward_check(p, nb, m, ckpt_every));
@@ -2304,6 +2377,8 @@ cheb_status cheb_filter_rr_backward(cheb_plan p, const void* X0, int ldx, int nb
     return ops.backward(static_cast<const C*>(X0), ldx, nb, m, c, r, nk, w_dev, ckpt_every, ritz_dev,
                         static_cast<C*>(dX), lddx, dV_dev, dD_dev, w);
   });
+} catch (...) {
+  return host_fail(p);
 }
 
 }  // extern "C"

@@ -34,6 +34,17 @@ def test_header_symbols_exported(lib):
     assert set(names) == set(cf.SYMBOLS)
 
 
+def test_status_codes_match_header():
+    txt = open(os.path.join(ROOT, "include", "chebfd.h")).read()
+    body = re.search(r"typedef enum \{(.*?)\} cheb_status;", txt, flags=re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    codes = {k: int(v) for k, v in re.findall(r"(CHEB_\w+)\s*=\s*(\d+)", body)}
+    assert "CHEB_ERR_HOST" in codes
+    for k, v in codes.items():
+        assert getattr(cf, k) == v, k
+    assert cf.STATUS_NAMES == sorted(codes, key=codes.get)
+
+
 def _desc(pb, n=None, gidx=None, off=None, prec=0):
     g = np.ascontiguousarray(pb.gidx if gidx is None else gidx, dtype=np.int32)
     k = np.ascontiguousarray(pb.kin[: g.shape[0]], dtype=np.float64)
