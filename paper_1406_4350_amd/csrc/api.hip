@@ -842,6 +842,13 @@ template <typename T> struct Ops {
     const long npw = p->npw;
     C* loc = static_cast<C*>(w.loc);
     CHK(hloc(X, ldx, nb, loc, npw, w.fft));
+    // the projections and their projector-space products first, so that the Gram timer below does not enclose
+    // the projection's own timer
+    if (np > 0) {
+      CHK(project(X, ldx, nb, w.p0, w, true));
+      HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, w.p0, np, w.Dp, np, st));
+      if (p->has_overlap) HIPCHK(diag_apply(np, nb, p->Q, w.p0, np, w.q, np, st));
+    }
     Timed t(p, st, CHEB_T_RR_GRAM, 3.0 * npw * nb * sizeof(C) + 2.0 * nb * nb * 16.0, 16.0 * npw * nb * nb);
     Epi<double> eh;
     eh.out = w.Hs; eh.ldo = nb; eh.real_only = p->gamma != 0;
@@ -855,14 +862,11 @@ template <typename T> struct Ops {
     HIPCHK((gemm<double, T, T, double>(GEMM_CN, nb, nb, p->npw, X, ldx, X, ldx, es,
                                        gemm_pick_splits(nb, nb, p->npw), w.part, st, ROLE_SUBSPACE)));
     if (np > 0) {
-      CHK(project(X, ldx, nb, w.p0, w, true));
-      HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, w.p0, np, w.Dp, np, st));
       Epi<double> e2;
       e2.out = w.Hs; e2.ldo = nb; e2.L = w.Hs; e2.ldl = nb; e2.bL = 1.0;
       HIPCHK((gemm<double, double, double, double>(GEMM_CN, nb, nb, np, w.p0, np, w.Dp, np, e2,
                                                    gemm_pick_splits(nb, nb, np), w.part, st)));
       if (p->has_overlap) {
-        HIPCHK(diag_apply(np, nb, p->Q, w.p0, np, w.q, np, st));
         Epi<double> e3;
         e3.out = w.Ss; e3.ldo = nb; e3.L = w.Ss; e3.ldl = nb; e3.bL = 1.0;
         HIPCHK((gemm<double, double, double, double>(GEMM_CN, nb, nb, np, w.p0, np, w.q, np, e3,
