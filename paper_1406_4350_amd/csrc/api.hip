@@ -134,7 +134,8 @@ struct Timed {
   cheb_plan p;
   hipStream_t st;
   hipEvent_t end = nullptr;
-  Timed(cheb_plan p_, hipStream_t st_, int kind, double bytes, double flops) : p(p_), st(st_) {
+  // count = false: a second interval of the same section (its time adds, the section's count does not)
+  Timed(cheb_plan p_, hipStream_t st_, int kind, double bytes, double flops, bool count = true) : p(p_), st(st_) {
     if (!p->prof_on) return;
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     if (!p->prof_free.empty()) {
@@ -154,7 +155,7 @@ struct Timed {
     p->prof_pending.push_back({ev.first, ev.second, kind});
     p->prof_bytes[kind] += bytes;
     p->prof_flops[kind] += flops;
-    p->prof_n[kind] += 1;
+    p->prof_n[kind] += count ? 1 : 0;
   }
   ~Timed() {
     if (end) (void)hipEventRecord(end, st);
@@ -1194,36 +1195,41 @@ template <typename T> struct Ops {
       HIPCHK(scale_rows(nb, nb, w.Hs, nb, w.d, st));
     }
     C* Ynew = static_cast<C*>(w.Ynew);
-    Timed tr(p, st, CHEB_T_RR_ROTATE, (resid ? 4.0 : 2.0) * npw * nb * sizeof(C) + nb * nb * 16.0,
-             (resid ? 16.0 : 8.0) * npw * nb * nb);
-    Epi<T> er;
-    er.out = Ynew; er.ldo = npw;
-    HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, nb, X, ldx, w.Hs, nb, er, 1, nullptr, st, ROLE_SUBSPACE)));
-    if (resid) {
-      // H u - lambda S u = loc Z + P (D pZ - lambda Q pZ) - lambda u
-      C* R = static_cast<C*>(w.R);
-      Epi<T> e1;
-      e1.out = R; e1.ldo = npw;
-      HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, nb, static_cast<C*>(w.loc), npw, w.Hs, nb, e1, 1, nullptr,
-                                    st, ROLE_SUBSPACE)));
-      if (np > 0) {
-        Epi<double> ez;
-        ez.out = w.q; ez.ldo = np;
-        HIPCHK((gemm<double, double, double, double>(GEMM_NN, np, nb, nb, w.p0, np, w.Hs, nb, ez,
-                                                     gemm_pick_splits(np, nb, nb), w.part, st)));
-        HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, w.q, np, w.Dp, np, st));
-        const c128* t = w.Dp;
-        if (p->has_overlap) {
-          HIPCHK(diag_apply(np, nb, p->Q, w.q, np, w.w, np, st));
-          HIPCHK(sub_scaled_cols(np, nb, w.Dp, w.w, ritz, w.w, st));
-          t = w.w;
+    C* R = static_cast<C*>(w.R);
+    const c128* t = w.Dp;
+    {
+      Timed tr(p, st, CHEB_T_RR_ROTATE, (resid ? 4.0 : 2.0) * npw * nb * sizeof(C) + nb * nb * 16.0,
+               (resid ? 16.0 : 8.0) * npw * nb * nb);
+      Epi<T> er;
+      er.out = Ynew; er.ldo = npw;
+      HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, nb, X, ldx, w.Hs, nb, er, 1, nullptr, st, ROLE_SUBSPACE)));
+      if (resid) {
+        // H u - lambda S u = loc Z + P (D pZ - lambda Q pZ) - lambda u
+        Epi<T> e1;
+        e1.out = R; e1.ldo = npw;
+        HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, nb, static_cast<C*>(w.loc), npw, w.Hs, nb, e1, 1, nullptr,
+                                      st, ROLE_SUBSPACE)));
+        if (np > 0) {
+          Epi<double> ez;
+          ez.out = w.q; ez.ldo = np;
+          HIPCHK((gemm<double, double, double, double>(GEMM_NN, np, nb, nb, w.p0, np, w.Hs, nb, ez,
+                                                       gemm_pick_splits(np, nb, nb), w.part, st)));
+          HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, w.q, np, w.Dp, np, st));
+          if (p->has_overlap) {
+            HIPCHK(diag_apply(np, nb, p->Q, w.q, np, w.w, np, st));
+            HIPCHK(sub_scaled_cols(np, nb, w.Dp, w.w, ritz, w.w, st));
+            t = w.w;
+          }
         }
-        Epi<T> e2;
-        e2.out = R; e2.ldo = npw; e2.L = R; e2.ldl = npw; e2.bL = 1.0;
-        CHK(backproject(t, nb, e2, w));
       }
-      HIPCHK((col_resid_norms<T>(npw, nb, R, npw, Ynew, npw, ritz, resid, st)));
     }
+    if (resid && np > 0) {  // the back-projection keeps its own timer, outside the rotation's
+      Epi<T> e2;
+      e2.out = R; e2.ldo = npw; e2.L = R; e2.ldl = npw; e2.bL = 1.0;
+      CHK(backproject(t, nb, e2, w));
+    }
+    Timed tr(p, st, CHEB_T_RR_ROTATE, 0.0, 0.0, false);
+    if (resid) HIPCHK((col_resid_norms<T>(npw, nb, R, npw, Ynew, npw, ritz, resid, st)));
     HIPCHK((convert_copy<T, T>(npw, nb, Ynew, npw, X, ldx, st)));
     return CHEB_OK;
   }
