@@ -10,7 +10,7 @@ Rayleigh-Ritz) on the same workload with its accuracy against the FP64 path, per
 HIP events in the timed region, the roofline of the dominant kernel class, and the FP64 CPU oracle timed
 on the host cores over a bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--config 2] [--no-cpu] [--no-mixed]
+    python bench.py [--steps K] [--warmup W] [--config paw48] [--no-cpu] [--no-mixed]
 """
 from __future__ import annotations
 
@@ -321,14 +321,14 @@ def lobpcg_report(cf, pb, tol, iters):
     return out
 
 
-def gamma_report(cf, cfg_index, steps, warmup):
+def gamma_report(cf, name, steps, warmup):
     """The same workload at the Gamma point (real wavefunctions on the half sphere, two bands per complex
     transform): FP64 filter + Rayleigh-Ritz steps and the filter alone, FP64 and mixed."""
     import torch
 
     from paper_1406_4350_amd import workload as wl
 
-    gp = wl.make_gamma_problem(cfg_index)
+    gp = wl.make_gamma_problem(name)
     probe = cf.plan_from_problem(gp, cf.CHEB_FP64)
     lam_plus = probe.upper_bound(torch.from_numpy(gp.v0), 10)
     probe.close()
@@ -394,7 +394,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", default="paw48", help="workload name (paw48, paw64, paw96, paw128, nc16)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--ref-iters", type=int, default=30,

@@ -47,13 +47,13 @@ CHANNELS = {"sp": 4, "2s2p": 8, "2s2p1d": 13}
 # The five named workloads. Their shapes follow the paper's systems where it gives them:
 # Npw ~ 7000 with 100-200 bands (Sec. 6.1), 256 atoms with 2048 bands (Sec. 6.2), 1-40 projectors
 # per atom (Sec. 2.1), n_inner = 4 by default (Sec. 5.3).
-CONFIGS = {
-    1: Config("nc16", 16, 4, 10.0, "random", 1, 2, "sp", False, 16, 4, 20, 8, 1),
-    2: Config("paw48", 48, 12, 12.0, "fcc", 2, 32, "2s2p", True, 256, 8, 20, 128, 2),
-    3: Config("paw96", 96, 24, 24.0, "bcc", 4, 128, "2s2p1d", True, 1024, 10, 50, 512, 3),
-    4: Config("paw64", 64, 16, 16.0, "sc", 4, 64, "2s2p", True, 512, 8, 1, 256, 4),
-    5: Config("paw128", 128, 32, 32.0, "fcc", 4, 256, "2s2p1d", True, 2048, 12, 3, 1024, 5),
-}
+CONFIGS = {c.name: c for c in (
+    Config("nc16", 16, 4, 10.0, "random", 1, 2, "sp", False, 16, 4, 20, 8, 1),
+    Config("paw48", 48, 12, 12.0, "fcc", 2, 32, "2s2p", True, 256, 8, 20, 128, 2),
+    Config("paw96", 96, 24, 24.0, "bcc", 4, 128, "2s2p1d", True, 1024, 10, 50, 512, 3),
+    Config("paw64", 64, 16, 16.0, "sc", 4, 64, "2s2p", True, 512, 8, 1, 256, 4),
+    Config("paw128", 128, 32, 32.0, "fcc", 4, 256, "2s2p1d", True, 2048, 12, 3, 1024, 5),
+)}
 
 # Small problems for parity tests: several GEMM / FFT tiles and ragged tails, oracle-friendly.
 SMALL = {
@@ -180,12 +180,16 @@ def _projectors(cfg: Config, gidx: np.ndarray, atoms: np.ndarray, real_space_rea
     return P, off
 
 
-def make_problem(cfg: Config | int | str, nb: int | None = None, ndir: int = 0) -> Problem:
-    """Draw the problem for a named config (1-5), a SMALL key, or a Config."""
-    if isinstance(cfg, int):
-        cfg = CONFIGS[cfg]
-    elif isinstance(cfg, str):
-        cfg = SMALL[cfg]
+def config(cfg: Config | str) -> Config:
+    """A Config, or the one named: a workload of CONFIGS or a small problem of SMALL."""
+    if isinstance(cfg, Config):
+        return cfg
+    return CONFIGS[cfg] if cfg in CONFIGS else SMALL[cfg]
+
+
+def make_problem(cfg: Config | str, nb: int | None = None, ndir: int = 0) -> Problem:
+    """Draw the problem for a named workload (CONFIGS or SMALL) or a Config."""
+    cfg = config(cfg)
     if nb is not None:
         cfg = cfg.replace(nb=nb)
     if cfg.n < 2 * cfg.radius + 1:
@@ -215,7 +219,7 @@ def make_problem(cfg: Config | int | str, nb: int | None = None, ndir: int = 0) 
     return Problem(cfg, gidx, kin, atoms, V, P, off, D, Q, X0, v0, w, dV)
 
 
-def free_electron(cfg: Config | int | str, nb: int | None = None) -> Problem:
+def free_electron(cfg: Config | str, nb: int | None = None) -> Problem:
     """Same basis and start block, with V = 0 and no projectors (S = I)."""
     pb = make_problem(cfg, nb=nb)
     natom = pb.cfg.natom
@@ -262,7 +266,7 @@ class GammaProblem:
         return self.full.cfg
 
 
-def make_gamma_problem(cfg: Config | int | str, nb: int | None = None) -> GammaProblem:
+def make_gamma_problem(cfg: Config | str, nb: int | None = None) -> GammaProblem:
     """The problem of make_problem with real-space-real projectors ((-i)^l factor) and real start vectors."""
     pb = make_problem(cfg, nb=nb)
     cfg = pb.cfg

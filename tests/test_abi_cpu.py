@@ -97,7 +97,7 @@ def test_rejects_bad_descriptors(lib):
 
 
 def test_create_rejects_missing_buffer(lib):
-    pb = wl.make_problem(1)
+    pb = wl.make_problem("nc16")
     d, keep = _desc(pb)
     h = ctypes.c_void_p()
     assert lib.cheb_plan_create(ctypes.byref(d), None, 0, None, ctypes.byref(h)) == cf.CHEB_ERR_WORKSPACE
@@ -106,8 +106,7 @@ def test_create_rejects_missing_buffer(lib):
 
 def test_named_configs_validate(lib):
     """Every named workload fits the kernels' limits (LDS of the plane pass) in both precisions."""
-    for cid in (1, 2, 3, 4, 5):
-        cfg = wl.CONFIGS[cid]
+    for cfg in wl.CONFIGS.values():
         g = wl.sphere(cfg.radius)
         kin = np.zeros(g.shape[0])
         nl = wl.CHANNELS[cfg.channels]
@@ -116,7 +115,7 @@ def test_named_configs_validate(lib):
             d = cf.cheb_desc(cfg.n, g.shape[0], g.ctypes.data, kin.ctypes.data, cfg.natom, off.ctypes.data,
                              int(cfg.overlap), prec)
             out = ctypes.c_size_t()
-            assert lib.cheb_plan_persistent_bytes(ctypes.byref(d), ctypes.byref(out)) == cf.CHEB_OK, (cid, prec)
+            assert lib.cheb_plan_persistent_bytes(ctypes.byref(d), ctypes.byref(out)) == cf.CHEB_OK, (cfg.name, prec)
 
 
 def test_locking_degrees_host_function(lib):

@@ -17,8 +17,7 @@ def _rel(a, b):
 
 
 def _setup(name, nb, nk, m):
-    base = wl.SMALL[name] if isinstance(name, str) else wl.CONFIGS[name]
-    pb = wl.make_problem(base.replace(nb=nb))
+    pb = wl.make_problem(wl.config(name).replace(nb=nb))
     ops = matfree.Operators.from_problem(pb)
     lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
     lm = float(np.max(matfree.rayleigh_quotients(ops, pb.X0)))
@@ -27,7 +26,7 @@ def _setup(name, nb, nk, m):
     return pb, ops, c, r, w, m
 
 
-CASES = [("tiny_paw", 10, 6, 3), ("mid_nc", 20, 9, 4), ("mid_paw", 16, 8, 5), (1, 16, 8, 4)]
+CASES = [("tiny_paw", 10, 6, 3), ("mid_nc", 20, 9, 4), ("mid_paw", 16, 8, 5), ("nc16", 16, 8, 4)]
 
 
 @pytest.fixture(scope="module", params=CASES, ids=lambda c: f"{c[0]}-nb{c[1]}-m{c[3]}")

@@ -21,7 +21,7 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-@pytest.fixture(scope="module", params=["tiny_paw", "mid_paw", 2], ids=str)
+@pytest.fixture(scope="module", params=["tiny_paw", "mid_paw", "paw48"], ids=str)
 def case(request):
     pb = wl.make_problem(request.param)
     if pb.cfg.nb > 64:  # full-size workload: a slice of the block keeps the oracle quick
@@ -95,7 +95,7 @@ def test_outer_loop_with_refined_capacitance(case):
 
 
 def test_capacitance_solver_errors():
-    pb = wl.make_problem(1)  # S = I
+    pb = wl.make_problem("nc16")  # S = I
     plan = cf.plan_from_problem(pb, cf.CHEB_FP64)
     with pytest.raises(cf.ChebError) as e:
         plan.set_capacitance_solver(5)

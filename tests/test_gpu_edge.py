@@ -52,7 +52,7 @@ def test_padded_leading_dimension(tiny):
 
 def test_free_electron_spectrum_on_gpu():
     """No projectors, V = 0: the filter + Rayleigh-Ritz loop converges to the kinetic shells."""
-    fe = wl.free_electron(1)
+    fe = wl.free_electron("nc16")
     plan = cf.Plan(fe.gidx, fe.kin, fe.cfg.n, fe.proj_off, False)
     plan.set_potential(torch.zeros((16, 16, 16), dtype=torch.float64))
     plan.set_projectors(torch.zeros((0, fe.npw), dtype=torch.complex128), None)

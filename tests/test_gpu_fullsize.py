@@ -33,7 +33,7 @@ def _sampled_filter_check(pb, Xd, m, c, r, cols, tol):
 
 
 def test_paw48_bench_block():
-    pb = wl.make_problem(2)
+    pb = wl.make_problem("paw48")
     print(f"[case] paw48 npw={pb.npw} nb={pb.cfg.nb}", flush=True)
     plan = cf.plan_from_problem(pb, cf.CHEB_FP64)
     c, r, lp = _interval(plan, pb, torch.complex128)
@@ -56,7 +56,7 @@ def test_paw48_bench_block():
 def test_paw48_filter_degrees():
     """Locking at the bench shape: per-band degrees 0..m in scrambled order; sampled bands of each degree
     against the oracle filter of that degree on that band alone."""
-    pb = wl.make_problem(2)
+    pb = wl.make_problem("paw48")
     plan = cf.plan_from_problem(pb, cf.CHEB_FP64)
     c, r, _ = _interval(plan, pb, torch.complex128)
     m = pb.cfg.m
@@ -74,7 +74,7 @@ def test_paw48_filter_degrees():
 
 
 def test_paw64_backward_full():
-    pb = wl.make_problem(4, ndir=1)
+    pb = wl.make_problem("paw64", ndir=1)
     print(f"[case] paw64 npw={pb.npw} nb={pb.cfg.nb} nk={pb.cfg.nk}", flush=True)
     p64 = cf.plan_from_problem(pb, cf.CHEB_FP64)
     c, r, lp = _interval(p64, pb, torch.complex128)
@@ -111,9 +111,9 @@ def test_paw64_backward_full():
     assert ev < 1e-3 and ed < 1e-3
 
 
-@pytest.mark.parametrize("cfgid", [3, 5])
-def test_large_shapes_mixed(cfgid):
-    pb = wl.make_problem(cfgid)
+@pytest.mark.parametrize("name", ["paw96", "paw128"])
+def test_large_shapes_mixed(name):
+    pb = wl.make_problem(name)
     print(f"[case] {pb.cfg.name} npw={pb.npw} nb={pb.cfg.nb} nproj={pb.nproj}", flush=True)
     plan = cf.plan_from_problem(pb, cf.CHEB_MIXED)
     print("[step] plan ready", flush=True)

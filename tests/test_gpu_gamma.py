@@ -14,7 +14,7 @@ from paper_1406_4350_amd import chebfd as cf  # noqa: E402
 from paper_1406_4350_amd import workload as wl  # noqa: E402
 from paper_1406_4350_amd.driver import chebfsi  # noqa: E402
 
-CASES = [1, "tiny_paw", "mid_paw", "mid_nc"]
+CASES = ["nc16", "tiny_paw", "mid_paw", "mid_nc"]
 
 
 def _rel(a, b):
@@ -117,7 +117,7 @@ def test_gamma_unavailable_and_bad_half_sphere(case):
 
 def test_gamma_paw48_sampled():
     """The paw48 shape as a Gamma plan: sampled bands of the filter against the oracle, one band at a time."""
-    gp = wl.make_gamma_problem(2)
+    gp = wl.make_gamma_problem("paw48")
     plan = cf.plan_from_problem(gp, cf.CHEB_FP64)
     ops = go.GammaOperators.from_problem(gp)
     lp = plan.upper_bound(torch.from_numpy(gp.v0), 10)

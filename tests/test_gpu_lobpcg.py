@@ -17,7 +17,7 @@ from paper_1406_4350_amd import chebfd as cf  # noqa: E402
 from paper_1406_4350_amd import workload as wl  # noqa: E402
 from paper_1406_4350_amd.driver import lobpcg  # noqa: E402
 
-CASES = [1, "tiny_paw", "mid_paw", "mid_nc"]
+CASES = ["nc16", "tiny_paw", "mid_paw", "mid_nc"]
 
 
 @pytest.fixture(scope="module", params=CASES, ids=str)

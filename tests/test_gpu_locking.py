@@ -15,7 +15,7 @@ from paper_1406_4350_amd import chebfd as cf  # noqa: E402
 from paper_1406_4350_amd import workload as wl  # noqa: E402
 from paper_1406_4350_amd.driver import chebfsi  # noqa: E402
 
-CASES = [1, "tiny_paw", "mid_paw", "mid_nc"]
+CASES = ["nc16", "tiny_paw", "mid_paw", "mid_nc"]
 
 
 def _col_rel(a, b):

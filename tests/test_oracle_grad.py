@@ -12,7 +12,7 @@ def setup(request):
     if request.param == "tiny_paw":
         pb = wl.make_problem(wl.SMALL["tiny_paw"].replace(nb=10), ndir=2)
     else:
-        pb = wl.make_problem(wl.CONFIGS[1].replace(nb=10), ndir=2)
+        pb = wl.make_problem(wl.CONFIGS["nc16"].replace(nb=10), ndir=2)
     ops = matfree.Operators.from_problem(pb)
     lam = dense.eig_pencil(dense.hamiltonian(pb.gidx, pb.kin, pb.V, pb.P, pb.D), dense.overlap(pb.npw, pb.P, pb.Q))[0]
     c, r = 0.5 * (lam[-1] + lam[12]), 0.5 * (lam[-1] - lam[12]) + 0.1

@@ -22,7 +22,7 @@ def tiny():
 
 @pytest.fixture(scope="module")
 def cfg1():
-    pb = wl.make_problem(1)
+    pb = wl.make_problem("nc16")
     H = dense.hamiltonian(pb.gidx, pb.kin, pb.V, pb.P, pb.D)
     S = dense.overlap(pb.npw, pb.P, pb.Q)
     return pb, H, S, matfree.Operators.from_problem(pb)
@@ -41,7 +41,7 @@ def test_sphere_sizes():
 
 def test_free_electron_spectrum():
     """V = 0, no projectors: eigenvalues are the kinetic shells 1/2 |2 pi g/L|^2 (Sec. 2.1), golden table."""
-    fe = wl.free_electron(1)
+    fe = wl.free_electron("nc16")
     H = dense.hamiltonian(fe.gidx, fe.kin, fe.V, fe.P, fe.D)
     lam = np.linalg.eigvalsh(H)
     rows = golden("free_electron_L10_R4.txt")
@@ -375,7 +375,7 @@ def test_tpa_preconditioner_function():
     assert abs(K(1e6) * 2e6 - 1.0) < 1e-5
 
 
-@pytest.mark.parametrize("name", [1, "tiny_paw"])
+@pytest.mark.parametrize("name", ["nc16", "tiny_paw"])
 def test_lobpcg_converges_to_dense_eigenpairs(name):
     pb = wl.make_problem(name)
     ops = matfree.Operators.from_problem(pb)
