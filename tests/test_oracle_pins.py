@@ -21,7 +21,7 @@ def tiny():
 
 
 @pytest.fixture(scope="module")
-def cfg1():
+def nc16():
     pb = wl.make_problem("nc16")
     H = dense.hamiltonian(pb.gidx, pb.kin, pb.V, pb.P, pb.D)
     S = dense.overlap(pb.npw, pb.P, pb.Q)
@@ -80,9 +80,9 @@ def test_parseval_and_single_plane_wave():
     assert np.allclose(back, box, atol=1e-13)
 
 
-def test_constant_potential_shifts_spectrum(cfg1):
+def test_constant_potential_shifts_spectrum(nc16):
     """V = V0: V_loc = V0 I, so every eigenvalue of H moves by V0."""
-    pb, H, S, _ = cfg1
+    pb, H, S, _ = nc16
     V0 = -0.731
     Hl = dense.h_local(pb.gidx, np.full_like(pb.V, V0))
     assert np.allclose(Hl, V0 * np.eye(pb.npw), atol=1e-13)
@@ -91,9 +91,9 @@ def test_constant_potential_shifts_spectrum(cfg1):
     assert np.allclose(ops.apply_H(pb.X0) - ops0.apply_H(pb.X0), V0 * pb.X0, atol=1e-12)
 
 
-def test_hloc_structure(cfg1):
+def test_hloc_structure(nc16):
     """Hermitian, depends only on g_i - g_k, trace = Npw mean(V)."""
-    pb = cfg1[0]
+    pb = nc16[0]
     Hl = dense.h_local(pb.gidx, pb.V)
     assert np.allclose(Hl, Hl.conj().T, atol=1e-14)
     assert abs(np.trace(Hl) - pb.npw * pb.V.mean()) < 1e-11
@@ -108,7 +108,7 @@ def test_hloc_structure(cfg1):
 
 
 # ---- operators ---------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("which", ["cfg1", "tiny"])
+@pytest.mark.parametrize("which", ["nc16", "tiny"])
 def test_matrix_free_equals_dense(which, request):
     pb, H, S, ops = request.getfixturevalue(which)
     X = pb.X0[:, :5]
@@ -190,8 +190,8 @@ def test_rayleigh_ritz_properties(tiny):
     assert np.all(res3 < 1e-10)
 
 
-def test_lanczos_upper_bound(tiny, cfg1):
-    for pb, H, S, ops in (tiny, cfg1):
+def test_lanczos_upper_bound(tiny, nc16):
+    for pb, H, S, ops in (tiny, nc16):
         lmax = dense.eig_pencil(H, S)[0][-1]
         lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
         assert lp >= lmax
