@@ -104,6 +104,16 @@ def test_create_rejects_missing_buffer(lib):
     assert not h.value
 
 
+def test_workload_names_resolve():
+    """Every workload is drawn by its name; names are unique across the full-size and the small tables."""
+    assert not set(wl.CONFIGS) & set(wl.SMALL)
+    for name, c in {**wl.CONFIGS, **wl.SMALL}.items():
+        assert wl.config(name) is c and c.name == name
+    assert wl.config(wl.CONFIGS["paw48"]) is wl.CONFIGS["paw48"]
+    with pytest.raises(KeyError):
+        wl.config("paw49")
+
+
 def test_named_configs_validate(lib):
     """Every named workload fits the kernels' limits (LDS of the plane pass) in both precisions."""
     for cfg in wl.CONFIGS.values():
