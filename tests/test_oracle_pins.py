@@ -190,12 +190,87 @@ def test_rayleigh_ritz_properties(tiny):
     assert np.all(res3 < 1e-10)
 
 
+def _rq_pin_failures(rq, ops, H, S, X):
+    """Failures of a Rayleigh-quotient routine rq(ops, X) against facts of the pencil (first step of Alg. 2):
+    the quotient of an exact eigenvector is its eigenvalue; quotients do not change when a column is scaled by
+    a complex number; every quotient lies in [lambda_1, lambda_max]."""
+    lam, V = dense.eig_pencil(H, S)
+    bad = []
+    cols = [0, 1, 7, len(lam) // 2, len(lam) - 1]
+    q = rq(ops, V[:, cols])
+    if not np.allclose(q, lam[cols], rtol=0, atol=1e-12 * max(1.0, np.abs(lam).max())):
+        bad.append("eigenvector quotients differ from the eigenvalues")
+    s = np.exp(1j * np.arange(X.shape[1])) * np.logspace(-3, 3, X.shape[1])
+    q1, q2 = rq(ops, X), rq(ops, X * s[None, :])
+    if not np.allclose(q1, q2, rtol=1e-12, atol=1e-12):
+        bad.append("not invariant under column scaling")
+    if not (np.all(q1 >= lam[0] - 1e-12) and np.all(q1 <= lam[-1] + 1e-12)):
+        bad.append("quotient outside [lambda_1, lambda_max]")
+    return bad
+
+
+def test_rayleigh_quotients_pins(tiny, nc16):
+    """Pins of matfree.rayleigh_quotients (first step of Alg. 2) on a PAW pencil (S != I) and an S = I one."""
+    for pb, H, S, ops in (tiny, nc16):
+        assert _rq_pin_failures(matfree.rayleigh_quotients, ops, H, S, pb.X0) == []
+
+
+def _krylov_ritz(H, S, v0, k):
+    """Ritz values of the pencil on span{v0, A v0, ..., A^(k-1) v0}, A = S^-1 H, from an S-orthonormal basis
+    built by Arnoldi with two Gram-Schmidt passes (dense matrices; no Lanczos three-term shortcut). Returns
+    (Ritz values ascending, coefficient vectors of the basis)."""
+    A = np.linalg.solve(S, H)
+    V = np.zeros((H.shape[0], k), dtype=np.complex128)
+    v = np.asarray(v0, dtype=np.complex128)
+    V[:, 0] = v / np.sqrt(np.real(v.conj() @ S @ v))
+    for j in range(1, k):
+        w = A @ V[:, j - 1]
+        for _ in range(2):
+            w = w - V[:, :j] @ (V[:, :j].conj().T @ (S @ w))
+        V[:, j] = w / np.sqrt(np.real(w.conj() @ S @ w))
+    th, Y = scipy.linalg.eigh(V.conj().T @ H @ V, V.conj().T @ S @ V)
+    return th, Y, V, A
+
+
+def _lanczos_pin_failures(lanczos, ops, H, S, v0):
+    """Failures of a Lanczos routine lanczos(ops, v0, k) -> (bound, alphas, betas) on A = S^-1 H in the S inner
+    product (Sec. 5.3): the eigenvalues of T_k are the Rayleigh-Ritz values of the pencil on the Krylov space
+    (computed independently above) and lie in [lambda_1, lambda_max]; the last beta times the last component
+    of T_k's top eigenvector is the S-norm of the top Ritz pair's residual A x - theta x; the bound of k = 10
+    steps is >= lambda_max; and with k = 80 on a 257-dimensional pencil (top gap 2e-3 .. 2e-2 Ha here) the top
+    Ritz value has converged to lambda_max."""
+    lam = dense.eig_pencil(H, S)[0]
+    bad = []
+    for k in range(1, 11):
+        bound, al, be = lanczos(ops, v0, k)
+        T = np.diag(al) + np.diag(be[:-1], 1) + np.diag(be[:-1], -1)
+        th, Y = np.linalg.eigh(T)
+        thr, Yr, V, A = _krylov_ritz(H, S, v0, k)
+        if not np.allclose(th, thr, rtol=0, atol=1e-9 * max(1.0, np.abs(lam).max())):
+            bad.append(f"k={k}: T_k eigenvalues differ from the Krylov Ritz values")
+        if th.min() < lam[0] - 1e-10 or th.max() > lam[-1] + 1e-10:
+            bad.append(f"k={k}: T_k eigenvalue outside the spectrum")
+        x = V @ Yr[:, -1]
+        rr = A @ x - thr[-1] * x
+        rnorm = np.sqrt(np.real(rr.conj() @ S @ rr))
+        if abs(be[-1] * abs(Y[-1, -1]) - rnorm) > 1e-8 * max(1.0, rnorm):
+            bad.append(f"k={k}: last beta does not give the top Ritz residual")
+        if k == 10 and bound < lam[-1]:
+            bad.append("k=10: bound below lambda_max")
+    _, al, be = lanczos(ops, v0, 80)
+    th80 = np.linalg.eigvalsh(np.diag(al) + np.diag(be[:-1], 1) + np.diag(be[:-1], -1))
+    if abs(th80.max() - lam[-1]) > 1e-8 * max(1.0, abs(lam[-1])):
+        bad.append("k=80: top Ritz value not converged to lambda_max")
+    return bad
+
+
 def test_lanczos_upper_bound(tiny, nc16):
+    """Pins of matfree.lanczos_upper_bound (Sec. 5.3) on a PAW pencil and an S = I one."""
     for pb, H, S, ops in (tiny, nc16):
         lmax = dense.eig_pencil(H, S)[0][-1]
         lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
-        assert lp >= lmax
-        assert lp < lmax + 2.0
+        assert lmax <= lp < lmax + 2.0
+        assert _lanczos_pin_failures(matfree.lanczos_upper_bound, ops, H, S, pb.v0) == []
 
 
 def test_driver_converges_to_pencil(tiny):
@@ -244,6 +319,37 @@ def test_planted_recurrence_error_is_caught(tiny, monkeypatch):
             prev, cur = cur, (2.0 / r) * (ops.apply_A(cur) - c * cur) - prev
         return cur
     assert np.linalg.norm(bad_filter(ops, X, 4, c, r) - ref) > 1e-6 * np.linalg.norm(ref)
+
+
+def test_planted_rayleigh_quotient_error_is_caught(tiny):
+    """Dividing by x^H x instead of x^H S x (S forgotten in the denominator) fails the quotient pins."""
+    pb, H, S, ops = tiny
+
+    def bad_rq(ops, X):
+        HX = ops.apply_H(X)
+        return np.real(np.sum(X.conj() * HX, axis=0)) / np.real(np.sum(X.conj() * X, axis=0))
+    assert _rq_pin_failures(bad_rq, ops, H, S, pb.X0) != []
+
+
+def test_planted_euclidean_lanczos_is_caught(tiny):
+    """Lanczos on S^-1 H with Euclidean inner products (the S inner product forgotten) fails the Lanczos pins."""
+    pb, H, S, ops = tiny
+
+    def bad_lanczos(ops, v0, k=10):
+        v = np.asarray(v0, dtype=np.complex128).reshape(-1, 1)
+        v = v / np.linalg.norm(v)
+        v_prev, beta, al, be = np.zeros_like(v), 0.0, [], []
+        for _ in range(k):
+            f = ops.apply_A(v)
+            alpha = float(np.real(np.vdot(v, f)))
+            f = f - alpha * v - beta * v_prev
+            beta = float(np.linalg.norm(f))
+            al.append(alpha)
+            be.append(beta)
+            v_prev, v = v, f / beta
+        T = np.diag(al) + np.diag(be[:-1], 1) + np.diag(be[:-1], -1)
+        return float(np.linalg.eigvalsh(T)[-1] + be[-1]), np.array(al), np.array(be)
+    assert _lanczos_pin_failures(bad_lanczos, ops, H, S, pb.v0) != []
 
 
 def test_planted_woodbury_error_is_caught(tiny):
