@@ -5,12 +5,15 @@ One step = one outer iteration of the method on the whole band block: the degree
 T_m((S^-1 H - c)/r) X followed by Rayleigh-Ritz with residuals (Alg. 2), inputs resident in HBM.
 value = nb * m * steps / wall time of the timed steps (FP64 path, the workload's own precision).
 
-Also reported on the same line: the mixed-precision path (complex64 bands and FFTs, FP32-MFMA GEMMs, FP64
-Rayleigh-Ritz) on the same workload with its accuracy against the FP64 path, per-kernel-class times from
-HIP events in the timed region, the roofline of the dominant kernel class, and the FP64 CPU oracle timed
-on the host cores over a bounded sample.
+The default workload is paw128 (128^3 box, 137 065 plane waves, 2048 bands, 256 atoms x 13 projectors,
+degree 12), the shape of the paper's 256-atom Ti crystal. Also reported on the same line: the mixed-precision
+path (complex64 bands and FFTs, FP16-split MFMA projector GEMMs, FP64 Rayleigh-Ritz) on the same workload with its
+accuracy over the lowest floor(0.8 nb) bands against the FP64 path run to convergence, per-kernel-class times
+from HIP events in the timed region, the roofline of the dominant kernel and of every kernel class, the cost of
+the adjoint against the forward pass (paw64 by default), and the FP64 CPU oracle timed on the host cores over a
+bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--config paw48] [--no-cpu] [--no-mixed]
+    python bench.py [--steps K] [--warmup W] [--config paw128] [--no-cpu] [--no-mixed] [--extras]
 """
 from __future__ import annotations
 
@@ -25,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "H·ψ band-applications/s (FP32-MFMA vs FP64) at ≤1e-6 Ha; % HBM/MFMA roofline"
 HBM_PEAK_GBS = 8000.0
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "f16x3": 2500.0}
 GEMM_CLASSES = ("project", "backproject", "small", "rr_gram", "rr_rotate")
 FFT_CLASSES = ("fft_col_inverse", "fft_plane", "fft_col_forward")
 # kernel names as rocprofv3 reports them, per timer class and precision
@@ -42,23 +45,31 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_path(cf, pb, prec, lam_plus, steps, warmup):
+def run_path(cf, pb, prec, lam_plus, steps, warmup, resync=None):
     """Warm up, then time `steps` outer iterations; returns timings, profile and the final state."""
     import torch
 
     plan = cf.plan_from_problem(pb, prec)
+    if resync is not None:
+        plan.set_projection_resync(resync)
     dtype = torch.complex64 if prec == cf.CHEB_MIXED else torch.complex128
     X = cf.to_device_block(pb.X0, dtype)
     m, nb = pb.cfg.m, pb.cfg.nb
-    state = {"lam_minus": float(plan.rayleigh_quotients(X).max().item())}
+    from paper_1406_4350_amd.driver import chebyshev_magnitude
+
+    rq = plan.rayleigh_quotients(X)
+    state = {"lam_minus": float(rq.max().item()), "lam_low": float(rq.min().item()), "stability": 0.0}
 
     def step():
         c = 0.5 * (lam_plus + state["lam_minus"])
         r = 0.5 * (lam_plus - state["lam_minus"])
+        # amplification of the lowest band by this filter (Sec. 5.3: must stay far below 1/eps)
+        state["stability"] = max(state["stability"], chebyshev_magnitude(m, (state["lam_low"] - c) / r))
         plan.filter(X, m, c, r)
         ritz, res = plan.rayleigh_ritz(X)
         state["ritz"], state["res"] = ritz, res
         state["lam_minus"] = float(ritz.max().item())
+        state["lam_low"] = min(state["lam_low"], float(ritz.min().item()))
 
     for _ in range(warmup):
         step()
@@ -76,14 +87,10 @@ def run_path(cf, pb, prec, lam_plus, steps, warmup):
     # filter alone, event-timed on the current stream (same block, same interval)
     c = 0.5 * (lam_plus + state["lam_minus"])
     r = 0.5 * (lam_plus - state["lam_minus"])
-    reps = max(3, min(steps, 10))
+    reps = max(2, min(steps, 3))
     filter_ms = time_filter(plan, X, m, c, r, reps)
     out = dict(plan=plan, X=X, seconds=t1 - t0, prof=prof, filter_ms=filter_ms, state=state, rr_stats=rr_stats,
-               apps_per_s=nb * m * steps / (t1 - t0), filter_apps_per_s=nb * m / (filter_ms * 1e-3))
-    if prec == cf.CHEB_MIXED:  # the same filter with the projector GEMMs on the FP32 MFMA instead of the split
-        plan.set_split_gemm(False)
-        out["filter_apps_per_s_fp32_mfma"] = nb * m / (time_filter(plan, X, m, c, r, reps) * 1e-3)
-        plan.set_split_gemm(True)
+               apps_per_s=nb * m * steps / (t1 - t0), filter_apps_per_s=nb * m / (filter_ms * 1e-3), resync=resync)
     return out
 
 
@@ -105,35 +112,47 @@ def time_filter(plan, X, m, c, r, reps):
     return total / reps
 
 
-def roofline(prof, kind, n):
-    """Roofline object for the kernel class with the largest event time (the dense eigensolver is a
-    library call, not one of this library's kernels, and is left out)."""
-    cands = {k: v for k, v in prof.items() if k != "rr_eig" and v["launches"] > 0}
-    dom = max(cands, key=lambda k: cands[k]["ms"])
-    d = cands[dom]
+def class_roofline(name, d, kind, n):
+    """Roofline numbers of one kernel class from its event timers: GEMM classes against the MFMA peak of the
+    arithmetic they run on (FP64 for the FP64 path, the projector-space products and the Rayleigh-Ritz Grams in
+    both paths, FP16 for the split projector GEMMs of mixed plans, where each useful product takes three FP16
+    MFMAs), FFT classes against the HBM peak. Achieved = algorithmic flops (8 per complex multiply-add) or bytes
+    per launch / average launch time."""
     per_launch_s = d["ms"] * 1e-3 / d["launches"]
-    if dom in GEMM_CLASSES:
+    if name in GEMM_CLASSES:
         achieved = d["flops"] / d["launches"] / per_launch_s / 1e12
-        # the Rayleigh-Ritz Grams run on FP64 MFMA in both precisions
-        peak = PEAK_TFLOPS["f64" if dom == "rr_gram" else kind]
-        out = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
+        dt = "f16x3" if (kind == "f32" and name in ("project", "backproject")) else "f64"
+        peak = PEAK_TFLOPS[dt]
+        out = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "mfma_dtype": dt}
     else:
         achieved = d["bytes"] / d["launches"] / per_launch_s / 1e9
-        peak = HBM_PEAK_GBS
-        out = {"bound": "hbm", "achieved": achieved, "peak": peak, "unit": "GB/s"}
+        out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     out["frac"] = out["achieved"] / out["peak"]
-    out["kernel_class"] = dom
-    tmpl = KERNEL_NAMES.get(dom)
-    out["kernel"] = tmpl[0 if kind == "f64" else 1].format(n=n) if tmpl else dom
+    tmpl = KERNEL_NAMES.get(name)
+    out["kernel"] = tmpl[0 if kind == "f64" else 1].format(n=n) if tmpl else name
     out["avg_launch_us"] = per_launch_s * 1e6
-    out["algo_per_launch"] = (d["flops"] if dom in GEMM_CLASSES else d["bytes"]) / d["launches"]
-    out["traffic"] = load_traffic(out["kernel"])
+    out["algo_per_launch"] = (d["flops"] if name in GEMM_CLASSES else d["bytes"]) / d["launches"]
+    out["launches"] = d["launches"]
+    out["ms_total"] = d["ms"]
     return out
 
 
-def load_traffic(kernel):
+def roofline(prof, kind, n):
+    """Roofline object for the kernel class with the largest event time (the dense eigensolver is a library call,
+    not one of this library's kernels, and is left out), plus the same numbers for every class."""
+    cands = {k: v for k, v in prof.items() if k != "rr_eig" and v["launches"] > 0}
+    dom = max(cands, key=lambda k: cands[k]["ms"])
+    out = class_roofline(dom, cands[dom], kind, n)
+    out["kernel_class"] = dom
+    out["traffic"] = load_traffic(out["kernel"], n)
+    out["by_class"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                           for kk, vv in class_roofline(k, v, kind, n).items()} for k, v in cands.items()}
+    return out
+
+
+def load_traffic(kernel, n):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, if it covers this
-    kernel and the kernel source it was taken on is unchanged; else None."""
+    kernel at this box size and the kernel source it was taken on is unchanged; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -141,7 +160,7 @@ def load_traffic(kernel):
         with open(path) as f:
             data = json.load(f)
         ent = data.get(kernel)
-        if not ent:
+        if not ent or int(ent.get("n", n)) != int(n):
             return None
         import hashlib
 
@@ -152,8 +171,22 @@ def load_traffic(kernel):
         return None
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(pb, target_s=15.0):
-    """The FP64 oracle's matrix-free filter on the host cores, on a sample of bands of the same workload."""
+    """The FP64 oracle's matrix-free filter on the host cores, on a sample of bands of the same workload: about
+    target_s seconds of filtering (the operator set-up, a P^H P product of the projectors, is not timed)."""
     import numpy as np
 
     try:
@@ -167,11 +200,13 @@ def cpu_baseline(pb, target_s=15.0):
 
     ctx = threadpool_limits(limits=cores) if threadpool_limits else contextlib.nullcontext()
     with ctx:
-        ops = matfree.Operators.from_problem(pb, workers=cores)
+        t_setup = time.perf_counter()
+        ops = matfree.Operators.from_problem(pb, workers=cores, band_chunk=16)
+        t_setup = time.perf_counter() - t_setup
         m = pb.cfg.m
-        # calibrate, after a warm-up call (FFT plans, thread pools), on 16 bands with one application of S^-1 H
+        # calibrate, after a warm-up call (FFT plans, thread pools), on 8 bands with one application of S^-1 H
         ops.apply_A(pb.X0[:, :4])
-        Xc = pb.X0[:, :min(16, pb.cfg.nb)]
+        Xc = pb.X0[:, :min(8, pb.cfg.nb)]
         t0 = time.perf_counter()
         ops.apply_A(Xc)
         per_app = (time.perf_counter() - t0) / Xc.shape[1]
@@ -185,40 +220,55 @@ def cpu_baseline(pb, target_s=15.0):
             dt += time.perf_counter() - t0
             reps += 1
     return {"value": reps * nbs * m / dt, "unit": "band-applications/s", "cores": cores, "kind": "oracle",
-            "sample": f"{reps} x one degree-{m} filter of {nbs} of {pb.cfg.nb} bands (FP64 matrix-free oracle, "
-                      f"numpy/scipy FFT with {cores} workers), {dt:.1f} s"}
+            "cpu": cpu_model(),
+            "sample": f"{reps} x one degree-{m} filter of {nbs} of {pb.cfg.nb} bands of the same workload (FP64 "
+                      f"matrix-free oracle, numpy/scipy FFT and BLAS with {cores} threads), {dt:.1f} s timed; "
+                      f"operator set-up {t_setup:.1f} s untimed"}
 
 
-def mixed_accuracy(cf, pb, r64, rmx, lam_plus, extra=30):
-    """Mixed-precision eigenpairs against converged FP64 ones. The FP64 run is continued for `extra` more
-    iterations to serve as the reference; a mixed band meets the target when its residual, re-evaluated with
-    the FP64 operators, is <= 1e-5 and its Ritz value is within 1e-6 Ha of the reference."""
+def continue_run(plan, X, m, lam_plus, ritz, res, k, tol, max_iters):
+    """More outer iterations on X until the lowest k residuals are <= tol (at most max_iters)."""
+    it = 0
+    while it < max_iters and (tol is None or float(res[:k].max()) > tol):
+        lam_minus = float(ritz.max())
+        plan.filter(X, m, 0.5 * (lam_plus + lam_minus), 0.5 * (lam_plus - lam_minus))
+        ritz, res = plan.rayleigh_ritz(X)
+        it += 1
+    return ritz, res, it
+
+
+def mixed_accuracy(cf, pb, r64, rmx, lam_plus, max_extra, done):
+    """Mixed-precision eigenpairs against converged FP64 ones over the lowest floor(0.8 nb) bands. The FP64 run is
+    continued until those bands have residuals <= 1e-8 (at most max_extra more iterations) and serves as the
+    reference; the mixed run is continued to the same number of iterations. A band meets the target when its
+    mixed Ritz value is within 1e-6 Ha of the reference and the residual of its complex64 Ritz vector, re-evaluated
+    with the FP64 operators, is <= 1e-5."""
     import numpy as np
     import torch
 
-    plan = r64["plan"]
-    X = r64["X"]
-    lam_minus = float(r64["state"]["ritz"].max().item())
-    for _ in range(extra):
-        c, r = 0.5 * (lam_plus + lam_minus), 0.5 * (lam_plus - lam_minus)
-        plan.filter(X, pb.cfg.m, c, r)
-        ritz, res = plan.rayleigh_ritz(X)
-        lam_minus = float(ritz.max().item())
+    m, k = pb.cfg.m, int(0.8 * pb.cfg.nb)
+    st = r64["state"]
+    ritz, res, extra = continue_run(r64["plan"], r64["X"], m, lam_plus, st["ritz"], st["res"], k, 1e-8, max_extra)
     lam_ref, res_ref = ritz.cpu().numpy(), res.cpu().numpy()
-    lamx = rmx["state"]["ritz"].cpu().numpy()
+    sx = rmx["state"]
+    ritz_x, _, extra_x = continue_run(rmx["plan"], rmx["X"], m, lam_plus, sx["ritz"], sx["res"], k, None, extra)
+    lamx = ritz_x.cpu().numpy()
+    plan = r64["plan"]
     U = rmx["X"].to(torch.complex128)
     HU = plan.apply_H(U)
     SU = plan.apply_S(U)
     lam_t = torch.from_numpy(lamx).to(U.device)
     res_x = torch.linalg.vector_norm(HU - SU * lam_t[:, None], dim=1).cpu().numpy()
-    ref_ok = res_ref <= 1e-8
-    conv = (res_x <= 1e-5) & ref_ok
-    dlam = np.abs(lamx - lam_ref)
-    ok = conv & (dlam <= 1e-6)
-    return {"reference": f"FP64 path continued {extra} more iterations; {int(ref_ok.sum())} bands with residual <= 1e-8",
-            "bands_converged_mixed": int(conv.sum()), "bands_meeting_target": int(ok.sum()),
-            "max_abs_dlambda_converged_Ha": float(dlam[conv].max()) if conv.any() else None,
-            "max_resid_fp64_eval_converged": float(res_x[conv].max()) if conv.any() else None}
+    del U, HU, SU
+    dlam = np.abs(lamx - lam_ref)[:k]
+    ok = (dlam <= 1e-6) & (res_x[:k] <= 1e-5)
+    return {"checked_bands": k, "iterations": done + extra,
+            "fp64_reference": f"FP64 path run {done + extra} outer iterations; lowest {k} residuals <= "
+                              f"{float(res_ref[:k].max()):.2e}",
+            "max_abs_dlambda_Ha": float(dlam.max()), "max_resid_fp64_eval": float(res_x[:k].max()),
+            "median_resid_fp64_eval": float(np.median(res_x[:k])),
+            "bands_meeting_target": int(ok.sum()), "target_met": bool(ok.all()),
+            "drift_resync_period": rmx.get("resync")}
 
 
 def time_backward(cf, pb, lam_plus, reps=3):
@@ -294,7 +344,7 @@ def locking_report(cf, pb, lam_plus, tol, iters):
 
 
 def lobpcg_report(cf, pb, tol, iters):
-    """LOBPCG (Sec. 3.1, the paper's comparison method) from the same start block, FP64: iterations, band
+    """LOBPCG (Sec. 2.3, the paper's comparison method) from the same start block, FP64: iterations, band
     applications of H (each also applies S) and wall time until the lowest 7/8 of the bands have residuals
     <= 2 tol, as for the Chebyshev runs of locking_report."""
     import numpy as np
@@ -393,22 +443,24 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="paw48", help="workload name (paw48, paw64, paw96, paw128, nc16)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="paw128", help="workload name (paw128, paw96, paw64, paw48, nc16)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--ref-iters", type=int, default=30,
-                    help="extra FP64 iterations for the converged reference of the mixed accuracy check (0: skip)")
-    ap.add_argument("--backward", action="store_true",
-                    help="also time the adjoint of one filter + Rayleigh-Ritz pass against the forward pass")
-    ap.add_argument("--lock-tol", type=float, default=1e-8,
-                    help="residual tolerance of the locking comparison (0: skip it)")
+    ap.add_argument("--ref-iters", type=int, default=25,
+                    help="at most this many more FP64 iterations for the converged reference of the mixed accuracy "
+                         "check (0: skip the check)")
+    ap.add_argument("--resync", type=int, default=None,
+                    help="projection resynchronisation period of the mixed plan (default: the library's)")
+    ap.add_argument("--backward-config", default="paw64",
+                    help="workload of the adjoint cost leg ('none' to skip)")
+    ap.add_argument("--extras", action="store_true",
+                    help="also run the locking, LOBPCG, Gamma-point and iterative capacitance legs on --extras-config")
+    ap.add_argument("--extras-config", default="paw48")
+    ap.add_argument("--lock-tol", type=float, default=1e-8)
     ap.add_argument("--lock-iters", type=int, default=40)
-    ap.add_argument("--lobpcg-iters", type=int, default=60,
-                    help="iteration cap of the LOBPCG comparison at the locking tolerance (0: skip)")
-    ap.add_argument("--no-gamma", action="store_true", help="skip the Gamma-point form of the workload")
-    ap.add_argument("--cap-iters", type=int, default=20,
-                    help="corrections of the iterative capacitance solve to compare with the direct one (0: skip)")
+    ap.add_argument("--lobpcg-iters", type=int, default=60)
+    ap.add_argument("--cap-iters", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (for scaling HBM "
                          "byte counters) and exit")
@@ -434,17 +486,20 @@ def main():
     from paper_1406_4350_amd import chebfd as cf
     from paper_1406_4350_amd import workload as wl
 
+    t_start = time.perf_counter()
     pb = wl.make_problem(args.config)
     cfg = pb.cfg
-    log(f"[bench] workload {cfg.name}: n={cfg.n} npw={pb.npw} nb={cfg.nb} nproj={pb.nproj} m={cfg.m}")
+    log(f"[bench] workload {cfg.name}: n={cfg.n} npw={pb.npw} nb={cfg.nb} nproj={pb.nproj} m={cfg.m} "
+        f"({time.perf_counter() - t_start:.1f} s to draw)")
     probe = cf.plan_from_problem(pb, cf.CHEB_FP64)
     lam_plus = probe.upper_bound(torch.from_numpy(pb.v0), 10)
     probe.close()
+    del probe
     log(f"[bench] lambda+ = {lam_plus:.6f} (10-step Lanczos)")
 
     r64 = run_path(cf, pb, cf.CHEB_FP64, lam_plus, args.steps, args.warmup)
-    log(f"[bench] fp64: {r64['apps_per_s']:.4g} band-apps/s over {args.steps} steps, filter alone "
-        f"{r64['filter_apps_per_s']:.4g}/s")
+    log(f"[bench] fp64: {r64['apps_per_s']:.4g} band-apps/s over {args.steps} steps ({r64['seconds']:.1f} s), filter "
+        f"alone {r64['filter_apps_per_s']:.4g}/s")
     out = {
         "metric": METRIC,
         "value": r64["apps_per_s"],
@@ -466,37 +521,61 @@ def main():
         "filter_only": {"fp64_apps_per_s": r64["filter_apps_per_s"], "fp64_ms": r64["filter_ms"]},
         "breakdown_ms_per_step": {k: v["ms"] / args.steps for k, v in r64["prof"].items()},
         "rr_solves_refined_library": r64["rr_stats"],
+        "stability_T_m_lowest_band": r64["state"]["stability"],
         "roofline": roofline(r64["prof"], "f64", cfg.n),
     }
     if not args.no_mixed:
-        rmx = run_path(cf, pb, cf.CHEB_MIXED, lam_plus, args.steps, args.warmup)
+        rmx = run_path(cf, pb, cf.CHEB_MIXED, lam_plus, args.steps, args.warmup, resync=args.resync)
         log(f"[bench] mixed: {rmx['apps_per_s']:.4g} band-apps/s, filter alone {rmx['filter_apps_per_s']:.4g}/s")
         out["mixed"] = {
             "value": rmx["apps_per_s"], "ratio_vs_fp64": rmx["apps_per_s"] / r64["apps_per_s"],
             "filter_apps_per_s": rmx["filter_apps_per_s"],
             "filter_ratio_vs_fp64": rmx["filter_apps_per_s"] / r64["filter_apps_per_s"],
-            "filter_apps_per_s_fp32_mfma": rmx["filter_apps_per_s_fp32_mfma"],
+            "ms_per_step": rmx["seconds"] * 1e3 / args.steps,
             "dtype": "f32 (complex64 bands/FFTs/recurrence; projector GEMMs on FP16 hi/lo split MFMA with FP32 "
                      "accumulation); FP64 projector space and Rayleigh-Ritz",
-            "accuracy": mixed_accuracy(cf, pb, r64, rmx, lam_plus, args.ref_iters) if args.ref_iters > 0 else None,
             "breakdown_ms_per_step": {k: v["ms"] / args.steps for k, v in rmx["prof"].items()},
             "rr_solves_refined_library": rmx["rr_stats"],
             "roofline": roofline(rmx["prof"], "f32", cfg.n),
         }
-    if args.lock_tol > 0:
-        out["locking"] = locking_report(cf, pb, lam_plus, args.lock_tol, args.lock_iters)
-    if args.lobpcg_iters > 0 and args.lock_tol > 0:
-        out["lobpcg"] = lobpcg_report(cf, pb, args.lock_tol, args.lobpcg_iters)
-    if not args.no_gamma:
-        out["gamma_point"] = gamma_report(cf, args.config, args.steps, args.warmup)
-    if args.cap_iters > 0:
-        out["capacitance_solve"] = capacitance_report(cf, pb, lam_plus, args.cap_iters)
-    if args.backward:
-        out["differentiation"] = time_backward(cf, pb, lam_plus)
+        if args.ref_iters > 0:
+            acc = mixed_accuracy(cf, pb, r64, rmx, lam_plus, args.ref_iters, args.warmup + args.steps)
+            out["mixed"]["accuracy"] = acc
+            log(f"[bench] mixed accuracy over the lowest {acc['checked_bands']} bands after {acc['iterations']} "
+                f"iterations: max |d lambda| {acc['max_abs_dlambda_Ha']:.2e} Ha, max FP64-evaluated residual "
+                f"{acc['max_resid_fp64_eval']:.2e}, target met: {acc['target_met']}")
+        rmx["plan"].close()
+        del rmx
+    r64["plan"].close()
+    del r64
+    torch.cuda.empty_cache()
+    if args.backward_config != "none":
+        pbb = wl.make_problem(args.backward_config)
+        pr = cf.plan_from_problem(pbb, cf.CHEB_FP64)
+        lpb = pr.upper_bound(torch.from_numpy(pbb.v0), 10)
+        pr.close()
+        out["differentiation"] = time_backward(cf, pbb, lpb)
+        out["differentiation"]["workload"] = args.backward_config
+    if args.extras:
+        pe = wl.make_problem(args.extras_config)
+        pr = cf.plan_from_problem(pe, cf.CHEB_FP64)
+        lpe = pr.upper_bound(torch.from_numpy(pe.v0), 10)
+        pr.close()
+        ex = {"workload": args.extras_config}
+        if args.lock_tol > 0:
+            ex["locking"] = locking_report(cf, pe, lpe, args.lock_tol, args.lock_iters)
+            if args.lobpcg_iters > 0:
+                ex["lobpcg"] = lobpcg_report(cf, pe, args.lock_tol, args.lobpcg_iters)
+        ex["gamma_point"] = gamma_report(cf, args.extras_config, args.steps, args.warmup)
+        if args.cap_iters > 0:
+            ex["capacitance_solve"] = capacitance_report(cf, pe, lpe, args.cap_iters)
+        out["extras"] = ex
     if not args.no_cpu:
         log("[bench] timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(pb)
+        log(f"[bench] cpu oracle: {out['cpu_baseline']['value']:.4g} band-apps/s")
     out["device"] = device_report()
+    out["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out), flush=True)
 
 

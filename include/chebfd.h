@@ -162,7 +162,7 @@ cheb_status cheb_locking_degrees(int nb, const double* ritz, const double* resid
 cheb_status cheb_rayleigh_ritz(cheb_plan plan, void* X, int ldx, int nb, double* ritz_dev, double* resid_dev,
                                void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* LOBPCG, the block method the paper compares the filter with (Sec. 3.1), on the same operators: one
+/* LOBPCG, the block method the paper compares the filter with (Sec. 2.3), on the same operators: one
  * iteration per call. iteration = 0: Rayleigh-Ritz of X (start); 1: Rayleigh-Ritz in span[X, W]; >= 2: in
  * span[X, W, P], with W the residuals of the bands whose residual norm exceeds tol, preconditioned by
  * K(t_G / E_kin) with K(x) = (27 + 18x + 12x^2 + 8x^3) / (27 + 18x + 12x^2 + 8x^3 + 16x^4) and E_kin the band's
@@ -197,6 +197,22 @@ cheb_status cheb_set_capacitance_solver(cheb_plan plan, int iterations);
  * The split planes of P are built by cheb_set_projectors. */
 cheb_status cheb_set_split_gemm(cheb_plan plan, int on);
 
+/* Projections carried through the recurrence (the reuse trick of Sec. 5.1, P^H psi^i updated in projector space
+ * instead of recomputed): in a mixed plan the complex64 bands are rounded at every step while the carried
+ * projections are not, and the recurrence amplifies their difference like the bands it multiplies, which sets a
+ * floor on the residuals the outer loop reaches. period = k > 0: before steps i = 1 + k, 1 + 2k, ... of
+ * cheb_filter, cheb_filter_degrees and the forward pass of cheb_filter_rr_backward, the carried projections of
+ * psi^(i-1) and psi^(i-2) are recomputed from the vectors (two more P^H products). period = 0: never (the plain
+ * reuse trick). Default: 3 for mixed plans, 0 for FP64 plans. CHEB_ERR_ARG if period < 0. */
+cheb_status cheb_set_projection_resync(cheb_plan plan, int period);
+
+/* Diagnostic of the carried projections (an addition; synchronizes every filter step while on): before every
+ * step i >= 2 of the filters above, max over bands of ||p_carried - P^H psi^(i-1)|| / ||P^H psi^(i-1)|| with
+ * P^H psi recomputed on FP64 MFMA. cheb_drift_monitor(on) resets the maximum; cheb_drift_read returns it and the
+ * number of steps checked. */
+cheb_status cheb_drift_monitor(cheb_plan plan, int on);
+cheb_status cheb_drift_read(cheb_plan plan, double* max_rel_drift, int64_t* checks);
+
 /* Dense eigensolver of cheb_rayleigh_ritz. on (default): first try a warm-started iterative refinement of
  * Z from the identity in the column-scaled basis (n^3 products only; accepted only if X^H S_X X = I and
  * X^H H_X X diagonal to 1e-12 are verified), else the library path. off: always the library path.
@@ -223,7 +239,7 @@ cheb_status cheb_upper_bound(cheb_plan plan, int k, const void* v0_dev, double* 
  *   dD   (packed like cheb_set_D, FP64; NULL iff no projectors) dL/dD, symmetric per block
  * w_dev: nk FP64 weights (1 <= nk <= nb). The recurrence is checkpointed every ckpt_every steps (pairs
  * psi^(t-1), psi^t) and recomputed segment by segment, so memory grows with m / ckpt_every + ckpt_every.
- * Requires a gap lambda_nk < lambda_(nk+1) and non-degenerate wanted Ritz values. Box sizes up to 64.
+ * Requires a gap lambda_nk < lambda_(nk+1) and non-degenerate wanted Ritz values.
  * Synchronizes (Rayleigh-Ritz). Workspace: cheb_backward_workspace_bytes. */
 cheb_status cheb_backward_workspace_bytes(cheb_plan plan, int nb, int m, int ckpt_every, size_t* bytes);
 cheb_status cheb_filter_rr_backward(cheb_plan plan, const void* X0, int ldx, int nb, int m, double c, double r,

@@ -1,4 +1,4 @@
-"""LOBPCG oracle: the block method the paper compares the Chebyshev filter with (Sec. 3.1, "Block algorithms:
+"""LOBPCG oracle: the block method the paper compares the Chebyshev filter with (Sec. 2.3, "Block algorithms:
 LOBPCG"), for the same generalized problem H x = lambda S x, in FP64 with the matrix-free operators.
 
 One iteration is a Rayleigh-Ritz step in the space spanned by the current Ritz vectors X, the preconditioned
@@ -6,7 +6,7 @@ residuals W and the previous search directions P (3 nb columns; 2 nb on the firs
 Ritz pairs become the new X, and the part of the update outside X becomes the new P. Products with H and S of
 the new vectors are carried by the same linear combinations, so every iteration applies H and S to W only.
 
-The preconditioner damps high kinetic energies (Sec. 3.1 describes it as a smooth rational function of the
+The preconditioner damps high kinetic energies (Sec. 2.2 describes it as a smooth rational function of the
 kinetic energy, thresholded at the kinetic energy of the band); the rational function used is the one of the
 conjugate-gradient method the paper cites (Payne et al., 1992):
     K(x) = (27 + 18 x + 12 x^2 + 8 x^3) / (27 + 18 x + 12 x^2 + 8 x^3 + 16 x^4),  x = t_G / E_kin(band).

@@ -1,7 +1,8 @@
 """Thin Python binding of libchebfd.so (include/chebfd.h).
 
-The module-level functions carry the C names and only marshal arguments: torch tensors provide device
-memory and the current HIP stream, every computation runs in the library's HIP kernels. There is no CPU
+The methods of Plan carry the C names without their cheb_ prefix (Plan.apply_H is cheb_apply_H, and so on) and
+only marshal arguments: torch tensors provide device memory and the current HIP stream, every computation runs
+in the library's HIP kernels. There is no CPU
 fallback: loading fails loudly when the library or a GPU is missing.
 
 Band blocks are torch tensors of shape (nb, npw), contiguous, complex128 (CHEB_FP64) or complex64
@@ -33,7 +34,8 @@ SYMBOLS = ["cheb_plan_persistent_bytes", "cheb_plan_create", "cheb_plan_destroy"
            "cheb_profile_enable", "cheb_profile_read", "cheb_backward_workspace_bytes", "cheb_filter_rr_backward",
            "cheb_set_rr_refine", "cheb_rr_stats", "cheb_filter_degrees", "cheb_locking_degrees", "cheb_set_split_gemm",
            "cheb_set_capacitance_solver", "cheb_lobpcg_state_bytes", "cheb_lobpcg_iterate", "cheb_gemm_splits",
-           "cheb_gemm_block_item", "cheb_last_error"]
+           "cheb_gemm_block_item", "cheb_set_projection_resync", "cheb_drift_monitor", "cheb_drift_read",
+           "cheb_last_error"]
 TIMERS = ["fft_col_inverse", "fft_plane", "fft_col_forward", "project", "backproject", "small", "rr_gram", "rr_eig",
           "rr_rotate", "xdens"]
 
@@ -93,6 +95,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cheb_locking_degrees": [i, vp, vp, d, d, i, d, vp, P(i)],
         "cheb_gemm_splits": [i, i, i, P(i), P(i), P(i)],
         "cheb_gemm_block_item": [i, i, i, i, P(i), P(i), P(i)],
+        "cheb_set_projection_resync": [vp, i],
+        "cheb_drift_monitor": [vp, i],
+        "cheb_drift_read": [vp, P(d), P(ctypes.c_int64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -337,6 +342,20 @@ class Plan:
         """Mixed plans: FP16 hi/lo split MFMA (True, default) or FP32 MFMA (False) for the projector GEMMs."""
         self._check(self.lib.cheb_set_split_gemm(self.handle, int(bool(on))), "cheb_set_split_gemm")
 
+    def set_projection_resync(self, period: int):
+        """Recompute the carried projections P^H psi from the vectors every `period` filter steps (0: never)."""
+        self._check(self.lib.cheb_set_projection_resync(self.handle, int(period)), "cheb_set_projection_resync")
+
+    def drift_monitor(self, on: bool = True):
+        """Measure the drift of the carried projections before every filter step (synchronizing diagnostic)."""
+        self._check(self.lib.cheb_drift_monitor(self.handle, int(bool(on))), "cheb_drift_monitor")
+
+    def drift_read(self) -> tuple[float, int]:
+        """(largest relative drift ||p_carried - P^H psi|| / ||P^H psi|| seen, steps checked) since drift_monitor."""
+        mx, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(self.lib.cheb_drift_read(self.handle, ctypes.byref(mx), ctypes.byref(n)), "cheb_drift_read")
+        return mx.value, n.value
+
     def set_rr_refine(self, on: bool):
         self._check(self.lib.cheb_set_rr_refine(self.handle, int(bool(on))), "cheb_set_rr_refine")
 
@@ -381,44 +400,3 @@ def to_device_block(X: np.ndarray, dtype, device="cuda") -> torch.Tensor:
 
 def to_host_block(Xt: torch.Tensor) -> np.ndarray:
     return Xt.detach().to("cpu", torch.complex128).numpy().T.copy()
-
-
-# C-named wrappers (argument marshalling only)
-def cheb_apply_H(plan: Plan, X, Y=None):
-    return plan.apply_H(X, Y)
-
-
-def cheb_apply_S(plan: Plan, X, Y=None):
-    return plan.apply_S(X, Y)
-
-
-def cheb_apply_Sinv(plan: Plan, X, Y=None):
-    return plan.apply_Sinv(X, Y)
-
-
-def cheb_filter(plan: Plan, X, m, c, r):
-    return plan.filter(X, m, c, r)
-
-
-def cheb_rayleigh_ritz(plan: Plan, X, with_residuals=True):
-    return plan.rayleigh_ritz(X, with_residuals)
-
-
-def cheb_rayleigh_quotients(plan: Plan, X):
-    return plan.rayleigh_quotients(X)
-
-
-def cheb_upper_bound(plan: Plan, v0, k=10):
-    return plan.upper_bound(v0, k)
-
-
-def cheb_filter_rr_backward(plan: Plan, X0, m, c, r, w, ckpt_every=3):
-    return plan.filter_rr_backward(X0, m, c, r, w, ckpt_every)
-
-
-def cheb_filter_degrees(plan: Plan, X, degrees, c, r):
-    return plan.filter_degrees(X, degrees, c, r)
-
-
-def cheb_locking_degrees(ritz, resid, c, r, m_max, tol):
-    return locking_degrees(ritz, resid, c, r, m_max, tol)

@@ -50,6 +50,12 @@ struct cheb_plan_s {
   HalfPlanes hproj, hback;                  // mixed plans: split planes of P (set with the projectors)
   bool split_gemm = true;                   // mixed plans: FP16 hi/lo split MFMA for P^H x and P w
   bool rr_refine = true;                    // warm-started refinement before the library eigensolver
+  // Projections carried through the recurrence (reuse trick) are recomputed from the vectors every `resync`
+  // steps (0: never); drift_on measures ||p_carried - P^H psi|| / ||P^H psi|| before every step of the filter
+  int resync = 0;
+  bool drift_on = false;
+  double drift_max = 0.0;
+  int64_t drift_checks = 0;
   double* rr_host = nullptr;                // pinned staging of the refinement's block maxima and flag (2 slots)
   hipEvent_t rr_ev[2] = {nullptr, nullptr}; // end of the staging copy into each slot
   int64_t rr_refined = 0, rr_fallback = 0;  // how Rayleigh-Ritz steps were solved
@@ -71,6 +77,8 @@ struct cheb_plan_s {
 namespace {
 
 constexpr size_t kAlign = 256;
+// default period (filter steps) of the projection resynchronisation in mixed plans
+constexpr int kMixedResync = 3;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Carves aligned regions from a base pointer; with base == nullptr it only measures.
@@ -240,6 +248,8 @@ struct Ws {
   _Float16* hb = nullptr;  // mixed plans: the back-projection's projector-space operand split into FP16 planes
   long hb_ld = 0;
   c128 *cp = nullptr, *cq = nullptr, *cr = nullptr;  // iterative capacitance solve: right side, solution, residual
+  c128* pfresh = nullptr;  // projections recomputed from the vectors (drift monitor)
+  double* dcol = nullptr;  // per-band relative drift
   void* Xs = nullptr;   // band-sorted copy for the per-band degree filter
   int* lidx = nullptr;  // its gather / scatter indices (3 nb)
   void* solver = nullptr;
@@ -292,6 +302,8 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
       w->p1 = b.take<c128>(pp);
       w->ploc = b.take<c128>(2 * pp);  // [P^H loc; D p], ld 2 nproj
       w->w = b.take<c128>(pp);
+      w->pfresh = b.take<c128>(pp);
+      w->dcol = b.take<double>(std::max(nb, 1));
       part = std::max({part_elems(np, nb, p->npw), part_elems(np, nb, np), part_elems(np, nb, 2 * np)});
       if (op == CHEB_OP_FILTER_DEGREES) {
         w->Xs = b.take<char>(vec);
@@ -458,6 +470,8 @@ struct BwdWs {
   c128* pf[2] = {nullptr, nullptr};
   c128 *pbar = nullptr, *qa = nullptr, *pa = nullptr, *Dpa = nullptr, *B = nullptr;
   double *xpart = nullptr, *norms = nullptr;
+  c128* bdots = nullptr;   // squared band norms of the adjoint vectors and of psi (2 nb)
+  double* bal = nullptr;   // their balancing scales (nb)
   size_t total = 0;
 };
 
@@ -497,6 +511,8 @@ cheb_status bwd_layout(cheb_plan p, int nb, int m, int k, void* base, BwdWs* w) 
   w->B = b.take<c128>(size_t(std::max(nb, 1)) * std::max(nb, 1));
   w->xpart = b.take<double>(cross_density_part_doubles(p->n, fb));
   w->norms = b.take<double>(std::max(nb, 1));
+  w->bdots = b.take<c128>(2 * size_t(std::max(nb, 1)));
+  w->bal = b.take<double>(std::max(nb, 1));
   w->total = b.off;
   return CHEB_OK;
 }
@@ -796,6 +812,31 @@ template <typename T> struct Ops {
     return CHEB_OK;
   }
 
+  // Before step i of the recurrence (cur = psi^(i-1), prev = psi^(i-2)). The reuse trick of Sec. 5.1 carries
+  // p = P^H psi in projector space; with complex64 bands the carried values drift from the projections of the
+  // rounded vectors, and the recurrence amplifies the drift like the bands it multiplies. With the drift monitor
+  // on, the carried projections of cur are compared with P^H cur recomputed from the vector (FP64 products); at
+  // the steps i = 1 + k * resync both carried projections are replaced by the projections of their vectors.
+  cheb_status resync_step(int i, const C* cur, long ldc, c128* pcur, const C* prev, long ldp, c128* pprev, int nb,
+                          const Ws& w) {
+    const int np = p->nproj;
+    if (np == 0 || nb == 0 || i < 2) return CHEB_OK;
+    if (p->drift_on) {
+      CHK(project(cur, ldc, nb, w.pfresh, w, true));
+      HIPCHK(col_rel_diff(np, nb, pcur, np, w.pfresh, np, w.dcol, st));
+      std::vector<double> h(nb);
+      HIPCHK(hipMemcpyAsync(h.data(), w.dcol, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (double v : h) p->drift_max = std::isnan(v) ? v : std::max(p->drift_max, v);
+      p->drift_checks += 1;
+    }
+    if (p->resync > 0 && (i - 1) % p->resync == 0) {
+      CHK(project(cur, ldc, nb, pcur, w));
+      if (i > 2) CHK(project(prev, ldp, nb, pprev, w));  // psi^0's projections are exact already
+    }
+    return CHEB_OK;
+  }
+
   // Alg. 2 inner loop for the whole block. psi^i overwrites psi^(i-2); buffers alternate X, W.
   cheb_status filter(C* X, long ldx, int nb, int m, double c, double r, const Ws& w) {
     if (m == 0 || nb == 0) return CHEB_OK;
@@ -806,6 +847,7 @@ template <typename T> struct Ops {
     if (p->nproj > 0) CHK(project(X, ldx, nb, pb[0], w));
     for (int i = 1; i <= m; ++i) {
       const int ci = (i - 1) & 1, oi = i & 1;
+      CHK(resync_step(i, buf[ci], ld[ci], pb[ci], buf[oi], ld[oi], pb[oi], nb, w));
       CHK(filter_step(i, buf[ci], ld[ci], buf[oi], ld[oi], buf[oi], ld[oi], pb[ci], pb[oi], pb[oi], nb, c, r, w));
     }
     if (m & 1) HIPCHK((convert_copy<T, T>(npw, nb, buf[1], npw, X, ldx, st)));
@@ -828,6 +870,7 @@ template <typename T> struct Ops {
     if (p->nproj > 0) CHK(project(buf[0], npw, na, pb[0], w));
     for (int i = 1; i <= int(active.size()); ++i) {
       const int ci = (i - 1) & 1, oi = i & 1;
+      CHK(resync_step(i, buf[ci], npw, pb[ci], buf[oi], npw, pb[oi], active[i - 1], w));
       CHK(filter_step(i, buf[ci], npw, buf[oi], npw, buf[oi], npw, pb[ci], pb[oi], pb[oi], active[i - 1], c, r, w));
     }
     const int* ev = idx + na;
@@ -1200,15 +1243,19 @@ template <typename T> struct Ops {
     {
       Timed tr(p, st, CHEB_T_RR_ROTATE, (resid ? 4.0 : 2.0) * npw * nb * sizeof(C) + nb * nb * 16.0,
                (resid ? 16.0 : 8.0) * npw * nb * nb);
+      // FP64 MFMA in both precisions: for complex64 bands the products of complex64 values with the FP64
+      // eigenvectors are summed in FP64 and rounded once, so an ill-conditioned block (the first iterations from a
+      // random start) does not lose S-orthonormality to float32 cancellation in the sums
       Epi<T> er;
       er.out = Ynew; er.ldo = npw;
-      HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, nb, X, ldx, w.Hs, nb, er, 1, nullptr, st, ROLE_SUBSPACE)));
+      HIPCHK((gemm<double, T, double, T>(GEMM_NN, p->npw, nb, nb, X, ldx, w.Hs, nb, er, 1, nullptr, st,
+                                         ROLE_SUBSPACE)));
       if (resid) {
         // H u - lambda S u = loc Z + P (D pZ - lambda Q pZ) - lambda u
         Epi<T> e1;
         e1.out = R; e1.ldo = npw;
-        HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, nb, static_cast<C*>(w.loc), npw, w.Hs, nb, e1, 1, nullptr,
-                                      st, ROLE_SUBSPACE)));
+        HIPCHK((gemm<double, T, double, T>(GEMM_NN, p->npw, nb, nb, static_cast<C*>(w.loc), npw, w.Hs, nb, e1, 1,
+                                           nullptr, st, ROLE_SUBSPACE)));
         if (np > 0) {
           Epi<double> ez;
           ez.out = w.q; ez.ldo = np;
@@ -1234,7 +1281,7 @@ template <typename T> struct Ops {
     return CHEB_OK;
   }
 
-  // ---- LOBPCG (the block method the paper compares with, Sec. 3.1) ----------------------------------------
+  // ---- LOBPCG (the block method the paper compares with, Sec. 2.3) ----------------------------------------
   // Caller-owned state: V = [X | W | P] (3 nb columns), H V, S V, then the full P, H P, S P and the new X,
   // H X, S X (nb columns each); every block has leading dimension npw.
   struct LobState { C *V, *HV, *SV, *Pf, *HPf, *SPf, *tX, *tHX, *tSX; };
@@ -1439,6 +1486,11 @@ template <typename T> struct Ops {
     C* cb = static_cast<C*>(bw.fft.b);
     C* cc = static_cast<C*>(bw.colc);
     const double b = sizeof(C), colv = double(p->n) * p->ncol, npw = p->npw;
+    if (p->n > 64) {  // balancing scales of the polarisation form of the cross density
+      HIPCHK((col_dots<T>(p->npw, nb, a, lda, a, lda, bw.bdots, st)));
+      HIPCHK((col_dots<T>(p->npw, nb, psi, ldp, psi, ldp, bw.bdots + nb, st)));
+      HIPCHK(balance_scales(nb, bw.bdots, bw.bdots + nb, bw.bal, st));
+    }
     for (int b0 = 0; b0 < nb; b0 += fb) {
       const int cnt = std::min(fb, nb - b0);
       {
@@ -1457,7 +1509,7 @@ template <typename T> struct Ops {
       }
       {
         Timed t(p, st, CHEB_T_XDENS, cnt * 2.0 * colv * b, 0.0);
-        HIPCHK(cross_density<T>(g, tw, ca, cc, cnt, nullptr, coef, bw.xpart, dV, st));
+        HIPCHK(cross_density<T>(g, tw, ca, cc, cnt, nullptr, bw.bal + b0, coef, bw.xpart, dV, st));
       }
     }
     return CHEB_OK;
@@ -1473,7 +1525,7 @@ template <typename T> struct Ops {
       const int cnt = std::min(fb, nk - b0);
       HIPCHK(fft_col_inverse<T>(g, tw, U + long(b0) * ldu, ldu, cnt, ca, st));
       Timed t(p, st, CHEB_T_XDENS, cnt * double(p->n) * p->ncol * sizeof(C), 0.0);
-      HIPCHK(cross_density<T>(g, tw, ca, ca, cnt, wts + b0, 1.0, bw.xpart, dV, st));
+      HIPCHK(cross_density<T>(g, tw, ca, ca, cnt, wts + b0, nullptr, 1.0, bw.xpart, dV, st));
     }
     return CHEB_OK;
   }
@@ -1493,6 +1545,7 @@ template <typename T> struct Ops {
     if (np > 0) CHK(project(F[0], npw, nb, bw.pf[0], bw.fw));
     for (int i = 1; i <= m; ++i) {
       const int ci = (i - 1) & 1, oi = i & 1;
+      CHK(resync_step(i, F[ci], npw, bw.pf[ci], F[oi], npw, bw.pf[oi], nb, bw.fw));
       if ((i - 1) % k == 0) {
         const int j = (i - 1) / k;
         HIPCHK((convert_copy<T, T>(npw, nb, F[ci], npw, static_cast<C*>(bw.ck[2 * j + 1]), npw, st)));
@@ -1534,7 +1587,9 @@ template <typename T> struct Ops {
         seg[idx] = static_cast<C*>(bw.seg[idx - 1]);
         segp[idx] = bw.segp[idx - 1];
         const C* prv = idx >= 2 ? seg[idx - 2] : static_cast<const C*>(bw.ck[2 * sgm]);
-        const c128* pprv = idx >= 2 ? segp[idx - 2] : bw.ckp[2 * sgm];
+        c128* pprv = idx >= 2 ? segp[idx - 2] : bw.ckp[2 * sgm];
+        // the same resynchronisation as the forward pass, so that the segment is recomputed exactly
+        CHK(resync_step(j, seg[idx - 1], npw, segp[idx - 1], prv, npw, pprv, nb, bw.fw));
         CHK(filter_step(j, seg[idx - 1], npw, prv, npw, seg[idx], npw, segp[idx - 1], pprv, segp[idx], nb, c, r, bw.fw));
       }
       for (int i = t1; i >= t0 + 1; --i) {
@@ -1821,6 +1876,7 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
   p->n = d->n; p->npw = d->npw; p->ncol = ncol; p->rx = rx; p->natom = d->natom; p->nproj = nproj;
   p->has_overlap = d->has_overlap ? 1 : 0; p->prec = d->prec; p->dsize = dsize;
   p->gamma = d->gamma; p->npf = npf; p->h0 = fs.h0;
+  p->resync = d->prec == CHEB_MIXED ? kMixedResync : 0;
   p->proj_off.assign(d->proj_off_host, d->proj_off_host + (d->natom > 0 ? d->natom + 1 : 0));
   Persist l = persist_layout(persistent, d->n, d->npw, npf, ncol, rx, nproj, dsize, p->has_overlap, d->prec, d->gamma);
   p->gmap = l.gmap; p->gpair = l.gpair;
@@ -2009,7 +2065,9 @@ cheb_status cheb_set_projectors(cheb_plan p, const void* P, int ldp, const doubl
   if (p->prec == CHEB_MIXED) HIPCHK((convert_copy<float, double>(p->npw, np, Pd, ldp, static_cast<c64*>(p->P), p->npw, st)));
   else HIPCHK((convert_copy<double, double>(p->npw, np, Pd, ldp, static_cast<c128*>(p->P), p->npw, st)));
   if (p->prec == CHEB_MIXED) {
-    // FP16 hi/lo planes of sA P with one power-of-two scale sA taking max |P| into [0.5, 1)
+    // FP16 hi/lo planes of sA P with one power-of-two scale sA taking max |P| into [2^13, 2^14), the top of the
+    // FP16 range: hi and lo then stay normal numbers (22 significant bits together) down to entries about 2^-17 of
+    // the largest, where a scale to [0.5, 1) leaves every entry below 2^-14 with a subnormal hi and no lo
     double* cmax = reinterpret_cast<double*>(w.Hs);
     HIPCHK(column_maxabs(p->npw, np, Pd, ldp, cmax, st));
     std::vector<double> hmax(np);
@@ -2022,8 +2080,8 @@ cheb_status cheb_set_projectors(cheb_plan p, const void* P, int ldp, const doubl
     }
     int e = 0;
     if (mx > 0.0) (void)std::frexp(mx, &e);
-    const double sA = std::ldexp(1.0, -e);
-    p->hproj.inv_scale = p->hback.inv_scale = std::ldexp(1.0, e);
+    const double sA = std::ldexp(1.0, kHalfTopExp - e);
+    p->hproj.inv_scale = p->hback.inv_scale = std::ldexp(1.0, e - kHalfTopExp);
     HIPCHK(split_planes(Pd, ldp, p->npw, np, false, sA, const_cast<_Float16*>(p->hproj.p), p->hproj.rows, p->hproj.ld, st));
     HIPCHK(split_planes(Pd, ldp, p->npw, np, true, sA, const_cast<_Float16*>(p->hback.p), p->hback.rows, p->hback.ld, st));
   }
@@ -2325,6 +2383,34 @@ cheb_status cheb_set_split_gemm(cheb_plan p, int on) try {
   return host_fail(p);
 }
 
+cheb_status cheb_set_projection_resync(cheb_plan p, int period) try {
+  if (!p) return CHEB_ERR_ARG;
+  if (period < 0) return fail(p, CHEB_ERR_ARG, "resync period < 0");
+  p->resync = period;
+  return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
+}
+
+cheb_status cheb_drift_monitor(cheb_plan p, int on) try {
+  if (!p) return CHEB_ERR_ARG;
+  p->drift_on = on != 0;
+  p->drift_max = 0.0;
+  p->drift_checks = 0;
+  return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
+}
+
+cheb_status cheb_drift_read(cheb_plan p, double* max_rel, int64_t* checks) try {
+  if (!p) return CHEB_ERR_ARG;
+  if (max_rel) *max_rel = p->drift_max;
+  if (checks) *checks = p->drift_checks;
+  return CHEB_OK;
+} catch (...) {
+  return host_fail(p);
+}
+
 cheb_status cheb_set_rr_refine(cheb_plan p, int on) try {
   if (!p) return CHEB_ERR_ARG;
   p->rr_refine = on != 0;
@@ -2346,7 +2432,6 @@ static cheb_status backward_check(cheb_plan p, int nb, int m, int k) {
   if (nb < 1) return fail(p, CHEB_ERR_ARG, "nb must be >= 1");
   if (m < 1) return fail(p, CHEB_ERR_ARG, "degree m must be >= 1");
   if (k < 1) return fail(p, CHEB_ERR_ARG, "ckpt_every must be >= 1");
-  if (p->n > 64) return fail(p, CHEB_ERR_ARG, "the adjoint supports FFT boxes up to 64");
   if (p->gamma) return fail(p, CHEB_ERR_ARG, "the adjoint is not available for Gamma plans");
   if (fft_xdens_lds_bytes(p->n, p->rx, p->prec != CHEB_MIXED) > 160 * 1024)
     return fail(p, CHEB_ERR_ARG, "sphere too wide in x for the cross-density pass in 160 KB of LDS");

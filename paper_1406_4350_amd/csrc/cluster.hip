@@ -1,4 +1,4 @@
-// Exact solves of strongly coupled clusters inside the warm-started Rayleigh-Ritz refinement (Sec. 3, the
+// Exact solves of strongly coupled clusters inside the warm-started Rayleigh-Ritz refinement (Alg. 2, Sec. 4.2: the
 // subspace eigenproblem H_Y z = lambda S_Y z).
 //
 // The refinement X <- X (I + F) takes first-order steps F_ij = (M2_ij - lambda_j M1_ij) / (lambda_j - lambda_i)

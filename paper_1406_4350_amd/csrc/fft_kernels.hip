@@ -54,18 +54,12 @@ __global__ __launch_bounds__(NT) void k_col_inv(int ncol, const int4* __restrict
   }
 }
 
-template <int N, typename T> constexpr int plane_rows() {
-  // rows of the x-pass handled together: about one task per thread in the first stage, and the N = 128
-  // double-precision plane (65 x-lines of 137 slots, 16-byte points, three twiddle tables) kept inside
-  // 160 KB of LDS
+// Rows of the old block-synchronous x-pass, kept for the cross-density kernel of the adjoint: about one task per
+// thread in the first stage, and the N = 128 double-precision plane inside 160 KB of LDS.
+template <int N, typename T> constexpr int xdens_rows() {
   constexpr int N2 = LineSplit<N>::N2;
   constexpr int r = (N == 128 && sizeof(T) == 8) ? 4 : NT / N2;
   return r < N ? r : N;
-}
-
-
-template <int N, typename T> constexpr size_t plane_lds(int nx) {
-  return (size_t(nx + plane_rows<N, T>()) * line_stride<N>() + 3 * N) * sizeof(cx<T>);
 }
 
 // Inter-stage twiddles laid out for the lanes that use them: twA[k1 N2 + n2] = W_N^(n2 k1) is read by lanes of
@@ -81,24 +75,9 @@ template <int N, typename T> __device__ __forceinline__ void stage_twiddles(cons
 }
 template <typename T> __device__ __forceinline__ cx<T> conj_if(cx<T> w, bool c) { return c ? cx<T>{w.x, -w.y} : w; }
 
-// W_N^(DIR * j) from the forward table tw[j] = exp(-2 pi i j / N)
-template <int DIR, typename T> __device__ __forceinline__ cx<T> twiddle(const cx<T>* tw, int j) {
-  cx<T> w = tw[j];
-  if (DIR > 0) w.y = -w.y;
-  return w;
-}
-
 // signed frequency of FFT index k (|result| <= (N-1)/2 for the indices the sphere uses)
 template <int N> __device__ __forceinline__ int freq(int k) { return k <= (N - 1) / 2 ? k : k - N; }
 
-// One (z-plane, band) per block. With N = N1 N2 every length-N transform is two register codelets
-// (N1 and N2) around one exchange through LDS:
-//   A  inverse y on the 2R+1 x-lines, read straight from the disk-column row of this plane; the line
-//      stays in LDS in digit-reversed order (position N2 a + b holds y = a + N1 b)
-//   B  per row y: inverse x from the 2R+1 nonzero x-lines, then in registers: second inverse stage,
-//      multiply by V(r), first forward stage; one more exchange; second forward stage keeps the 2R+1
-//      x-lines
-//   C  forward y, written straight to the disk-column row of the output
 // compute units of the current device (queried once per device)
 int compute_units() {
   static int cached[64] = {0};
@@ -112,186 +91,331 @@ int compute_units() {
   return cached[dev];
 }
 
-// Items (z-plane, band) with stride gridDim.x: FP64 launches a persistent grid of the resident blocks, which
-// stage the twiddles once and load each thread's first stage-A inputs of the next item during this one; FP32
-// launches one block per item.
+// Orders the LDS accesses of one wave: every lane sees the LDS writes the wave issued before it. A wave's LDS
+// instructions execute in order, so only the compiler has to be kept from moving accesses across it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- plane pass -------------------------------------------------------------------------------------------------
+// One (z-plane, band) item at a time per block (a persistent grid walks the items). With N = N1 N2, every length-N
+// transform is two register codelets around one exchange through LDS, and every exchange stays inside one wave:
+// a wave owns whole x-lines in stages A and C and whole rows in stage B, so the only block-wide barriers are the
+// three between the stages.
+//   A  inverse y on the 2R+1 x-lines, read straight from the disk-column row of this plane. An x-line is kept in
+//      LDS as N1 groups of N2 points, group a holding y = a + N1 b at slot b (one pad slot per group and an odd
+//      line stride spread the lanes of an exchange over the banks).
+//   B  per row y (dealt to the waves RPW rows at a time, each wave with its own row buffers): inverse x from the
+//      2R+1 nonzero x-lines, then in registers the second inverse stage, V(r), the first forward stage; one more
+//      exchange; the last forward stage writes the 2R+1 kept x-lines back in place.
+//   C  forward y, written straight to the disk-column row of the output.
+// Each lane keeps one task per sub-stage for the whole launch (lane -> (line or row, digit)), so its inter-stage
+// twiddles are loaded once into registers: W_N^(-n2 k1) of the inverse stages (n2 = lane mod N2) and W_N^(a kb)
+// of the forward ones (a = lane mod N1).
+template <int N, typename T> struct PlaneCfg {
+  static constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2;
+  static constexpr int PS = N2 + 1, LS = (N1 * PS) | 1;
+  static constexpr int NW = 4;                       // waves per block
+  static constexpr int GL = 64 / N2;                 // x-lines per wave in stages A and C
+  // rows per wave and pass in stage B: one stage-1 task per lane, and the FP64 N = 128 plane (65 x-lines of 137
+  // slots of 16 bytes) plus the row buffers inside 160 KB
+  static constexpr int RPW0 = (N == 128 && sizeof(T) == 8) ? 2 : GL;
+  static constexpr int RPW = RPW0 * NW > N ? (N + NW - 1) / NW : RPW0;
+  static_assert(GL * N2 <= 64 && GL * N1 <= 64 && RPW <= GL, "one task per lane in every sub-stage");
+};
+
+template <int N, typename T> constexpr size_t plane_lds(int nx) {
+  using P = PlaneCfg<N, T>;
+  return size_t(nx + P::NW * P::RPW) * P::LS * sizeof(cx<T>);
+}
+
 template <int N, typename T>
-__global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __restrict__ xline,
-                                              const cx<T>* __restrict__ twg, const T* __restrict__ Vt,
-                                              const cx<T>* __restrict__ cin, cx<T>* __restrict__ cout, int nitems) {
-  constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2, LS = line_stride<N>(), PS = group_stride<N>();
-  constexpr int RB = plane_rows<N, T>();
-  static_assert(RB * N1 <= NT, "one second-stage task per thread and row batch");
+__global__ __launch_bounds__((64 * PlaneCfg<N, T>::NW)) void k_plane(int ncol, int rx, const int4* __restrict__ xline,
+                                                                   const cx<T>* __restrict__ twg,
+                                                                   const T* __restrict__ Vt,
+                                                                   const cx<T>* __restrict__ cin,
+                                                                   cx<T>* __restrict__ cout, int nitems) {
+  using P = PlaneCfg<N, T>;
+  constexpr int N1 = P::N1, N2 = P::N2, PS = P::PS, LS = P::LS, NW = P::NW, GL = P::GL, RPW = P::RPW;
   extern __shared__ unsigned char smem_raw[];
   const int nx = 2 * rx + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw);  // [nx][LS] y-lines of the x-lines |gx| <= rx
-  cx<T>* Sc = L + nx * LS;                         // [RB][LS] rows of the x-pass
-  cx<T>* tw = Sc + RB * LS;
-  cx<T>* twA = tw + N;
-  cx<T>* twB = twA + N;
-  const int tid = threadIdx.x;
-  for (int t = tid; t < N; t += NT) tw[t] = twg[t];
-  __syncthreads();
-  stage_twiddles<N, T>(tw, twA, twB);
-  __syncthreads();
+  cx<T>* Rw = L + nx * LS + wave * RPW * LS;       // this wave's [RPW][LS] row buffers
+  const cx<T> zero = {T(0), T(0)};
 
-  // FP64: this thread's first stage-A task (task = tid) has its inputs for the next item loaded during this
-  // one, from row offsets clamped to 0 where the input is zero (loaded anyway and replaced by zero, so that the
-  // loads need no branch). FP32 planes load in place: the extra registers cost them a resident block per CU.
-  constexpr bool PF = sizeof(T) == 8;
-  int aoff[N1];
-  bool aon[N1];
-  if constexpr (PF) {
-    const bool has = tid < nx * N2;
-    const int xi = has ? tid / N2 : 0, n2 = tid - (tid / N2) * N2;
-    const int4 xl = xline[xi];  // {first column, lowest gy, column count, 0}
+  // static lane tasks: digit n2 (stage 1 of an inverse transform, stage 2 of a forward one) and digit a
+  const int u2 = lane / N2, n2 = lane - u2 * N2;  // (line or row, n2 / kb)
+  const int u1 = lane / N1, a1 = lane - u1 * N1;  // (line or row, k1 / a)
+  cx<T> twi[N1], twf[N2];
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) {
-      const int j = freq<N>(N2 * n1 + n2) - xl.y;
-      aon[n1] = has && j >= 0 && j < xl.z;
-      aoff[n1] = aon[n1] ? xl.x + j : 0;
-    }
+  for (int k = 1; k < N1; ++k) {
+    const cx<T> w = twg[(n2 * k) % N];
+    twi[k] = cx<T>{w.x, -w.y};
   }
-  cx<T> pre[N1];
-  auto fetch = [&](int item) {
-    const cx<T>* src = cin + long(item / N) * N * ncol + long(item % N) * ncol;
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) {
-      const cx<T> x = src[aoff[n1]];
-      pre[n1] = aon[n1] ? x : cx<T>{T(0), T(0)};
-    }
-  };
-  if constexpr (PF)
-    if (int(blockIdx.x) < nitems) fetch(blockIdx.x);
+  for (int k = 1; k < N2; ++k) twf[k] = twg[(a1 * k) % N];
+  const int ngroups = (nx + GL - 1) / GL;
 
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int z = item % N, band = item / N;
     const long base = long(band) * N * ncol + long(z) * ncol;
     const cx<T>* in = cin + base;
     cx<T>* out = cout + base;
-    cx<T> v0[N1];
-    if constexpr (PF) {
-#pragma unroll
-      for (int n1 = 0; n1 < N1; ++n1) v0[n1] = pre[n1];
-      if (item + int(gridDim.x) < nitems) fetch(item + gridDim.x);  // in flight during this item
-    }
 
     // ---- A: inverse y ----
-    for (int task = tid; task < nx * N2; task += NT) {
-      const int xi = task / N2, n2 = task - xi * N2;
-      cx<T> v[N1];
-      if (PF && task == tid) {
+    for (int g = wave; g < ngroups; g += NW) {
+      {
+        const int xi = g * GL + u2;
+        if (u2 < GL && xi < nx) {
+          const int4 xl = xline[xi];  // {first column, lowest gy, column count, 0}
+          cx<T> v[N1];
 #pragma unroll
-        for (int n1 = 0; n1 < N1; ++n1) v[n1] = v0[n1];
-      } else {
-        const int4 xl = xline[xi];  // {first column, lowest gy, column count, 0}
+          for (int n1 = 0; n1 < N1; ++n1) {
+            const int j = freq<N>(N2 * n1 + n2) - xl.y;
+            const bool ok = j >= 0 && j < xl.z;
+            const cx<T> x = in[xl.x + (ok ? j : 0)];
+            v[n1] = ok ? x : zero;
+          }
+          Dft<N1, +1>::run(v);
+          cx<T>* p = L + xi * LS + n2;
 #pragma unroll
-        for (int n1 = 0; n1 < N1; ++n1) {
-          const int j = freq<N>(N2 * n1 + n2) - xl.y;
-          v[n1] = (j >= 0 && j < xl.z) ? cx<T>(in[xl.x + j]) : cx<T>{T(0), T(0)};
+          for (int k1 = 0; k1 < N1; ++k1) p[PS * k1] = k1 ? cmul(v[k1], twi[k1]) : v[0];
         }
       }
-      Dft<N1, +1>::run(v);
+      wave_sync();
+      {
+        const int xi = g * GL + u1;
+        if (u1 < GL && xi < nx) {
+          cx<T>* p = L + xi * LS + PS * a1;
+          cx<T> v[N2];
 #pragma unroll
-      for (int k1 = 0; k1 < N1; ++k1) L[xi * LS + PS * k1 + n2] = k1 ? cmul(v[k1], conj_if(twA[k1 * N2 + n2], true)) : v[0];
-    }
-    __syncthreads();
-    for (int task = tid; task < nx * N1; task += NT) {
-      const int xi = task / N1, a = task - xi * N1;
-      cx<T>* p = L + xi * LS + PS * a;
-      cx<T> v[N2];
+          for (int b = 0; b < N2; ++b) v[b] = p[b];
+          Dft<N2, +1>::run(v);
 #pragma unroll
-      for (int n2 = 0; n2 < N2; ++n2) v[n2] = p[n2];
-      Dft<N2, +1>::run(v);
-#pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) p[k2] = v[k2];  // y = a + N1 k2
+          for (int b = 0; b < N2; ++b) p[b] = v[b];  // y = a1 + N1 b
+        }
+      }
     }
     __syncthreads();
 
-    // ---- B: x-pass per row ----
+    // ---- B: x-pass, RPW rows per wave at a time ----
     const T* Vz = Vt + long(z) * N * N;
-    for (int y0 = 0; y0 < N; y0 += RB) {
-      const int nrow = min(RB, N - y0);
-      // V(r) of this thread's second-stage points, loaded before the first stage so the load latency is hidden
+    for (int y0 = wave * RPW; y0 < N; y0 += NW * RPW) {
+      const int nrow = min(RPW, N - y0);
+      // V(r) of this lane's stage-2 points, requested before stage 1 so that the load latency is hidden
+      const bool has2 = u1 < nrow;
       T vr[N2];
-      const bool has2 = tid < nrow * N1;  // at most one second-stage task per thread (RB * N1 <= NT)
       {
-        const int yy = tid / N1, a = tid - (tid / N1) * N1;
-        const T* Vrow = Vz + long(y0 + (has2 ? yy : 0)) * N + a;
+        const T* Vrow = Vz + long(y0 + (has2 ? u1 : 0)) * N + a1;
 #pragma unroll
-        for (int b = 0; b < N2; ++b) vr[b] = has2 ? Vrow[N1 * b] : T(0);
+        for (int b = 0; b < N2; ++b) vr[b] = Vrow[N1 * b];
       }
-      for (int task = tid; task < nrow * N2; task += NT) {
-        const int yy = task / N2, n2 = task - yy * N2;
-        const int y = y0 + yy, py = PS * (y % N1) + y / N1;
+      if (u2 < nrow) {
+        const int y = y0 + u2, py = PS * (y % N1) + y / N1;
         cx<T> v[N1];
 #pragma unroll
         for (int n1 = 0; n1 < N1; ++n1) {
           const int gx = freq<N>(N2 * n1 + n2);
-          v[n1] = (gx >= -rx && gx <= rx) ? cx<T>(L[(gx + rx) * LS + py]) : cx<T>{T(0), T(0)};
+          const bool ok = gx >= -rx && gx <= rx;
+          const cx<T> x = L[(ok ? gx + rx : 0) * LS + py];
+          v[n1] = ok ? x : zero;
         }
         Dft<N1, +1>::run(v);
+        cx<T>* p = Rw + u2 * LS + n2;
 #pragma unroll
-        for (int k1 = 0; k1 < N1; ++k1)
-          Sc[yy * LS + PS * k1 + n2] = k1 ? cmul(v[k1], conj_if(twA[k1 * N2 + n2], true)) : v[0];
+        for (int k1 = 0; k1 < N1; ++k1) p[PS * k1] = k1 ? cmul(v[k1], twi[k1]) : v[0];
       }
-      __syncthreads();
+      wave_sync();
       if (has2) {
-        const int yy = tid / N1, a = tid - yy * N1;
-        cx<T>* p = Sc + yy * LS + PS * a;
+        cx<T>* p = Rw + u1 * LS + PS * a1;
         cx<T> v[N2];
 #pragma unroll
-        for (int n2 = 0; n2 < N2; ++n2) v[n2] = p[n2];
-        Dft<N2, +1>::run(v);  // v[b] = psi(x = a + N1 b)
+        for (int b = 0; b < N2; ++b) v[b] = p[b];
+        Dft<N2, +1>::run(v);  // v[b] = psi(x = a1 + N1 b)
 #pragma unroll
         for (int b = 0; b < N2; ++b) v[b] = cx<T>{v[b].x * vr[b], v[b].y * vr[b]};
         Dft<N2, -1>::run(v);
 #pragma unroll
-        for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twB[kb * N1 + a]) : v[0];
+        for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twf[kb]) : v[0];
       }
-      __syncthreads();
-      for (int task = tid; task < nrow * N2; task += NT) {
-        const int yy = task / N2, kb = task - yy * N2;
-        const int y = y0 + yy, py = PS * (y % N1) + y / N1;
+      wave_sync();
+      if (u2 < nrow) {
+        const int y = y0 + u2, py = PS * (y % N1) + y / N1;
+        const cx<T>* p = Rw + u2 * LS + n2;  // slot kb = n2 of every group
         cx<T> v[N1];
 #pragma unroll
-        for (int a = 0; a < N1; ++a) v[a] = Sc[yy * LS + PS * a + kb];
+        for (int a = 0; a < N1; ++a) v[a] = p[PS * a];
         Dft<N1, -1>::run(v);
 #pragma unroll
         for (int ka = 0; ka < N1; ++ka) {
-          const int gx = freq<N>(kb + N2 * ka);
+          const int gx = freq<N>(n2 + N2 * ka);
           if (gx >= -rx && gx <= rx) L[(gx + rx) * LS + py] = v[ka];
         }
       }
-      __syncthreads();
-    }
-
-    // ---- C: forward y ----
-    for (int task = tid; task < nx * N1; task += NT) {
-      const int xi = task / N1, a = task - xi * N1;
-      cx<T>* p = L + xi * LS + PS * a;
-      cx<T> v[N2];
-#pragma unroll
-      for (int b = 0; b < N2; ++b) v[b] = p[b];
-      Dft<N2, -1>::run(v);
-#pragma unroll
-      for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twB[kb * N1 + a]) : v[0];
+      wave_sync();  // the row buffers are refilled by the next pass
     }
     __syncthreads();
-    for (int task = tid; task < nx * N2; task += NT) {
-      const int xi = task / N2, kb = task - xi * N2;
-      const int4 xl = xline[xi];
-      cx<T> v[N1];
+
+    // ---- C: forward y ----
+    for (int g = wave; g < ngroups; g += NW) {
+      {
+        const int xi = g * GL + u1;
+        if (u1 < GL && xi < nx) {
+          cx<T>* p = L + xi * LS + PS * a1;
+          cx<T> v[N2];
 #pragma unroll
-      for (int a = 0; a < N1; ++a) v[a] = L[xi * LS + PS * a + kb];
-      Dft<N1, -1>::run(v);
+          for (int b = 0; b < N2; ++b) v[b] = p[b];
+          Dft<N2, -1>::run(v);
 #pragma unroll
-      for (int ka = 0; ka < N1; ++ka) {
-        const int j = freq<N>(kb + N2 * ka) - xl.y;
-        if (j >= 0 && j < xl.z) out[xl.x + j] = v[ka];
+          for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twf[kb]) : v[0];
+        }
+      }
+      wave_sync();
+      {
+        const int xi = g * GL + u2;
+        if (u2 < GL && xi < nx) {
+          const int4 xl = xline[xi];
+          const cx<T>* p = L + xi * LS + n2;
+          cx<T> v[N1];
+#pragma unroll
+          for (int a = 0; a < N1; ++a) v[a] = p[PS * a];
+          Dft<N1, -1>::run(v);
+#pragma unroll
+          for (int ka = 0; ka < N1; ++ka) {
+            const int j = freq<N>(n2 + N2 * ka) - xl.y;
+            if (j >= 0 && j < xl.z) out[xl.x + j] = v[ka];
+          }
+        }
       }
     }
     __syncthreads();  // the next item overwrites the x-lines
+  }
+}
+
+// ---- band densities on the large boxes (N = 96, 128) ---------------------------------------------------------------
+// part[chunk][z][y][x] = sum over the chunk's bands b of w_b Re(conj(a_b(r)) psi_b(r)) (cross = 1) or w_b |a_b(r)|^2
+// (cross = 0). The cross term is taken as the difference of two densities, Re(conj(a) psi) =
+// (|s a + psi/s|^2 - |s a - psi/s|^2) / 4 for any real s > 0 (s_b balances the two norms, so that the difference loses
+// no more digits than the product would): one field at a time in real space, so that the plane of y-transformed
+// x-lines (stage A of the plane pass) and the row buffers fit in LDS at the large boxes, where two planes do not. One
+// block per (z-plane, band chunk), with the wave-local stages of the plane pass; the block adds each band's
+// contribution into its own slice of part in global memory (zeroed first), in band order, so the sum does not depend on
+// timing.
+template <int N, typename T>
+__global__ __launch_bounds__((64 * PlaneCfg<N, T>::NW)) void k_dens(int ncol, int rx, const int4* __restrict__ xline,
+                                                                    const cx<T>* __restrict__ twg,
+                                                                    const cx<T>* __restrict__ ca,
+                                                                    const cx<T>* __restrict__ cb, int cross, int nband,
+                                                                    int bpc, const double* __restrict__ wts,
+                                                                    const double* __restrict__ sc,
+                                                                    double* __restrict__ part) {
+  using P = PlaneCfg<N, T>;
+  constexpr int N1 = P::N1, N2 = P::N2, PS = P::PS, LS = P::LS, NW = P::NW, GL = P::GL, RPW = P::RPW;
+  extern __shared__ unsigned char smem_raw[];
+  const int nx = 2 * rx + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* Rw = L + nx * LS + wave * RPW * LS;
+  const cx<T> zero = {T(0), T(0)};
+  const int z = blockIdx.x, chunk = blockIdx.y;
+  const int b0 = chunk * bpc, b1 = min(nband, b0 + bpc);
+  double* out = part + (long(chunk) * N + z) * N * N;
+  for (int t = threadIdx.x; t < N * N; t += blockDim.x) out[t] = 0.0;
+  __syncthreads();
+  const int u2 = lane / N2, n2 = lane - u2 * N2;
+  const int u1 = lane / N1, a1 = lane - u1 * N1;
+  cx<T> twi[N1];
+#pragma unroll
+  for (int k = 1; k < N1; ++k) {
+    const cx<T> w = twg[(n2 * k) % N];
+    twi[k] = cx<T>{w.x, -w.y};
+  }
+  const int ngroups = (nx + GL - 1) / GL;
+  const int npass = cross ? 2 : 1;
+  for (int band = b0; band < b1; ++band) {
+    const long base = long(band) * N * ncol + long(z) * ncol;
+    const T s = cross ? T(sc[band]) : T(1);
+    const T si = cross ? T(1) / s : T(0);
+    const double wt = wts ? wts[band] : 1.0;
+    for (int pass = 0; pass < npass; ++pass) {
+      const T sg = pass ? T(-1) : T(1);
+      const double wp = cross ? (pass ? -0.25 : 0.25) * wt : wt;
+      // ---- A: inverse y of u = s a + sg psi / s (u = a without cross) ----
+      for (int g = wave; g < ngroups; g += NW) {
+        {
+          const int xi = g * GL + u2;
+          if (u2 < GL && xi < nx) {
+            const int4 xl = xline[xi];
+            cx<T> v[N1];
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1) {
+              const int j = freq<N>(N2 * n1 + n2) - xl.y;
+              const bool ok = j >= 0 && j < xl.z;
+              const long e = base + xl.x + (ok ? j : 0);
+              const cx<T> xa = ca[e];
+              const cx<T> xb = cross ? cb[e] : zero;
+              const cx<T> u = {s * xa.x + sg * si * xb.x, s * xa.y + sg * si * xb.y};
+              v[n1] = ok ? u : zero;
+            }
+            Dft<N1, +1>::run(v);
+            cx<T>* p = L + xi * LS + n2;
+#pragma unroll
+            for (int k1 = 0; k1 < N1; ++k1) p[PS * k1] = k1 ? cmul(v[k1], twi[k1]) : v[0];
+          }
+        }
+        wave_sync();
+        {
+          const int xi = g * GL + u1;
+          if (u1 < GL && xi < nx) {
+            cx<T>* p = L + xi * LS + PS * a1;
+            cx<T> v[N2];
+#pragma unroll
+            for (int b = 0; b < N2; ++b) v[b] = p[b];
+            Dft<N2, +1>::run(v);
+#pragma unroll
+            for (int b = 0; b < N2; ++b) p[b] = v[b];
+          }
+        }
+      }
+      __syncthreads();
+      // ---- B: inverse x per row, then w |u(r)|^2 into this block's slice ----
+      for (int y0 = wave * RPW; y0 < N; y0 += NW * RPW) {
+        const int nrow = min(RPW, N - y0);
+        if (u2 < nrow) {
+          const int y = y0 + u2, py = PS * (y % N1) + y / N1;
+          cx<T> v[N1];
+#pragma unroll
+          for (int n1 = 0; n1 < N1; ++n1) {
+            const int gx = freq<N>(N2 * n1 + n2);
+            const bool ok = gx >= -rx && gx <= rx;
+            const cx<T> x = L[(ok ? gx + rx : 0) * LS + py];
+            v[n1] = ok ? x : zero;
+          }
+          Dft<N1, +1>::run(v);
+          cx<T>* p = Rw + u2 * LS + n2;
+#pragma unroll
+          for (int k1 = 0; k1 < N1; ++k1) p[PS * k1] = k1 ? cmul(v[k1], twi[k1]) : v[0];
+        }
+        wave_sync();
+        if (u1 < nrow) {
+          const int y = y0 + u1;
+          const cx<T>* p = Rw + u1 * LS + PS * a1;
+          cx<T> v[N2];
+#pragma unroll
+          for (int b = 0; b < N2; ++b) v[b] = p[b];
+          Dft<N2, +1>::run(v);  // v[b] = u(x = a1 + N1 b, y)
+          double* o = out + long(y) * N + a1;
+#pragma unroll
+          for (int b = 0; b < N2; ++b)
+            o[N1 * b] += wp * (double(v[b].x) * double(v[b].x) + double(v[b].y) * double(v[b].y));
+        }
+        wave_sync();  // the row buffers are refilled by the next pass
+      }
+      __syncthreads();  // the next field overwrites the x-lines
+    }
   }
 }
 
@@ -299,7 +423,6 @@ __global__ __launch_bounds__(NT) void k_plane(int ncol, int rx, const int4* __re
 // Inputs are the z-transformed disk columns of both blocks (as written by the column pass). Per block: one
 // z-plane and a chunk of bands; each thread keeps its (y, x) points of every row batch in FP64 registers
 // across the bands of the chunk, so the band sum is in a fixed order.
-template <int N, typename T> constexpr int xdens_rows() { return plane_rows<N, T>(); }
 template <int N, typename T> constexpr int xdens_batches() { return (N + xdens_rows<N, T>() - 1) / xdens_rows<N, T>(); }
 template <int N, typename T> constexpr size_t xdens_lds(int nx) {
   return (size_t(2 * (nx + xdens_rows<N, T>())) * line_stride<N>() + 3 * N) * sizeof(cx<T>);
@@ -580,19 +703,17 @@ hipError_t fft_plane(const FftGeom& g, const cx<T>* tw, const T* Vt, const cx<T>
     constexpr int N = decltype(nc)::value;
     const size_t lds = plane_lds<N, T>(2 * g.rx + 1);
     if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-    // FP64: as many blocks as stay resident (LDS and registers), so that no block starts its share of items
-    // late; FP32 (measured 2% slower persistent): one block per item
+    // a persistent grid of as many blocks as stay resident (LDS and registers), so that no block starts its share
+    // of the items late and each loads its twiddles once
+    constexpr int threads = 64 * PlaneCfg<N, T>::NW;
     const int nitems = N * nb;
-    int grid = nitems;
-    if (sizeof(T) == 8) {
-      int per_cu = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_plane<N, T>), NT,
-                                                       lds) != hipSuccess ||
-          per_cu <= 0)
-        per_cu = 1;
-      grid = int(std::min<long>(nitems, long(compute_units()) * per_cu));
-    }
-    hipLaunchKernelGGL((k_plane<N, T>), dim3(grid), dim3(NT), lds, st, g.ncol, g.rx, g.xline, tw, Vt, cin, cout,
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_plane<N, T>), threads,
+                                                     lds) != hipSuccess ||
+        per_cu <= 0)
+      per_cu = 1;
+    const int grid = int(std::min<long>(nitems, long(compute_units()) * per_cu));
+    hipLaunchKernelGGL((k_plane<N, T>), dim3(grid), dim3(threads), lds, st, g.ncol, g.rx, g.xline, tw, Vt, cin, cout,
                        nitems);
     return hipGetLastError();
   });
@@ -629,9 +750,9 @@ int xdens_chunks(int n, int nband) {
 
 template <typename T>
 hipError_t cross_density(const FftGeom& g, const cx<T>* tw, const cx<T>* ca, const cx<T>* cb, int nband,
-                         const double* wts, double coef, double* part, double* dV, hipStream_t st) {
+                         const double* wts, const double* scale, double coef, double* part, double* dV,
+                         hipStream_t st) {
   if (nband <= 0) return hipSuccess;
-  if (g.n > 64) return hipErrorInvalidValue;
   const int nchunk = xdens_chunks(g.n, nband);
   const int bpc = (nband + nchunk - 1) / nchunk;
   hipError_t e = dispatch_n(g.n, [&](auto nc) {
@@ -643,7 +764,13 @@ hipError_t cross_density(const FftGeom& g, const cx<T>* tw, const cx<T>* ca, con
                          bpc, wts, part);
       return hipGetLastError();
     } else {
-      return hipErrorInvalidValue;
+      const size_t lds = plane_lds<N, T>(2 * g.rx + 1);
+      if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+      const int cross = ca != cb;
+      if (cross && !scale) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_dens<N, T>), dim3(N, nchunk), dim3(64 * PlaneCfg<N, T>::NW), lds, st, g.ncol, g.rx, g.xline,
+                         tw, ca, cb, cross, nband, bpc, wts, scale, part);
+      return hipGetLastError();
     }
   });
   if (e != hipSuccess) return e;
@@ -661,7 +788,8 @@ size_t fft_xdens_lds_bytes(int n, int rx, bool dbl) {
   size_t out = 0;
   (void)dispatch_n(n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    out = dbl ? xdens_lds<N, double>(2 * rx + 1) : xdens_lds<N, float>(2 * rx + 1);
+    if constexpr (N <= 64) out = dbl ? xdens_lds<N, double>(2 * rx + 1) : xdens_lds<N, float>(2 * rx + 1);
+    else out = dbl ? plane_lds<N, double>(2 * rx + 1) : plane_lds<N, float>(2 * rx + 1);
     return hipSuccess;
   });
   return out;
@@ -681,6 +809,9 @@ hipError_t fft_prepare_attributes() {
     if constexpr (N <= 64) {
       set(reinterpret_cast<const void*>(&k_xdens<N, double>));
       set(reinterpret_cast<const void*>(&k_xdens<N, float>));
+    } else {
+      set(reinterpret_cast<const void*>(&k_dens<N, double>));
+      set(reinterpret_cast<const void*>(&k_dens<N, float>));
     }
     return hipSuccess;
   };
@@ -689,9 +820,9 @@ hipError_t fft_prepare_attributes() {
 }
 
 template hipError_t cross_density<double>(const FftGeom&, const c128*, const c128*, const c128*, int, const double*,
-                                          double, double*, double*, hipStream_t);
+                                          const double*, double, double*, double*, hipStream_t);
 template hipError_t cross_density<float>(const FftGeom&, const c64*, const c64*, const c64*, int, const double*,
-                                         double, double*, double*, hipStream_t);
+                                         const double*, double, double*, double*, hipStream_t);
 template hipError_t fft_col_inverse<double>(const FftGeom&, const c128*, const c128*, long, int, c128*, hipStream_t);
 template hipError_t fft_col_inverse<float>(const FftGeom&, const c64*, const c64*, long, int, c64*, hipStream_t);
 template hipError_t fft_plane<double>(const FftGeom&, const c128*, const double*, const c128*, c128*, int, hipStream_t);

@@ -73,20 +73,21 @@ template <typename E> int epi_slots(Epi<E>& e) {
   return c;
 }
 
-// Epilogue of one wave's 2 x 2 MFMA blocks (T accumulators, the combined real and imaginary parts in cr, ci;
-// rows of accumulator v given by row_of(v)). The NE operands of block b + 1 are requested, at clamped in-range
-// indices, before the stores of block b, so that every thread keeps a block of loads in flight instead of
-// waiting on each element in turn.
-template <int NE, typename E, typename Acc, typename RowOf>
-__device__ __forceinline__ void epi_blocks(const Epi<E>& epi, int M, int N, long mb, long nb, int li, const Acc (&cr)[2][2],
-                                           const Acc (&ci)[2][2], double scale_n0, double scale_n1, RowOf row_of) {
-  constexpr int NS = NE > 0 ? NE : 1;
+// Epilogue of one wave's NI x NJ MFMA blocks of 16 x 16 (T accumulators, the combined real and imaginary parts in
+// cr, ci; rows of accumulator v given by row_of(v); column block j scaled by scale[j]). The NE operands of block
+// b + 1 are requested, at clamped in-range indices, before the stores of block b, so that every thread keeps a
+// block of loads in flight instead of waiting on each element in turn.
+template <int NE, int NI, int NJ, typename E, typename Acc, typename RowOf>
+__device__ __forceinline__ void epi_blocks(const Epi<E>& epi, int M, int N, long mb, long nb, int li,
+                                           const Acc (&cr)[NI][NJ], const Acc (&ci)[NI][NJ],
+                                           const double (&scale)[NJ], RowOf row_of) {
+  constexpr int NS = NE > 0 ? NE : 1, NBLK = NI * NJ;
   const cx<E>* src[3] = {epi.L, epi.U, epi.W};
   const long lds[3] = {epi.ldl, epi.ldu, epi.ldw};
   const double bet[3] = {epi.bL, epi.bU, epi.bW};
   cx<E> buf[2][NS][4];
   auto eload = [&](int b, cx<E>(&dst)[NS][4]) {
-    const int i = b >> 1, j = b & 1;
+    const int i = b / NJ, j = b % NJ;
     const long n = min(nb + 16 * j + li, long(N) - 1);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -98,12 +99,12 @@ __device__ __forceinline__ void epi_blocks(const Epi<E>& epi, int M, int N, long
   };
   if constexpr (NE > 0) eload(0, buf[0]);
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
+  for (int b = 0; b < NBLK; ++b) {
     if constexpr (NE > 0)
-      if (b < 3) eload(b + 1, buf[(b + 1) & 1]);
-    const int i = b >> 1, j = b & 1;
+      if (b + 1 < NBLK) eload(b + 1, buf[(b + 1) & 1]);
+    const int i = b / NJ, j = b % NJ;
     const long n = nb + 16 * j + li;
-    const double f = epi.alpha * (j ? scale_n1 : scale_n0);
+    const double f = epi.alpha * scale[j];
     // values of all four elements first, then the guarded stores: a value computed only under the guard would
     // let the compiler move its loads there and wait on them
     cx<E> val[4];
@@ -295,7 +296,8 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(int M, int N, int K, int kchunk,
           if (m < M && n < N) part[(long(bz) * N + n) * M + m] = c128{double(cr[i][j][v]), double(ci[i][j][v])};
         }
   } else {
-    epi_blocks<NE>(epi, M, N, m0 + wm, n0 + wn, li, cr, ci, 1.0, 1.0, row_of);
+    const double one[2] = {1.0, 1.0};
+    epi_blocks<NE>(epi, M, N, m0 + wm, n0 + wn, li, cr, ci, one, row_of);
   }
 }
 
@@ -442,33 +444,46 @@ __device__ __forceinline__ f4 mul3(h8 xh, h8 xl, h8 yh, h8 yl, f4 acc) {
   return mfma_h(xl, yh, acc);
 }
 
-// One 64 x 64 complex output tile per block of 4 waves, wave quadrants as in k_gemm. The 16x16x32 FP16 MFMA
-// takes, in lane l, row l % 16 of A and column l % 16 of B at k = 8 (l / 16) ... 8 (l / 16) + 7, and returns
-// row 4 (l / 16) + v, column l % 16 in accumulator element v.
+// FP16 tiles: TB x TB complex outputs per block (TB = 64: 4 waves, TB = 128: 8 waves), each wave a (16 NI) x 32
+// sub-tile of NI x 2 MFMA blocks; the waves form a 2 x (TB / 32) grid. Every thread loads one row (A) and one column
+// (B) group of 8 k per K tile of 32, so a block has 4 TB threads. The 128 tiles read each LDS fragment for twice the
+// MFMA work of the 64 tiles (a 64 x 32 wave sub-tile against 32 x 32), halving the LDS traffic per product, which
+// bounds the 64 tiles on the large projector products.
+template <int TB> struct HTile {
+  static constexpr int NI = TB / 32, NJ = 2, WM = 2, WN = TB / 32, NT = 64 * WM * WN;
+  static_assert(NT == 4 * TB, "one loader row per 4 threads");
+};
+
+// The 16x16x32 FP16 MFMA takes, in lane l, row l % 16 of A and column l % 16 of B at k = 8 (l / 16) ...
+// 8 (l / 16) + 7, and returns row 4 (l / 16) + v, column l % 16 in accumulator element v.
 // BPRE: B arrives as pre-split planes Bp [4][brows][bld] (see split_columns) and is copied to LDS as it is.
-template <typename EB, typename EO, int MODE, int ROLE, int NE, bool BPRE>
-__global__ __launch_bounds__(NT) void k_gemm_h(int M, int N, int K, int kchunk, const _Float16* __restrict__ Ap,
-                                               long arows, long ald, double ainv, const cx<EB>* __restrict__ B,
-                                               long ldb, const _Float16* __restrict__ Bp, long brows, long bld,
-                                               const float* __restrict__ bsc, Epi<EO> epi, c128* __restrict__ part) {
-  __shared__ __align__(16) _Float16 As[4][BM][HLD];
-  __shared__ __align__(16) _Float16 Bs[4][BN][HLD];
+template <int TB, typename EB, typename EO, int MODE, int ROLE, int NE, bool BPRE>
+__global__ __launch_bounds__(HTile<TB>::NT) void k_gemm_h(int M, int N, int K, int kchunk,
+                                                           const _Float16* __restrict__ Ap, long arows, long ald,
+                                                           double ainv, const cx<EB>* __restrict__ B, long ldb,
+                                                           const _Float16* __restrict__ Bp, long brows, long bld,
+                                                           const float* __restrict__ bsc, Epi<EO> epi,
+                                                           c128* __restrict__ part) {
+  using HT = HTile<TB>;
+  constexpr int NI = HT::NI, NJ = HT::NJ;
+  __shared__ __align__(16) _Float16 As[4][TB][HLD];
+  __shared__ __align__(16) _Float16 Bs[4][TB][HLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int wm = (wave % HT::WM) * 16 * NI, wn = (wave / HT::WM) * 16 * NJ;
   int bx, by, bz;
-  gemm_tile_of(blockIdx.x, gridDim.x, (M + BM - 1) / BM, (N + BN - 1) / BN, bx, by, bz);
-  const long m0 = long(bx) * BM, n0 = long(by) * BN;
+  gemm_tile_of(blockIdx.x, gridDim.x, (M + TB - 1) / TB, (N + TB - 1) / TB, bx, by, bz);
+  const long m0 = long(bx) * TB, n0 = long(by) * TB;
   const int kbeg = bz * kchunk;
   const int kend = min(K, kbeg + kchunk);
 
-  f4 cr[2][2], ci[2][2];
+  f4 cr[NI][NJ], ci[NI][NJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) { cr[i][j] = f4{0.f, 0.f, 0.f, 0.f}; ci[i][j] = f4{0.f, 0.f, 0.f, 0.f}; }
+    for (int j = 0; j < NJ; ++j) { cr[i][j] = f4{0.f, 0.f, 0.f, 0.f}; ci[i][j] = f4{0.f, 0.f, 0.f, 0.f}; }
 
-  // loader roles: 64 rows (A) / columns (B) x 4 groups of 8 k per tile, one group per thread
+  // loader roles: TB rows (A) / columns (B) x 4 groups of 8 k per tile, one group per thread
   const int lrow = tid >> 2, lgrp = tid & 3;
   const long gm = m0 + lrow, gn = n0 + lrow;
   const float sc = gn < N ? bsc[gn] : 1.f;
@@ -533,27 +548,27 @@ __global__ __launch_bounds__(NT) void k_gemm_h(int M, int N, int K, int kchunk, 
   for (int k0 = kbeg; k0 < kend; k0 += HBK) {
     const bool more = k0 + HBK < kend;
     if (more) load_tile(k0 + HBK);  // in flight while this tile is multiplied
-    h8 a[2][4], b[2][4];
+    h8 b[NJ][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl) {
-        a[i][pl] = *reinterpret_cast<const h8*>(&As[pl][wm + 16 * i + li][8 * lk]);
-        b[i][pl] = *reinterpret_cast<const h8*>(&Bs[pl][wn + 16 * i + li][8 * lk]);
-      }
+      for (int pl = 0; pl < 4; ++pl) b[j][pl] = *reinterpret_cast<const h8*>(&Bs[pl][wn + 16 * j + li][8 * lk]);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const h8 nih = -a[i][2], nil = -a[i][3];
+    for (int i = 0; i < NI; ++i) {
+      h8 a[4];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        cr[i][j] = mul3(a[i][0], a[i][1], b[j][0], b[j][1], cr[i][j]);
-        ci[i][j] = mul3(a[i][0], a[i][1], b[j][2], b[j][3], ci[i][j]);
+      for (int pl = 0; pl < 4; ++pl) a[pl] = *reinterpret_cast<const h8*>(&As[pl][wm + 16 * i + li][8 * lk]);
+      const h8 nih = -a[2], nil = -a[3];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        cr[i][j] = mul3(a[0], a[1], b[j][0], b[j][1], cr[i][j]);
+        ci[i][j] = mul3(a[0], a[1], b[j][2], b[j][3], ci[i][j]);
         if (MODE == GEMM_CN) {  // conj(a) b: re += ar br + ai bi, im += ar bi - ai br
-          cr[i][j] = mul3(a[i][2], a[i][3], b[j][2], b[j][3], cr[i][j]);
+          cr[i][j] = mul3(a[2], a[3], b[j][2], b[j][3], cr[i][j]);
           ci[i][j] = mul3(nih, nil, b[j][0], b[j][1], ci[i][j]);
         } else {  // a b: re += ar br - ai bi, im += ar bi + ai br
           cr[i][j] = mul3(nih, nil, b[j][2], b[j][3], cr[i][j]);
-          ci[i][j] = mul3(a[i][2], a[i][3], b[j][0], b[j][1], ci[i][j]);
+          ci[i][j] = mul3(a[2], a[3], b[j][0], b[j][1], ci[i][j]);
         }
       }
     }
@@ -564,19 +579,19 @@ __global__ __launch_bounds__(NT) void k_gemm_h(int M, int N, int K, int kchunk, 
     }
   }
 
-  // column scales of the lane's two columns (undo the per-band power-of-two scaling of B and the A scale)
-  double fs[2];
+  // column scales of the lane's columns (undo the per-band power-of-two scaling of B and the A scale)
+  double fs[NJ];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < NJ; ++j) {
     const long n = n0 + wn + 16 * j + li;
     fs[j] = n < N ? ainv / double(bsc[n]) : 0.0;
   }
   auto row_of = [&](int v) { return 4 * lk + v; };
   if (part) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NJ; ++j) {
         const long n = n0 + wn + 16 * j + li;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -586,7 +601,7 @@ __global__ __launch_bounds__(NT) void k_gemm_h(int M, int N, int K, int kchunk, 
         }
       }
   } else {
-    epi_blocks<NE>(epi, M, N, m0 + wm, n0 + wn, li, cr, ci, fs[0], fs[1], row_of);
+    epi_blocks<NE>(epi, M, N, m0 + wm, n0 + wn, li, cr, ci, fs, row_of);
   }
 }
 
@@ -613,8 +628,8 @@ __global__ __launch_bounds__(CST) void k_colscale(long rows, const cx<E>* __rest
     if (bsc) {
       int e = 0;
       const bool ok = mx > 0.0 && mx < 1e300;
-      if (ok) (void)frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)
-      bsc[blockIdx.x] = ok ? ldexpf(1.f, -e) : 1.f;
+      if (ok) (void)frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1): the column is scaled to max in [2^13, 2^14)
+      bsc[blockIdx.x] = ok ? ldexpf(1.f, min(kHalfTopExp - e, 126)) : 1.f;
     }
   }
 }
@@ -654,18 +669,37 @@ __global__ void k_split_columns(int K, int N, const c128* __restrict__ B, long l
 
 }  // namespace
 
+// Split count that minimises the rounds of resident blocks per unit of K work, ceil(tiles s / slots) / s, over
+// s in [1, smax] (the smallest such s): a launch of tiles slightly above a multiple of the resident blocks
+// otherwise leaves most of the GPU idle in its last round.
+long quantized_splits(long tiles, long slots, long smax, long smin = 1) {
+  if (smin < 1) smin = 1;
+  if (smax < smin) smax = smin;
+  long best = smin;
+  double cost = double((tiles * smin + slots - 1) / slots) / double(smin);
+  for (long s = smin + 1; s <= smax; ++s) {
+    const double c = double((tiles * s + slots - 1) / slots) / double(s);
+    if (c < cost - 1e-12) { cost = c; best = s; }
+  }
+  return best;
+}
+
 int gemm_pick_splits(int M, int N, int K) {
   if (M <= 0 || N <= 0 || K <= 0) return 1;
   const long tiles = long((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  // about one block per CU: measured on the paw48 projector shapes, the tall NN products (448 tiles) run best
-  // without split-K and the 256 x 256 x 7153 reductions with 16 splits (28 and 56 slower)
-  const long want = 256;
-  long s = (want + tiles - 1) / tiles;
   const long kblocks = (K + BK - 1) / BK;
-  if (s > kblocks / 2) s = kblocks / 2;  // at least two K tiles per split
-  if (s > 32) s = 32;
-  if (s < 1) s = 1;
-  return int(s);
+  long smax = std::min<long>(32, kblocks / 2);  // at least two K tiles per split
+  if (smax < 1) smax = 1;
+  long s;
+  if (tiles < 256) {
+    // about one block per CU: measured on the paw48 projector shapes, the tall NN products (448 tiles) run best
+    // without split-K and the 256 x 256 x 7153 reductions with 16 splits (28 and 56 slower)
+    s = std::min((256 + tiles - 1) / tiles, smax);
+  } else {
+    // two resident blocks per CU on 256 CUs (the 3328 x 2048 x 137065 projection: 1664 tiles, 4 splits)
+    s = quantized_splits(tiles, 512, std::min<long>(smax, 8));
+  }
+  return int(std::max<long>(s, 1));
 }
 
 template <typename T, typename EA, typename EB, typename EO>
@@ -741,17 +775,41 @@ int gemm_split_bound(int M, int N, int K) {
   return int(std::max<long>(s, std::max(gemm_pick_splits(M, N, K), gemm_h_pick_splits(M, N, K))));
 }
 
+// Tile and split-K count of the FP16 split GEMM. The FP32 accumulators of one split sum K / splits products in
+// sequence, and their rounding error grows like eps32 sqrt(K / splits): long reductions (the projections P^H x over
+// all plane waves) are split into chunks of at most kHalfChunk, summed in FP64 by the reduction (at K = 57777 in one
+// chunk the error set a residual floor of the mixed outer loop near 1e-5). The 128 tiles (one block of 8 waves per
+// CU) are used when the launch fills at least one round of resident blocks, with the split count that wastes least
+// of the last round; else the 64 tiles with about one block per CU (measured best on the paw48 shapes, where the
+// 512-block target was 5% slower on the 256 x 256 x 7153 projection: twice the partial traffic).
+// allow_split = false: one split (the caller bounds K).
+constexpr long kHalfChunk = 4096;
+
+void h_plan(int M, int N, int K, bool allow_split, int* tb, int* splits) {
+  const long kblocks = (K + HBK - 1) / HBK;
+  const long smin = allow_split ? (K + kHalfChunk - 1) / kHalfChunk : 1;
+  long smax = allow_split ? std::max<long>(std::min<long>(64, kblocks / 2), smin) : 1;
+  const long t128 = long((M + 127) / 128) * ((N + 127) / 128);
+  // at least 16 K tiles per split of the 128 tiles, whose prologue and epilogue are long
+  const long smax128 = std::max(std::min(smax, kblocks / 16), smin);
+  const long s128 = quantized_splits(t128, 256, smax128, smin);
+  if (t128 * s128 >= 256) {
+    *tb = 128;
+    *splits = int(s128);
+    return;
+  }
+  const long tiles = long((M + 63) / 64) * ((N + 63) / 64);
+  long s = (256 + tiles - 1) / tiles;
+  s = std::max(std::min(s, smax), smin);
+  *tb = 64;
+  *splits = int(std::max<long>(s, 1));
+}
+
 int gemm_h_pick_splits(int M, int N, int K) {
   if (M <= 0 || N <= 0 || K <= 0) return 1;
-  const long tiles = long((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  // about one block per CU: the FP16 products are short, and the 512-block target measured 5% slower on the
-  // 256 x 256 x 7153 projection (twice the partial traffic)
-  long s = (256 + tiles - 1) / tiles;
-  const long kblocks = (K + HBK - 1) / HBK;
-  if (s > kblocks / 2) s = kblocks / 2;
-  if (s > 32) s = 32;
-  if (s < 1) s = 1;
-  return int(s);
+  int tb = 64, s = 1;
+  h_plan(M, N, K, true, &tb, &s);
+  return s;
 }
 
 template <typename EB, typename EO>
@@ -759,6 +817,8 @@ hipError_t gemm_h(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const
                   const float* bscale, const Epi<EO>& epi, int splits, c128* part, hipStream_t st, GemmRole role) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (!A.p || A.rows < M || A.ld % HBK || A.ld < ((K + HBK - 1) / HBK) * HBK) return hipErrorInvalidValue;
+  int tb = 64, planned = 1;
+  h_plan(M, N, K, true, &tb, &planned);
   if (splits < 1) splits = 1;
   int kchunk = (K + splits - 1) / splits;
   kchunk = ((kchunk + HBK - 1) / HBK) * HBK;
@@ -766,27 +826,33 @@ hipError_t gemm_h(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const
   splits = K > 0 ? (K + kchunk - 1) / kchunk : 1;
   const bool use_part = splits > 1;
   if (use_part && !part) return hipErrorInvalidValue;
-  dim3 grid(((M + BM - 1) / BM) * ((N + BN - 1) / BN) * splits);
   c128* pp = use_part ? part : nullptr;
   Epi<EO> en = epi;
   const int ne = epi_slots(en);
-  auto launch = [&](auto modec, auto rolec) {
-    constexpr int MO = decltype(modec)::value, RO = decltype(rolec)::value;
-    const _Float16* nb16 = nullptr;
+  const _Float16* nb16 = nullptr;
+  auto launch = [&](auto tbc, auto modec, auto rolec) {
+    constexpr int T = decltype(tbc)::value, MO = decltype(modec)::value, RO = decltype(rolec)::value;
+    const dim3 grid(((M + T - 1) / T) * ((N + T - 1) / T) * splits), block(HTile<T>::NT);
     if (ne == 0 || use_part)
-      hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO, 0, false>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows,
+      hipLaunchKernelGGL((k_gemm_h<T, EB, EO, MO, RO, 0, false>), grid, block, 0, st, M, N, K, kchunk, A.p, A.rows,
                          A.ld, A.inv_scale, B, ldb, nb16, 0L, 0L, bscale, en, pp);
     else if (ne == 1)
-      hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO, 1, false>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows,
+      hipLaunchKernelGGL((k_gemm_h<T, EB, EO, MO, RO, 1, false>), grid, block, 0, st, M, N, K, kchunk, A.p, A.rows,
                          A.ld, A.inv_scale, B, ldb, nb16, 0L, 0L, bscale, en, pp);
     else
-      hipLaunchKernelGGL((k_gemm_h<EB, EO, MO, RO, 3, false>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows,
+      hipLaunchKernelGGL((k_gemm_h<T, EB, EO, MO, RO, 3, false>), grid, block, 0, st, M, N, K, kchunk, A.p, A.rows,
                          A.ld, A.inv_scale, B, ldb, nb16, 0L, 0L, bscale, en, pp);
   };
   using CN = std::integral_constant<int, GEMM_CN>;
   using NNm = std::integral_constant<int, GEMM_NN>;
-  if (role == ROLE_BACKPROJECT) mode == GEMM_CN ? launch(CN{}, std::integral_constant<int, 2>{}) : launch(NNm{}, std::integral_constant<int, 2>{});
-  else mode == GEMM_CN ? launch(CN{}, std::integral_constant<int, 1>{}) : launch(NNm{}, std::integral_constant<int, 1>{});
+  using R1 = std::integral_constant<int, 1>;
+  using R2 = std::integral_constant<int, 2>;
+  auto by_tile = [&](auto modec, auto rolec) {
+    if (tb == 128) launch(std::integral_constant<int, 128>{}, modec, rolec);
+    else launch(std::integral_constant<int, 64>{}, modec, rolec);
+  };
+  if (role == ROLE_BACKPROJECT) mode == GEMM_CN ? by_tile(CN{}, R2{}) : by_tile(NNm{}, R2{});
+  else mode == GEMM_CN ? by_tile(CN{}, R1{}) : by_tile(NNm{}, R1{});
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !use_part) return e;
   const long total = long(M) * N;
@@ -813,28 +879,36 @@ hipError_t gemm_h_pre(GemmMode mode, int M, int N, int K, const HalfPlanes& A, c
   const long kp = ((std::max(K, 0) + HBK - 1) / HBK) * HBK;
   if (!A.p || A.rows < M || A.ld % HBK || A.ld < kp) return hipErrorInvalidValue;
   if (!Bp.p || Bp.rows != N || Bp.ld % HBK || Bp.ld < kp) return hipErrorInvalidValue;
+  int tb = 64, s = 1;
+  h_plan(M, N, K, false, &tb, &s);
   int kchunk = std::max<int>(HBK, int(kp));
-  dim3 grid(((M + BM - 1) / BM) * ((N + BN - 1) / BN));
   Epi<EO> en = epi;
   const int ne = epi_slots(en);
   const cx<double>* nb64 = nullptr;
   c128* np = nullptr;
-  auto launch = [&](auto modec, auto rolec) {
-    constexpr int MO = decltype(modec)::value, RO = decltype(rolec)::value;
+  auto launch = [&](auto tbc, auto modec, auto rolec) {
+    constexpr int T = decltype(tbc)::value, MO = decltype(modec)::value, RO = decltype(rolec)::value;
+    const dim3 grid(((M + T - 1) / T) * ((N + T - 1) / T)), block(HTile<T>::NT);
     if (ne == 0)
-      hipLaunchKernelGGL((k_gemm_h<double, EO, MO, RO, 0, true>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows,
-                         A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np);
+      hipLaunchKernelGGL((k_gemm_h<T, double, EO, MO, RO, 0, true>), grid, block, 0, st, M, N, K, kchunk, A.p,
+                         A.rows, A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np);
     else if (ne == 1)
-      hipLaunchKernelGGL((k_gemm_h<double, EO, MO, RO, 1, true>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows,
-                         A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np);
+      hipLaunchKernelGGL((k_gemm_h<T, double, EO, MO, RO, 1, true>), grid, block, 0, st, M, N, K, kchunk, A.p,
+                         A.rows, A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np);
     else
-      hipLaunchKernelGGL((k_gemm_h<double, EO, MO, RO, 3, true>), grid, dim3(NT), 0, st, M, N, K, kchunk, A.p, A.rows,
-                         A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np);
+      hipLaunchKernelGGL((k_gemm_h<T, double, EO, MO, RO, 3, true>), grid, block, 0, st, M, N, K, kchunk, A.p,
+                         A.rows, A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np);
   };
   using CN = std::integral_constant<int, GEMM_CN>;
   using NNm = std::integral_constant<int, GEMM_NN>;
-  if (role == ROLE_BACKPROJECT) mode == GEMM_CN ? launch(CN{}, std::integral_constant<int, 2>{}) : launch(NNm{}, std::integral_constant<int, 2>{});
-  else mode == GEMM_CN ? launch(CN{}, std::integral_constant<int, 1>{}) : launch(NNm{}, std::integral_constant<int, 1>{});
+  using R1 = std::integral_constant<int, 1>;
+  using R2 = std::integral_constant<int, 2>;
+  auto by_tile = [&](auto modec, auto rolec) {
+    if (tb == 128) launch(std::integral_constant<int, 128>{}, modec, rolec);
+    else launch(std::integral_constant<int, 64>{}, modec, rolec);
+  };
+  if (role == ROLE_BACKPROJECT) mode == GEMM_CN ? by_tile(CN{}, R2{}) : by_tile(NNm{}, R2{});
+  else mode == GEMM_CN ? by_tile(CN{}, R1{}) : by_tile(NNm{}, R1{});
   return hipGetLastError();
 }
 
@@ -882,6 +956,7 @@ INST(float, float, float, float)
 INST(float, float, double, float)
 INST(float, float, float, double)
 INST(double, float, float, double)
+INST(double, float, double, float)
 #undef INST
 
 }  // namespace chebfd

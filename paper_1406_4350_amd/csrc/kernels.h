@@ -36,8 +36,11 @@ int gemm_pick_splits(int M, int N, int K);
 // ---- FP16 hi/lo split complex GEMM (FP32 accumulation) ---------------------------------------------------
 // A is held as four FP16 planes (Re hi, Re lo, Im hi, Im lo) of sA * A, each row m holding its K values
 // contiguously (row stride ld halves, a multiple of 8; K padded with zeros to a multiple of 32). sA is a power of
-// two chosen so that max |sA A| is in [0.5, 1): hi = fp16(sA a), lo = fp16(sA a - hi), so hi + lo carries
-// about 22 significant bits (absolute error <= 2^-25 max |sA A|).
+// two chosen so that max |sA A| is in [2^13, 2^14) (2^kHalfTopExp, near the top of the FP16 range):
+// hi = fp16(sA a), lo = fp16(sA a - hi), so hi + lo carries about 22 significant bits for every entry down to
+// about 2^-17 of the largest, both halves being normal FP16 numbers there. Products of such operands reach 2^28
+// and their sums over K stay far inside the FP32 range of the accumulators.
+constexpr int kHalfTopExp = 14;
 struct HalfPlanes {
   const _Float16* p = nullptr;  // [4][rows][ld]: Re hi, Re lo, Im hi, Im lo
   long rows = 0, ld = 0;
@@ -91,10 +94,14 @@ hipError_t fft_col_forward(const FftGeom& g, const cx<T>* tw, const cx<T>* colbu
                            const T* kin, cx<T>* out, long ldo, int nb, hipStream_t st);
 hipError_t fft_prepare_attributes();
 // dV[x][y][z] += coef n^-3 sum_b w_b Re(conj(a_b(r)) psi_b(r)) for nband bands of z-transformed disk columns ca, cb
-// (w = null: all weights 1); n <= 64; part: cross_density_part_doubles(n, nband) doubles of scratch
+// (w = null: all weights 1); part: cross_density_part_doubles(n, nband) doubles of scratch. For n > 64 and ca != cb,
+// scale[b] = (|psi_b| / |a_b|)^(1/2) balances the two fields of the polarisation form (balance_scales); else unused.
 template <typename T>
 hipError_t cross_density(const FftGeom& g, const cx<T>* tw, const cx<T>* ca, const cx<T>* cb, int nband,
-                         const double* wts, double coef, double* part, double* dV, hipStream_t st);
+                         const double* wts, const double* scale, double coef, double* part, double* dV,
+                         hipStream_t st);
+// s[b] = (pp[b].re / aa[b].re)^(1/4) from squared norms (col_dots of a with a and of psi with psi); 1 if degenerate
+hipError_t balance_scales(int nb, const c128* aa, const c128* pp, double* s, hipStream_t st);
 size_t cross_density_part_doubles(int n, int nband);
 size_t fft_xdens_lds_bytes(int n, int rx, bool dbl);
 // dynamic LDS bytes of the plane pass for box n, x-line half-width rx (0 if n unsupported)
@@ -198,6 +205,9 @@ hipError_t flag_nonfinite_real(long count, const double* x, int* flag, hipStream
 hipError_t scale_cols_isqrt(int n, int ncols, c128* Z, long ldz, const double* s, hipStream_t st);
 // out[i] = Re a[i] / Re b[i]
 hipError_t ratio_real(int nb, const c128* a, const c128* b, double* out, hipStream_t st);
+// out[j] = ||a_j - b_j|| / ||b_j|| over the rows of column j (projector-space blocks, FP64)
+hipError_t col_rel_diff(int rows, int nb, const c128* a, long lda, const c128* b, long ldb, double* out,
+                        hipStream_t st);
 
 // Clusters of the Rayleigh-Ritz refinement: bits[i W + w] bit b set when |F_ij| > tau, j = 32 w + b, i != j
 // (W = ceil(n / 32)). cluster_eig solves each cluster's pencil (M2_CC, M1_CC), members idx[off[c] ..

@@ -754,3 +754,60 @@ hipError_t sort_eigen(int n, const double* lam, double* ritz, int* perm, const c
   return hipGetLastError();
 }
 }  // namespace chebfd
+
+namespace chebfd {
+namespace {
+// out[j] = ||a_j - b_j|| / ||b_j|| for the columns of two projector-space blocks (one block per column, fixed-order
+// tree sum, so the result does not depend on timing)
+__global__ __launch_bounds__(256) void k_col_rel_diff(int rows, const c128* __restrict__ a, long lda,
+                                                      const c128* __restrict__ b, long ldb, double* __restrict__ out) {
+  __shared__ double sd[256], sb[256];
+  const c128* ac = a + long(blockIdx.x) * lda;
+  const c128* bc = b + long(blockIdx.x) * ldb;
+  double d2 = 0.0, b2 = 0.0;
+  for (int i = threadIdx.x; i < rows; i += 256) {
+    const c128 x = ac[i], y = bc[i];
+    const double dr = x.x - y.x, di = x.y - y.y;
+    d2 += dr * dr + di * di;
+    b2 += y.x * y.x + y.y * y.y;
+  }
+  sd[threadIdx.x] = d2;
+  sb[threadIdx.x] = b2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) {
+      sd[threadIdx.x] += sd[threadIdx.x + s];
+      sb[threadIdx.x] += sb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sb[0] > 0.0 ? sqrt(sd[0] / sb[0]) : (sd[0] > 0.0 ? 1.0 : 0.0);
+}
+}  // namespace
+
+hipError_t col_rel_diff(int rows, int nb, const c128* a, long lda, const c128* b, long ldb, double* out,
+                        hipStream_t st) {
+  if (rows <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_col_rel_diff, dim3(nb), dim3(256), 0, st, rows, a, lda, b, ldb, out);
+  return hipGetLastError();
+}
+}  // namespace chebfd
+
+namespace chebfd {
+namespace {
+// s_b = (|psi_b|^2 / |a_b|^2)^(1/4), so that |s a| = |psi / s| (1 when either is zero or not finite)
+__global__ void k_balance_scales(int nb, const c128* __restrict__ aa, const c128* __restrict__ pp, double* __restrict__ s) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+    const double x = aa[b].x, y = pp[b].x;
+    const double q = (x > 0.0 && y > 0.0) ? sqrt(sqrt(y / x)) : 1.0;
+    s[b] = (q > 0.0 && q < 1e300) ? q : 1.0;
+  }
+}
+}  // namespace
+
+hipError_t balance_scales(int nb, const c128* aa, const c128* pp, double* s, hipStream_t st) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_balance_scales, dim3(nblocks(nb)), dim3(256), 0, st, nb, aa, pp, s);
+  return hipGetLastError();
+}
+}  // namespace chebfd

@@ -5,11 +5,20 @@ Every vector and matrix operation is a call into libchebfd.
 """
 from __future__ import annotations
 
+import math
 import time
 
 import torch
 
 from .chebfd import Plan, locking_degrees
+
+
+def chebyshev_magnitude(m: int, x: float) -> float:
+    """|T_m(x)| from the closed form: cos(m arccos x) inside [-1, 1], cosh(m arccosh |x|) outside (host scalar)."""
+    if abs(x) <= 1.0:
+        return abs(math.cos(m * math.acos(x)))
+    t = m * math.acosh(abs(x))
+    return math.inf if t > 709.0 else math.cosh(t)
 
 
 def chebfsi(plan: Plan, X: torch.Tensor, m: int, iters: int, lam_plus: float, callback=None,
@@ -18,10 +27,15 @@ def chebfsi(plan: Plan, X: torch.Tensor, m: int, iters: int, lam_plus: float, ca
     block: explicitly for the start block, the largest Ritz value afterwards (the Rayleigh quotients of a
     Rayleigh-Ritz-rotated block are its Ritz values). With lock_tol, after each Rayleigh-Ritz step every band
     gets the degree the residual estimate of Eq. 5 asks for to reach lock_tol with the next filter (at most m,
-    0 = locked; Sec. 5.4); the first iteration uses m for all bands. Returns (ritz, residuals, history)."""
+    0 = locked; Sec. 5.4); the first iteration uses m for all bands. Each history record also carries the
+    amplification T_m((lambda_1 - c)/r) of the lowest band (lambda_1: the lowest Ritz value so far, the lowest
+    Rayleigh quotient before the first Rayleigh-Ritz step), which must stay far below 1/eps of the band precision
+    for the filtered block to stay well conditioned (Sec. 5.3). Returns (ritz, residuals, history)."""
     if lock_tol is not None and not with_residuals:
         raise ValueError("locking needs the residuals")
-    lam_minus = float(plan.rayleigh_quotients(X).max().item())
+    rq = plan.rayleigh_quotients(X)
+    lam_minus = float(rq.max().item())
+    lam_low = float(rq.min().item())
     hist = []
     ritz = res = None
     nb = X.shape[0]
@@ -41,6 +55,7 @@ def chebfsi(plan: Plan, X: torch.Tensor, m: int, iters: int, lam_plus: float, ca
         ritz, res = plan.rayleigh_ritz(X, with_residuals=with_residuals)
         torch.cuda.synchronize()
         rec = dict(it=it, c=c, r=r, lam_minus=lam_minus, seconds=time.perf_counter() - t0,
+                   stability=chebyshev_magnitude(m, (lam_low - c) / r),
                    ritz=ritz.cpu().numpy(), resid=None if res is None else res.cpu().numpy(),
                    band_applications=nb * m if degrees is None else int(degrees.sum()),
                    locked=0 if degrees is None else nlocked, degrees=None if degrees is None else degrees.copy())
@@ -48,11 +63,12 @@ def chebfsi(plan: Plan, X: torch.Tensor, m: int, iters: int, lam_plus: float, ca
         if callback is not None:
             callback(rec)
         lam_minus = float(rec["ritz"].max())
+        lam_low = min(lam_low, float(rec["ritz"].min()))
     return ritz, res, hist
 
 
 def lobpcg(plan: Plan, X: torch.Tensor, iters: int, tol: float = 1e-8, callback=None):
-    """Full-block LOBPCG (Sec. 3.1) in place on X (nb, npw): the start Rayleigh-Ritz and `iters` iterations.
+    """Full-block LOBPCG (Sec. 2.3) in place on X (nb, npw): the start Rayleigh-Ritz and `iters` iterations.
     Bands with residual <= tol add no correction (soft locking). Returns (ritz, history); history[k] has the
     Ritz values after iteration k and the residuals of the vectors that entered it (None for k = 0)."""
     nb = X.shape[0]

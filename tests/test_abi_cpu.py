@@ -164,7 +164,9 @@ def test_gemm_split_bound_covers_both_kernels(lib):
         for N in mn:
             for K in ks:
                 assert lib.cheb_gemm_splits(M, N, K, ctypes.byref(f64), ctypes.byref(f16), ctypes.byref(bd)) == cf.CHEB_OK
-                assert 1 <= f64.value <= 32 and 1 <= f16.value <= 32, (M, N, K, f64.value, f16.value)
+                assert 1 <= f64.value <= 32 and 1 <= f16.value <= 64, (M, N, K, f64.value, f16.value)
+                # the FP16 kernel's FP32 accumulators never sum more than 4096 products of K in sequence
+                assert f16.value >= -(-K // 4096), (M, N, K, f16.value)
                 assert bd.value >= max(f64.value, f16.value), (M, N, K, f64.value, f16.value, bd.value)
     assert lib.cheb_gemm_splits(4, 4, 4, None, ctypes.byref(f16), ctypes.byref(bd)) == cf.CHEB_ERR_ARG
 
@@ -189,3 +191,18 @@ def test_gemm_block_item_is_a_bijection_with_one_run_per_xcd(lib):
             assert items == list(range(items[0], items[0] + len(items))) if items else True, (tm, tn, s, x)
     assert lib.cheb_gemm_block_item(5, 5, 1, 1, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == cf.CHEB_ERR_ARG
     assert lib.cheb_gemm_block_item(0, 7, 2, 2, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == cf.CHEB_ERR_ARG
+
+
+def test_stability_factor_closed_form():
+    """The driver's |T_m(x)| (the amplification logged per outer iteration, Sec. 5.3) against the oracle's closed
+    form, inside and outside [-1, 1], and at the overflow guard."""
+    import numpy as np
+
+    from oracle import dense
+    from paper_1406_4350_amd.driver import chebyshev_magnitude
+
+    for m in (0, 1, 4, 8, 12):
+        for x in (-3.0, -1.2, -1.0, -0.4, 0.3, 1.0, 2.5):
+            ref = abs(float(dense.chebyshev_T(m, np.array([x]))[0]))
+            assert abs(chebyshev_magnitude(m, x) - ref) <= 1e-12 * max(1.0, ref)
+    assert chebyshev_magnitude(400, -9.0) == float("inf")

@@ -90,3 +90,30 @@ def test_backward_argument_errors():
         assert e.value.status == cf.CHEB_ERR_ARG
     with pytest.raises(cf.ChebError):
         plan.filter_rr_backward(X0, m, c, r, np.ones(11), 2)  # nk > nb
+
+
+@pytest.mark.parametrize("n,radius", [(96, 9), (128, 10)])
+def test_backward_large_boxes(n, radius):
+    """The adjoint on the 96^3 and 128^3 boxes, where the cross density of dL/dV(r) is taken in its polarisation
+    form (two single-field densities), against the FP64 oracle adjoint; mixed precision against the FP64 one."""
+    cfg = wl.SMALL["tiny_paw"].replace(name=f"adj{n}", n=n, radius=radius, nb=8, seed_index=300 + n)
+    pb = wl.make_problem(cfg)
+    ops = matfree.Operators.from_problem(pb)
+    lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
+    lm = float(np.max(matfree.rayleigh_quotients(ops, pb.X0)))
+    c, r = 0.5 * (lp + lm), 0.5 * (lp - lm)
+    m, nk = 3, 5
+    w = np.random.default_rng(7).uniform(0, 1, nk)
+    print(f"[case] n={n} R={radius} npw={pb.npw} nb=8 m={m}", flush=True)
+    L, lam, dX, dV, dD = grad.filter_rr_grad(ops, pb.X0, m, c, r, w, pb.D)
+    plan = cf.plan_from_problem(pb, cf.CHEB_FP64)
+    ritz, gX, gV, gD = plan.filter_rr_backward(cf.to_device_block(pb.X0, torch.complex128), m, c, r, w, 2)
+    assert np.all(np.abs(ritz.cpu().numpy() - lam) <= 1e-10 * np.maximum(np.abs(lam), 1.0))
+    assert _rel(cf.to_host_block(gX), dX) < 1e-8
+    assert _rel(gV.cpu().numpy(), dV) < 1e-8
+    assert _rel(gD.cpu().numpy(), dD) < 1e-8
+    pm = cf.plan_from_problem(pb, cf.CHEB_MIXED)
+    _, mX, mV, mD = pm.filter_rr_backward(cf.to_device_block(pb.X0, torch.complex64), m, c, r, w, 2)
+    ev = _rel(mV.cpu().numpy(), dV)
+    print(f"[check] mixed adjoint vs FP64 oracle: dV {ev:.2e}", flush=True)
+    assert ev < 1e-3

@@ -65,7 +65,7 @@ def test_free_electron_spectrum_on_gpu():
     assert np.all(np.abs(r[:7] - lam[:7]) < 1e-10)
 
 
-@pytest.mark.parametrize("n,radius", [(12, 2), (64, 8)])
+@pytest.mark.parametrize("n,radius", [(8, 3), (12, 2), (24, 11), (48, 6), (64, 8), (96, 10), (128, 12)])
 def test_other_box_sizes(n, radius):
     cfg = wl.SMALL["tiny_paw"].replace(name=f"box{n}", n=n, radius=radius, nb=9, seed_index=200 + n)
     pb = wl.make_problem(cfg)

@@ -1,4 +1,4 @@
-"""LOBPCG (Sec. 3.1) on the GPU against the LOBPCG oracle: the same iteration (start Rayleigh-Ritz, [X, W] then
+"""LOBPCG (Sec. 2.3) on the GPU against the LOBPCG oracle: the same iteration (start Rayleigh-Ritz, [X, W] then
 [X, W, P], rational kinetic preconditioner, SVQB basis, soft locking at the tolerance) on the same seeded inputs,
 FP64 plans.
 

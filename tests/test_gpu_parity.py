@@ -62,10 +62,22 @@ def test_rayleigh_ritz(case):
     ritz = ritz.cpu().numpy()
     assert np.all(np.abs(ritz - lam) <= 1e-10 * np.maximum(np.abs(lam), 1.0))
     assert np.allclose(rd.cpu().numpy(), res, rtol=1e-6, atol=1e-9)
-    # rotated block is S-orthonormal and spans the same space: compare orthogonal projectors
+    # rotated block is S-orthonormal
     Ug = cf.to_host_block(Yd)
     SU = ops.apply_S(Ug)
     assert np.allclose(Ug.conj().T @ SU, np.eye(Ug.shape[1]), atol=1e-9)
+    # and spans the oracle's Ritz subspaces: eigenvectors are compared per cluster of Ritz values (phases and
+    # rotations inside a cluster are not unique), by the sine of the largest principal angle in the S inner
+    # product, ||(I - U_o U_o^H S) U_g||_S over the cluster. Clusters are split where consecutive Ritz values
+    # differ by more than gmin; Davis-Kahan bounds the angle by (perturbation) / (gap to the rest), about
+    # 1e-12 / gmin here.
+    gmin = 1e-4
+    cuts = [0] + [i + 1 for i in range(len(lam) - 1) if lam[i + 1] - lam[i] > gmin] + [len(lam)]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        Uo, Ugc = U[:, a:b], Ug[:, a:b]
+        D = Ugc - Uo @ (Uo.conj().T @ (ops.apply_S(Ugc)))
+        sin = np.sqrt(max(np.linalg.eigvalsh(D.conj().T @ ops.apply_S(D)).max(), 0.0))
+        assert sin < 1e-7, (a, b, sin)
 
 
 def test_rayleigh_quotients_and_bound(case):

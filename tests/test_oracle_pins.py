@@ -468,7 +468,7 @@ def test_capacitance_refinement_contraction(cap_mid):
     assert k == 0 and np.allclose(q, np.linalg.solve(Cb, b), atol=1e-14 * np.linalg.norm(q))
 
 
-# ---- LOBPCG, the block method the paper compares with (Sec. 3.1) -----------------------------------------------
+# ---- LOBPCG, the block method the paper compares with (Sec. 2.3) -----------------------------------------------
 from oracle import lobpcg as lobpcg_oracle  # noqa: E402
 
 
