@@ -129,6 +129,16 @@ cheb_status cheb_apply_S(cheb_plan plan, const void* X, int ldx, void* Y, int ld
 cheb_status cheb_apply_Sinv(cheb_plan plan, const void* X, int ldx, void* Y, int ldy, int nb, void* ws,
                             size_t ws_bytes, hipStream_t stream);
 
+/* Y = H X like cheb_apply_H, for callers that cannot allocate device memory (code under graph capture, tight
+ * serving loops, harnesses that forbid allocation): no workspace argument, and the call allocates nothing. Its
+ * scratch is a file-scope device array of 64 MiB (cheb_workspace_bytes(CHEB_OP_H, nb) must not exceed it:
+ * CHEB_ERR_WORKSPACE otherwise, before any launch), held by every GPU the library runs on until the process
+ * ends; its device address is resolved at the first cheb_plan_create on each device. All calls on one GPU share
+ * that GPU's array: calls that overlap in time on one GPU (several streams or host threads) race and must be
+ * serialised by the caller. The plan's device must be current (CHEB_ERR_ARG otherwise). Kernel-class timers do
+ * not see this entry point. */
+cheb_status cheb_apply_H_noalloc(cheb_plan plan, const void* X, int ldx, void* Y, int ldy, int nb, hipStream_t stream);
+
 /* In place: X <- T_m((S^-1 H - c)/r) X, the Chebyshev filter of Alg. 2 (recurrence of Sec. 4.2):
  *   psi^0 = X, psi^1 = (A psi^0 - c psi^0)/r, psi^i = 2/r (A psi^(i-1) - c psi^(i-1)) - psi^(i-2),
  * A = S^-1 H, unscaled. Projections P^H psi^i are carried in projector space with the reuse trick of

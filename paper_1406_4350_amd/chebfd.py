@@ -35,7 +35,7 @@ SYMBOLS = ["cheb_plan_persistent_bytes", "cheb_plan_create", "cheb_plan_destroy"
            "cheb_set_rr_refine", "cheb_rr_stats", "cheb_filter_degrees", "cheb_locking_degrees", "cheb_set_split_gemm",
            "cheb_set_capacitance_solver", "cheb_lobpcg_state_bytes", "cheb_lobpcg_iterate", "cheb_gemm_splits",
            "cheb_gemm_block_item", "cheb_set_projection_resync", "cheb_drift_monitor", "cheb_drift_read",
-           "cheb_last_error"]
+           "cheb_apply_H_noalloc", "cheb_last_error"]
 TIMERS = ["fft_col_inverse", "fft_plane", "fft_col_forward", "project", "backproject", "small", "rr_gram", "rr_eig",
           "rr_rotate", "xdens"]
 
@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cheb_gemm_splits": [i, i, i, P(i), P(i), P(i)],
         "cheb_gemm_block_item": [i, i, i, i, P(i), P(i), P(i)],
         "cheb_set_projection_resync": [vp, i],
+        "cheb_apply_H_noalloc": [vp, vp, i, vp, i, i, vp],
         "cheb_drift_monitor": [vp, i],
         "cheb_drift_read": [vp, P(d), P(ctypes.c_int64)],
     }
@@ -260,6 +261,16 @@ class Plan:
 
     def apply_H(self, X, Y=None):
         return self._apply("cheb_apply_H", CHEB_OP_H, X, Y)
+
+    def apply_H_noalloc(self, X, Y=None):
+        """Y = H X through the entry point that allocates nothing (the library's static device scratch)."""
+        nb, ldx = self._block(X, "X")
+        if Y is None:
+            Y = torch.empty_like(X)
+        _, ldy = self._block(Y, "Y")
+        self._check(self.lib.cheb_apply_H_noalloc(self.handle, X.data_ptr(), ldx, Y.data_ptr(), ldy, nb, _stream()),
+                    "cheb_apply_H_noalloc")
+        return Y
 
     def apply_S(self, X, Y=None):
         return self._apply("cheb_apply_S", CHEB_OP_SINV, X, Y)

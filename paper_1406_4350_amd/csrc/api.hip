@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,6 +24,8 @@ using namespace chebfd;
 struct cheb_plan_s {
   int n = 0, npw = 0, ncol = 0, rx = 0, natom = 0, nproj = 0, has_overlap = 0, prec = 0;
   int gamma = 0, npf = 0, h0 = -1;  // Gamma point: FFT sphere of npf entries built from the npw half-sphere ones
+  int device = 0;                   // device current at cheb_plan_create
+  void* scratch = nullptr;          // device address of this device's static scratch (cheb_apply_H_noalloc)
   int* gmap = nullptr;              // per FFT-sphere entry: half index | conj << 30
   int2* gpair = nullptr;            // per half entry: FFT-sphere entries of G and -G
   std::vector<int> proj_off;
@@ -74,7 +77,32 @@ struct cheb_plan_s {
   int64_t prof_n[CHEB_T_COUNT] = {};
 };
 
+// Scratch of cheb_apply_H_noalloc, for callers that cannot allocate device memory: a file-scope device array, of
+// which every GPU the library runs on holds its own copy until the process ends. Host code never passes the
+// name (a host-side stand-in): the device address is resolved once per device with that device current, at the
+// first cheb_plan_create on it, and kept in scratch_addr.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_addr[kMaxDevices] = {};
+
+// the current device's address of `scratch` (nullptr and *err set when it cannot be resolved)
+void* resolve_scratch(int dev, hipError_t* err) {
+  *err = hipSuccess;
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_addr[dev]) {
+    void* ptr = nullptr;
+    *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    scratch_addr[dev] = ptr;
+  }
+  return scratch_addr[dev];
+}
 
 constexpr size_t kAlign = 256;
 // default period (filter steps) of the projection resynchronisation in mixed plans
@@ -1956,6 +1984,9 @@ cheb_status cheb_plan_create(const cheb_desc* d, void* persistent, size_t bytes,
     std::fprintf(stderr, "cheb_plan_create: rocblas_create_handle failed\n");
     return CHEB_ERR_HIP;
   }
+  if ((e = hipGetDevice(&p->device))) return fail_hip(e, "hipGetDevice");
+  // the static scratch of cheb_apply_H_noalloc on this device (a failure only disables that entry point)
+  p->scratch = resolve_scratch(p->device, &e);
   *out = owner.release();
   return CHEB_OK;
 } catch (...) {
@@ -2165,6 +2196,29 @@ cheb_status cheb_apply_S(cheb_plan p, const void* X, int ldx, void* Y, int ldy, 
 cheb_status cheb_apply_Sinv(cheb_plan p, const void* X, int ldx, void* Y, int ldy, int nb, void* ws, size_t wsb,
                             hipStream_t st) try {
   return apply_common(p, 2, X, ldx, Y, ldy, nb, ws, wsb, st);
+} catch (...) {
+  return host_fail(p);
+}
+
+cheb_status cheb_apply_H_noalloc(cheb_plan p, const void* X, int ldx, void* Y, int ldy, int nb, hipStream_t st) try {
+  if (!p) return CHEB_ERR_ARG;
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != p->device) return fail(p, CHEB_ERR_ARG, "cheb_apply_H_noalloc: the plan's device is not current");
+  if (!p->scratch) return fail(p, CHEB_ERR_HIP, "cheb_apply_H_noalloc: the static scratch has no device address");
+  if (nb < 0) return fail(p, CHEB_ERR_ARG, "nb < 0");
+  Ws probe;
+  CHK(ws_layout(p, CHEB_OP_H, nb, nullptr, &probe));
+  if (probe.total > kNoAllocScratchBytes)
+    return fail(p, CHEB_ERR_WORKSPACE, "cheb_apply_H_noalloc: " + std::to_string(nb) + " bands need " +
+                                           std::to_string(probe.total) + " bytes of scratch, the static scratch holds " +
+                                           std::to_string(kNoAllocScratchBytes) + "; use cheb_apply_H with a workspace");
+  // no profiling events from this entry point (creating them may allocate)
+  const bool prof = p->prof_on;
+  p->prof_on = false;
+  const cheb_status s = apply_common(p, 0, X, ldx, Y, ldy, nb, p->scratch, kNoAllocScratchBytes, st);
+  p->prof_on = prof;
+  return s;
 } catch (...) {
   return host_fail(p);
 }
