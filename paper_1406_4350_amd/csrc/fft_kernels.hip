@@ -117,11 +117,16 @@ __device__ __forceinline__ void wave_sync() {
 template <int N, typename T> struct PlaneCfg {
   static constexpr int N1 = LineSplit<N>::N1, N2 = LineSplit<N>::N2;
   static constexpr int PS = N2 + 1, LS = (N1 * PS) | 1;
-  static constexpr int NW = 4;                       // waves per block
   static constexpr int GL = 64 / N2;                 // x-lines per wave in stages A and C
-  // rows per wave and pass in stage B: one stage-1 task per lane, and the FP64 N = 128 plane (65 x-lines of 137
-  // slots of 16 bytes) plus the row buffers inside 160 KB
-  static constexpr int RPW0 = (N == 128 && sizeof(T) == 8) ? 2 : GL;
+  // waves per block and rows per wave and pass in stage B (at most one stage-1 task per lane). The large boxes
+  // hold one block per CU (the plane of y-lines fills most of the LDS: 65 x-lines of 137 slots at N = 128), so they
+  // take 8 waves, two per SIMD, where the row buffers fit; the FP64 N = 128 plane leaves room for 8 row buffers,
+  // taken by 4 waves of 2 rows (more waves of fewer rows would issue the same instructions for fewer lanes). The
+  // smaller boxes keep 4 waves: more blocks per CU, each an independent item, hide more latency than more waves
+  // per item (6 waves at N = 48 measured 45% slower). Rows per pass: 96 = 3 x 8 x 4, 128 = 16 x 4 x 2 (FP64)
+  // or 4 x 8 x 4 (FP32).
+  static constexpr int NW = N == 128 ? (sizeof(T) == 8 ? 4 : 8) : (N == 96 ? 8 : 4);
+  static constexpr int RPW0 = N == 128 ? (sizeof(T) == 8 ? 2 : 4) : (N == 96 ? 4 : GL);
   static constexpr int RPW = RPW0 * NW > N ? (N + NW - 1) / NW : RPW0;
   static_assert(GL * N2 <= 64 && GL * N1 <= 64 && RPW <= GL, "one task per lane in every sub-stage");
 };
