@@ -128,13 +128,18 @@ template <int N, typename T> struct PlaneCfg {
   static constexpr int NW = N == 128 ? (sizeof(T) == 8 ? 4 : 8) : (N == 96 ? 8 : 4);
   static constexpr int RPW0 = N == 128 ? (sizeof(T) == 8 ? 2 : 4) : (N == 96 ? 4 : GL);
   static constexpr int RPW = RPW0 * NW > N ? (N + NW - 1) / NW : RPW0;
+  // loads one step ahead (see k_plane) where the LDS holds a single block per CU anyway; elsewhere the extra
+  // registers would cost resident blocks
+  static constexpr bool PF = N == 128 || (N == 96 && sizeof(T) == 8);
   static_assert(GL * N2 <= 64 && GL * N1 <= 64 && RPW <= GL, "one task per lane in every sub-stage");
 };
 
-template <int N, typename T> constexpr size_t plane_lds(int nx) {
+// bytes of the y-lines and row buffers, then the x-line table at the next 16-byte boundary
+template <int N, typename T> constexpr size_t plane_lines_bytes(int nx) {
   using P = PlaneCfg<N, T>;
-  return size_t(nx + P::NW * P::RPW) * P::LS * sizeof(cx<T>);
+  return ((size_t(nx + P::NW * P::RPW) * P::LS * sizeof(cx<T>)) + 15) / 16 * 16;
 }
+template <int N, typename T> constexpr size_t plane_lds(int nx) { return plane_lines_bytes<N, T>(nx) + size_t(nx) * 16; }
 
 template <int N, typename T>
 __global__ __launch_bounds__((64 * PlaneCfg<N, T>::NW)) void k_plane(int ncol, int rx, const int4* __restrict__ xline,
@@ -149,7 +154,9 @@ __global__ __launch_bounds__((64 * PlaneCfg<N, T>::NW)) void k_plane(int ncol, i
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw);  // [nx][LS] y-lines of the x-lines |gx| <= rx
   cx<T>* Rw = L + nx * LS + wave * RPW * LS;       // this wave's [RPW][LS] row buffers
+  int4* XL = reinterpret_cast<int4*>(smem_raw + plane_lines_bytes<N, T>(nx));  // the x-line table
   const cx<T> zero = {T(0), T(0)};
+  for (int t = threadIdx.x; t < nx; t += blockDim.x) XL[t] = xline[t];
 
   // static lane tasks: digit n2 (stage 1 of an inverse transform, stage 2 of a forward one) and digit a
   const int u2 = lane / N2, n2 = lane - u2 * N2;  // (line or row, n2 / kb)
@@ -163,27 +170,57 @@ __global__ __launch_bounds__((64 * PlaneCfg<N, T>::NW)) void k_plane(int ncol, i
 #pragma unroll
   for (int k = 1; k < N2; ++k) twf[k] = twg[(a1 * k) % N];
   const int ngroups = (nx + GL - 1) / GL;
+  __syncthreads();
 
+  // With PF, loads are issued one step ahead of their use and kept raw (the zero padding is selected at the use,
+  // since a select right after the load would wait for it): the stage-A inputs of the next group (of the next
+  // item's first group during stage C), and V(r) of the next row pass (of the first pass at the start of the item).
+  // Indices past the end are clamped to valid elements whose values are never used. Without PF, each group and
+  // pass loads its own inputs first.
+  cx<T> araw[N1];
+  int aly = 0, alz = 0;  // lowest gy and column count of the prefetched x-line
+  auto load_a = [&](const cx<T>* src, int g) {
+    const int xi = min(g * GL + u2, nx - 1);
+    const int4 xl = XL[xi];  // {first column, lowest gy, column count, 0}
+    aly = xl.y;
+    alz = xl.z;
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int j = freq<N>(N2 * n1 + n2) - xl.y;
+      araw[n1] = src[xl.x + ((j >= 0 && j < xl.z) ? j : 0)];
+    }
+  };
+  T vr[N2];
+  auto load_v = [&](const T* Vz, int y0) {
+    const T* Vrow = Vz + long(min(y0 + u1, N - 1)) * N + a1;
+#pragma unroll
+    for (int b = 0; b < N2; ++b) vr[b] = Vrow[N1 * b];
+  };
+  auto item_base = [&](int item) { return long(item / N) * N * ncol + long(item % N) * ncol; };
+
+  if (P::PF && int(blockIdx.x) < nitems) load_a(cin + item_base(blockIdx.x), wave);
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-    const int z = item % N, band = item / N;
-    const long base = long(band) * N * ncol + long(z) * ncol;
+    const int z = item % N;
+    const long base = item_base(item);
     const cx<T>* in = cin + base;
     cx<T>* out = cout + base;
+    const T* Vz = Vt + long(z) * N * N;
+    if constexpr (P::PF) load_v(Vz, wave * RPW);
 
     // ---- A: inverse y ----
     for (int g = wave; g < ngroups; g += NW) {
       {
         const int xi = g * GL + u2;
-        if (u2 < GL && xi < nx) {
-          const int4 xl = xline[xi];  // {first column, lowest gy, column count, 0}
-          cx<T> v[N1];
+        const bool mine = u2 < GL && xi < nx;
+        if constexpr (!P::PF) load_a(in, g);
+        cx<T> v[N1];
 #pragma unroll
-          for (int n1 = 0; n1 < N1; ++n1) {
-            const int j = freq<N>(N2 * n1 + n2) - xl.y;
-            const bool ok = j >= 0 && j < xl.z;
-            const cx<T> x = in[xl.x + (ok ? j : 0)];
-            v[n1] = ok ? x : zero;
-          }
+        for (int n1 = 0; n1 < N1; ++n1) {
+          const int j = freq<N>(N2 * n1 + n2) - aly;
+          v[n1] = (j >= 0 && j < alz) ? araw[n1] : zero;
+        }
+        if constexpr (P::PF) load_a(in, min(g + NW, ngroups - 1));
+        if (mine) {
           Dft<N1, +1>::run(v);
           cx<T>* p = L + xi * LS + n2;
 #pragma unroll
@@ -207,17 +244,10 @@ __global__ __launch_bounds__((64 * PlaneCfg<N, T>::NW)) void k_plane(int ncol, i
     __syncthreads();
 
     // ---- B: x-pass, RPW rows per wave at a time ----
-    const T* Vz = Vt + long(z) * N * N;
     for (int y0 = wave * RPW; y0 < N; y0 += NW * RPW) {
       const int nrow = min(RPW, N - y0);
-      // V(r) of this lane's stage-2 points, requested before stage 1 so that the load latency is hidden
       const bool has2 = u1 < nrow;
-      T vr[N2];
-      {
-        const T* Vrow = Vz + long(y0 + (has2 ? u1 : 0)) * N + a1;
-#pragma unroll
-        for (int b = 0; b < N2; ++b) vr[b] = Vrow[N1 * b];
-      }
+      if constexpr (!P::PF) load_v(Vz, y0);  // requested before stage 1 so that the latency is hidden
       if (u2 < nrow) {
         const int y = y0 + u2, py = PS * (y % N1) + y / N1;
         cx<T> v[N1];
@@ -246,6 +276,7 @@ __global__ __launch_bounds__((64 * PlaneCfg<N, T>::NW)) void k_plane(int ncol, i
 #pragma unroll
         for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twf[kb]) : v[0];
       }
+      if constexpr (P::PF) load_v(Vz, y0 + NW * RPW);  // the next pass (clamped past the last)
       wave_sync();
       if (u2 < nrow) {
         const int y = y0 + u2, py = PS * (y % N1) + y / N1;
@@ -263,6 +294,12 @@ __global__ __launch_bounds__((64 * PlaneCfg<N, T>::NW)) void k_plane(int ncol, i
       wave_sync();  // the row buffers are refilled by the next pass
     }
     __syncthreads();
+
+    // the next item's first stage-A inputs, in flight during stage C
+    if constexpr (P::PF) {
+      const int nxt = item + int(gridDim.x);
+      load_a(cin + item_base(nxt < nitems ? nxt : item), wave);
+    }
 
     // ---- C: forward y ----
     for (int g = wave; g < ngroups; g += NW) {
@@ -282,7 +319,7 @@ __global__ __launch_bounds__((64 * PlaneCfg<N, T>::NW)) void k_plane(int ncol, i
       {
         const int xi = g * GL + u2;
         if (u2 < GL && xi < nx) {
-          const int4 xl = xline[xi];
+          const int4 xl = XL[xi];
           const cx<T>* p = L + xi * LS + n2;
           cx<T> v[N1];
 #pragma unroll
