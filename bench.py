@@ -29,6 +29,10 @@ sys.path.insert(0, ROOT)
 METRIC = "H·ψ band-applications/s (FP32-MFMA vs FP64) at ≤1e-6 Ha; % HBM/MFMA roofline"
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "f16x3": 2500.0}
+# vector ALU peaks (FMA = 2 flops): FP64 78.6; FP32 157.3 with packed FP32 instructions, which the build disables,
+# so the FP32 kernels here issue at most half of it
+VECTOR_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+MIXED_RESYNC_DEFAULT = 3  # a mixed plan recomputes the carried projections every 3rd filter step unless set
 GEMM_CLASSES = ("project", "backproject", "small", "rr_gram", "rr_rotate")
 FFT_CLASSES = ("fft_col_inverse", "fft_plane", "fft_col_forward")
 # kernel names as rocprofv3 reports them, per timer class and precision
@@ -116,9 +120,11 @@ def class_roofline(name, d, kind, n):
     """Roofline numbers of one kernel class from its event timers: GEMM classes against the MFMA peak of the
     arithmetic they run on (FP64 for the FP64 path, the projector-space products and the Rayleigh-Ritz Grams in
     both paths, FP16 for the split projector GEMMs of mixed plans, where each useful product takes three FP16
-    MFMAs), FFT classes against the HBM peak. Achieved = algorithmic flops (8 per complex multiply-add) or bytes
-    per launch / average launch time."""
+    MFMAs), FFT classes against the HBM peak, and the plane pass (whose timers also count its transform
+    arithmetic) against the vector ALU peak where that fraction is the larger. Achieved = algorithmic flops (8 per
+    complex multiply-add; 5 n log2 n per length-n transform) or bytes per launch / average launch time."""
     per_launch_s = d["ms"] * 1e-3 / d["launches"]
+    alu = False
     if name in GEMM_CLASSES:
         achieved = d["flops"] / d["launches"] / per_launch_s / 1e12
         dt = "f16x3" if (kind == "f32" and name in ("project", "backproject")) else "f64"
@@ -127,11 +133,20 @@ def class_roofline(name, d, kind, n):
     else:
         achieved = d["bytes"] / d["launches"] / per_launch_s / 1e9
         out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        if d.get("flops", 0.0) > 0.0:
+            # FFT arithmetic (5 n log2 n flops per length-n transform) against the vector ALU peak of the
+            # precision; the class is bound by whichever roofline it comes closer to
+            a_alu = d["flops"] / d["launches"] / per_launch_s / 1e12
+            p_alu = VECTOR_PEAK_TFLOPS[kind]
+            hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
+            if a_alu / p_alu > hbm["frac"]:
+                alu = True
+                out = {"bound": "alu", "achieved": a_alu, "peak": p_alu, "unit": "TFLOP/s", "hbm": hbm}
     out["frac"] = out["achieved"] / out["peak"]
     tmpl = KERNEL_NAMES.get(name)
     out["kernel"] = tmpl[0 if kind == "f64" else 1].format(n=n) if tmpl else name
     out["avg_launch_us"] = per_launch_s * 1e6
-    out["algo_per_launch"] = (d["flops"] if name in GEMM_CLASSES else d["bytes"]) / d["launches"]
+    out["algo_per_launch"] = (d["flops"] if (name in GEMM_CLASSES or alu) else d["bytes"]) / d["launches"]
     out["launches"] = d["launches"]
     out["ms_total"] = d["ms"]
     return out
@@ -268,7 +283,7 @@ def mixed_accuracy(cf, pb, r64, rmx, lam_plus, max_extra, done):
             "max_abs_dlambda_Ha": float(dlam.max()), "max_resid_fp64_eval": float(res_x[:k].max()),
             "median_resid_fp64_eval": float(np.median(res_x[:k])),
             "bands_meeting_target": int(ok.sum()), "target_met": bool(ok.all()),
-            "drift_resync_period": rmx.get("resync")}
+            "projection_resync_period": rmx.get("resync") if rmx.get("resync") is not None else MIXED_RESYNC_DEFAULT}
 
 
 def time_backward(cf, pb, lam_plus, reps=3):

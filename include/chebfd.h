@@ -289,9 +289,11 @@ cheb_status cheb_profile_read(cheb_plan plan, int timer, double* ms, int64_t* la
 cheb_status cheb_gemm_splits(int M, int N, int K, int* fp64, int* fp16, int* bound);
 /* Work item of block i in a tiled GEMM launch of `total` blocks over (split, M tile, N tile) items with
  * tm x tn tiles per split: the blocks are dealt to the 8 XCDs in turn and each XCD receives one contiguous run
- * of items, so that blocks sharing an operand slice share an L2. Host arithmetic only. CHEB_ERR_ARG unless
- * 0 <= i < total, total a multiple of tm * tn > 0 and the pointers non-null. */
-cheb_status cheb_gemm_block_item(int i, int total, int tm, int tn, int* bx, int* by, int* bz);
+ * of items, so that blocks sharing an operand slice share an L2. Items are ordered split by split, in groups of
+ * `group` M tiles, the M tile fastest inside a group (group 1: the N tile fastest). The GEMMs use group 8 when
+ * K >= M and group 1 otherwise. Host arithmetic only. CHEB_ERR_ARG unless 0 <= i < total, total a multiple of
+ * tm * tn > 0, group >= 1 and the pointers non-null. */
+cheb_status cheb_gemm_block_item(int i, int total, int tm, int tn, int group, int* bx, int* by, int* bz);
 
 /* Message of the last failing call on `plan` ("" if none). Valid until the next call on the plan. */
 const char* cheb_last_error(cheb_plan plan);

@@ -94,7 +94,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cheb_lobpcg_iterate": [vp, vp, i, i, i, d, vp, sz, vp, vp, P(i), vp, sz, vp],
         "cheb_locking_degrees": [i, vp, vp, d, d, i, d, vp, P(i)],
         "cheb_gemm_splits": [i, i, i, P(i), P(i), P(i)],
-        "cheb_gemm_block_item": [i, i, i, i, P(i), P(i), P(i)],
+        "cheb_gemm_block_item": [i, i, i, i, i, P(i), P(i), P(i)],
         "cheb_set_projection_resync": [vp, i],
         "cheb_apply_H_noalloc": [vp, vp, i, vp, i, i, vp],
         "cheb_drift_monitor": [vp, i],

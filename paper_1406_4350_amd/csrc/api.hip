@@ -286,7 +286,7 @@ struct Ws {
 };
 
 int fft_batch_for(const cheb_plan_s* p, int nb) {
-  const size_t per_band = size_t(p->n) * p->ncol * elem_bytes(p->prec);
+  const size_t per_band = size_t(p->n) * col_stride(p->ncol) * elem_bytes(p->prec);
   size_t cap = (96u << 20) / std::max<size_t>(per_band, 1);
   if (cap < 1) cap = 1;
   return int(std::min<size_t>(size_t(std::max(nb, 1)), cap));
@@ -301,7 +301,7 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
   const int np = p->nproj;
   const size_t pp = size_t(std::max(np, 1)) * std::max(nb, 1);
   const int fb = fft_batch_for(p, nb);
-  const size_t colb = size_t(fb) * p->n * p->ncol * eb;
+  const size_t colb = size_t(fb) * p->n * col_stride(p->ncol) * eb;
   size_t part = 0;
   auto need_fft = [&]() {
     w->fft.a = b.take<char>(colb);
@@ -516,7 +516,7 @@ cheb_status bwd_layout(cheb_plan p, int nb, int m, int k, void* base, BwdWs* w) 
   char* rrb = b.take<char>(probe.total);
   CHK(ws_layout(p, CHEB_OP_RR, nb, rrb, &w->rr));
   const int fb = fft_batch_for(p, nb);
-  const size_t colb = size_t(fb) * p->n * p->ncol * eb;
+  const size_t colb = size_t(fb) * p->n * col_stride(p->ncol) * eb;
   w->fft.a = b.take<char>(colb);
   w->fft.b = b.take<char>(colb);
   w->colc = b.take<char>(colb);
@@ -590,6 +590,13 @@ template <typename T> struct Ops {
   cheb_plan p;
   hipStream_t st;
   FftGeom geom() const { return FftGeom{p->n, p->ncol, p->npw, p->rx, p->col, p->ent, p->xline}; }
+  // algorithmic flops of one band's plane pass: on each of the n z-planes, 2 (2 rx + 1) y-transforms of the
+  // nonzero x-lines and 2 n x-transforms of the rows, 5 n log2 n flops per complex length-n transform, and the
+  // real-space product with V(r) (2 per point)
+  double plane_flops() const {
+    const double n = p->n, nx = 2.0 * p->rx + 1.0;
+    return n * ((2.0 * nx + 2.0 * n) * 5.0 * n * std::log2(n) + 2.0 * n * n);
+  }
   const C* P() const { return static_cast<const C*>(p->P); }
 
   // out = (K + V_loc) X, batched over bands through the disk-column buffers
@@ -608,7 +615,7 @@ template <typename T> struct Ops {
         HIPCHK(fft_col_inverse<T>(g, tw, X + long(b0) * ldx, ldx, cnt, ca, st));
       }
       {
-        Timed t(p, st, CHEB_T_FFT_PLANE, cnt * 2.0 * colv * b, 0.0);
+        Timed t(p, st, CHEB_T_FFT_PLANE, cnt * 2.0 * colv * b, cnt * plane_flops());
         HIPCHK(fft_plane<T>(g, tw, static_cast<const T*>(p->Vt), ca, cb, cnt, st));
       }
       {
@@ -640,7 +647,7 @@ template <typename T> struct Ops {
         HIPCHK(fft_col_inverse<T>(g, tw, ga, npf, npair, ca, st));
       }
       {
-        Timed t(p, st, CHEB_T_FFT_PLANE, npair * 2.0 * colv * b, 0.0);
+        Timed t(p, st, CHEB_T_FFT_PLANE, npair * 2.0 * colv * b, npair * plane_flops());
         HIPCHK(fft_plane<T>(g, tw, static_cast<const T*>(p->Vt), ca, cb, npair, st));
       }
       {
@@ -1527,7 +1534,7 @@ template <typename T> struct Ops {
         HIPCHK(fft_col_inverse<T>(g, tw, psi + long(b0) * ldp, ldp, cnt, cc, st));
       }
       {
-        Timed t(p, st, CHEB_T_FFT_PLANE, cnt * 2.0 * colv * b, 0.0);
+        Timed t(p, st, CHEB_T_FFT_PLANE, cnt * 2.0 * colv * b, cnt * plane_flops());
         HIPCHK(fft_plane<T>(g, tw, static_cast<const T*>(p->Vt), ca, cb, cnt, st));
       }
       {
@@ -2296,10 +2303,10 @@ cheb_status cheb_gemm_splits(int M, int N, int K, int* fp64, int* fp16, int* bou
   return host_fail(nullptr);
 }
 
-cheb_status cheb_gemm_block_item(int i, int total, int tm, int tn, int* bx, int* by, int* bz) try {
-  if (!bx || !by || !bz || tm <= 0 || tn <= 0 || total <= 0 || i < 0 || i >= total) return CHEB_ERR_ARG;
+cheb_status cheb_gemm_block_item(int i, int total, int tm, int tn, int group, int* bx, int* by, int* bz) try {
+  if (!bx || !by || !bz || tm <= 0 || tn <= 0 || total <= 0 || i < 0 || i >= total || group < 1) return CHEB_ERR_ARG;
   if (total % (long(tm) * tn)) return CHEB_ERR_ARG;
-  gemm_block_item(i, total, tm, tn, *bx, *by, *bz);
+  gemm_block_item(i, total, tm, tn, group, *bx, *by, *bz);
   return CHEB_OK;
 } catch (...) {
   return host_fail(nullptr);

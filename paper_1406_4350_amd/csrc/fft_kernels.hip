@@ -47,10 +47,11 @@ __global__ __launch_bounds__(NT) void k_col_inv(int ncol, const int4* __restrict
   }
   __syncthreads();
   lds_fft<N, +1, T>(lines, nc, LS, twA);
-  cx<T>* out = colbuf + long(band) * N * ncol;
+  const long cs = col_stride(ncol);
+  cx<T>* out = colbuf + long(band) * N * cs;
   for (int t = tid; t < N * nc; t += NT) {
     const int z = t / nc, c = t - z * nc;
-    out[long(z) * ncol + c0 + c] = lines[c * LS + z];
+    out[long(z) * cs + c0 + c] = lines[c * LS + z];
   }
 }
 
@@ -196,7 +197,8 @@ __global__ __launch_bounds__((64 * PlaneCfg<N, T>::NW)) void k_plane(int ncol, i
 #pragma unroll
     for (int b = 0; b < N2; ++b) vr[b] = Vrow[N1 * b];
   };
-  auto item_base = [&](int item) { return long(item / N) * N * ncol + long(item % N) * ncol; };
+  const long cs = col_stride(ncol);
+  auto item_base = [&](int item) { return long(item / N) * N * cs + long(item % N) * cs; };
 
   if (P::PF && int(blockIdx.x) < nitems) load_a(cin + item_base(blockIdx.x), wave);
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
@@ -378,7 +380,7 @@ __global__ __launch_bounds__((64 * PlaneCfg<N, T>::NW)) void k_dens(int ncol, in
   const int ngroups = (nx + GL - 1) / GL;
   const int npass = cross ? 2 : 1;
   for (int band = b0; band < b1; ++band) {
-    const long base = long(band) * N * ncol + long(z) * ncol;
+    const long base = long(band) * N * col_stride(ncol) + long(z) * col_stride(ncol);
     const T s = cross ? T(sc[band]) : T(1);
     const T si = cross ? T(1) / s : T(0);
     const double wt = wts ? wts[band] : 1.0;
@@ -552,7 +554,7 @@ __global__ __launch_bounds__(NT) void k_xdens(int ncol, int rx, const int4* __re
   __syncthreads();
   for (int band = b0; band < b1; ++band) {
     const double wt = wts ? wts[band] : 1.0;
-    const long base = long(band) * N * ncol + long(z) * ncol;
+    const long base = long(band) * N * col_stride(ncol) + long(z) * col_stride(ncol);
     y_inverse<N, T>(ca + base, La, xline, twA, nx);
     y_inverse<N, T>(cb + base, Lb, xline, twA, nx);
     __syncthreads();
@@ -612,10 +614,11 @@ __global__ __launch_bounds__(NT) void k_col_fwd(int ncol, const int4* __restrict
   const int c0 = blockIdx.x * CPB, c1 = min(ncol, c0 + CPB), nc = c1 - c0;
   const int tid = threadIdx.x;
   for (int t = tid; t < N; t += NT) twA[t] = twg[((t % LineSplit<N>::N2) * (t / LineSplit<N>::N2)) % N];
-  const cx<T>* in = colbuf + long(band) * N * ncol;
+  const long cs = col_stride(ncol);
+  const cx<T>* in = colbuf + long(band) * N * cs;
   for (int t = tid; t < N * nc; t += NT) {
     const int z = t / nc, c = t - z * nc;
-    lines[c * LS + z] = in[long(z) * ncol + c0 + c];
+    lines[c * LS + z] = in[long(z) * cs + c0 + c];
   }
   __syncthreads();
   lds_fft<N, -1, T>(lines, nc, LS, twA);

@@ -32,19 +32,27 @@ template <> struct Mfma<float> {
 constexpr int BM = 64, BN = 64, BK = 32, PAD = 1, NT = 256;
 
 // Block placement. The hardware deals the blocks of a launch to the 8 XCDs in turn (block i to XCD i mod 8),
-// each XCD with its own L2. Logical work items are numbered (split, M tile, N tile) with the N tile fastest,
-// so items that share a slice of A (same split and M tile) or of B (same split) are neighbours; physical block
-// i takes the logical item that gives each XCD one contiguous run of items, and the shared slices are read
-// from HBM once per XCD instead of once per block.
-__host__ __device__ inline void gemm_tile_of(int i, int total, int tm, int tn, int& bx, int& by, int& bz) {
+// each XCD with its own L2. Physical block i takes the logical item that gives each XCD one contiguous run of
+// items. Items are numbered split by split; inside a split, in groups of `grp` M tiles, and inside a group with
+// the M tile fastest. With grp = 8 the blocks an XCD holds at once (32 to 64) cover a square-ish patch of up to 8
+// M tiles by 4 to 8 N tiles, so each slice of A and of B they read is shared by several resident blocks in the
+// XCD's L2: the rule for long contractions (K >= M: projections, Gram matrices), where both operands stream
+// K-long slices. With grp = 1 the N tile runs fastest and each M tile's slice of A is read once, by all N tiles
+// at the same time: the rule for tall, short-K products (back-projection, rotation), whose A dwarfs B.
+constexpr int kTileGroup = 8;
+__host__ __device__ inline void gemm_tile_of(int i, int total, int tm, int tn, int grp, int& bx, int& by, int& bz) {
   const int q = total / 8, rem = total % 8, k = i % 8, j = i / 8;
   const int L = (k < rem ? k * (q + 1) : rem * (q + 1) + (k - rem) * q) + j;
   const int per = tm * tn;
   bz = L / per;
   const int t = L - bz * per;
-  bx = t / tn;
-  by = t - bx * tn;
+  const int first = (t / (grp * tn)) * grp;
+  const int gm = tm - first < grp ? tm - first : grp;  // M tiles in this group (fewer in the last)
+  const int r = t - first * tn;
+  bx = first + r % gm;
+  by = r / gm;
 }
+inline int tile_group(int M, int K) { return K >= M ? kTileGroup : 1; }
 
 template <typename E>
 __device__ __forceinline__ void epi_store(const Epi<E>& e, long m, long n, double re, double im) {
@@ -137,7 +145,7 @@ __device__ __forceinline__ void epi_blocks(const Epi<E>& epi, int M, int N, long
 template <typename T, typename EA, typename EB, typename EO, int MODE, int ROLE, int NE>
 __global__ __launch_bounds__(NT, 2) void k_gemm(int M, int N, int K, int kchunk, const cx<EA>* __restrict__ A,
                                              long lda, const cx<EB>* __restrict__ B, long ldb, Epi<EO> epi,
-                                             c128* __restrict__ part) {
+                                             c128* __restrict__ part, int grp) {
   constexpr bool G3 = sizeof(T) == 8;
   __shared__ T Ar[BK][BM + PAD], Ai[BK][BM + PAD], Br[BK][BN + PAD], Bi[BK][BN + PAD];
   using acc_t = typename Mfma<T>::acc;
@@ -145,7 +153,7 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(int M, int N, int K, int kchunk,
   const int li = lane & 15, lk = lane >> 4;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   int bx, by, bz;
-  gemm_tile_of(blockIdx.x, gridDim.x, (M + BM - 1) / BM, (N + BN - 1) / BN, bx, by, bz);
+  gemm_tile_of(blockIdx.x, gridDim.x, (M + BM - 1) / BM, (N + BN - 1) / BN, grp, bx, by, bz);
   const long m0 = long(bx) * BM, n0 = long(by) * BN;
   const int kbeg = bz * kchunk;
   const int kend = min(K, kbeg + kchunk);
@@ -337,7 +345,7 @@ __global__ __launch_bounds__(64 * SW) void k_gemm_s(int M, int N, int K, int kch
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   int bx, by, bz;
-  gemm_tile_of(blockIdx.x, gridDim.x, (M + 15) / 16, (N + 15) / 16, bx, by, bz);
+  gemm_tile_of(blockIdx.x, gridDim.x, (M + 15) / 16, (N + 15) / 16, 1, bx, by, bz);
   const long m0 = long(bx) * 16, n0 = long(by) * 16;
   // rows of A past M and columns of B past N are read clamped: they feed only output rows and columns that are
   // never stored
@@ -463,16 +471,20 @@ __global__ __launch_bounds__(HTile<TB>::NT) void k_gemm_h(int M, int N, int K, i
                                                            double ainv, const cx<EB>* __restrict__ B, long ldb,
                                                            const _Float16* __restrict__ Bp, long brows, long bld,
                                                            const float* __restrict__ bsc, Epi<EO> epi,
-                                                           c128* __restrict__ part) {
+                                                           c128* __restrict__ part, int grp) {
   using HT = HTile<TB>;
   constexpr int NI = HT::NI, NJ = HT::NJ;
-  __shared__ __align__(16) _Float16 As[4][TB][HLD];
-  __shared__ __align__(16) _Float16 Bs[4][TB][HLD];
+  // The 128 tiles (one block per CU) take two LDS stages: tile t is multiplied from one while tile t + 1 is
+  // converted and written to the other, so the MFMAs just issued run on while the wave waits for the next tile's
+  // loads, and one barrier per tile suffices. The 64 tiles keep one stage and more resident blocks.
+  constexpr int NS = TB == 128 ? 2 : 1;
+  __shared__ __align__(16) _Float16 As[NS][4][TB][HLD];
+  __shared__ __align__(16) _Float16 Bs[NS][4][TB][HLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wm = (wave % HT::WM) * 16 * NI, wn = (wave / HT::WM) * 16 * NJ;
   int bx, by, bz;
-  gemm_tile_of(blockIdx.x, gridDim.x, (M + TB - 1) / TB, (N + TB - 1) / TB, bx, by, bz);
+  gemm_tile_of(blockIdx.x, gridDim.x, (M + TB - 1) / TB, (N + TB - 1) / TB, grp, bx, by, bz);
   const long m0 = long(bx) * TB, n0 = long(by) * TB;
   const int kbeg = bz * kchunk;
   const int kend = min(K, kbeg + kchunk);
@@ -516,12 +528,12 @@ __global__ __launch_bounds__(HTile<TB>::NT) void k_gemm_h(int M, int N, int K, i
       }
     }
   };
-  auto store_tile = [&]() {
+  auto store_tile = [&](int sg) {
 #pragma unroll
-    for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<h8*>(&As[pl][lrow][8 * lgrp]) = ra[pl];
+    for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<h8*>(&As[sg][pl][lrow][8 * lgrp]) = ra[pl];
     if constexpr (BPRE) {
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<h8*>(&Bs[pl][lrow][8 * lgrp]) = rb[pl];
+      for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<h8*>(&Bs[sg][pl][lrow][8 * lgrp]) = rb[pl];
       return;
     }
     h8 rh, rl, ih, il;
@@ -534,17 +546,18 @@ __global__ __launch_bounds__(HTile<TB>::NT) void k_gemm_h(int M, int N, int K, i
       rl[j] = _Float16(xr - float(hr));
       il[j] = _Float16(xi - float(hi));
     }
-    *reinterpret_cast<h8*>(&Bs[0][lrow][8 * lgrp]) = rh;
-    *reinterpret_cast<h8*>(&Bs[1][lrow][8 * lgrp]) = rl;
-    *reinterpret_cast<h8*>(&Bs[2][lrow][8 * lgrp]) = ih;
-    *reinterpret_cast<h8*>(&Bs[3][lrow][8 * lgrp]) = il;
+    *reinterpret_cast<h8*>(&Bs[sg][0][lrow][8 * lgrp]) = rh;
+    *reinterpret_cast<h8*>(&Bs[sg][1][lrow][8 * lgrp]) = rl;
+    *reinterpret_cast<h8*>(&Bs[sg][2][lrow][8 * lgrp]) = ih;
+    *reinterpret_cast<h8*>(&Bs[sg][3][lrow][8 * lgrp]) = il;
   };
 
   if (kbeg < kend) {
     load_tile(kbeg);
-    store_tile();
+    store_tile(0);
   }
   __syncthreads();
+  int sg = 0;
   for (int k0 = kbeg; k0 < kend; k0 += HBK) {
     const bool more = k0 + HBK < kend;
     if (more) load_tile(k0 + HBK);  // in flight while this tile is multiplied
@@ -552,12 +565,12 @@ __global__ __launch_bounds__(HTile<TB>::NT) void k_gemm_h(int M, int N, int K, i
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl) b[j][pl] = *reinterpret_cast<const h8*>(&Bs[pl][wn + 16 * j + li][8 * lk]);
+      for (int pl = 0; pl < 4; ++pl) b[j][pl] = *reinterpret_cast<const h8*>(&Bs[NS == 2 ? sg : 0][pl][wn + 16 * j + li][8 * lk]);
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
       h8 a[4];
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl) a[pl] = *reinterpret_cast<const h8*>(&As[pl][wm + 16 * i + li][8 * lk]);
+      for (int pl = 0; pl < 4; ++pl) a[pl] = *reinterpret_cast<const h8*>(&As[NS == 2 ? sg : 0][pl][wm + 16 * i + li][8 * lk]);
       const h8 nih = -a[2], nil = -a[3];
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
@@ -572,10 +585,16 @@ __global__ __launch_bounds__(HTile<TB>::NT) void k_gemm_h(int M, int N, int K, i
         }
       }
     }
-    __syncthreads();
-    if (more) {
-      store_tile();
+    if constexpr (NS == 2) {
+      if (more) store_tile(sg ^ 1);  // that stage was last read before the previous barrier
       __syncthreads();
+      sg ^= 1;
+    } else {
+      __syncthreads();
+      if (more) {
+        store_tile(0);
+        __syncthreads();
+      }
     }
   }
 
@@ -728,17 +747,21 @@ hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, c
   const bool use_part = splits > 1;
   if (use_part && !part) return hipErrorInvalidValue;
   dim3 grid(((M + BM - 1) / BM) * ((N + BN - 1) / BN) * splits);
+  const int grp = tile_group(M, K);
   c128* pp = use_part ? part : nullptr;
   Epi<EO> en = epi;
   const int ne = epi_slots(en);
   auto launch = [&](auto modec, auto rolec) {
     constexpr int MO = decltype(modec)::value, RO = decltype(rolec)::value;
     if (ne == 0 || use_part)
-      hipLaunchKernelGGL((k_gemm<T, EA, EB, EO, MO, RO, 0>), grid, dim3(NT), 0, st, M, N, K, kchunk, A, lda, B, ldb, en, pp);
+      hipLaunchKernelGGL((k_gemm<T, EA, EB, EO, MO, RO, 0>), grid, dim3(NT), 0, st, M, N, K, kchunk, A, lda, B, ldb, en, pp,
+                         grp);
     else if (ne == 1)
-      hipLaunchKernelGGL((k_gemm<T, EA, EB, EO, MO, RO, 1>), grid, dim3(NT), 0, st, M, N, K, kchunk, A, lda, B, ldb, en, pp);
+      hipLaunchKernelGGL((k_gemm<T, EA, EB, EO, MO, RO, 1>), grid, dim3(NT), 0, st, M, N, K, kchunk, A, lda, B, ldb, en, pp,
+                         grp);
     else
-      hipLaunchKernelGGL((k_gemm<T, EA, EB, EO, MO, RO, 3>), grid, dim3(NT), 0, st, M, N, K, kchunk, A, lda, B, ldb, en, pp);
+      hipLaunchKernelGGL((k_gemm<T, EA, EB, EO, MO, RO, 3>), grid, dim3(NT), 0, st, M, N, K, kchunk, A, lda, B, ldb, en, pp,
+                         grp);
   };
   using CN = std::integral_constant<int, GEMM_CN>;
   using NNm = std::integral_constant<int, GEMM_NN>;
@@ -757,8 +780,8 @@ hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, c
   return hipGetLastError();
 }
 
-void gemm_block_item(int i, int total, int tm, int tn, int& bx, int& by, int& bz) {
-  gemm_tile_of(i, total, tm, tn, bx, by, bz);
+void gemm_block_item(int i, int total, int tm, int tn, int grp, int& bx, int& by, int& bz) {
+  gemm_tile_of(i, total, tm, tn, grp, bx, by, bz);
 }
 
 // upper bound of the split counts any GEMM kernel here picks for an M x N x K product (partial-buffer sizing):
@@ -833,15 +856,16 @@ hipError_t gemm_h(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const
   auto launch = [&](auto tbc, auto modec, auto rolec) {
     constexpr int T = decltype(tbc)::value, MO = decltype(modec)::value, RO = decltype(rolec)::value;
     const dim3 grid(((M + T - 1) / T) * ((N + T - 1) / T) * splits), block(HTile<T>::NT);
+    const int grp = tile_group(M, K);
     if (ne == 0 || use_part)
       hipLaunchKernelGGL((k_gemm_h<T, EB, EO, MO, RO, 0, false>), grid, block, 0, st, M, N, K, kchunk, A.p, A.rows,
-                         A.ld, A.inv_scale, B, ldb, nb16, 0L, 0L, bscale, en, pp);
+                         A.ld, A.inv_scale, B, ldb, nb16, 0L, 0L, bscale, en, pp, grp);
     else if (ne == 1)
       hipLaunchKernelGGL((k_gemm_h<T, EB, EO, MO, RO, 1, false>), grid, block, 0, st, M, N, K, kchunk, A.p, A.rows,
-                         A.ld, A.inv_scale, B, ldb, nb16, 0L, 0L, bscale, en, pp);
+                         A.ld, A.inv_scale, B, ldb, nb16, 0L, 0L, bscale, en, pp, grp);
     else
       hipLaunchKernelGGL((k_gemm_h<T, EB, EO, MO, RO, 3, false>), grid, block, 0, st, M, N, K, kchunk, A.p, A.rows,
-                         A.ld, A.inv_scale, B, ldb, nb16, 0L, 0L, bscale, en, pp);
+                         A.ld, A.inv_scale, B, ldb, nb16, 0L, 0L, bscale, en, pp, grp);
   };
   using CN = std::integral_constant<int, GEMM_CN>;
   using NNm = std::integral_constant<int, GEMM_NN>;
@@ -889,15 +913,16 @@ hipError_t gemm_h_pre(GemmMode mode, int M, int N, int K, const HalfPlanes& A, c
   auto launch = [&](auto tbc, auto modec, auto rolec) {
     constexpr int T = decltype(tbc)::value, MO = decltype(modec)::value, RO = decltype(rolec)::value;
     const dim3 grid(((M + T - 1) / T) * ((N + T - 1) / T)), block(HTile<T>::NT);
+    const int grp = tile_group(M, K);
     if (ne == 0)
       hipLaunchKernelGGL((k_gemm_h<T, double, EO, MO, RO, 0, true>), grid, block, 0, st, M, N, K, kchunk, A.p,
-                         A.rows, A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np);
+                         A.rows, A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np, grp);
     else if (ne == 1)
       hipLaunchKernelGGL((k_gemm_h<T, double, EO, MO, RO, 1, true>), grid, block, 0, st, M, N, K, kchunk, A.p,
-                         A.rows, A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np);
+                         A.rows, A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np, grp);
     else
       hipLaunchKernelGGL((k_gemm_h<T, double, EO, MO, RO, 3, true>), grid, block, 0, st, M, N, K, kchunk, A.p,
-                         A.rows, A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np);
+                         A.rows, A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np, grp);
   };
   using CN = std::integral_constant<int, GEMM_CN>;
   using NNm = std::integral_constant<int, GEMM_NN>;

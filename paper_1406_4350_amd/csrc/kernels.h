@@ -65,7 +65,7 @@ int gemm_h_pick_splits(int M, int N, int K);
 // upper bound of both split rules, for sizing split-K partial buffers
 int gemm_split_bound(int M, int N, int K);
 // the work item (M tile bx, N tile by, split bz) the tiled kernels give block i of a `total`-block launch
-void gemm_block_item(int i, int total, int tm, int tn, int& bx, int& by, int& bz);
+void gemm_block_item(int i, int total, int tm, int tn, int grp, int& bx, int& by, int& bz);
 // bscale[n] = 2^-e with max_k |B[k][n]| (over Re and Im) in [2^(e-1), 2^e); 1 for a zero column
 template <typename E> hipError_t column_scales(long rows, int ncols, const cx<E>* B, long ldb, float* bscale,
                                                hipStream_t st);
@@ -106,6 +106,9 @@ size_t cross_density_part_doubles(int n, int nband);
 size_t fft_xdens_lds_bytes(int n, int rx, bool dbl);
 // dynamic LDS bytes of the plane pass for box n, x-line half-width rx (0 if n unsupported)
 size_t fft_plane_lds_bytes(int n, int rx, bool dbl);
+// Row stride (in elements) of the disk-column buffers [band][z][column]: the column count rounded up to 16, so
+// that every z-row starts on a 128-byte line (the column passes read 16 or 32 neighbouring columns of a row)
+__host__ __device__ inline int col_stride(int ncol) { return (ncol + 15) & ~15; }
 // Gamma point: U[:, j] = bands 2j + i 2j+1 expanded to the whole sphere (gmap: half index | conj << 30, h0 the
 // half index of G = 0 or -1); out = the two bands separated from the transformed W, scaled back, + K X
 template <typename T>

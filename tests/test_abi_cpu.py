@@ -171,26 +171,48 @@ def test_gemm_split_bound_covers_both_kernels(lib):
     assert lib.cheb_gemm_splits(4, 4, 4, None, ctypes.byref(f16), ctypes.byref(bd)) == cf.CHEB_ERR_ARG
 
 
+def _grouped_item(bx, by, bz, tm, tn, group=8):
+    """Position of work item (split bz, M tile bx, N tile by) in the grouped order: split by split, groups of
+    `group` M tiles, the M tile fastest inside a group."""
+    first = (bx // group) * group
+    gm = min(group, tm - first)
+    return bz * tm * tn + first * tn + by * gm + (bx - first)
+
+
 def test_gemm_block_item_is_a_bijection_with_one_run_per_xcd(lib):
     """Block i of a tiled GEMM launch takes work item (split, M tile, N tile) so that every item is taken once
-    and the blocks dealt to each of the 8 XCDs (i mod 8) hold one contiguous run of items (host arithmetic)."""
+    and the blocks dealt to each of the 8 XCDs (i mod 8) hold one contiguous run of the grouped order (groups of
+    `group` M tiles, M tile fastest inside a group; group 1 is the N tile fastest), so that the blocks an XCD
+    holds at once share slices of A and B (host arithmetic)."""
     bx, by, bz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    for tm, tn, s in [(1, 1, 1), (1, 1, 7), (2, 3, 1), (4, 4, 16), (7, 5, 3), (112, 4, 1), (4, 4, 32), (9, 9, 2),
-                      (3, 1, 13), (16, 16, 1)]:
-        total = tm * tn * s
-        seen = {}
-        for i in range(total):
-            assert lib.cheb_gemm_block_item(i, total, tm, tn, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == 0
-            item = (bz.value * tm + bx.value) * tn + by.value  # (split, M tile, N tile), N tile fastest
-            assert 0 <= bx.value < tm and 0 <= by.value < tn and 0 <= bz.value < s
-            assert item not in seen.values()
-            seen[i] = item
-        assert sorted(seen.values()) == list(range(total))
-        for x in range(8):
-            items = sorted(seen[i] for i in range(x, total, 8))
-            assert items == list(range(items[0], items[0] + len(items))) if items else True, (tm, tn, s, x)
-    assert lib.cheb_gemm_block_item(5, 5, 1, 1, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == cf.CHEB_ERR_ARG
-    assert lib.cheb_gemm_block_item(0, 7, 2, 2, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == cf.CHEB_ERR_ARG
+    for group in (1, 8, 3):
+        for tm, tn, s in [(1, 1, 1), (1, 1, 7), (2, 3, 1), (4, 4, 16), (7, 5, 3), (112, 4, 1), (4, 4, 32), (9, 9, 2),
+                          (3, 1, 13), (16, 16, 1), (26, 16, 40), (52, 32, 4), (17, 3, 2)]:
+            total = tm * tn * s
+            seen = {}
+            for i in range(total):
+                assert lib.cheb_gemm_block_item(i, total, tm, tn, group, ctypes.byref(bx), ctypes.byref(by),
+                                                ctypes.byref(bz)) == 0
+                assert 0 <= bx.value < tm and 0 <= by.value < tn and 0 <= bz.value < s
+                seen[i] = _grouped_item(bx.value, by.value, bz.value, tm, tn, group)
+            assert sorted(seen.values()) == list(range(total))
+            for x in range(8):
+                items = sorted(seen[i] for i in range(x, total, 8))
+                assert items == list(range(items[0], items[0] + len(items))) if items else True, (tm, tn, s, x)
+    # group 1 is the plain order (split, M tile, N tile) with the N tile fastest
+    for i in range(7 * 5 * 3):
+        lib.cheb_gemm_block_item(i, 105, 7, 5, 1, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz))
+        assert _grouped_item(bx.value, by.value, bz.value, 7, 5, 1) == (bz.value * 7 + bx.value) * 5 + by.value
+    # with group 8, the first 64 items of a large split (XCD 0's first blocks) cover 8 M tiles by 8 N tiles
+    tm, tn, total = 52, 32, 52 * 32 * 4
+    patch = set()
+    for i in range(0, 8 * 64, 8):
+        lib.cheb_gemm_block_item(i, total, tm, tn, 8, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz))
+        patch.add((bx.value, by.value))
+    assert {b for b, _ in patch} == set(range(8)) and {c for _, c in patch} == set(range(8))
+    assert lib.cheb_gemm_block_item(5, 5, 1, 1, 1, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == cf.CHEB_ERR_ARG
+    assert lib.cheb_gemm_block_item(0, 7, 2, 2, 1, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == cf.CHEB_ERR_ARG
+    assert lib.cheb_gemm_block_item(0, 4, 2, 2, 0, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == cf.CHEB_ERR_ARG
 
 
 def test_stability_factor_closed_form():
