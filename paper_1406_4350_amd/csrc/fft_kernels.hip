@@ -339,6 +339,221 @@ __global__ __launch_bounds__((64 * PlaneCfg<N, T>::NW)) void k_plane(int ncol, i
   }
 }
 
+// ---- plane pass in two halves (FP64, N = 128) --------------------------------------------------------------------
+// The whole plane of y-transformed x-lines (65 x-lines of 137 FP64 slots, 142 KB) leaves room for 8 row buffers:
+// one block of 4 waves per CU, 2 rows per wave. Here the plane is processed in two halves of the y residues mod N1
+// (half h holds groups a = 4h .. 4h + 3 of y = a + N1 b), 72 KB each, beside 8 waves x 4 row buffers: twice the
+// waves per CU and twice the rows per wave. Per half: stage A computes the first inverse stage in full and keeps
+// its four outputs of the half, then the second stage on those four groups; stage B takes the half's 64 rows
+// through the full x-pass; stage C runs the first forward stage on the four groups, and the second forward stage
+// (a length-8 DFT over the groups) as this half's share, sum over a in the half of x_a W8^(-a ka) =
+// (-1)^(h ka) Y[ka], Y the interleaved pair of length-4 DFTs of x and of x W8^(-a). The first half stores its
+// share to the output rows, the second adds its own to them (each entry stays with the same lane).
+struct Half128 {
+  static constexpr int N = 128, N1 = 8, N2 = 16, PS = N2 + 1, LS = (N1 * PS) | 1, G = 4;
+  static constexpr int LSH = (G * PS) | 1;  // slots of one x-line of a half plane
+  static constexpr int GL = 64 / N2;        // x-lines per wave and group in stages A and C
+  static constexpr int NW = 8, RPW = 4;     // waves per block, rows per wave and pass in stage B
+};
+constexpr size_t half128_lines_bytes(int nx) {
+  using H = Half128;
+  return (size_t(nx) * H::LSH + size_t(H::NW) * H::RPW * H::LS + H::N) * sizeof(c128);
+}
+constexpr size_t half128_lds(int nx) { return half128_lines_bytes(nx) + size_t(nx) * 16; }
+
+__global__ __launch_bounds__(64 * Half128::NW) void k_plane_half(int ncol, int rx, const int4* __restrict__ xline,
+                                                                 const c128* __restrict__ twg,
+                                                                 const double* __restrict__ Vt,
+                                                                 const c128* __restrict__ cin,
+                                                                 c128* __restrict__ cout, int nitems) {
+  using H = Half128;
+  using T = double;
+  constexpr int N = H::N, N1 = H::N1, N2 = H::N2, PS = H::PS, LS = H::LS, LSH = H::LSH, GL = H::GL, NW = H::NW,
+                RPW = H::RPW;
+  extern __shared__ unsigned char smem_raw[];
+  const int nx = 2 * rx + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  c128* L = reinterpret_cast<c128*>(smem_raw);                // [nx][LSH] half plane
+  c128* Rw = L + nx * LSH + wave * RPW * LS;                  // this wave's [RPW][LS] row buffers
+  c128* TW = L + nx * LSH + NW * RPW * LS;                    // [N] twiddles W_N^k (forward sign)
+  int4* XL = reinterpret_cast<int4*>(smem_raw + half128_lines_bytes(nx));
+  const c128 zero = {0.0, 0.0};
+  for (int t = threadIdx.x; t < nx; t += blockDim.x) XL[t] = xline[t];
+  for (int t = threadIdx.x; t < N; t += blockDim.x) TW[t] = twg[t];
+
+  const int u2 = lane / N2, n2 = lane - u2 * N2;  // (line or row, n2 / kb)
+  const int u1 = lane / N1, a1 = lane - u1 * N1;  // (row, k1 / a) of stage B
+  const int uq = lane / H::G, aq = lane - uq * H::G;  // (line, group within the half) of stages A2 and C1
+  c128 twi[N1], twf[N2];
+  twi[0] = c128{1.0, 0.0};
+#pragma unroll
+  for (int k = 1; k < N1; ++k) {
+    const c128 w = twg[(n2 * k) % N];
+    twi[k] = c128{w.x, -w.y};
+  }
+#pragma unroll
+  for (int k = 1; k < N2; ++k) twf[k] = twg[(a1 * k) % N];
+  const int ngroups = (nx + GL - 1) / GL;
+  __syncthreads();
+
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int z = item % N;
+    const long cs = col_stride(ncol);
+    const long base = long(item / N) * N * cs + long(z) * cs;
+    const c128* in = cin + base;
+    c128* out = cout + base;
+    const T* Vz = Vt + long(z) * N * N;
+
+    for (int h = 0; h < 2; ++h) {
+      // ---- A: inverse y, the half's four groups ----
+      for (int g = wave; g < ngroups; g += NW) {
+        {
+          const int xi = g * GL + u2;
+          if (xi < nx) {
+            const int4 xl = XL[xi];  // {first column, lowest gy, column count, 0}
+            c128 v[N1];
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1) {
+              const int j = freq<N>(N2 * n1 + n2) - xl.y;
+              const bool ok = j >= 0 && j < xl.z;
+              const c128 x = in[xl.x + (ok ? j : 0)];
+              v[n1] = ok ? x : zero;
+            }
+            Dft<N1, +1>::run(v);
+            c128* p = L + xi * LSH + n2;
+            const bool hh = h != 0;
+#pragma unroll
+            for (int q = 0; q < H::G; ++q) {
+              // the half's output k1 = q + 4h and its twiddle, selected per component (a select of whole values
+              // goes through private memory)
+              const c128 x = {hh ? v[q + H::G].x : v[q].x, hh ? v[q + H::G].y : v[q].y};
+              const c128 w = {hh ? twi[q + H::G].x : twi[q].x, hh ? twi[q + H::G].y : twi[q].y};
+              p[PS * q] = cmul(x, w);
+            }
+          }
+        }
+        wave_sync();
+        {
+          const int xi = g * GL + uq;
+          if (uq < GL && xi < nx) {
+            c128* p = L + xi * LSH + PS * aq;
+            c128 v[N2];
+#pragma unroll
+            for (int b = 0; b < N2; ++b) v[b] = p[b];
+            Dft<N2, +1>::run(v);
+#pragma unroll
+            for (int b = 0; b < N2; ++b) p[b] = v[b];  // y = (aq + 4h) + N1 b
+          }
+        }
+      }
+      __syncthreads();
+
+      // ---- B: the half's 64 rows (row r: y = 4h + r % 4 + N1 (r / 4), slot PS (r % 4) + r / 4) ----
+      for (int r0 = wave * RPW; r0 < N / 2; r0 += NW * RPW) {
+        T vr[N2];
+        {
+          const int r = r0 + (u1 < RPW ? u1 : 0);
+          const int y = H::G * h + (r % H::G) + N1 * (r / H::G);
+          const T* Vrow = Vz + long(y) * N + a1;
+#pragma unroll
+          for (int b = 0; b < N2; ++b) vr[b] = Vrow[N1 * b];
+        }
+        if (u2 < RPW) {
+          const int r = r0 + u2, py = PS * (r % H::G) + r / H::G;
+          c128 v[N1];
+#pragma unroll
+          for (int n1 = 0; n1 < N1; ++n1) {
+            const int gx = freq<N>(N2 * n1 + n2);
+            const bool ok = gx >= -rx && gx <= rx;
+            const c128 x = L[(ok ? gx + rx : 0) * LSH + py];
+            v[n1] = ok ? x : zero;
+          }
+          Dft<N1, +1>::run(v);
+          c128* p = Rw + u2 * LS + n2;
+#pragma unroll
+          for (int k1 = 0; k1 < N1; ++k1) p[PS * k1] = k1 ? cmul(v[k1], twi[k1]) : v[0];
+        }
+        wave_sync();
+        if (u1 < RPW) {
+          c128* p = Rw + u1 * LS + PS * a1;
+          c128 v[N2];
+#pragma unroll
+          for (int b = 0; b < N2; ++b) v[b] = p[b];
+          Dft<N2, +1>::run(v);  // v[b] = psi(x = a1 + N1 b)
+#pragma unroll
+          for (int b = 0; b < N2; ++b) v[b] = c128{v[b].x * vr[b], v[b].y * vr[b]};
+          Dft<N2, -1>::run(v);
+#pragma unroll
+          for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], twf[kb]) : v[0];
+        }
+        wave_sync();
+        if (u2 < RPW) {
+          const int r = r0 + u2, py = PS * (r % H::G) + r / H::G;
+          const c128* p = Rw + u2 * LS + n2;
+          c128 v[N1];
+#pragma unroll
+          for (int a = 0; a < N1; ++a) v[a] = p[PS * a];
+          Dft<N1, -1>::run(v);
+#pragma unroll
+          for (int ka = 0; ka < N1; ++ka) {
+            const int gx = freq<N>(n2 + N2 * ka);
+            if (gx >= -rx && gx <= rx) L[(gx + rx) * LSH + py] = v[ka];
+          }
+        }
+        wave_sync();  // the row buffers are refilled by the next pass
+      }
+      __syncthreads();
+
+      // ---- C: forward y, this half's share ----
+      for (int g = wave; g < ngroups; g += NW) {
+        {
+          const int xi = g * GL + uq;
+          if (uq < GL && xi < nx) {
+            c128* p = L + xi * LSH + PS * aq;
+            const int a = aq + H::G * h;
+            c128 v[N2];
+#pragma unroll
+            for (int b = 0; b < N2; ++b) v[b] = p[b];
+            Dft<N2, -1>::run(v);
+#pragma unroll
+            for (int kb = 0; kb < N2; ++kb) p[kb] = kb ? cmul(v[kb], TW[(a * kb) % N]) : v[0];
+          }
+        }
+        wave_sync();
+        {
+          const int xi = g * GL + u2;
+          if (xi < nx) {
+            const int4 xl = XL[xi];
+            const c128* p = L + xi * LSH + n2;
+            c128 e[H::G], o[H::G];
+            static_for<0, H::G>([&](auto qc) {
+              constexpr int q = decltype(qc)::value;
+              e[q] = p[PS * q];
+              o[q] = twc<N1, q, -1>(e[q]);
+            });
+            Dft<H::G, -1>::run(e);  // Y[2k]
+            Dft<H::G, -1>::run(o);  // Y[2k + 1]
+#pragma unroll
+            for (int ka = 0; ka < N1; ++ka) {
+              const int j = freq<N>(n2 + N2 * ka) - xl.y;
+              if (j >= 0 && j < xl.z) {
+                c128 yv = (ka & 1) ? o[ka >> 1] : e[ka >> 1];
+                if (h == 0) {
+                  out[xl.x + j] = yv;
+                } else {
+                  if (ka & 1) yv = c128{-yv.x, -yv.y};
+                  out[xl.x + j] = out[xl.x + j] + yv;  // this lane stored the first half's share there
+                }
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();  // the next half (item) overwrites the half plane
+    }
+  }
+}
+
 // ---- band densities on the large boxes (N = 96, 128) ---------------------------------------------------------------
 // part[chunk][z][y][x] = sum over the chunk's bands b of w_b Re(conj(a_b(r)) psi_b(r)) (cross = 1) or w_b |a_b(r)|^2
 // (cross = 0). The cross term is taken as the difference of two densities, Re(conj(a) psi) =
@@ -740,27 +955,44 @@ hipError_t fft_col_inverse(const FftGeom& g, const cx<T>* tw, const cx<T>* X, lo
   });
 }
 
+hipError_t plane_half_launch(const FftGeom& g, const c128* tw, const double* Vt, const c128* cin, c128* cout, int nitems,
+                             hipStream_t st) {
+  const size_t lds = half128_lds(2 * g.rx + 1);
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  const int grid = int(std::min<long>(nitems, long(compute_units())));  // one block per CU (LDS)
+  hipLaunchKernelGGL(k_plane_half, dim3(grid), dim3(64 * Half128::NW), lds, st, g.ncol, g.rx, g.xline, tw, Vt, cin,
+                     cout, nitems);
+  return hipGetLastError();
+}
+hipError_t plane_half_launch(const FftGeom&, const c64*, const float*, const c64*, c64*, int, hipStream_t) {
+  return hipErrorInvalidConfiguration;  // FP32 plans keep the whole plane
+}
+
 template <typename T>
 hipError_t fft_plane(const FftGeom& g, const cx<T>* tw, const T* Vt, const cx<T>* cin, cx<T>* cout, int nb,
                      hipStream_t st) {
   if (nb <= 0) return hipSuccess;
   return dispatch_n(g.n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    const size_t lds = plane_lds<N, T>(2 * g.rx + 1);
-    if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-    // a persistent grid of as many blocks as stay resident (LDS and registers), so that no block starts its share
-    // of the items late and each loads its twiddles once
-    constexpr int threads = 64 * PlaneCfg<N, T>::NW;
     const int nitems = N * nb;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_plane<N, T>), threads,
-                                                     lds) != hipSuccess ||
-        per_cu <= 0)
-      per_cu = 1;
-    const int grid = int(std::min<long>(nitems, long(compute_units()) * per_cu));
-    hipLaunchKernelGGL((k_plane<N, T>), dim3(grid), dim3(threads), lds, st, g.ncol, g.rx, g.xline, tw, Vt, cin, cout,
-                       nitems);
-    return hipGetLastError();
+    if constexpr (N == 128 && std::is_same<T, double>::value) {  // the plane in two halves (see k_plane_half)
+      return plane_half_launch(g, tw, Vt, cin, cout, nitems, st);
+    } else {
+      const size_t lds = plane_lds<N, T>(2 * g.rx + 1);
+      if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+      // a persistent grid of as many blocks as stay resident (LDS and registers), so that no block starts its share
+      // of the items late and each loads its twiddles once
+      constexpr int threads = 64 * PlaneCfg<N, T>::NW;
+      int per_cu = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_plane<N, T>),
+                                                       threads, lds) != hipSuccess ||
+          per_cu <= 0)
+        per_cu = 1;
+      const int grid = int(std::min<long>(nitems, long(compute_units()) * per_cu));
+      hipLaunchKernelGGL((k_plane<N, T>), dim3(grid), dim3(threads), lds, st, g.ncol, g.rx, g.xline, tw, Vt, cin,
+                         cout, nitems);
+      return hipGetLastError();
+    }
   });
 }
 
@@ -782,7 +1014,8 @@ size_t fft_plane_lds_bytes(int n, int rx, bool dbl) {
   size_t out = 0;
   (void)dispatch_n(n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    out = dbl ? plane_lds<N, double>(2 * rx + 1) : plane_lds<N, float>(2 * rx + 1);
+    if (N == 128 && dbl) out = half128_lds(2 * rx + 1);
+    else out = dbl ? plane_lds<N, double>(2 * rx + 1) : plane_lds<N, float>(2 * rx + 1);
     return hipSuccess;
   });
   return out;
@@ -849,7 +1082,8 @@ hipError_t fft_prepare_attributes() {
   };
   auto each = [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    set(reinterpret_cast<const void*>(&k_plane<N, double>));
+    if constexpr (N == 128) set(reinterpret_cast<const void*>(&k_plane_half));
+    else set(reinterpret_cast<const void*>(&k_plane<N, double>));
     set(reinterpret_cast<const void*>(&k_plane<N, float>));
     if constexpr (N <= 64) {
       set(reinterpret_cast<const void*>(&k_xdens<N, double>));
