@@ -65,7 +65,8 @@ def test_free_electron_spectrum_on_gpu():
     assert np.all(np.abs(r[:7] - lam[:7]) < 1e-10)
 
 
-@pytest.mark.parametrize("n,radius", [(8, 3), (12, 2), (24, 11), (48, 6), (64, 8), (96, 10), (128, 12)])
+# (128, 40): the largest sphere whose x-lines fit the halved FP64 plane of the 128 box (81 x-lines)
+@pytest.mark.parametrize("n,radius", [(8, 3), (12, 2), (24, 11), (48, 6), (64, 8), (96, 10), (128, 12), (128, 40)])
 def test_other_box_sizes(n, radius):
     cfg = wl.SMALL["tiny_paw"].replace(name=f"box{n}", n=n, radius=radius, nb=9, seed_index=200 + n)
     pb = wl.make_problem(cfg)
