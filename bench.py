@@ -145,6 +145,8 @@ def class_roofline(name, d, kind, n):
     out["frac"] = out["achieved"] / out["peak"]
     tmpl = KERNEL_NAMES.get(name)
     out["kernel"] = tmpl[0 if kind == "f64" else 1].format(n=n) if tmpl else name
+    if name == "fft_plane" and kind == "f64" and n == 128:
+        out["kernel"] = "k_plane_half"  # the FP64 128^3 plane pass runs in two halves of the y residues
     out["avg_launch_us"] = per_launch_s * 1e6
     out["algo_per_launch"] = (d["flops"] if (name in GEMM_CLASSES or alu) else d["bytes"]) / d["launches"]
     out["launches"] = d["launches"]
