@@ -1,7 +1,7 @@
 """FP64 CPU oracle for Chebyshev-filtered subspace iteration (Levitt & Torrent, arXiv:1406.4350).
 
 TEST INFRASTRUCTURE ONLY. Nothing in the product path imports, links or runs this package: only the
-tests, the smoke check of the graft entry point and the cpu_baseline leg of the benchmark do.
+tests, ``__graft_entry__.smoke()`` and the cpu_baseline leg of ``bench.py`` do.
 
 It computes, slowly and plainly, what the GPU path computes:
 
