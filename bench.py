@@ -130,6 +130,9 @@ def class_roofline(name, d, kind, n):
         dt = "f16x3" if (kind == "f32" and name in ("project", "backproject")) else "f64"
         peak = PEAK_TFLOPS[dt]
         out = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "mfma_dtype": dt}
+        # flops the matrix cores execute per algorithmic flop: the FP64 tiles take 3 real products per complex
+        # product (6 of the 8 counted flops), the FP16 split products 3 FP16 products per useful one
+        out["executed_frac"] = achieved * (0.75 if dt == "f64" else 3.0) / peak
     else:
         achieved = d["bytes"] / d["launches"] / per_launch_s / 1e9
         out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}

@@ -20,6 +20,8 @@ def test_gemm_class_against_the_mfma_peak_of_its_arithmetic():
     assert r["achieved"] == pytest.approx(70.0)
     assert r["frac"] == pytest.approx(70.0 / 78.6)
     assert r["kernel"] == "k_gemm<double, double, double, double, 0, 1>"
+    assert r["executed_frac"] == pytest.approx(0.75 * 70.0 / 78.6)  # three real products per complex one
+    assert bench.class_roofline("project", d, "f32", 128)["executed_frac"] == pytest.approx(3 * 70.0 / 2500.0)
     # mixed plans: the split projector products against the FP16 MFMA peak, the Grams against FP64
     assert bench.class_roofline("project", d, "f32", 128)["peak"] == 2500.0
     assert bench.class_roofline("rr_gram", d, "f32", 128)["peak"] == 78.6
