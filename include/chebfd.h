@@ -146,6 +146,18 @@ cheb_status cheb_apply_H_noalloc(cheb_plan plan, const void* X, int ldx, void* Y
 cheb_status cheb_filter(cheb_plan plan, void* X, int ldx, int nb, int m, double c, double r, void* ws,
                         size_t ws_bytes, hipStream_t stream);
 
+/* cheb_filter starting from given projections: the reuse trick of Sec. 5.1 extended over the Rayleigh-Ritz
+ * step, so an outer iteration computes P^H X once (inside Rayleigh-Ritz) instead of once per call. p_in: the
+ * projections P^H X of the input block (device, nproj x nb complex FP64, column j = band j, leading dimension
+ * nproj), normally p_out of cheb_rayleigh_ritz_carry on the same block; used instead of computing them (a plain
+ * copy). Caller-owned and not modified; the block must not change between the call that produced p_in and this
+ * one. May be NULL when the plan has no projectors, nb = 0 or m = 0; else NULL gives CHEB_ERR_ARG. Results
+ * equal cheb_filter's up to the rounding in p_in. Projections carried in both directions with no recomputation
+ * in between would let the difference between X and its projections grow by the filter's amplification at every
+ * outer iteration, which is why the filter takes projections but returns none. Same workspace as cheb_filter. */
+cheb_status cheb_filter_carry(cheb_plan plan, void* X, int ldx, int nb, int m, double c, double r, const void* p_in,
+                              void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Locking (Sec. 5.4): the same filter with its own degree per band, X[:, b] <- T_{deg[b]}((S^-1 H - c)/r) X[:, b].
  * degrees: nb host int32 values >= 0; a band of degree 0 is left unchanged (locked). Bands are gathered in
  * order of decreasing degree into the workspace, step i of the recurrence runs on the bands of degree >= i
@@ -171,6 +183,15 @@ cheb_status cheb_locking_degrees(int nb, const double* ritz, const double* resid
  * CHEB_ERR_NONFINITE on NaN/Inf, CHEB_ERR_EIG if the eigensolver fails. */
 cheb_status cheb_rayleigh_ritz(cheb_plan plan, void* X, int ldx, int nb, double* ritz_dev, double* resid_dev,
                                void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* cheb_rayleigh_ritz that also returns the projections of the rotated block, p_out = (P^H X) Z, formed from the
+ * exact projections of the input block that the subspace matrices need anyway (with residuals the product is
+ * already there; without, one nproj x nb x nb FP64 GEMM). p_out: device, nproj x nb complex FP64, column j =
+ * band j, leading dimension nproj, caller-owned; NULL only when the plan has no projectors or nb = 0, else
+ * CHEB_ERR_ARG. In a mixed plan the rotated block is rounded to complex64 after the product, so p_out matches it
+ * to float32 rounding. Same workspace as cheb_rayleigh_ritz. */
+cheb_status cheb_rayleigh_ritz_carry(cheb_plan plan, void* X, int ldx, int nb, double* ritz_dev, double* resid_dev,
+                                     void* p_out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* LOBPCG, the block method the paper compares the filter with (Sec. 2.3), on the same operators: one
  * iteration per call. iteration = 0: Rayleigh-Ritz of X (start); 1: Rayleigh-Ritz in span[X, W]; >= 2: in

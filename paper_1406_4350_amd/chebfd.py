@@ -35,7 +35,7 @@ SYMBOLS = ["cheb_plan_persistent_bytes", "cheb_plan_create", "cheb_plan_destroy"
            "cheb_set_rr_refine", "cheb_rr_stats", "cheb_filter_degrees", "cheb_locking_degrees", "cheb_set_split_gemm",
            "cheb_set_capacitance_solver", "cheb_lobpcg_state_bytes", "cheb_lobpcg_iterate", "cheb_gemm_splits",
            "cheb_gemm_block_item", "cheb_set_projection_resync", "cheb_drift_monitor", "cheb_drift_read",
-           "cheb_apply_H_noalloc", "cheb_last_error"]
+           "cheb_apply_H_noalloc", "cheb_filter_carry", "cheb_rayleigh_ritz_carry", "cheb_last_error"]
 TIMERS = ["fft_col_inverse", "fft_plane", "fft_col_forward", "project", "backproject", "small", "rr_gram", "rr_eig",
           "rr_rotate", "xdens"]
 
@@ -79,6 +79,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cheb_apply_Sinv": [vp, vp, i, vp, i, i, vp, sz, vp],
         "cheb_filter": [vp, vp, i, i, i, d, d, vp, sz, vp],
         "cheb_rayleigh_ritz": [vp, vp, i, i, vp, vp, vp, sz, vp],
+        "cheb_filter_carry": [vp, vp, i, i, i, d, d, vp, vp, sz, vp],
+        "cheb_rayleigh_ritz_carry": [vp, vp, i, i, vp, vp, vp, vp, sz, vp],
         "cheb_rayleigh_quotients": [vp, vp, i, i, vp, vp, sz, vp],
         "cheb_upper_bound": [vp, i, vp, P(d), vp, sz, vp],
         "cheb_profile_enable": [vp, i],
@@ -278,12 +280,34 @@ class Plan:
     def apply_Sinv(self, X, Y=None):
         return self._apply("cheb_apply_Sinv", CHEB_OP_SINV, X, Y)
 
-    def filter(self, X, m: int, c: float, r: float):
+    def filter(self, X, m: int, c: float, r: float, p_in=None):
+        """X <- T_m((S^-1 H - c)/r) X. p_in: None, or the projections P^H X of the block (a complex128 (nb, nproj)
+        device tensor, row j = band j, e.g. p_out of rayleigh_ritz; see cheb_filter_carry)."""
         nb, ldx = self._block(X, "X")
         ws = self.workspace(CHEB_OP_FILTER, nb)
-        self._check(self.lib.cheb_filter(self.handle, X.data_ptr(), ldx, nb, int(m), float(c), float(r),
-                                         ws.data_ptr(), ws.numel(), _stream()), "cheb_filter")
+        if p_in is None:
+            self._check(self.lib.cheb_filter(self.handle, X.data_ptr(), ldx, nb, int(m), float(c), float(r),
+                                             ws.data_ptr(), ws.numel(), _stream()), "cheb_filter")
+            return X
+        self._check(self.lib.cheb_filter_carry(self.handle, X.data_ptr(), ldx, nb, int(m), float(c), float(r),
+                                               self._proj(p_in, nb), ws.data_ptr(), ws.numel(), _stream()),
+                    "cheb_filter_carry")
         return X
+
+    def projections(self, nb: int) -> torch.Tensor:
+        """A device buffer for the projections of nb bands (complex128 (nb, nproj)) that rayleigh_ritz returns
+        and filter takes."""
+        return torch.zeros((nb, max(self.nproj, 1)), dtype=torch.complex128, device=self.device)
+
+    def _proj(self, t, nb):
+        if t is None:
+            return None
+        if (t.dtype != torch.complex128 or t.device.type != "cuda" or not t.is_contiguous() or t.dim() != 2
+                or t.shape[0] != nb or t.shape[1] < self.nproj):
+            raise ValueError(f"projections must be a contiguous complex128 ({nb}, {self.nproj}) device tensor")
+        if self.nproj > 0 and t.shape[1] != self.nproj:
+            raise ValueError(f"projections must have {self.nproj} columns")
+        return t.data_ptr()
 
     def filter_degrees(self, X, degrees, c: float, r: float):
         """Per-band degrees (locking): X[b] <- T_{degrees[b]}((S^-1 H - c)/r) X[b]; degree 0 leaves a band as is."""
@@ -297,13 +321,22 @@ class Plan:
                     "cheb_filter_degrees")
         return X
 
-    def rayleigh_ritz(self, X, with_residuals: bool = True):
+    def rayleigh_ritz(self, X, with_residuals: bool = True, p_out=None):
+        """In-place Rayleigh-Ritz; returns (Ritz values, residual norms or None). p_out: None, or a complex128
+        (nb, nproj) device tensor that receives the projections P^H X of the rotated block (see
+        cheb_rayleigh_ritz_carry)."""
         nb, ldx = self._block(X, "X")
         ritz = torch.empty(nb, dtype=torch.float64, device=self.device)
         res = torch.empty(nb, dtype=torch.float64, device=self.device) if with_residuals else None
         ws = self.workspace(CHEB_OP_RR, nb)
-        self._check(self.lib.cheb_rayleigh_ritz(self.handle, X.data_ptr(), ldx, nb, ritz.data_ptr(), _ptr(res),
-                                                ws.data_ptr(), ws.numel(), _stream()), "cheb_rayleigh_ritz")
+        if p_out is None:
+            self._check(self.lib.cheb_rayleigh_ritz(self.handle, X.data_ptr(), ldx, nb, ritz.data_ptr(), _ptr(res),
+                                                    ws.data_ptr(), ws.numel(), _stream()), "cheb_rayleigh_ritz")
+        else:
+            self._check(self.lib.cheb_rayleigh_ritz_carry(self.handle, X.data_ptr(), ldx, nb, ritz.data_ptr(),
+                                                          _ptr(res), self._proj(p_out, nb), ws.data_ptr(),
+                                                          ws.numel(), _stream()),
+                        "cheb_rayleigh_ritz_carry")
         return ritz, res
 
     def rayleigh_quotients(self, X):

@@ -872,14 +872,20 @@ template <typename T> struct Ops {
     return CHEB_OK;
   }
 
-  // Alg. 2 inner loop for the whole block. psi^i overwrites psi^(i-2); buffers alternate X, W.
-  cheb_status filter(C* X, long ldx, int nb, int m, double c, double r, const Ws& w) {
+  // Alg. 2 inner loop for the whole block. psi^i overwrites psi^(i-2); buffers alternate X, W. With pin, the
+  // projections P^H X come from the caller (those the previous Rayleigh-Ritz step returned for its rotated block)
+  // instead of a product over the sphere (nproj x nb, ld nproj).
+  cheb_status filter(C* X, long ldx, int nb, int m, double c, double r, const Ws& w, const c128* pin = nullptr) {
     if (m == 0 || nb == 0) return CHEB_OK;
+    const int np = p->nproj;
     const long npw = p->npw;
     C* buf[2] = {X, static_cast<C*>(w.W)};
     long ld[2] = {ldx, npw};
     c128* pb[2] = {w.p0, w.p1};
-    if (p->nproj > 0) CHK(project(X, ldx, nb, pb[0], w));
+    if (np > 0) {
+      if (pin) HIPCHK(hipMemcpyAsync(pb[0], pin, size_t(np) * nb * sizeof(c128), hipMemcpyDeviceToDevice, st));
+      else CHK(project(X, ldx, nb, pb[0], w));
+    }
     for (int i = 1; i <= m; ++i) {
       const int ci = (i - 1) & 1, oi = i & 1;
       CHK(resync_step(i, buf[ci], ld[ci], pb[ci], buf[oi], ld[oi], pb[oi], nb, w));
@@ -1151,7 +1157,9 @@ template <typename T> struct Ops {
     return true;
   }
 
-  cheb_status rayleigh_ritz(C* X, long ldx, int nb, double* ritz, double* resid, const Ws& w) {
+  // pout: the projections of the rotated block, (P^H X) Z with the exact P^H X (nproj x nb, ld nproj)
+  cheb_status rayleigh_ritz(C* X, long ldx, int nb, double* ritz, double* resid, const Ws& w,
+                            c128* pout = nullptr) {
     const int np = p->nproj;
     const long npw = p->npw;
     CHK(subspace(X, ldx, nb, w));
@@ -1313,6 +1321,16 @@ template <typename T> struct Ops {
     Timed tr(p, st, CHEB_T_RR_ROTATE, 0.0, 0.0, false);
     if (resid) HIPCHK((col_resid_norms<T>(npw, nb, R, npw, Ynew, npw, ritz, resid, st)));
     HIPCHK((convert_copy<T, T>(npw, nb, Ynew, npw, X, ldx, st)));
+    if (pout && np > 0) {  // P^H (X Z) = (P^H X) Z, already formed for the residuals
+      if (resid) {
+        HIPCHK(hipMemcpyAsync(pout, w.q, size_t(np) * nb * sizeof(c128), hipMemcpyDeviceToDevice, st));
+      } else {
+        Epi<double> ez;
+        ez.out = pout; ez.ldo = np;
+        HIPCHK((gemm<double, double, double, double>(GEMM_NN, np, nb, nb, w.p0, np, w.Hs, nb, ez,
+                                                     gemm_pick_splits(np, nb, nb), w.part, st)));
+      }
+    }
     return CHEB_OK;
   }
 
@@ -2246,6 +2264,23 @@ cheb_status cheb_filter(cheb_plan p, void* X, int ldx, int nb, int m, double c, 
   return host_fail(p);
 }
 
+cheb_status cheb_filter_carry(cheb_plan p, void* X, int ldx, int nb, int m, double c, double r, const void* p_in,
+                              void* ws, size_t wsb, hipStream_t st) try {
+  if (!p) return CHEB_ERR_ARG;
+  CHK(check_block(p, X, ldx, nb, "X"));
+  if (m < 0) return fail(p, CHEB_ERR_ARG, "degree m < 0");
+  if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite(c)) return fail(p, CHEB_ERR_ARG, "need finite c and r > 0");
+  if (nb > 0 && m > 0 && p->nproj > 0 && !p_in) return fail(p, CHEB_ERR_ARG, "p_in is null");
+  if (nb == 0) return CHEB_OK;
+  OP_PRELUDE(CHEB_OP_FILTER, nb);
+  return with_prec(p, st, [&](auto ops) {
+    using C = typename decltype(ops)::C;
+    return ops.filter(static_cast<C*>(X), ldx, nb, m, c, r, w, static_cast<const c128*>(p_in));
+  });
+} catch (...) {
+  return host_fail(p);
+}
+
 cheb_status cheb_filter_degrees(cheb_plan p, void* X, int ldx, int nb, const int32_t* degrees, double c, double r,
                                 void* ws, size_t wsb, hipStream_t st) try {
   if (!p) return CHEB_ERR_ARG;
@@ -2352,6 +2387,22 @@ cheb_status cheb_rayleigh_ritz(cheb_plan p, void* X, int ldx, int nb, double* ri
   return with_prec(p, st, [&](auto ops) {
     using C = typename decltype(ops)::C;
     return ops.rayleigh_ritz(static_cast<C*>(X), ldx, nb, ritz, resid, w);
+  });
+} catch (...) {
+  return host_fail(p);
+}
+
+cheb_status cheb_rayleigh_ritz_carry(cheb_plan p, void* X, int ldx, int nb, double* ritz, double* resid,
+                                     void* p_out, void* ws, size_t wsb, hipStream_t st) try {
+  if (!p) return CHEB_ERR_ARG;
+  CHK(check_block(p, X, ldx, nb, "X"));
+  if (nb > 0 && !ritz) return fail(p, CHEB_ERR_ARG, "ritz is null");
+  if (nb > 0 && p->nproj > 0 && !p_out) return fail(p, CHEB_ERR_ARG, "p_out is null");
+  if (nb == 0) return CHEB_OK;
+  OP_PRELUDE(CHEB_OP_RR, nb);
+  return with_prec(p, st, [&](auto ops) {
+    using C = typename decltype(ops)::C;
+    return ops.rayleigh_ritz(static_cast<C*>(X), ldx, nb, ritz, resid, w, static_cast<c128*>(p_out));
   });
 } catch (...) {
   return host_fail(p);

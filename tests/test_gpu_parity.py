@@ -90,16 +90,78 @@ def test_rayleigh_quotients_and_bound(case):
     assert abs(lp - lp_ref) <= 1e-10 * max(abs(lp_ref), 1.0)
 
 
-def test_outer_loop_trajectory(case):
+@pytest.mark.parametrize("carry", [False, True], ids=["recomputed", "carried"])
+def test_outer_loop_trajectory(case, carry):
+    """The outer loop against the oracle's; with carry, the projections P^H X go from each filter and
+    Rayleigh-Ritz call to the next instead of being recomputed (the oracle recomputes them every step)."""
     pb, ops, plan = case
     iters = min(pb.cfg.iters, 6)
     lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
     lam_o, _, res_o, hist_o = matfree.chebfsi(ops, pb.X0, pb.cfg.m, iters, lp)
     Xd = cf.to_device_block(pb.X0, torch.complex128)
-    ritz, res, hist = chebfsi(plan, Xd, pb.cfg.m, iters, lp)
+    ritz, res, hist = chebfsi(plan, Xd, pb.cfg.m, iters, lp, carry=carry)
     for ho, hg in zip(hist_o, hist):
         assert abs(ho["lam_minus"] - hg["lam_minus"]) <= 1e-10 * max(abs(ho["lam_minus"]), 1.0)
         assert np.all(np.abs(hg["ritz"] - ho["ritz"]) <= 1e-10 * np.maximum(np.abs(ho["ritz"]), 1.0))
+
+
+def test_carried_projections_match_recomputed(case):
+    """cheb_rayleigh_ritz_carry returns P^H of its rotated block, with and without residuals; cheb_filter_carry
+    started from those projections equals cheb_filter, in FP64 and in mixed plans."""
+    pb, ops, plan = case
+    nb, m = pb.cfg.nb, pb.cfg.m
+    lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
+    lm = float(np.max(matfree.rayleigh_quotients(ops, pb.X0)))
+    c, r = 0.5 * (lp + lm), 0.5 * (lp - lm)
+    PH = ops.P.conj().T if pb.nproj > 0 else None
+    for with_res in (True, False):
+        X = cf.to_device_block(pb.X0, torch.complex128)
+        Xr = cf.to_device_block(pb.X0, torch.complex128)
+        pz = plan.projections(nb)
+        ra, _ = plan.rayleigh_ritz(Xr, with_residuals=with_res)
+        rb, _ = plan.rayleigh_ritz(X, with_residuals=with_res, p_out=pz)
+        assert torch.equal(ra, rb) and torch.equal(X, Xr)
+        if PH is not None:
+            assert _rel(pz.cpu().numpy().T, PH @ cf.to_host_block(X)) < 1e-12
+    # the filter from the returned projections against the filter that computes them, and the oracle
+    Xa = X.clone()
+    plan.filter(Xa, m, c, r)
+    plan.filter(X, m, c, r, p_in=pz)
+    assert _rel(cf.to_host_block(X), cf.to_host_block(Xa)) < 1e-11
+    assert _rel(cf.to_host_block(X), matfree.chebyshev_filter(ops, cf.to_host_block(Xr), m, c, r)) < 1e-11
+    # m = 0 leaves the block as it is
+    Xa.copy_(X)
+    plan.filter(Xa, 0, c, r, p_in=pz)
+    assert torch.equal(Xa, X)
+    # mixed plan: the FP64 projections of the rotated complex64 block start the filter
+    pm = cf.plan_from_problem(pb, cf.CHEB_MIXED)
+    Xm = cf.to_device_block(pb.X0, torch.complex64)
+    pzm = pm.projections(nb)
+    pm.rayleigh_ritz(Xm, p_out=pzm)
+    Y = cf.to_host_block(Xm)
+    if PH is not None:
+        assert _rel(pzm.cpu().numpy().T, PH @ Y) < 1e-6
+    ref = matfree.chebyshev_filter(ops, Y, m, c, r)
+    Xn = Xm.clone()
+    pm.filter(Xn, m, c, r)
+    pm.filter(Xm, m, c, r, p_in=pzm)
+    assert _rel(cf.to_host_block(Xn), ref) < 1e-4
+    assert _rel(cf.to_host_block(Xm), ref) < 1e-4
+    # wrong buffers are refused by the binding, missing ones by the library when the plan has projectors
+    with pytest.raises(ValueError):
+        plan.filter(X, m, c, r, p_in=pz.to(torch.complex64))
+    with pytest.raises(ValueError):
+        plan.rayleigh_ritz(X, p_out=pz[: nb - 1])
+    if PH is not None:
+        ws = plan.workspace(cf.CHEB_OP_FILTER, nb)
+        st = plan.lib.cheb_filter_carry(plan.handle, X.data_ptr(), X.shape[1], nb, m, c, r, None, ws.data_ptr(),
+                                        ws.numel(), cf._stream())
+        assert st == cf.CHEB_ERR_ARG
+        ritz = torch.empty(nb, dtype=torch.float64, device=X.device)
+        ws = plan.workspace(cf.CHEB_OP_RR, nb)
+        st = plan.lib.cheb_rayleigh_ritz_carry(plan.handle, X.data_ptr(), X.shape[1], nb, ritz.data_ptr(), None,
+                                               None, ws.data_ptr(), ws.numel(), cf._stream())
+        assert st == cf.CHEB_ERR_ARG
 
 
 @pytest.mark.parametrize("split", [True, False], ids=["fp16x2-split", "fp32-mfma"])
