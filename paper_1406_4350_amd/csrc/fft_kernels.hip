@@ -393,8 +393,17 @@ __global__ __launch_bounds__(64 * Half128::NW) void k_plane_half(int ncol, int r
   }
 #pragma unroll
   for (int k = 1; k < N2; ++k) twf[k] = twg[(a1 * k) % N];
-  const int ngroups = (nx + GL - 1) / GL;
   __syncthreads();
+  // The outermost x-lines (gx = -rx, rx) of a sphere of integer radius hold one column, at gy = 0: their inverse y
+  // transform is that value on every y, and their one forward output (gy = 0) the sum over y. They are set and
+  // summed by the last wave directly, and the others go through the transforms in groups of GL, 63 lines in 16
+  // groups at 128^3 (two per wave) instead of 65 in 17 (a third round on one wave).
+  const int trim = (nx >= 3 && XL[0].z == 1 && XL[0].y == 0 && XL[nx - 1].z == 1 && XL[nx - 1].y == 0) ? 1 : 0;
+  const int xend = nx - trim;  // lines trim .. xend - 1 take the transforms
+  const int ngroups = (xend - trim + GL - 1) / GL;
+  const bool edge_wave = trim && wave == NW - 1;  // a wave with no more groups than any other
+  const int et = lane >> 5, es = lane & 31;        // edge line (0: gx = -rx, 1: gx = rx) and slot of a lane
+  const int exi = et ? nx - 1 : 0;
 
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int z = item % N;
@@ -408,8 +417,8 @@ __global__ __launch_bounds__(64 * Half128::NW) void k_plane_half(int ncol, int r
       // ---- A: inverse y, the half's four groups ----
       for (int g = wave; g < ngroups; g += NW) {
         {
-          const int xi = g * GL + u2;
-          if (xi < nx) {
+          const int xi = trim + g * GL + u2;
+          if (xi < xend) {
             const int4 xl = XL[xi];  // {first column, lowest gy, column count, 0}
             c128 v[N1];
 #pragma unroll
@@ -434,8 +443,8 @@ __global__ __launch_bounds__(64 * Half128::NW) void k_plane_half(int ncol, int r
         }
         wave_sync();
         {
-          const int xi = g * GL + uq;
-          if (uq < GL && xi < nx) {
+          const int xi = trim + g * GL + uq;
+          if (uq < GL && xi < xend) {
             c128* p = L + xi * LSH + PS * aq;
             c128 v[N2];
 #pragma unroll
@@ -445,6 +454,12 @@ __global__ __launch_bounds__(64 * Half128::NW) void k_plane_half(int ncol, int r
             for (int b = 0; b < N2; ++b) p[b] = v[b];  // y = (aq + 4h) + N1 b
           }
         }
+      }
+      if (edge_wave) {  // the edge lines: their one value on the half's 64 slots PS q + b, two slots per lane
+        const c128 c = in[XL[exi].x];
+        c128* p = L + exi * LSH;
+#pragma unroll
+        for (int e = es; e < H::G * N2; e += 32) p[PS * (e / N2) + e % N2] = c;
       }
       __syncthreads();
 
@@ -507,8 +522,8 @@ __global__ __launch_bounds__(64 * Half128::NW) void k_plane_half(int ncol, int r
       // ---- C: forward y, this half's share ----
       for (int g = wave; g < ngroups; g += NW) {
         {
-          const int xi = g * GL + uq;
-          if (uq < GL && xi < nx) {
+          const int xi = trim + g * GL + uq;
+          if (uq < GL && xi < xend) {
             c128* p = L + xi * LSH + PS * aq;
             const int a = aq + H::G * h;
             c128 v[N2];
@@ -521,8 +536,8 @@ __global__ __launch_bounds__(64 * Half128::NW) void k_plane_half(int ncol, int r
         }
         wave_sync();
         {
-          const int xi = g * GL + u2;
-          if (xi < nx) {
+          const int xi = trim + g * GL + u2;
+          if (xi < xend) {
             const int4 xl = XL[xi];
             const c128* p = L + xi * LSH + n2;
             c128 e[H::G], o[H::G];
@@ -547,6 +562,20 @@ __global__ __launch_bounds__(64 * Half128::NW) void k_plane_half(int ncol, int r
               }
             }
           }
+        }
+      }
+      if (edge_wave) {  // the edge lines: the sum over the half's 64 y values, 32 lanes per line
+        const c128* p = L + exi * LSH;
+        c128 acc = p[PS * (es / N2) + es % N2] + p[PS * ((es + 32) / N2) + (es + 32) % N2];
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) {
+          acc.x += __shfl_xor(acc.x, o, 64);
+          acc.y += __shfl_xor(acc.y, o, 64);
+        }
+        if (es == 0) {
+          const int c = XL[exi].x;
+          if (h == 0) out[c] = acc;
+          else out[c] = out[c] + acc;  // this lane stored the first half's sum there
         }
       }
       __syncthreads();  // the next half (item) overwrites the half plane

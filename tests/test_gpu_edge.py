@@ -78,6 +78,29 @@ def test_other_box_sizes(n, radius):
         assert _rel(cf.to_host_block(plan.apply_H(Xd)), ops.apply_H(pb.X0)) < tol
 
 
+def test_box128_without_single_column_edge_lines():
+    """A sphere of integer radius has one column (gy = 0) on each outermost x-line, which the FP64 plane pass at
+    128^3 sets and sums directly; without the points (+-R, 0, 0) the basis has no such lines and every x-line
+    takes the transforms. Both forms against the oracle, FP64 and mixed."""
+    import dataclasses
+
+    cfg = wl.SMALL["tiny_paw"].replace(name="box128e", n=128, radius=12, nb=9, seed_index=329)
+    full = wl.make_problem(cfg)
+    g = full.gidx
+    keep = ~((np.abs(g[:, 0]) == 12) & (g[:, 1] == 0) & (g[:, 2] == 0))
+    assert keep.sum() == full.npw - 2
+    cut = dataclasses.replace(full, gidx=np.ascontiguousarray(g[keep]), kin=full.kin[keep],
+                              P=np.asfortranarray(full.P[keep]), X0=np.asfortranarray(full.X0[keep]),
+                              v0=full.v0[keep])
+    for pb in (full, cut):
+        ops = matfree.Operators.from_problem(pb)
+        ref = ops.apply_H(pb.X0)
+        for prec, tol in ((cf.CHEB_FP64, 1e-12), (cf.CHEB_MIXED, 2e-5)):
+            plan = cf.plan_from_problem(pb, prec)
+            dt = torch.complex64 if prec == cf.CHEB_MIXED else torch.complex128
+            assert _rel(cf.to_host_block(plan.apply_H(cf.to_device_block(pb.X0, dt))), ref) < tol
+
+
 def test_error_paths(tiny):
     pb, ops, plan = tiny
     Xd = cf.to_device_block(pb.X0, torch.complex128)
