@@ -289,7 +289,20 @@ int fft_batch_for(const cheb_plan_s* p, int nb) {
   const size_t per_band = size_t(p->n) * col_stride(p->ncol) * elem_bytes(p->prec);
   size_t cap = (96u << 20) / std::max<size_t>(per_band, 1);
   if (cap < 1) cap = 1;
-  return int(std::min<size_t>(size_t(std::max(nb, 1)), cap));
+  if (size_t(std::max(nb, 1)) <= cap) return std::max(nb, 1);
+  // The plane pass takes n (z-plane, transform) items per transform on its resident blocks in rounds; of the
+  // batches from cap / 2 to cap, take the one with the fewest rounds per band (the largest on a tie), so that the
+  // last round of a launch does not leave blocks idle (15 bands at 128^3 FP64 are 1920 items on 256 blocks, 7.5
+  // rounds; 14 are 7).
+  const long R = std::max(1, fft_plane_blocks(p->n, p->rx, p->prec == CHEB_FP64));
+  const int per = p->gamma ? 2 : 1;  // bands per transform
+  long best = long(cap), best_rounds = 0;
+  for (long b = long(cap); b >= std::max<long>(1, long(cap) / 2); --b) {
+    const long items = long(p->n) * ((b + per - 1) / per);
+    const long rounds = (items + R - 1) / R;
+    if (b == long(cap) || rounds * best < best_rounds * b) { best = b; best_rounds = rounds; }
+  }
+  return int(best);
 }
 
 cheb_status solver_query(cheb_plan p, int op, int nb, size_t* bytes);

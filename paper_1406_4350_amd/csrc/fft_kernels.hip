@@ -997,6 +997,27 @@ hipError_t plane_half_launch(const FftGeom&, const c64*, const float*, const c64
   return hipErrorInvalidConfiguration;  // FP32 plans keep the whole plane
 }
 
+// resident blocks of k_plane<N, T> on the device (LDS and registers): the persistent grid of the plane pass
+template <int N, typename T> int plane_resident_blocks(int rx) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_plane<N, T>),
+                                                   64 * PlaneCfg<N, T>::NW, plane_lds<N, T>(2 * rx + 1)) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  return compute_units() * per_cu;
+}
+
+int fft_plane_blocks(int n, int rx, bool dbl) {
+  int out = compute_units();
+  (void)dispatch_n(n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    if (N == 128 && dbl) out = compute_units();  // k_plane_half: one block per CU
+    else out = dbl ? plane_resident_blocks<N, double>(rx) : plane_resident_blocks<N, float>(rx);
+    return hipSuccess;
+  });
+  return out;
+}
+
 template <typename T>
 hipError_t fft_plane(const FftGeom& g, const cx<T>* tw, const T* Vt, const cx<T>* cin, cx<T>* cout, int nb,
                      hipStream_t st) {
@@ -1012,12 +1033,7 @@ hipError_t fft_plane(const FftGeom& g, const cx<T>* tw, const T* Vt, const cx<T>
       // a persistent grid of as many blocks as stay resident (LDS and registers), so that no block starts its share
       // of the items late and each loads its twiddles once
       constexpr int threads = 64 * PlaneCfg<N, T>::NW;
-      int per_cu = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_plane<N, T>),
-                                                       threads, lds) != hipSuccess ||
-          per_cu <= 0)
-        per_cu = 1;
-      const int grid = int(std::min<long>(nitems, long(compute_units()) * per_cu));
+      const int grid = int(std::min<long>(nitems, long(plane_resident_blocks<N, T>(g.rx))));
       hipLaunchKernelGGL((k_plane<N, T>), dim3(grid), dim3(threads), lds, st, g.ncol, g.rx, g.xline, tw, Vt, cin,
                          cout, nitems);
       return hipGetLastError();

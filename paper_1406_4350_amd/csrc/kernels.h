@@ -106,6 +106,8 @@ size_t cross_density_part_doubles(int n, int nband);
 size_t fft_xdens_lds_bytes(int n, int rx, bool dbl);
 // dynamic LDS bytes of the plane pass for box n, x-line half-width rx (0 if n unsupported)
 size_t fft_plane_lds_bytes(int n, int rx, bool dbl);
+// blocks of the plane pass resident on the current device at once (its persistent grid for large batches)
+int fft_plane_blocks(int n, int rx, bool dbl);
 // Row stride (in elements) of the disk-column buffers [band][z][column]: the column count rounded up to 16, so
 // that every z-row starts on a 128-byte line (the column passes read 16 or 32 neighbouring columns of a row)
 __host__ __device__ inline int col_stride(int ncol) { return (ncol + 15) & ~15; }
