@@ -275,6 +275,8 @@ struct Ws {
   float* bsc = nullptr;  // per-band power-of-two scales of the split GEMMs
   _Float16* hb = nullptr;  // mixed plans: the back-projection's projector-space operand split into FP16 planes
   long hb_ld = 0;
+  _Float16* hx = nullptr;  // mixed plans, filters: the projected bands split into FP16 planes
+  long hx_ld = 0;
   c128 *cp = nullptr, *cq = nullptr, *cr = nullptr;  // iterative capacitance solve: right side, solution, residual
   c128* pfresh = nullptr;  // projections recomputed from the vectors (drift monitor)
   double* dcol = nullptr;  // per-band relative drift
@@ -452,6 +454,10 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
   if (p->prec == CHEB_MIXED && np > 0) {
     w->hb_ld = ((np + 31) / 32) * 32;
     w->hb = b.take<_Float16>(4 * size_t(std::max(nb, 1)) * w->hb_ld);
+    if (op == CHEB_OP_FILTER || op == CHEB_OP_FILTER_DEGREES) {
+      w->hx_ld = ((long(p->npw) + 31) / 32) * 32;
+      w->hx = b.take<_Float16>(4 * size_t(std::max(nb, 1)) * w->hx_ld);
+    }
   }
   if (p->has_overlap && p->cap_iters > 0 && op != CHEB_OP_SETUP && op != CHEB_OP_RR) {
     w->cp = b.take<c128>(pp);
@@ -693,8 +699,21 @@ template <typename T> struct Ops {
     } else if (use_split()) {
       if constexpr (std::is_same<T, float>::value) {
         HIPCHK(column_scales<float>(p->npw, nb, X, ldx, w.bsc, st));
-        HIPCHK((gemm_h<float, double>(GEMM_CN, p->nproj, nb, p->npw, p->hproj, X, ldx, w.bsc, e,
-                                      gemm_h_pick_splits(p->nproj, nb, p->npw), w.part, st, ROLE_PROJECT)));
+        const int splits = gemm_h_pick_splits(p->nproj, nb, p->npw);
+        if (w.hx) {
+          // the filters' workspaces hold the bands split once into FP16 planes (the same values the GEMM would
+          // split on the fly), which the GEMM then reads as plain 16-byte rows
+          HIPCHK(split_columns(p->npw, nb, X, ldx, w.bsc, w.hx, w.hx_ld, st));
+          HalfPlanes xp;
+          xp.p = w.hx;
+          xp.rows = nb;
+          xp.ld = w.hx_ld;
+          HIPCHK((gemm_h_pre<double>(GEMM_CN, p->nproj, nb, p->npw, p->hproj, xp, w.bsc, e, splits, w.part, st,
+                                     ROLE_PROJECT)));
+        } else {
+          HIPCHK((gemm_h<float, double>(GEMM_CN, p->nproj, nb, p->npw, p->hproj, X, ldx, w.bsc, e, splits, w.part,
+                                        st, ROLE_PROJECT)));
+        }
       }
     } else {
       HIPCHK((gemm<T, T, T, double>(GEMM_CN, p->nproj, nb, p->npw, P(), p->npw, X, ldx, e,
@@ -719,7 +738,8 @@ template <typename T> struct Ops {
         bp.p = w.hb;
         bp.rows = nb;
         bp.ld = w.hb_ld;
-        HIPCHK((gemm_h_pre<float>(GEMM_NN, p->npw, nb, p->nproj, p->hback, bp, w.bsc, e, st, ROLE_BACKPROJECT)));
+        HIPCHK((gemm_h_pre<float>(GEMM_NN, p->npw, nb, p->nproj, p->hback, bp, w.bsc, e, 1, nullptr, st,
+                                  ROLE_BACKPROJECT)));
       }
     } else {
       HIPCHK((gemm<T, T, double, T>(GEMM_NN, p->npw, nb, p->nproj, P(), p->npw, wv, ldw, e, 1, nullptr, st,

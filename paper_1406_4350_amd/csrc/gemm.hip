@@ -669,14 +669,15 @@ __global__ void k_split_planes(const c128* __restrict__ X, long ldx, int ksrc, b
   }
 }
 
-__global__ void k_split_columns(int K, int N, const c128* __restrict__ B, long ldb, const float* __restrict__ bsc,
+template <typename E>
+__global__ void k_split_columns(int K, int N, const cx<E>* __restrict__ B, long ldb, const float* __restrict__ bsc,
                                 _Float16* __restrict__ P, long pld) {
   const long total = long(N) * pld;
   for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
     const long n = t / pld, k = t - n * pld;
-    c128 v = {0.0, 0.0};
+    cx<E> v = {E(0), E(0)};
     if (k < K) v = B[k + n * ldb];
-    const double sc = double(bsc[n]);  // the same operations as the on-the-fly split in k_gemm_h
+    const E sc = E(bsc[n]);  // the same operations as the on-the-fly split in k_gemm_h
     const float xr = float(v.x * sc), xi = float(v.y * sc);
     const _Float16 hr = _Float16(xr), hi = _Float16(xi);
     P[t] = hr;
@@ -886,35 +887,51 @@ hipError_t gemm_h(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const
   return hipGetLastError();
 }
 
-hipError_t split_columns(int K, int N, const c128* B, long ldb, const float* bscale, _Float16* planes, long pld,
-                         hipStream_t st) {
+template <typename E>
+hipError_t split_columns_t(int K, int N, const cx<E>* B, long ldb, const float* bscale, _Float16* planes, long pld,
+                           hipStream_t st) {
   if (N <= 0) return hipSuccess;
   if (K < 0 || pld < K || pld % HBK || ldb < K) return hipErrorInvalidValue;
   const long total = long(N) * pld;
   const long blocks = std::min<long>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_split_columns, dim3(unsigned(blocks)), dim3(256), 0, st, K, N, B, ldb, bscale, planes, pld);
+  hipLaunchKernelGGL((k_split_columns<E>), dim3(unsigned(blocks)), dim3(256), 0, st, K, N, B, ldb, bscale, planes,
+                     pld);
   return hipGetLastError();
+}
+hipError_t split_columns(int K, int N, const c128* B, long ldb, const float* bscale, _Float16* planes, long pld,
+                         hipStream_t st) {
+  return split_columns_t<double>(K, N, B, ldb, bscale, planes, pld, st);
+}
+hipError_t split_columns(int K, int N, const c64* B, long ldb, const float* bscale, _Float16* planes, long pld,
+                         hipStream_t st) {
+  return split_columns_t<float>(K, N, B, ldb, bscale, planes, pld, st);
 }
 
 template <typename EO>
 hipError_t gemm_h_pre(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const HalfPlanes& Bp,
-                      const float* bscale, const Epi<EO>& epi, hipStream_t st, GemmRole role) {
+                      const float* bscale, const Epi<EO>& epi, int splits, c128* part, hipStream_t st, GemmRole role) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const long kp = ((std::max(K, 0) + HBK - 1) / HBK) * HBK;
   if (!A.p || A.rows < M || A.ld % HBK || A.ld < kp) return hipErrorInvalidValue;
   if (!Bp.p || Bp.rows != N || Bp.ld % HBK || Bp.ld < kp) return hipErrorInvalidValue;
   int tb = 64, s = 1;
-  h_plan(M, N, K, false, &tb, &s);
-  int kchunk = std::max<int>(HBK, int(kp));
+  h_plan(M, N, K, splits > 1, &tb, &s);
+  if (splits < 1) splits = 1;
+  int kchunk = (K + splits - 1) / splits;
+  kchunk = ((kchunk + HBK - 1) / HBK) * HBK;
+  if (kchunk < HBK) kchunk = HBK;
+  splits = K > 0 ? (K + kchunk - 1) / kchunk : 1;
+  const bool use_part = splits > 1;
+  if (use_part && !part) return hipErrorInvalidValue;
   Epi<EO> en = epi;
   const int ne = epi_slots(en);
   const cx<double>* nb64 = nullptr;
-  c128* np = nullptr;
+  c128* np = use_part ? part : nullptr;
   auto launch = [&](auto tbc, auto modec, auto rolec) {
     constexpr int T = decltype(tbc)::value, MO = decltype(modec)::value, RO = decltype(rolec)::value;
-    const dim3 grid(((M + T - 1) / T) * ((N + T - 1) / T)), block(HTile<T>::NT);
+    const dim3 grid(((M + T - 1) / T) * ((N + T - 1) / T) * splits), block(HTile<T>::NT);
     const int grp = tile_group(M, K);
-    if (ne == 0)
+    if (ne == 0 || use_part)
       hipLaunchKernelGGL((k_gemm_h<T, double, EO, MO, RO, 0, true>), grid, block, 0, st, M, N, K, kchunk, A.p,
                          A.rows, A.ld, A.inv_scale, nb64, 0L, Bp.p, Bp.rows, Bp.ld, bscale, en, np, grp);
     else if (ne == 1)
@@ -934,6 +951,12 @@ hipError_t gemm_h_pre(GemmMode mode, int M, int N, int K, const HalfPlanes& A, c
   };
   if (role == ROLE_BACKPROJECT) mode == GEMM_CN ? by_tile(CN{}, R2{}) : by_tile(NNm{}, R2{});
   else mode == GEMM_CN ? by_tile(CN{}, R1{}) : by_tile(NNm{}, R1{});
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !use_part) return e;
+  const long total = long(M) * N;
+  int blocks = int((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((k_reduce<EO>), dim3(blocks), dim3(256), 0, st, M, N, splits, part, epi);
   return hipGetLastError();
 }
 
@@ -969,7 +992,9 @@ template hipError_t gemm_h<float, double>(GemmMode, int, int, int, const HalfPla
 template hipError_t gemm_h<double, float>(GemmMode, int, int, int, const HalfPlanes&, const c128*, long,
                                           const float*, const Epi<float>&, int, c128*, hipStream_t, GemmRole);
 template hipError_t gemm_h_pre<float>(GemmMode, int, int, int, const HalfPlanes&, const HalfPlanes&, const float*,
-                                       const Epi<float>&, hipStream_t, GemmRole);
+                                       const Epi<float>&, int, c128*, hipStream_t, GemmRole);
+template hipError_t gemm_h_pre<double>(GemmMode, int, int, int, const HalfPlanes&, const HalfPlanes&, const float*,
+                                        const Epi<double>&, int, c128*, hipStream_t, GemmRole);
 template hipError_t column_scales<float>(long, int, const c64*, long, float*, hipStream_t);
 template hipError_t column_scales<double>(long, int, const c128*, long, float*, hipStream_t);
 

@@ -57,10 +57,13 @@ hipError_t gemm_h(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const
 // Im hi, Im lo; zero for K <= k < pld), pld >= K a multiple of 32
 hipError_t split_columns(int K, int N, const c128* B, long ldb, const float* bscale, _Float16* planes, long pld,
                          hipStream_t st);
-// gemm_h with B given as such planes (Bp.rows = N, Bp.ld = pld, Bp.inv_scale unused); no split-K
+hipError_t split_columns(int K, int N, const c64* B, long ldb, const float* bscale, _Float16* planes, long pld,
+                         hipStream_t st);
+// gemm_h with B given as such planes (Bp.rows = N, Bp.ld = pld, Bp.inv_scale unused); splits > 1 sums split-K
+// partials in part as gemm_h does (same results as gemm_h with the same splits)
 template <typename EO>
 hipError_t gemm_h_pre(GemmMode mode, int M, int N, int K, const HalfPlanes& A, const HalfPlanes& Bp,
-                      const float* bscale, const Epi<EO>& epi, hipStream_t st, GemmRole role);
+                      const float* bscale, const Epi<EO>& epi, int splits, c128* part, hipStream_t st, GemmRole role);
 int gemm_h_pick_splits(int M, int N, int K);
 // upper bound of both split rules, for sizing split-K partial buffers
 int gemm_split_bound(int M, int N, int K);
