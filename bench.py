@@ -38,7 +38,7 @@ FFT_CLASSES = ("fft_col_inverse", "fft_plane", "fft_col_forward")
 # kernel names as rocprofv3 reports them, per timer class and precision
 KERNEL_NAMES = {  # kernel of each timer class, FP64 / mixed plan
     "backproject": ("k_gemm<double, double, double, double, 1, 2>", "k_gemm_h<double, float, 1, 2>"),
-    "project": ("k_gemm<double, double, double, double, 0, 1>", "k_gemm_h<float, double, 0, 1>"),
+    "project": ("k_gemm<double, double, double, double, 0, 1>", "k_gemm_h<double, double, 0, 1>"),
     "fft_plane": ("k_plane<{n}, double>", "k_plane<{n}, float>"),
     "fft_col_inverse": ("k_col_inv<{n}, double>", "k_col_inv<{n}, float>"),
     "fft_col_forward": ("k_col_fwd<{n}, double>", "k_col_fwd<{n}, float>"),
