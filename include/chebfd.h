@@ -312,8 +312,10 @@ cheb_status cheb_gemm_splits(int M, int N, int K, int* fp64, int* fp16, int* bou
  * tm x tn tiles per split: the blocks are dealt to the 8 XCDs in turn and each XCD receives one contiguous run
  * of items, so that blocks sharing an operand slice share an L2. Items are ordered split by split, in groups of
  * `group` M tiles, the M tile fastest inside a group (group 1: the N tile fastest). The GEMMs use group 8 when
- * K >= M and group 1 otherwise. Host arithmetic only. CHEB_ERR_ARG unless 0 <= i < total, total a multiple of
- * tm * tn > 0, group >= 1 and the pointers non-null. */
+ * K >= M and group 1 otherwise. group = -1: the order of the Hermitian products (the Rayleigh-Ritz matrices), which
+ * form only the tiles bx <= by of a square grid (tn = tm), tm (tm + 1) / 2 per split, column by column. Host
+ * arithmetic only. CHEB_ERR_ARG unless 0 <= i < total, total a multiple of the tiles per split (tm * tn, or
+ * tm (tm + 1) / 2 for group -1) > 0, group >= 1 or -1 and the pointers non-null. */
 cheb_status cheb_gemm_block_item(int i, int total, int tm, int tn, int group, int* bx, int* by, int* bz);
 
 /* Message of the last failing call on `plan` ("" if none). Valid until the next call on the plan. */

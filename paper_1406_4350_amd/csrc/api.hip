@@ -252,6 +252,11 @@ size_t part_elems(int M, int N, int K) {
   const int s = gemm_split_bound(M, N, K);
   return s > 1 ? size_t(s) * M * N : 0;
 }
+// partials of an upper-triangle (Hermitian) product, N x N x K
+size_t upper_part_elems(int N, int K) {
+  const int s = gemm_upper_splits(N, K);
+  return s > 1 ? size_t(s) * N * N : 0;
+}
 
 // Scratch of the FFT passes: two disk-column buffers for a batch of bands.
 struct FftWs { void* a; void* b; void* ga = nullptr; void* gb = nullptr; };  // ga, gb: Gamma band pairs
@@ -393,7 +398,7 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
       }
       part = std::max({part_elems(np, nb, p->npw), part_elems(nb, nb, p->npw), part_elems(nb, nb, np),
                        part_elems(np, nb, nb), part_elems(nb, nb, nb), part_elems(2 * nb, nb, nb),
-                       part_elems(nb, 2 * nb, nb)});
+                       part_elems(nb, 2 * nb, nb), upper_part_elems(nb, p->npw), upper_part_elems(nb, np)});
       CHK(solver_query(p, CHEB_OP_RR, nb, &w->solver_bytes));
       w->solver = b.take<char>(std::max<size_t>(w->solver_bytes, 1));
       break;
@@ -973,24 +978,29 @@ template <typename T> struct Ops {
     // FP64 MFMA in both precisions: with complex64 blocks the products are exact and the sums over npw
     // terms keep FP64 rounding, so the subspace matrices (and the Ritz values) are limited by the FP32
     // rounding of H X only, not by FP32 accumulation over the sphere.
+    // H_X and S_X are Hermitian: the products form the tiles on and above the diagonal only (half the work), and
+    // the strictly lower part is their conjugate transpose (the eigensolver reads one triangle; the refinement
+    // the whole matrices)
     HIPCHK((gemm<double, T, T, double>(GEMM_CN, nb, nb, p->npw, X, ldx, loc, npw, eh,
-                                       gemm_pick_splits(nb, nb, p->npw), w.part, st, ROLE_SUBSPACE)));
+                                       gemm_upper_splits(nb, p->npw), w.part, st, ROLE_SUBSPACE, true)));
     Epi<double> es;
     es.out = w.Ss; es.ldo = nb; es.real_only = p->gamma != 0;
     HIPCHK((gemm<double, T, T, double>(GEMM_CN, nb, nb, p->npw, X, ldx, X, ldx, es,
-                                       gemm_pick_splits(nb, nb, p->npw), w.part, st, ROLE_SUBSPACE)));
+                                       gemm_upper_splits(nb, p->npw), w.part, st, ROLE_SUBSPACE, true)));
     if (np > 0) {
       Epi<double> e2;
       e2.out = w.Hs; e2.ldo = nb; e2.L = w.Hs; e2.ldl = nb; e2.bL = 1.0;
       HIPCHK((gemm<double, double, double, double>(GEMM_CN, nb, nb, np, w.p0, np, w.Dp, np, e2,
-                                                   gemm_pick_splits(nb, nb, np), w.part, st)));
+                                                   gemm_upper_splits(nb, np), w.part, st, ROLE_SMALL, true)));
       if (p->has_overlap) {
         Epi<double> e3;
         e3.out = w.Ss; e3.ldo = nb; e3.L = w.Ss; e3.ldl = nb; e3.bL = 1.0;
         HIPCHK((gemm<double, double, double, double>(GEMM_CN, nb, nb, np, w.p0, np, w.q, np, e3,
-                                                     gemm_pick_splits(nb, nb, np), w.part, st)));
+                                                     gemm_upper_splits(nb, np), w.part, st, ROLE_SMALL, true)));
       }
     }
+    HIPCHK(hermitian_lower(nb, w.Hs, nb, st));
+    HIPCHK(hermitian_lower(nb, w.Ss, nb, st));
     return CHEB_OK;
   }
 
@@ -2372,8 +2382,12 @@ cheb_status cheb_gemm_splits(int M, int N, int K, int* fp64, int* fp16, int* bou
 }
 
 cheb_status cheb_gemm_block_item(int i, int total, int tm, int tn, int group, int* bx, int* by, int* bz) try {
-  if (!bx || !by || !bz || tm <= 0 || tn <= 0 || total <= 0 || i < 0 || i >= total || group < 1) return CHEB_ERR_ARG;
-  if (total % (long(tm) * tn)) return CHEB_ERR_ARG;
+  if (!bx || !by || !bz || tm <= 0 || tn <= 0 || total <= 0 || i < 0 || i >= total) return CHEB_ERR_ARG;
+  if (group == -1) {  // upper-triangle tiles of a square grid
+    if (tn != tm || total % (long(tm) * (tm + 1) / 2)) return CHEB_ERR_ARG;
+  } else if (group < 1 || total % (long(tm) * tn)) {
+    return CHEB_ERR_ARG;
+  }
   gemm_block_item(i, total, tm, tn, group, *bx, *by, *bz);
   return CHEB_OK;
 } catch (...) {

@@ -40,9 +40,21 @@ constexpr int BM = 64, BN = 64, BK = 32, PAD = 1, NT = 256;
 // K-long slices. With grp = 1 the N tile runs fastest and each M tile's slice of A is read once, by all N tiles
 // at the same time: the rule for tall, short-K products (back-projection, rotation), whose A dwarfs B.
 constexpr int kTileGroup = 8;
+constexpr int kUpperTiles = -1;  // group value of the upper-triangle tile order (Hermitian products)
 __host__ __device__ inline void gemm_tile_of(int i, int total, int tm, int tn, int grp, int& bx, int& by, int& bz) {
   const int q = total / 8, rem = total % 8, k = i % 8, j = i / 8;
   const int L = (k < rem ? k * (q + 1) : rem * (q + 1) + (k - rem) * q) + j;
+  if (grp == kUpperTiles) {  // the tiles bx <= by of a square grid, column by column: t = by (by + 1) / 2 + bx
+    const int per = tm * (tm + 1) / 2;
+    bz = L / per;
+    const int t = L - bz * per;
+    int c = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (c * (c + 1) / 2 > t) --c;
+    while ((c + 1) * (c + 2) / 2 <= t) ++c;
+    by = c;
+    bx = t - c * (c + 1) / 2;
+    return;
+  }
   const int per = tm * tn;
   bz = L / per;
   const int t = L - bz * per;
@@ -309,11 +321,14 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(int M, int N, int K, int kchunk,
   }
 }
 
+// upper: only the elements of tiles bx <= by (the others' partials were not written)
 template <typename EO>
-__global__ __launch_bounds__(256) void k_reduce(int M, int N, int splits, const c128* __restrict__ part, Epi<EO> epi) {
+__global__ __launch_bounds__(256) void k_reduce(int M, int N, int splits, const c128* __restrict__ part, Epi<EO> epi,
+                                                int upper = 0) {
   const long total = long(M) * N;
   for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
     const long n = t / M, m = t - n * M;
+    if (upper && m / BM > n / BN) continue;
     double re = 0.0, im = 0.0;
     for (int s = 0; s < splits; ++s) {
       c128 v = part[long(s) * total + t];
@@ -724,8 +739,9 @@ int gemm_pick_splits(int M, int N, int K) {
 
 template <typename T, typename EA, typename EB, typename EO>
 hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, const cx<EB>* B, long ldb,
-                const Epi<EO>& epi, int splits, c128* part, hipStream_t st, GemmRole role) {
+                const Epi<EO>& epi, int splits, c128* part, hipStream_t st, GemmRole role, bool upper) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (upper && M != N) return hipErrorInvalidValue;
   if constexpr (std::is_same<T, double>::value && std::is_same<EA, double>::value && std::is_same<EB, double>::value) {
     const long blocks = long((M + 15) / 16) * ((N + 15) / 16);
     if (K <= SKMAX && blocks <= SBLKMAX) {  // splits and part are not used
@@ -747,8 +763,9 @@ hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, c
   splits = K > 0 ? (K + kchunk - 1) / kchunk : 1;
   const bool use_part = splits > 1;
   if (use_part && !part) return hipErrorInvalidValue;
-  dim3 grid(((M + BM - 1) / BM) * ((N + BN - 1) / BN) * splits);
-  const int grp = tile_group(M, K);
+  const long tm = (M + BM - 1) / BM;
+  dim3 grid(unsigned((upper ? tm * (tm + 1) / 2 : tm * ((N + BN - 1) / BN)) * splits));
+  const int grp = upper ? kUpperTiles : tile_group(M, K);
   c128* pp = use_part ? part : nullptr;
   Epi<EO> en = epi;
   const int ne = epi_slots(en);
@@ -777,7 +794,36 @@ hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, c
   const long total = long(M) * N;
   int blocks = int((total + 255) / 256);
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL((k_reduce<EO>), dim3(blocks), dim3(256), 0, st, M, N, splits, part, epi);
+  hipLaunchKernelGGL((k_reduce<EO>), dim3(blocks), dim3(256), 0, st, M, N, splits, part, epi, upper ? 1 : 0);
+  return hipGetLastError();
+}
+
+// split count of an upper-triangle product (tm (tm + 1) / 2 tiles): the fewest rounds of 512 resident blocks per
+// unit of K work, at most 8 splits and two K tiles per split
+int gemm_upper_splits(int N, int K) {
+  if (N <= 0 || K <= 0) return 1;
+  const long tm = (N + BM - 1) / BM;
+  const long kblocks = (K + BK - 1) / BK;
+  const long smax = std::max<long>(1, std::min<long>(8, kblocks / 2));
+  return int(quantized_splits(tm * (tm + 1) / 2, 512, smax));
+}
+
+__global__ void k_hermitian_lower(int n, c128* __restrict__ A, long lda) {
+  const long total = long(n) * n;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const long j = t / n, i = t - j * n;
+    if (i > j) {
+      const c128 v = A[j + i * lda];
+      A[i + j * lda] = c128{v.x, -v.y};
+    }
+  }
+}
+
+hipError_t hermitian_lower(int n, c128* A, long lda, hipStream_t st) {
+  if (n <= 1) return hipSuccess;
+  const long total = long(n) * n;
+  const int blocks = int(std::min<long>((total + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_hermitian_lower, dim3(blocks), dim3(256), 0, st, n, A, lda);
   return hipGetLastError();
 }
 
@@ -1000,7 +1046,7 @@ template hipError_t column_scales<double>(long, int, const c128*, long, float*, 
 
 #define INST(T, EA, EB, EO)                                                                               \
   template hipError_t gemm<T, EA, EB, EO>(GemmMode, int, int, int, const cx<EA>*, long, const cx<EB>*, long, \
-                                          const Epi<EO>&, int, c128*, hipStream_t, GemmRole);
+                                          const Epi<EO>&, int, c128*, hipStream_t, GemmRole, bool);
 INST(double, double, double, double)
 INST(float, float, float, float)
 INST(float, float, double, float)

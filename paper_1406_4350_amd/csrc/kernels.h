@@ -26,9 +26,15 @@ enum GemmRole { ROLE_SMALL = 0, ROLE_PROJECT = 1, ROLE_BACKPROJECT = 2, ROLE_SUB
 // T is the MFMA arithmetic type; EA/EB are the storage types of A and B (converted on load).
 // splits > 1: K is split, FP64 partial products go to `part` (splits * M * N complex doubles) and a
 // deterministic reduction applies the epilogue; splits == 1: the epilogue is applied directly.
+// upper = true (M = N, a Hermitian result): only the 64 x 64 output tiles with row tile <= column tile are
+// computed (the others are not written; hermitian_lower fills them), splits from gemm_upper_splits.
 template <typename T, typename EA, typename EB, typename EO>
 hipError_t gemm(GemmMode mode, int M, int N, int K, const cx<EA>* A, long lda, const cx<EB>* B, long ldb,
-                const Epi<EO>& epi, int splits, c128* part, hipStream_t st, GemmRole role = ROLE_SMALL);
+                const Epi<EO>& epi, int splits, c128* part, hipStream_t st, GemmRole role = ROLE_SMALL,
+                bool upper = false);
+int gemm_upper_splits(int N, int K);
+// A[i][j] = conj(A[j][i]) for i > j (n x n, column-major)
+hipError_t hermitian_lower(int n, c128* A, long lda, hipStream_t st);
 
 // number of K splits the launcher would like for an (M, N, K) product on 256 CUs
 int gemm_pick_splits(int M, int N, int K);

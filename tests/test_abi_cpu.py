@@ -215,6 +215,30 @@ def test_gemm_block_item_is_a_bijection_with_one_run_per_xcd(lib):
     assert lib.cheb_gemm_block_item(0, 4, 2, 2, 0, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == cf.CHEB_ERR_ARG
 
 
+def test_gemm_upper_triangle_items(lib):
+    """group -1 (the Hermitian Rayleigh-Ritz products): the blocks of a launch take every tile bx <= by of a square
+    tm x tm grid once per split and no tile below the diagonal, column by column inside a split, each XCD (i mod 8)
+    one contiguous run (host arithmetic)."""
+    bx, by, bz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    for tm, s in [(1, 1), (1, 5), (2, 1), (3, 4), (7, 3), (32, 8), (33, 2), (64, 1), (5, 13)]:
+        per = tm * (tm + 1) // 2
+        total = per * s
+        order = {}
+        for i in range(total):
+            assert lib.cheb_gemm_block_item(i, total, tm, tm, -1, ctypes.byref(bx), ctypes.byref(by),
+                                            ctypes.byref(bz)) == 0
+            assert 0 <= bx.value <= by.value < tm and 0 <= bz.value < s
+            order[i] = bz.value * per + by.value * (by.value + 1) // 2 + bx.value
+        assert sorted(order.values()) == list(range(total)), (tm, s)
+        for x in range(8):
+            items = sorted(order[i] for i in range(x, total, 8))
+            assert not items or items == list(range(items[0], items[0] + len(items))), (tm, s, x)
+    # tn must equal tm and total be a multiple of the tiles per split
+    assert lib.cheb_gemm_block_item(0, 6, 3, 2, -1, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == cf.CHEB_ERR_ARG
+    assert lib.cheb_gemm_block_item(0, 7, 3, 3, -1, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == cf.CHEB_ERR_ARG
+    assert lib.cheb_gemm_block_item(0, 9, 3, 3, -2, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == cf.CHEB_ERR_ARG
+
+
 def test_stability_factor_closed_form():
     """The driver's |T_m(x)| (the amplification logged per outer iteration, Sec. 5.3) against the oracle's closed
     form, inside and outside [-1, 1], and at the overflow guard."""
