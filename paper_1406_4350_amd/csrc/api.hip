@@ -43,7 +43,7 @@ struct cheb_plan_s {
   double* D = nullptr;
   double* Q = nullptr;
   c128* G = nullptr;
-  c128* Cinv = nullptr;  // [C^-1 | C^-1 G], C = Q^-1 + P^H P
+  c128* Cinv = nullptr;  // C^-1, C = Q^-1 + P^H P
   c128* Cmat = nullptr;  // C itself and the inverses of its atom blocks, for the iterative solve
   c128* Minv = nullptr;
   int cap_iters = 0;     // 0: C^-1 applied directly; k > 0: k preconditioned refinement corrections
@@ -227,7 +227,7 @@ Persist persist_layout(void* base, int n, int npw, int npf, int ncol, int rx, in
   l.D = b.take<double>(std::max<size_t>(dsize, 1));
   l.Q = b.take<double>(std::max(nproj, 1));
   l.G = b.take<c128>(size_t(nproj) * nproj);
-  l.Cinv = overlap ? b.take<c128>(2 * size_t(nproj) * nproj) : nullptr;  // [C^-1 | C^-1 G]
+  l.Cinv = overlap ? b.take<c128>(size_t(nproj) * nproj) : nullptr;  // C^-1
   l.Cmat = overlap ? b.take<c128>(size_t(nproj) * nproj) : nullptr;
   l.Minv = overlap ? b.take<c128>(std::max<size_t>(dsize, 1)) : nullptr;
   l.Hproj = l.Hback = nullptr;
@@ -842,8 +842,10 @@ template <typename T> struct Ops {
     }
     // projector space, stacked [p_loc; D p] (ld 2 np): p_loc = P^H loc, D p from the carried p = P^H psi.
     // With p_phi = P^H H psi = p_loc + G D p and q = C^-1 p_phi (Sec. 5.1):
-    //   S^-1 H psi = loc + P w,  w = D p - q = D p - [C^-1 | C^-1 G] [p_loc; D p]
-    //   P^H S^-1 H psi = p_phi - G q = p_loc + G w   (reuse trick; S = I: w = D p)
+    //   S^-1 H psi = loc + P w,  w = D p - q,   P^H S^-1 H psi = p_phi - G q = p_loc + G w   (reuse trick)
+    // With an overlap, C = Q^-1 + G gives C^-1 G = I - C^-1 Q^-1 and G = C - Q^-1, hence
+    //   w = C^-1 (Q^-1 D p - p_loc),   P^H S^-1 H psi = Q^-1 (D p - w):
+    // one nproj x nproj product per step. S = I: w = D p and P^H H psi = p_loc + G D p.
     const long l2 = 2L * np;
     c128* pl = w.ploc;
     c128* dp = w.ploc + np;
@@ -851,20 +853,9 @@ template <typename T> struct Ops {
     HIPCHK(block_diag_apply(np, nb, p->pinfo, p->D, pcur, np, dp, l2, st));
     const c128* wv = dp;
     long ldw = l2;
-    if (p->has_overlap && p->cap_iters > 0) {
-      // iterative capacitance solve: p_phi, q = C^-1 p_phi by refinement, w = D p - q
-      Epi<double> e1;
-      e1.out = w.cp; e1.ldo = np; e1.L = pl; e1.ldl = l2; e1.bL = 1.0;
-      CHK(small(p->G, np, np, dp, l2, nb, e1, w.part));
-      CHK(cinv(w.cp, np, nb, w.cq, np, w));
-      HIPCHK((axpbypcz<double>(np, nb, 1.0, dp, l2, -1.0, w.cq, np, 0.0, nullptr, 0, w.w, np, st)));
-      wv = w.w;
-      ldw = np;
-    } else if (p->has_overlap) {
-      Epi<double> e2;
-      e2.out = w.w; e2.ldo = np; e2.alpha = -1.0;
-      e2.L = dp; e2.ldl = l2; e2.bL = 1.0;
-      CHK(small(p->Cinv, np, 2 * np, pl, l2, nb, e2, w.part));
+    if (p->has_overlap) {
+      HIPCHK(overlap_rhs(np, nb, p->Q, dp, l2, pl, l2, pl, l2, st));  // u over p_loc, which is not needed after
+      CHK(cinv(pl, l2, nb, w.w, np, w));
       wv = w.w;
       ldw = np;
     }
@@ -875,6 +866,12 @@ template <typename T> struct Ops {
     e.U = cur; e.ldu = ldc; e.bU = -s1 * c;
     if (i > 1) { e.W = prev; e.ldw = ldp; e.bW = -s2; }
     CHK(backproject(wv, nb, e, w, ldw));
+    if (p->has_overlap) {
+      // p^i = s1 (Q^-1 (D p - w) - c p^(i-1)) - s2 p^(i-2)
+      HIPCHK(overlap_recur(np, nb, p->Q, dp, l2, w.w, np, s1, c, pcur, np, s2, i > 1 ? pprev : nullptr, np, pout, np,
+                           st));
+      return CHEB_OK;
+    }
     // p^i = s1 (p_loc + G w - c p^(i-1)) - s2 p^(i-2)
     Epi<double> e3;
     e3.out = pout; e3.ldo = np; e3.alpha = s1;
@@ -2209,11 +2206,6 @@ cheb_status cheb_set_projectors(cheb_plan p, const void* P, int ldp, const doubl
     if (info[0] != 0 || info[1] != 0) return fail(p, CHEB_ERR_NOT_PD, "capacitance matrix Q^-1 + P^H P is not positive definite");
     p->cap_blocks_ok = info[2] == 0;
     HIPCHK(hermitian_from_lower(np, p->Cinv, np, st));
-    // C^-1 G beside C^-1: one product then gives C^-1 p_phi = C^-1 p_loc + C^-1 G D p in the filter
-    Epi<double> ec;
-    ec.out = p->Cinv + size_t(np) * np; ec.ldo = np;
-    HIPCHK((gemm<double, double, double, double>(GEMM_NN, np, np, np, p->Cinv, np, p->G, np, ec,
-                                                 gemm_pick_splits(np, np, np), w.part, st)));
   }
   HIPCHK(hipStreamSynchronize(st));
   p->have_P = true;

@@ -142,6 +142,13 @@ hipError_t block_diag_apply_c(int nproj, int nb, const int4* pinfo, const c128* 
                               long ldo, bool accumulate, hipStream_t st);
 hipError_t diag_apply(int nproj, int nb, const double* d, const c128* in, long ldi, c128* out, long ldo,
                       hipStream_t st);
+// Projector-space steps of the filter with an overlap (S = I + P Q P^H, Q diagonal, C = Q^-1 + P^H P):
+// u = Q^-1 Dp - ploc (u may alias ploc), and out = s1 (Q^-1 (Dp - w) - c cur) - s2 prev (prev may be null)
+hipError_t overlap_rhs(int nproj, int nb, const double* Q, const c128* Dp, long ldd, const c128* ploc, long ldl,
+                       c128* u, long ldu, hipStream_t st);
+hipError_t overlap_recur(int nproj, int nb, const double* Q, const c128* Dp, long ldd, const c128* w, long ldw,
+                         double s1, double c, const c128* cur, long ldc, double s2, const c128* prev, long ldp,
+                         c128* out, long ldo, hipStream_t st);
 // out = a x + b y (+ c z), complex, any storage type
 template <typename E>
 hipError_t axpbypcz(long rows, int nb, double a, const cx<E>* x, long ldx, double b, const cx<E>* y, long ldy,

@@ -103,6 +103,38 @@ __global__ void k_block_diag_c(int nproj, int nb, const int4* __restrict__ pinfo
   }
 }
 
+// u = Q^-1 Dp - ploc (u may be ploc)
+__global__ void k_overlap_rhs(int nproj, int nb, const double* __restrict__ Q, const c128* __restrict__ Dp, long ldd,
+                              const c128* ploc, long ldl, c128* u, long ldu) {
+  const long total = long(nproj) * nb;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const int b = int(t / nproj), i = int(t - long(b) * nproj);
+    const c128 d = Dp[long(b) * ldd + i], l = ploc[long(b) * ldl + i];
+    const double q = Q[i];
+    u[long(b) * ldu + i] = c128{d.x / q - l.x, d.y / q - l.y};
+  }
+}
+
+// out = s1 (Q^-1 (Dp - w) - c cur) - s2 prev (prev may be null)
+__global__ void k_overlap_recur(int nproj, int nb, const double* __restrict__ Q, const c128* __restrict__ Dp, long ldd,
+                                const c128* __restrict__ w, long ldw, double s1, double c, const c128* __restrict__ cur,
+                                long ldc, double s2, const c128* __restrict__ prev, long ldp, c128* __restrict__ out,
+                                long ldo) {
+  const long total = long(nproj) * nb;
+  for (long t = blockIdx.x * long(blockDim.x) + threadIdx.x; t < total; t += long(gridDim.x) * blockDim.x) {
+    const int b = int(t / nproj), i = int(t - long(b) * nproj);
+    const c128 d = Dp[long(b) * ldd + i], v = w[long(b) * ldw + i], x = cur[long(b) * ldc + i];
+    const double q = Q[i];
+    double re = s1 * ((d.x - v.x) / q - c * x.x), im = s1 * ((d.y - v.y) / q - c * x.y);
+    if (prev) {
+      const c128 y = prev[long(b) * ldp + i];
+      re -= s2 * y.x;
+      im -= s2 * y.y;
+    }
+    out[long(b) * ldo + i] = c128{re, im};
+  }
+}
+
 __global__ void k_diag(int nproj, int nb, const double* __restrict__ d, const c128* __restrict__ in, long ldi,
                        c128* __restrict__ out, long ldo) {
   const long total = long(nproj) * nb;
@@ -333,6 +365,21 @@ hipError_t block_diag_apply_c(int nproj, int nb, const int4* pinfo, const c128* 
   if (nproj <= 0 || nb <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_block_diag_c, dim3(nblocks(long(nproj) * nb)), dim3(256), 0, st, nproj, nb, pinfo, M, in, ldi,
                      out, ldo, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t overlap_rhs(int nproj, int nb, const double* Q, const c128* Dp, long ldd, const c128* ploc, long ldl,
+                       c128* u, long ldu, hipStream_t st) {
+  if (nproj <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_overlap_rhs, dim3(nblocks(long(nproj) * nb)), dim3(256), 0, st, nproj, nb, Q, Dp, ldd, ploc, ldl,
+                     u, ldu);
+  return hipGetLastError();
+}
+hipError_t overlap_recur(int nproj, int nb, const double* Q, const c128* Dp, long ldd, const c128* w, long ldw,
+                         double s1, double c, const c128* cur, long ldc, double s2, const c128* prev, long ldp,
+                         c128* out, long ldo, hipStream_t st) {
+  if (nproj <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_overlap_recur, dim3(nblocks(long(nproj) * nb)), dim3(256), 0, st, nproj, nb, Q, Dp, ldd, w, ldw,
+                     s1, c, cur, ldc, s2, prev, ldp, out, ldo);
   return hipGetLastError();
 }
 hipError_t diag_apply(int nproj, int nb, const double* d, const c128* in, long ldi, c128* out, long ldo,
