@@ -24,13 +24,16 @@ constexpr int NT = 256;
 template <int N> constexpr int group_stride() { return LineSplit<N>::N2 + 1; }
 template <int N> constexpr int line_stride() { return (LineSplit<N>::N1 * group_stride<N>()) | 1; }
 
-template <typename T> constexpr int cpb() { return sizeof(T) == 8 ? 16 : 32; }  // columns per block
+// columns per block of the column passes: 16 (FP64) or 32 (FP32) on the small boxes; from 96^3 up, 8 or 16 (more,
+// smaller blocks: at 128^3 the FP32 passes took 43.3 / 55.1 us per 30-band launch with 32 and 36.7 / 39.6 with 16,
+// the FP64 forward pass 35.7 against 34.3 us; at 48^3 the smaller blocks were slower)
+template <int N, typename T> constexpr int cpb() { return N >= 96 ? (sizeof(T) == 8 ? 8 : 16) : (sizeof(T) == 8 ? 16 : 32); }
 
 template <int N, typename T>
 __global__ __launch_bounds__(NT) void k_col_inv(int ncol, const int4* __restrict__ col, const int* __restrict__ ent,
                                                 const cx<T>* __restrict__ twg, const cx<T>* __restrict__ X, long ldx,
                                                 cx<T>* __restrict__ colbuf) {
-  constexpr int CPB = cpb<T>(), LS = line_stride<N>();
+  constexpr int CPB = cpb<N, T>(), LS = line_stride<N>();
   __shared__ cx<T> lines[CPB * LS];
   __shared__ cx<T> twA[N];
   const int band = blockIdx.y;
@@ -851,7 +854,7 @@ __global__ __launch_bounds__(NT) void k_col_fwd(int ncol, const int4* __restrict
                                                 const cx<T>* __restrict__ twg, const cx<T>* __restrict__ colbuf,
                                                 const cx<T>* __restrict__ X, long ldx, const T* __restrict__ kin,
                                                 cx<T>* __restrict__ out, long ldo, T scale) {
-  constexpr int CPB = cpb<T>(), LS = line_stride<N>();
+  constexpr int CPB = cpb<N, T>(), LS = line_stride<N>();
   __shared__ cx<T> lines[CPB * LS];
   __shared__ cx<T> twA[N];
   const int band = blockIdx.y;
@@ -978,7 +981,7 @@ hipError_t fft_col_inverse(const FftGeom& g, const cx<T>* tw, const cx<T>* X, lo
   if (nb <= 0) return hipSuccess;
   return dispatch_n(g.n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    dim3 grid((g.ncol + cpb<T>() - 1) / cpb<T>(), nb);
+    dim3 grid((g.ncol + cpb<N, T>() - 1) / cpb<N, T>(), nb);
     hipLaunchKernelGGL((k_col_inv<N, T>), grid, dim3(NT), 0, st, g.ncol, g.col, g.ent, tw, X, ldx, colbuf);
     return hipGetLastError();
   });
@@ -1048,7 +1051,7 @@ hipError_t fft_col_forward(const FftGeom& g, const cx<T>* tw, const cx<T>* colbu
   const T scale = T(1.0 / (double(g.n) * g.n * g.n));
   return dispatch_n(g.n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    dim3 grid((g.ncol + cpb<T>() - 1) / cpb<T>(), nb);
+    dim3 grid((g.ncol + cpb<N, T>() - 1) / cpb<N, T>(), nb);
     hipLaunchKernelGGL((k_col_fwd<N, T>), grid, dim3(NT), 0, st, g.ncol, g.col, g.ent, tw, colbuf, X, ldx, kin, out,
                        ldo, scale);
     return hipGetLastError();
