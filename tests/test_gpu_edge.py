@@ -101,6 +101,26 @@ def test_box128_without_single_column_edge_lines():
             assert _rel(cf.to_host_block(plan.apply_H(cf.to_device_block(pb.X0, dt))), ref) < tol
 
 
+@pytest.mark.parametrize("qscale", [1.0, 0.01], ids=["q", "q_small"])
+def test_filter_with_small_overlap_coefficients(qscale):
+    """With an overlap the filter's projector-space step uses w = C^-1 (Q^-1 D p - p_loc) and P^H S^-1 H psi =
+    Q^-1 (D p - w) (C = Q^-1 + P^H P); its rounding grows with 1 / min |Q_i|. Overlap coefficients 100x smaller
+    than the workloads' (1 / Q up to 1000) keep the FP64 filter within the parity bound against the oracle."""
+    import dataclasses
+
+    pb = wl.make_problem("tiny_paw")
+    pb = dataclasses.replace(pb, Q=pb.Q * qscale)
+    ops = matfree.Operators.from_problem(pb)
+    plan = cf.plan_from_problem(pb, cf.CHEB_FP64)
+    lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
+    lm = float(np.max(matfree.rayleigh_quotients(ops, pb.X0)))
+    c, r = 0.5 * (lp + lm), 0.5 * (lp - lm)
+    Xd = cf.to_device_block(pb.X0, torch.complex128)
+    plan.filter(Xd, pb.cfg.m, c, r)
+    ref = matfree.chebyshev_filter(ops, pb.X0, pb.cfg.m, c, r)
+    assert _rel(cf.to_host_block(Xd), ref) < 1e-11
+
+
 def test_error_paths(tiny):
     pb, ops, plan = tiny
     Xd = cf.to_device_block(pb.X0, torch.complex128)
