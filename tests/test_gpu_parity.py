@@ -80,6 +80,25 @@ def test_rayleigh_ritz(case):
         assert sin < 1e-7, (a, b, sin)
 
 
+@pytest.mark.parametrize("name", ["mid_paw", "mid_nc"])
+def test_rayleigh_ritz_multi_tile(name):
+    """150 bands: the Hermitian Grams take 3 x 3 tiles of 64 (6 on and above the diagonal, the last row and column
+    ragged) and mirror the rest. Ritz values, residuals and S-orthonormality against the oracle, with and without
+    an overlap."""
+    pb = wl.make_problem(name, nb=150)
+    ops = matfree.Operators.from_problem(pb)
+    plan = cf.plan_from_problem(pb, cf.CHEB_FP64)
+    Y = matfree.chebyshev_filter(ops, pb.X0, 2, 1.0, 3.0)
+    lam, U, res = matfree.rayleigh_ritz(ops, Y)
+    Yd = cf.to_device_block(Y, torch.complex128)
+    ritz, rd = plan.rayleigh_ritz(Yd)
+    ritz = ritz.cpu().numpy()
+    assert np.all(np.abs(ritz - lam) <= 1e-10 * np.maximum(np.abs(lam), 1.0))
+    assert np.allclose(rd.cpu().numpy(), res, rtol=1e-6, atol=1e-9)
+    Ug = cf.to_host_block(Yd)
+    assert np.allclose(Ug.conj().T @ ops.apply_S(Ug), np.eye(Ug.shape[1]), atol=1e-9)
+
+
 def test_rayleigh_quotients_and_bound(case):
     pb, ops, plan = case
     Xd = cf.to_device_block(pb.X0, torch.complex128)
