@@ -352,13 +352,13 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
       w->w = b.take<c128>(pp);
       w->pfresh = b.take<c128>(pp);
       w->dcol = b.take<double>(std::max(nb, 1));
-      part = std::max({part_elems(np, nb, p->npw), part_elems(np, nb, np), part_elems(np, nb, 2 * np)});
+      part = std::max({part_elems(np, nb, p->npw), part_elems(np, nb, np)});
       if (op == CHEB_OP_FILTER_DEGREES) {
         w->Xs = b.take<char>(vec);
         w->lidx = b.take<int>(3 * size_t(std::max(nb, 1)));
         // the active block shrinks step by step; split-K partials are sized for every width up to nb
         for (int k = 1; k < nb; ++k)
-          part = std::max({part, part_elems(np, k, p->npw), part_elems(np, k, np), part_elems(np, k, 2 * np)});
+          part = std::max({part, part_elems(np, k, p->npw), part_elems(np, k, np)});
       }
       break;
     }
@@ -423,7 +423,7 @@ cheb_status ws_layout(cheb_plan p, int op, int nb, void* base, Ws* w) {
       w->lidx = b.take<int>(n3);
       // split-K partials for every width the iteration may use (active sets shrink the blocks)
       for (int k = 1; k <= std::max(nb, 1); ++k)
-        part = std::max({part, part_elems(np, k, p->npw), part_elems(np, k, np), part_elems(np, k, 2 * np)});
+        part = std::max({part, part_elems(np, k, p->npw), part_elems(np, k, np)});
       for (int k = std::max(nb, 1); k <= n3; ++k) part = std::max(part, part_elems(k, k, p->npw));
       CHK(solver_query(p, CHEB_OP_RR, n3, &w->solver_bytes));
       w->solver = b.take<char>(std::max<size_t>(w->solver_bytes, 1));
