@@ -48,6 +48,18 @@ def test_padded_leading_dimension(tiny):
     ref = matfree.chebyshev_filter(ops, pb.X0, 4, 0.5 * (lp + 1.0), 0.5 * (lp - 1.0))
     assert _rel(cf.to_host_block(Xv), ref) < 1e-11
     assert torch.all(buf[:, pb.npw:] == 7.0 + 3.0j)
+    # the carried-projection entry points on the same padded rows: Rayleigh-Ritz returns P^H of its rotated block
+    # and the filter starts from it
+    Y = cf.to_host_block(Xv)
+    pz = plan.projections(pb.cfg.nb)
+    plan.rayleigh_ritz(Xv, p_out=pz)
+    Yr = cf.to_host_block(Xv)
+    assert _rel(pz.cpu().numpy().T, ops.P.conj().T @ Yr) < 1e-12
+    lam, _, _ = matfree.rayleigh_ritz(ops, Y)
+    c, r = 0.5 * (lp + lam.max()), 0.5 * (lp - lam.max())
+    plan.filter(Xv, 3, c, r, p_in=pz)
+    assert _rel(cf.to_host_block(Xv), matfree.chebyshev_filter(ops, Yr, 3, c, r)) < 1e-11
+    assert torch.all(buf[:, pb.npw:] == 7.0 + 3.0j)
 
 
 def test_free_electron_spectrum_on_gpu():
