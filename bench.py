@@ -63,9 +63,11 @@ def run_path(cf, pb, prec, lam_plus, steps, warmup, resync=None):
 
     rq = plan.rayleigh_quotients(X)
     state = {"lam_minus": float(rq.max().item()), "lam_low": float(rq.min().item()), "stability": 0.0}
-    # Rayleigh-Ritz hands the projections P^H X of its rotated block to the next filter (cheb_rayleigh_ritz_carry,
-    # cheb_filter_carry), so a step computes them once
+    # Rayleigh-Ritz hands the projections P^H X and (K + V) X of its rotated block to the next filter
+    # (cheb_rayleigh_ritz_carry, cheb_filter_carry), so a step computes the projections once and transforms the
+    # block m + 1 times
     pc = plan.projections(nb) if plan.nproj > 0 else None
+    hx = torch.empty_like(X)
     state["carried"] = False
 
     def step():
@@ -73,9 +75,9 @@ def run_path(cf, pb, prec, lam_plus, steps, warmup, resync=None):
         r = 0.5 * (lam_plus - state["lam_minus"])
         # amplification of the lowest band by this filter (Sec. 5.3: must stay far below 1/eps)
         state["stability"] = max(state["stability"], chebyshev_magnitude(m, (state["lam_low"] - c) / r))
-        plan.filter(X, m, c, r, p_in=pc if state["carried"] else None)
-        ritz, res = plan.rayleigh_ritz(X, p_out=pc)
-        state["carried"] = pc is not None
+        plan.filter(X, m, c, r, p_in=pc if state["carried"] else None, hx_in=hx if state["carried"] else None)
+        ritz, res = plan.rayleigh_ritz(X, p_out=pc, hx_out=hx)
+        state["carried"] = True
         state["ritz"], state["res"] = ritz, res
         state["lam_minus"] = float(ritz.max().item())
         state["lam_low"] = min(state["lam_low"], float(ritz.min().item()))
@@ -97,19 +99,20 @@ def run_path(cf, pb, prec, lam_plus, steps, warmup, resync=None):
     c = 0.5 * (lam_plus + state["lam_minus"])
     r = 0.5 * (lam_plus - state["lam_minus"])
     reps = max(2, min(steps, 3))
-    filter_ms = time_filter(plan, X, m, c, r, reps, pc)
+    filter_ms = time_filter(plan, X, m, c, r, reps, pc, hx)
     out = dict(plan=plan, X=X, seconds=t1 - t0, prof=prof, filter_ms=filter_ms, state=state, rr_stats=rr_stats,
                apps_per_s=nb * m * steps / (t1 - t0), filter_apps_per_s=nb * m / (filter_ms * 1e-3), resync=resync)
     return out
 
 
-def time_filter(plan, X, m, c, r, reps, pc=None):
+def time_filter(plan, X, m, c, r, reps, pc=None, hx=None):
     """Mean event time (ms) of the filter on a fresh copy of X, as the bench step calls it (starting from the
-    projections pc that Rayleigh-Ritz returned for X, when given); the copies are outside the timed events."""
+    projections pc and (K + V) X hx that Rayleigh-Ritz returned for X, when given); the copies are outside the
+    timed events."""
     import torch
 
     Xf = X.clone()
-    kw = {} if pc is None else {"p_in": pc}
+    kw = {"p_in": pc, "hx_in": hx}
     plan.filter(Xf, m, c, r, **kw)  # warm-up
     total = 0.0
     for _ in range(reps):

@@ -146,17 +146,20 @@ cheb_status cheb_apply_H_noalloc(cheb_plan plan, const void* X, int ldx, void* Y
 cheb_status cheb_filter(cheb_plan plan, void* X, int ldx, int nb, int m, double c, double r, void* ws,
                         size_t ws_bytes, hipStream_t stream);
 
-/* cheb_filter starting from given projections: the reuse trick of Sec. 5.1 extended over the Rayleigh-Ritz
- * step, so an outer iteration computes P^H X once (inside Rayleigh-Ritz) instead of once per call. p_in: the
- * projections P^H X of the input block (device, nproj x nb complex FP64, column j = band j, leading dimension
- * nproj), normally p_out of cheb_rayleigh_ritz_carry on the same block; used instead of computing them (a plain
- * copy). Caller-owned and not modified; the block must not change between the call that produced p_in and this
- * one. May be NULL when the plan has no projectors, nb = 0 or m = 0; else NULL gives CHEB_ERR_ARG. Results
- * equal cheb_filter's up to the rounding in p_in. Projections carried in both directions with no recomputation
- * in between would let the difference between X and its projections grow by the filter's amplification at every
- * outer iteration, which is why the filter takes projections but returns none. Same workspace as cheb_filter. */
+/* cheb_filter starting from quantities of the input block that the caller already holds: the reuse trick of
+ * Sec. 5.1 extended over the Rayleigh-Ritz step, so that an outer iteration computes P^H X once (inside
+ * Rayleigh-Ritz) instead of once per call, and transforms the block one time fewer. p_in: NULL, or the projections
+ * P^H X of the input block (device, nproj x nb complex FP64, column j = band j, leading dimension nproj); hx_in:
+ * NULL, or (K + V) X of the input block, the local part of H X (device, nb rows of npw values in the plan
+ * precision, leading dimension npw). Normally both are the outputs of cheb_rayleigh_ritz_carry on the same block;
+ * each is used instead of computing it (a NULL one is computed as cheb_filter does). Caller-owned and not
+ * modified; the block must not change between the call that produced them and this one. Results equal
+ * cheb_filter's up to the rounding of the given values. Projections carried in both directions with no
+ * recomputation in between would let the difference between X and its projections grow by the filter's
+ * amplification at every outer iteration, which is why the filter takes these quantities but returns none.
+ * Same workspace as cheb_filter. */
 cheb_status cheb_filter_carry(cheb_plan plan, void* X, int ldx, int nb, int m, double c, double r, const void* p_in,
-                              void* ws, size_t ws_bytes, hipStream_t stream);
+                              const void* hx_in, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Locking (Sec. 5.4): the same filter with its own degree per band, X[:, b] <- T_{deg[b]}((S^-1 H - c)/r) X[:, b].
  * degrees: nb host int32 values >= 0; a band of degree 0 is left unchanged (locked). Bands are gathered in
@@ -184,14 +187,17 @@ cheb_status cheb_locking_degrees(int nb, const double* ritz, const double* resid
 cheb_status cheb_rayleigh_ritz(cheb_plan plan, void* X, int ldx, int nb, double* ritz_dev, double* resid_dev,
                                void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* cheb_rayleigh_ritz that also returns the projections of the rotated block, p_out = (P^H X) Z, formed from the
- * exact projections of the input block that the subspace matrices need anyway (with residuals the product is
- * already there; without, one nproj x nb x nb FP64 GEMM). p_out: device, nproj x nb complex FP64, column j =
- * band j, leading dimension nproj, caller-owned; NULL only when the plan has no projectors or nb = 0, else
- * CHEB_ERR_ARG. In a mixed plan the rotated block is rounded to complex64 after the product, so p_out matches it
- * to float32 rounding. Same workspace as cheb_rayleigh_ritz. */
+/* cheb_rayleigh_ritz that also returns two quantities of the rotated block for the next cheb_filter_carry.
+ * p_out: NULL, or P^H of the rotated block, (P^H X) Z, formed from the exact projections of the input block that
+ * the subspace matrices need anyway (with residuals the product is already there; without, one nproj x nb x nb
+ * FP64 GEMM); device, nproj x nb complex FP64, column j = band j, leading dimension nproj. hx_out: NULL, or
+ * (K + V) of the rotated block, ((K + V) X) Z, formed from the local part of H X that the subspace matrices use
+ * (with residuals the product is already there, one copy; without, one npw x nb x nb GEMM); device, nb rows of
+ * npw values in the plan precision, leading dimension npw. Both caller-owned. In a mixed plan the rotated block
+ * is rounded to complex64 after the products, so the outputs match it to float32 rounding. Same workspace as
+ * cheb_rayleigh_ritz. */
 cheb_status cheb_rayleigh_ritz_carry(cheb_plan plan, void* X, int ldx, int nb, double* ritz_dev, double* resid_dev,
-                                     void* p_out, void* ws, size_t ws_bytes, hipStream_t stream);
+                                     void* p_out, void* hx_out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* LOBPCG, the block method the paper compares the filter with (Sec. 2.3), on the same operators: one
  * iteration per call. iteration = 0: Rayleigh-Ritz of X (start); 1: Rayleigh-Ritz in span[X, W]; >= 2: in

@@ -79,8 +79,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cheb_apply_Sinv": [vp, vp, i, vp, i, i, vp, sz, vp],
         "cheb_filter": [vp, vp, i, i, i, d, d, vp, sz, vp],
         "cheb_rayleigh_ritz": [vp, vp, i, i, vp, vp, vp, sz, vp],
-        "cheb_filter_carry": [vp, vp, i, i, i, d, d, vp, vp, sz, vp],
-        "cheb_rayleigh_ritz_carry": [vp, vp, i, i, vp, vp, vp, vp, sz, vp],
+        "cheb_filter_carry": [vp, vp, i, i, i, d, d, vp, vp, vp, sz, vp],
+        "cheb_rayleigh_ritz_carry": [vp, vp, i, i, vp, vp, vp, vp, vp, sz, vp],
         "cheb_rayleigh_quotients": [vp, vp, i, i, vp, vp, sz, vp],
         "cheb_upper_bound": [vp, i, vp, P(d), vp, sz, vp],
         "cheb_profile_enable": [vp, i],
@@ -280,18 +280,19 @@ class Plan:
     def apply_Sinv(self, X, Y=None):
         return self._apply("cheb_apply_Sinv", CHEB_OP_SINV, X, Y)
 
-    def filter(self, X, m: int, c: float, r: float, p_in=None):
+    def filter(self, X, m: int, c: float, r: float, p_in=None, hx_in=None):
         """X <- T_m((S^-1 H - c)/r) X. p_in: None, or the projections P^H X of the block (a complex128 (nb, nproj)
-        device tensor, row j = band j, e.g. p_out of rayleigh_ritz; see cheb_filter_carry)."""
+        device tensor, row j = band j); hx_in: None, or (K + V) X (an (nb, npw) device tensor of the plan's dtype);
+        normally the p_out and hx_out of rayleigh_ritz (see cheb_filter_carry)."""
         nb, ldx = self._block(X, "X")
         ws = self.workspace(CHEB_OP_FILTER, nb)
-        if p_in is None:
+        if p_in is None and hx_in is None:
             self._check(self.lib.cheb_filter(self.handle, X.data_ptr(), ldx, nb, int(m), float(c), float(r),
                                              ws.data_ptr(), ws.numel(), _stream()), "cheb_filter")
             return X
         self._check(self.lib.cheb_filter_carry(self.handle, X.data_ptr(), ldx, nb, int(m), float(c), float(r),
-                                               self._proj(p_in, nb), ws.data_ptr(), ws.numel(), _stream()),
-                    "cheb_filter_carry")
+                                               self._proj(p_in, nb), self._local(hx_in, nb), ws.data_ptr(),
+                                               ws.numel(), _stream()), "cheb_filter_carry")
         return X
 
     def projections(self, nb: int) -> torch.Tensor:
@@ -309,6 +310,13 @@ class Plan:
             raise ValueError(f"projections must have {self.nproj} columns")
         return t.data_ptr()
 
+    def _local(self, t, nb):
+        if t is None:
+            return None
+        if t.dtype != self.dtype or t.device.type != "cuda" or not t.is_contiguous() or tuple(t.shape) != (nb, self.npw):
+            raise ValueError(f"(K + V) X must be a contiguous {self.dtype} ({nb}, {self.npw}) device tensor")
+        return t.data_ptr()
+
     def filter_degrees(self, X, degrees, c: float, r: float):
         """Per-band degrees (locking): X[b] <- T_{degrees[b]}((S^-1 H - c)/r) X[b]; degree 0 leaves a band as is."""
         nb, ldx = self._block(X, "X")
@@ -321,21 +329,22 @@ class Plan:
                     "cheb_filter_degrees")
         return X
 
-    def rayleigh_ritz(self, X, with_residuals: bool = True, p_out=None):
+    def rayleigh_ritz(self, X, with_residuals: bool = True, p_out=None, hx_out=None):
         """In-place Rayleigh-Ritz; returns (Ritz values, residual norms or None). p_out: None, or a complex128
-        (nb, nproj) device tensor that receives the projections P^H X of the rotated block (see
+        (nb, nproj) device tensor that receives the projections P^H X of the rotated block; hx_out: None, or an
+        (nb, npw) device tensor of the plan's dtype that receives (K + V) X of the rotated block (see
         cheb_rayleigh_ritz_carry)."""
         nb, ldx = self._block(X, "X")
         ritz = torch.empty(nb, dtype=torch.float64, device=self.device)
         res = torch.empty(nb, dtype=torch.float64, device=self.device) if with_residuals else None
         ws = self.workspace(CHEB_OP_RR, nb)
-        if p_out is None:
+        if p_out is None and hx_out is None:
             self._check(self.lib.cheb_rayleigh_ritz(self.handle, X.data_ptr(), ldx, nb, ritz.data_ptr(), _ptr(res),
                                                     ws.data_ptr(), ws.numel(), _stream()), "cheb_rayleigh_ritz")
         else:
             self._check(self.lib.cheb_rayleigh_ritz_carry(self.handle, X.data_ptr(), ldx, nb, ritz.data_ptr(),
-                                                          _ptr(res), self._proj(p_out, nb), ws.data_ptr(),
-                                                          ws.numel(), _stream()),
+                                                          _ptr(res), self._proj(p_out, nb), self._local(hx_out, nb),
+                                                          ws.data_ptr(), ws.numel(), _stream()),
                         "cheb_rayleigh_ritz_carry")
         return ritz, res
 

@@ -828,14 +828,20 @@ template <typename T> struct Ops {
   // One step of the recurrence (Alg. 2 inner loop): out = s1 (S^-1 H cur - c cur) - s2 prev, with the
   // projections p = P^H psi carried alongside (reuse trick, Sec. 5.1). out may alias prev (and pout pprev);
   // prev / pprev are unused for i = 1.
+  // loc_in: (K + V) cur given by the caller (ld npw), else computed here
   cheb_status filter_step(int i, const C* cur, long ldc, const C* prev, long ldp, C* out, long ldo,
-                          const c128* pcur, const c128* pprev, c128* pout, int nb, double c, double r, const Ws& w) {
+                          const c128* pcur, const c128* pprev, c128* pout, int nb, double c, double r, const Ws& w,
+                          const C* loc_in = nullptr) {
     const int np = p->nproj;
     const long npw = p->npw;
-    C* loc = static_cast<C*>(w.loc);
     const double s1 = (i == 1 ? 1.0 : 2.0) / r;
     const double s2 = (i == 1 ? 0.0 : 1.0);
-    CHK(hloc(cur, ldc, nb, loc, npw, w.fft));
+    const C* loc = loc_in;
+    if (!loc) {
+      C* lw = static_cast<C*>(w.loc);
+      CHK(hloc(cur, ldc, nb, lw, npw, w.fft));
+      loc = lw;
+    }
     if (np == 0) {
       HIPCHK((axpbypcz<T>(npw, nb, s1, loc, npw, -s1 * c, cur, ldc, -s2, i == 1 ? nullptr : prev, ldp, out, ldo, st)));
       return CHEB_OK;
@@ -909,8 +915,10 @@ template <typename T> struct Ops {
 
   // Alg. 2 inner loop for the whole block. psi^i overwrites psi^(i-2); buffers alternate X, W. With pin, the
   // projections P^H X come from the caller (those the previous Rayleigh-Ritz step returned for its rotated block)
-  // instead of a product over the sphere (nproj x nb, ld nproj).
-  cheb_status filter(C* X, long ldx, int nb, int m, double c, double r, const Ws& w, const c128* pin = nullptr) {
+  // instead of a product over the sphere (nproj x nb, ld nproj); with hxin, so does (K + V) X (nb rows of npw),
+  // which the first step then does not transform.
+  cheb_status filter(C* X, long ldx, int nb, int m, double c, double r, const Ws& w, const c128* pin = nullptr,
+                     const C* hxin = nullptr) {
     if (m == 0 || nb == 0) return CHEB_OK;
     const int np = p->nproj;
     const long npw = p->npw;
@@ -924,7 +932,8 @@ template <typename T> struct Ops {
     for (int i = 1; i <= m; ++i) {
       const int ci = (i - 1) & 1, oi = i & 1;
       CHK(resync_step(i, buf[ci], ld[ci], pb[ci], buf[oi], ld[oi], pb[oi], nb, w));
-      CHK(filter_step(i, buf[ci], ld[ci], buf[oi], ld[oi], buf[oi], ld[oi], pb[ci], pb[oi], pb[oi], nb, c, r, w));
+      CHK(filter_step(i, buf[ci], ld[ci], buf[oi], ld[oi], buf[oi], ld[oi], pb[ci], pb[oi], pb[oi], nb, c, r, w,
+                      i == 1 ? hxin : nullptr));
     }
     if (m & 1) HIPCHK((convert_copy<T, T>(npw, nb, buf[1], npw, X, ldx, st)));
     return CHEB_OK;
@@ -1197,9 +1206,10 @@ template <typename T> struct Ops {
     return true;
   }
 
-  // pout: the projections of the rotated block, (P^H X) Z with the exact P^H X (nproj x nb, ld nproj)
+  // pout: the projections of the rotated block, (P^H X) Z with the exact P^H X (nproj x nb, ld nproj);
+  // hxout: (K + V) of the rotated block, ((K + V) X) Z (nb rows of npw)
   cheb_status rayleigh_ritz(C* X, long ldx, int nb, double* ritz, double* resid, const Ws& w,
-                            c128* pout = nullptr) {
+                            c128* pout = nullptr, C* hxout = nullptr) {
     const int np = p->nproj;
     const long npw = p->npw;
     CHK(subspace(X, ldx, nb, w));
@@ -1339,6 +1349,14 @@ template <typename T> struct Ops {
         e1.out = R; e1.ldo = npw;
         HIPCHK((gemm<double, T, double, T>(GEMM_NN, p->npw, nb, nb, static_cast<C*>(w.loc), npw, w.Hs, nb, e1, 1,
                                            nullptr, st, ROLE_SUBSPACE)));
+        if (hxout) HIPCHK((convert_copy<T, T>(npw, nb, R, npw, hxout, npw, st)));  // before P t is added
+      } else if (hxout) {
+        Epi<T> e1;
+        e1.out = hxout; e1.ldo = npw;
+        HIPCHK((gemm<double, T, double, T>(GEMM_NN, p->npw, nb, nb, static_cast<C*>(w.loc), npw, w.Hs, nb, e1, 1,
+                                           nullptr, st, ROLE_SUBSPACE)));
+      }
+      if (resid) {
         if (np > 0) {
           Epi<double> ez;
           ez.out = w.q; ez.ldo = np;
@@ -2300,17 +2318,17 @@ cheb_status cheb_filter(cheb_plan p, void* X, int ldx, int nb, int m, double c, 
 }
 
 cheb_status cheb_filter_carry(cheb_plan p, void* X, int ldx, int nb, int m, double c, double r, const void* p_in,
-                              void* ws, size_t wsb, hipStream_t st) try {
+                              const void* hx_in, void* ws, size_t wsb, hipStream_t st) try {
   if (!p) return CHEB_ERR_ARG;
   CHK(check_block(p, X, ldx, nb, "X"));
   if (m < 0) return fail(p, CHEB_ERR_ARG, "degree m < 0");
   if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite(c)) return fail(p, CHEB_ERR_ARG, "need finite c and r > 0");
-  if (nb > 0 && m > 0 && p->nproj > 0 && !p_in) return fail(p, CHEB_ERR_ARG, "p_in is null");
   if (nb == 0) return CHEB_OK;
   OP_PRELUDE(CHEB_OP_FILTER, nb);
   return with_prec(p, st, [&](auto ops) {
     using C = typename decltype(ops)::C;
-    return ops.filter(static_cast<C*>(X), ldx, nb, m, c, r, w, static_cast<const c128*>(p_in));
+    return ops.filter(static_cast<C*>(X), ldx, nb, m, c, r, w, static_cast<const c128*>(p_in),
+                      static_cast<const C*>(hx_in));
   });
 } catch (...) {
   return host_fail(p);
@@ -2432,16 +2450,16 @@ cheb_status cheb_rayleigh_ritz(cheb_plan p, void* X, int ldx, int nb, double* ri
 }
 
 cheb_status cheb_rayleigh_ritz_carry(cheb_plan p, void* X, int ldx, int nb, double* ritz, double* resid,
-                                     void* p_out, void* ws, size_t wsb, hipStream_t st) try {
+                                     void* p_out, void* hx_out, void* ws, size_t wsb, hipStream_t st) try {
   if (!p) return CHEB_ERR_ARG;
   CHK(check_block(p, X, ldx, nb, "X"));
   if (nb > 0 && !ritz) return fail(p, CHEB_ERR_ARG, "ritz is null");
-  if (nb > 0 && p->nproj > 0 && !p_out) return fail(p, CHEB_ERR_ARG, "p_out is null");
   if (nb == 0) return CHEB_OK;
   OP_PRELUDE(CHEB_OP_RR, nb);
   return with_prec(p, st, [&](auto ops) {
     using C = typename decltype(ops)::C;
-    return ops.rayleigh_ritz(static_cast<C*>(X), ldx, nb, ritz, resid, w, static_cast<c128*>(p_out));
+    return ops.rayleigh_ritz(static_cast<C*>(X), ldx, nb, ritz, resid, w, static_cast<c128*>(p_out),
+                             static_cast<C*>(hx_out));
   });
 } catch (...) {
   return host_fail(p);

@@ -28,8 +28,8 @@ def chebfsi(plan: Plan, X: torch.Tensor, m: int, iters: int, lam_plus: float, ca
     Rayleigh-Ritz-rotated block are its Ritz values). With lock_tol, after each Rayleigh-Ritz step every band
     gets the degree the residual estimate of Eq. 5 asks for to reach lock_tol with the next filter (at most m,
     0 = locked; Sec. 5.4); the first iteration uses m for all bands. With carry, Rayleigh-Ritz returns the
-    projections P^H X of the rotated block and the next filter starts from them instead of recomputing them
-    (see cheb_filter_carry). Each history record
+    projections P^H X and (K + V) X of the rotated block and the next filter starts from them instead of
+    recomputing them (see cheb_filter_carry). Each history record
     also carries the amplification T_m((lambda_1 - c)/r) of the lowest band (lambda_1: the lowest Ritz value so
     far, the lowest Rayleigh quotient before the first Rayleigh-Ritz step), which must stay far below 1/eps of
     the band precision for the filtered block to stay well conditioned (Sec. 5.3). Returns (ritz, residuals,
@@ -42,9 +42,10 @@ def chebfsi(plan: Plan, X: torch.Tensor, m: int, iters: int, lam_plus: float, ca
     hist = []
     ritz = res = None
     nb = X.shape[0]
-    # carry: Rayleigh-Ritz hands the projections of its rotated block to the next filter
+    # carry: Rayleigh-Ritz hands the projections and (K + V) X of its rotated block to the next filter
     # (cheb_rayleigh_ritz_carry, cheb_filter_carry), which then does not compute them
     pc = plan.projections(nb) if carry and plan.nproj > 0 else None
+    hx = torch.empty((nb, X.shape[1]), dtype=X.dtype, device=X.device) if carry else None
     have = False
     for it in range(iters):
         if not lam_plus > lam_minus:
@@ -56,11 +57,11 @@ def chebfsi(plan: Plan, X: torch.Tensor, m: int, iters: int, lam_plus: float, ca
             degrees, nlocked = locking_degrees(hist[-1]["ritz"], hist[-1]["resid"], c, r, m, lock_tol)
         t0 = time.perf_counter()
         if degrees is None:
-            plan.filter(X, m, c, r, p_in=pc if have else None)
+            plan.filter(X, m, c, r, p_in=pc if have else None, hx_in=hx if have else None)
         else:
             plan.filter_degrees(X, degrees, c, r)
-        ritz, res = plan.rayleigh_ritz(X, with_residuals=with_residuals, p_out=pc)
-        have = pc is not None
+        ritz, res = plan.rayleigh_ritz(X, with_residuals=with_residuals, p_out=pc, hx_out=hx)
+        have = carry
         torch.cuda.synchronize()
         rec = dict(it=it, c=c, r=r, lam_minus=lam_minus, seconds=time.perf_counter() - t0,
                    stability=chebyshev_magnitude(m, (lam_low - c) / r),

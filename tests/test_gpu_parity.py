@@ -125,62 +125,73 @@ def test_outer_loop_trajectory(case, carry):
 
 
 def test_carried_projections_match_recomputed(case):
-    """cheb_rayleigh_ritz_carry returns P^H of its rotated block, with and without residuals; cheb_filter_carry
-    started from those projections equals cheb_filter, in FP64 and in mixed plans."""
+    """cheb_rayleigh_ritz_carry returns P^H and (K + V) of its rotated block, with and without residuals;
+    cheb_filter_carry started from them equals cheb_filter, in FP64 and in mixed plans."""
     pb, ops, plan = case
     nb, m = pb.cfg.nb, pb.cfg.m
     lp = matfree.lanczos_upper_bound(ops, pb.v0, 10)[0]
     lm = float(np.max(matfree.rayleigh_quotients(ops, pb.X0)))
     c, r = 0.5 * (lp + lm), 0.5 * (lp - lm)
     PH = ops.P.conj().T if pb.nproj > 0 else None
+
+    def local(Y):  # (K + V) Y
+        return ops.kin[:, None] * Y + ops.vloc(Y)
+
     for with_res in (True, False):
         X = cf.to_device_block(pb.X0, torch.complex128)
         Xr = cf.to_device_block(pb.X0, torch.complex128)
         pz = plan.projections(nb)
+        hz = torch.empty_like(X)
         ra, _ = plan.rayleigh_ritz(Xr, with_residuals=with_res)
-        rb, _ = plan.rayleigh_ritz(X, with_residuals=with_res, p_out=pz)
+        rb, _ = plan.rayleigh_ritz(X, with_residuals=with_res, p_out=pz, hx_out=hz)
         assert torch.equal(ra, rb) and torch.equal(X, Xr)
         if PH is not None:
             assert _rel(pz.cpu().numpy().T, PH @ cf.to_host_block(X)) < 1e-12
-    # the filter from the returned projections against the filter that computes them, and the oracle
+        assert _rel(cf.to_host_block(hz), local(cf.to_host_block(X))) < 1e-12
+    # the filter from the returned quantities against the filter that computes them, and the oracle
     Xa = X.clone()
     plan.filter(Xa, m, c, r)
-    plan.filter(X, m, c, r, p_in=pz)
-    assert _rel(cf.to_host_block(X), cf.to_host_block(Xa)) < 1e-11
+    Xb = X.clone()
+    plan.filter(Xb, m, c, r, hx_in=hz)
+    plan.filter(X, m, c, r, p_in=pz, hx_in=hz)
+    for Y in (X, Xb):
+        assert _rel(cf.to_host_block(Y), cf.to_host_block(Xa)) < 1e-11
     assert _rel(cf.to_host_block(X), matfree.chebyshev_filter(ops, cf.to_host_block(Xr), m, c, r)) < 1e-11
     # m = 0 leaves the block as it is
     Xa.copy_(X)
-    plan.filter(Xa, 0, c, r, p_in=pz)
+    plan.filter(Xa, 0, c, r, p_in=pz, hx_in=hz)
     assert torch.equal(Xa, X)
-    # mixed plan: the FP64 projections of the rotated complex64 block start the filter
+    # mixed plan: the quantities of the rotated complex64 block start the filter
     pm = cf.plan_from_problem(pb, cf.CHEB_MIXED)
     Xm = cf.to_device_block(pb.X0, torch.complex64)
     pzm = pm.projections(nb)
-    pm.rayleigh_ritz(Xm, p_out=pzm)
+    hzm = torch.empty_like(Xm)
+    pm.rayleigh_ritz(Xm, p_out=pzm, hx_out=hzm)
     Y = cf.to_host_block(Xm)
     if PH is not None:
         assert _rel(pzm.cpu().numpy().T, PH @ Y) < 1e-6
+    assert _rel(cf.to_host_block(hzm), local(Y)) < 1e-5
     ref = matfree.chebyshev_filter(ops, Y, m, c, r)
     Xn = Xm.clone()
     pm.filter(Xn, m, c, r)
-    pm.filter(Xm, m, c, r, p_in=pzm)
+    pm.filter(Xm, m, c, r, p_in=pzm, hx_in=hzm)
     assert _rel(cf.to_host_block(Xn), ref) < 1e-4
     assert _rel(cf.to_host_block(Xm), ref) < 1e-4
-    # wrong buffers are refused by the binding, missing ones by the library when the plan has projectors
+    # wrong buffers are refused by the binding; NULL ones are computed by the library
     with pytest.raises(ValueError):
         plan.filter(X, m, c, r, p_in=pz.to(torch.complex64))
     with pytest.raises(ValueError):
+        plan.filter(X, m, c, r, hx_in=hz.to(torch.complex64))
+    with pytest.raises(ValueError):
         plan.rayleigh_ritz(X, p_out=pz[: nb - 1])
-    if PH is not None:
-        ws = plan.workspace(cf.CHEB_OP_FILTER, nb)
-        st = plan.lib.cheb_filter_carry(plan.handle, X.data_ptr(), X.shape[1], nb, m, c, r, None, ws.data_ptr(),
-                                        ws.numel(), cf._stream())
-        assert st == cf.CHEB_ERR_ARG
-        ritz = torch.empty(nb, dtype=torch.float64, device=X.device)
-        ws = plan.workspace(cf.CHEB_OP_RR, nb)
-        st = plan.lib.cheb_rayleigh_ritz_carry(plan.handle, X.data_ptr(), X.shape[1], nb, ritz.data_ptr(), None,
-                                               None, ws.data_ptr(), ws.numel(), cf._stream())
-        assert st == cf.CHEB_ERR_ARG
+    with pytest.raises(ValueError):
+        plan.rayleigh_ritz(X, hx_out=hz[: nb - 1])
+    Xc, Xd = X.clone(), X.clone()
+    plan.filter(Xc, m, c, r)
+    ws = plan.workspace(cf.CHEB_OP_FILTER, nb)
+    st = plan.lib.cheb_filter_carry(plan.handle, Xd.data_ptr(), Xd.shape[1], nb, m, c, r, None, None, ws.data_ptr(),
+                                    ws.numel(), cf._stream())
+    assert st == 0 and torch.equal(Xc, Xd)
 
 
 @pytest.mark.parametrize("split", [True, False], ids=["fp16x2-split", "fp32-mfma"])
