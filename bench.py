@@ -65,7 +65,7 @@ def run_path(cf, pb, prec, lam_plus, steps, warmup, resync=None):
     state = {"lam_minus": float(rq.max().item()), "lam_low": float(rq.min().item()), "stability": 0.0}
     # Rayleigh-Ritz hands the projections P^H X and (K + V) X of its rotated block to the next filter
     # (cheb_rayleigh_ritz_carry, cheb_filter_carry), so a step computes the projections once and transforms the
-    # block m + 1 times
+    # block m times (the filter's steps 2 .. m and Rayleigh-Ritz)
     pc = plan.projections(nb) if plan.nproj > 0 else None
     hx = torch.empty_like(X)
     state["carried"] = False
